@@ -1,0 +1,185 @@
+/*
+ * seasd.h - C ABI of the MI355X (gfx950) Spectral Ewald far-field mobility
+ * library: the periodic grand-mobility product of Spectral Ewald accelerated
+ * Stokesian Dynamics and the GMRES far-field solve that calls it.
+ *
+ * Reference: M. Wang and J. F. Brady, "Spectral Ewald Acceleration of
+ * Stokesian Dynamics for polydisperse suspensions" (arXiv:1506.08481).
+ *
+ * Operator. For N spheres with centres r_i and radii a_i in a periodic cell,
+ * y = M x with 12 components per sphere:
+ *   x_i = (F_i[3], T_i[3], S_i[5], s_i)  force, torque, traceless stresslet
+ *         and pressure-moment coordinate, all exerted by sphere i on the fluid;
+ *   y_i = (U_i[3], W_i[3], E_i[5], e_i)  velocity, spin, (minus the ambient)
+ *         rate of strain and its trace coordinate.
+ * The five traceless coordinates use the orthonormal basis
+ *   Y0 = (xx - yy)/sqrt2, Y1 = (2zz - xx - yy)/sqrt6,
+ *   Y2 = (xy + yx)/sqrt2, Y3 = (xz + zx)/sqrt2, Y4 = (yz + zy)/sqrt2,
+ * and the trace coordinate is trace/sqrt3, so that S:E is a plain dot product.
+ * M is the Rotne-Prager-level grand mobility built from the Faxen laws and
+ * multipole expansion (Sec. 2.1, eqs. faxen-f, faxen-t, faxen-s,
+ * mul-expand), the periodic Oseen tensor (Sec. 2.2, eq. oseen-peridoic) and
+ * the compressible-solvent pressure-moment couplings (Sec. 2.3, eqs.
+ * pres-vel-disturb, faxen-p, pres-multi-expans, wave-dist-S). The 11x11
+ * incompressible block is symmetric positive definite; the trace row is the
+ * one-way pressure coupling of Sec. 2.3, so M as a whole is not symmetric.
+ *
+ * Evaluation (Sec. 3): Hasimoto's Ewald split (Sec. 2.2, eqs.
+ * oseen-ewald-rs, oseen-ewald-ws, source-split) into
+ *   - a real-space pair sum over neighbour bins within
+ *     r_c = rc_factor (a_i + a_j) (Sec. 3.3), recomputed on every call;
+ *   - a Spectral Ewald wave-space part (Sec. 3.1-3.2, eqs. rp-wave-tq,
+ *     shape, grid-space, wave-result, parseval-sum): Gaussian spreading of
+ *     the force moments to an M^3 grid with the Faxen operators applied to the
+ *     window (the real-space size approach of Sec. 3.2), forward 3-D FFT,
+ *     k-space Green's-function multiply with deconvolution, inverse FFT and
+ *     Gaussian gather by the trapezoid rule;
+ *   - the single-sphere self terms minus the wave-space self terms
+ *     (eq. uf-self and its analogues).
+ *
+ * Conventions for every entry point:
+ *   - Device arrays are caller-owned (for example torch tensor data pointers)
+ *     and must stay valid until the work queued on `stream` has finished.
+ *     The library never frees them. It owns only its workspace, which it
+ *     allocates on first use for a given size and keeps with the handle.
+ *   - Layouts are row-major: pos [n][3], radius [n], x/y/b [n][12], all FP64
+ *     whatever the internal precision.
+ *   - box is a HOST array of 9 doubles holding the lattice vectors a1, a2, a3
+ *     as consecutive triples (the columns of the paper's matrix A, Sec. 2.2).
+ *     This version accepts cubic cells only (a1 = (L,0,0), a2 = (0,L,0),
+ *     a3 = (0,0,L)); anything else returns SEASD_E_UNSUPPORTED.
+ *   - Work is queued on `stream` (a hipStream_t; NULL = default stream).
+ *     seasd_mobility_apply returns without synchronising unless the
+ *     configuration asks for input checks; seasd_solve_farfield synchronises.
+ *   - Return value: 0 on success, negative on error, positive for warnings.
+ *   - A handle is not thread safe; use one handle per host thread / stream.
+ *     Calls made through different handles may overlap on one GPU.
+ */
+#ifndef SEASD_H
+#define SEASD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes --------------------------------------------------------- */
+#define SEASD_OK                0
+#define SEASD_E_INVALID_ARG    -1   /* bad pointer, size or parameter           */
+#define SEASD_E_NONFINITE      -2   /* NaN or Inf in positions, radii or x      */
+#define SEASD_E_OVERLAP        -3   /* two spheres closer than a_i + a_j        */
+#define SEASD_E_CUTOFF         -4   /* cut-off or window does not fit the cell  */
+#define SEASD_E_SINGULAR       -5   /* a preconditioner block is singular       */
+#define SEASD_E_HIP            -6   /* a HIP runtime call failed                */
+#define SEASD_E_NOMEM          -7   /* workspace allocation failed              */
+#define SEASD_E_UNSUPPORTED    -8   /* valid request this build does not handle */
+#define SEASD_W_NOT_CONVERGED   1   /* solve stopped at max_iter above tol      */
+
+/* ---- configuration --------------------------------------------------------- */
+#define SEASD_FP64 0
+#define SEASD_FP32 1
+
+#define SEASD_PARTS_REAL 1  /* real-space pair sum (Sec. 3.3)                 */
+#define SEASD_PARTS_WAVE 2  /* Spectral Ewald wave-space sum (Sec. 3.1)       */
+#define SEASD_PARTS_SELF 4  /* single-sphere terms minus wave-space self      */
+#define SEASD_PARTS_ALL  7
+
+#define SEASD_PRECOND_NONE      0
+#define SEASD_PRECOND_BLOCKDIAG 1   /* per-sphere inverse of the self block (Sec. 4.2) */
+
+typedef struct seasd_config {
+    int32_t grid;           /* M, grid points per dimension: power of two, 8..512            */
+    int32_t P;              /* window support in grid points per dimension: even, 4..min(M,32) */
+    double  m;              /* window shape parameter (eq. theta-param); <= 0: sqrt(pi P)   */
+    double  xi;             /* Ewald splitting parameter, Beenakker convention (Sec. 2.2)   */
+    double  rc_factor;      /* real-space cut-off r_c = rc_factor (a_i + a_j), > 1           */
+    double  eta;            /* solvent viscosity, > 0                                        */
+    int32_t precision;      /* SEASD_FP64 or SEASD_FP32: spreading, FFTs and gather; the     */
+                            /* real-space pair sum and the solver always run in FP64        */
+    int32_t parts;          /* SEASD_PARTS_* bit mask; SEASD_PARTS_ALL for the operator      */
+    int32_t compressible;   /* 1: include the pressure-moment row and column; 0: zero them  */
+    int32_t checks;         /* 1: check inputs (finite, no overlap) and synchronise          */
+    /* far-field solve (seasd_solve_farfield) */
+    double  tol;            /* stop when ||b - M x||_2 / ||b||_2 <= tol                      */
+    int32_t max_iter;       /* total GMRES iterations (matrix-vector products) allowed       */
+    int32_t restart;        /* Krylov subspace size before restart, 1..200                   */
+    int32_t precond;        /* SEASD_PRECOND_*                                               */
+} seasd_config;
+
+typedef struct seasd_solve_stats {
+    int32_t iterations;      /* Arnoldi steps taken (one M x each)                  */
+    int32_t restarts;        /* completed restart cycles                            */
+    int32_t matvecs;         /* all products with M, true-residual checks included  */
+    int32_t converged;       /* 1 if the true residual met tol                      */
+    double  true_residual;   /* ||b - M x|| / ||b|| from a fresh product at exit     */
+    double  setup_ms;        /* preconditioner construction                          */
+    double  solve_ms;        /* total wall time of the call                          */
+} seasd_solve_stats;
+
+typedef struct seasd_handle_s* seasd_handle;
+
+/* Create a handle bound to HIP device `device` (the caller's device ordinal).
+ * Allocates nothing on the device yet. Returns SEASD_E_HIP if the device
+ * cannot be selected or is not a gfx950 part. */
+int seasd_create(seasd_handle* handle, int32_t device);
+
+/* Release the handle and all workspace it owns. Safe on NULL. */
+int seasd_destroy(seasd_handle handle);
+
+/* Fill *cfg with defaults: M=64, P=16, m=sqrt(pi P), xi=0.5, rc_factor=4
+ * (the paper's r_c = 4(a_i+a_j), Sec. 5.1.2 and 5.3), eta=1, FP64, all parts,
+ * compressible, checks on, tol 1e-6, max_iter 1000, restart 50, block-diagonal
+ * preconditioner. */
+int seasd_default_config(seasd_config* cfg);
+
+/* Validate and store the configuration (parameters of Sec. 5.1: M, P, m, xi,
+ * r_c). Workspace is sized lazily on the next call that needs it. Returns
+ * SEASD_E_INVALID_ARG for out-of-range values. */
+int seasd_set_config(seasd_handle handle, const seasd_config* cfg);
+
+/* y = M x (Sec. 3, "the action of M on the force moments").
+ *   n      number of spheres, >= 1
+ *   pos    device [n][3] centres (any real coordinates; wrapped into the cell)
+ *   radius device [n] radii, > 0
+ *   box    host [9] lattice vectors (cubic only, see above)
+ *   x      device [n][12] force moments
+ *   y      device [n][12] output, overwritten (may not alias x)
+ * Errors: SEASD_E_INVALID_ARG, SEASD_E_UNSUPPORTED (non-cubic cell),
+ * SEASD_E_CUTOFF (window wider than the grid), SEASD_E_NOMEM, SEASD_E_HIP; with
+ * checks on also SEASD_E_NONFINITE and SEASD_E_OVERLAP (y is then undefined). */
+int seasd_mobility_apply(seasd_handle handle, int64_t n,
+                         const double* pos, const double* radius, const double* box,
+                         const double* x, double* y, void* stream);
+
+/* Far-field solve M x = b for all 12n unknowns (Sec. 4.1, eq. HI-ff with no
+ * near-field resistance), by right-preconditioned restarted GMRES in FP64 on
+ * the device, with the block-diagonal far-field preconditioner of Sec. 4.2
+ * (each sphere's 12x12 block with its own periodic images, inverted in FP64).
+ *   b      device [n][12] right-hand side
+ *   x      device [n][12] in: initial guess, out: solution
+ *   stats  host, may be NULL
+ * Synchronises `stream`. Returns SEASD_W_NOT_CONVERGED if max_iter was reached
+ * with the true residual above tol (x then holds the last iterate), and the
+ * errors of seasd_mobility_apply or SEASD_E_SINGULAR. */
+int seasd_solve_farfield(seasd_handle handle, int64_t n,
+                         const double* pos, const double* radius, const double* box,
+                         const double* b, double* x, seasd_solve_stats* stats, void* stream);
+
+/* Per-phase timing of the most recent mobility product, recorded with HIP
+ * events on the call's stream when enabled (off by default, costs one event
+ * pair per phase). Phases, in order: bin, pair, spread, fft_x_fwd, fft_y_fwd,
+ * fft_z_scale, fft_y_inv, fft_x_inv, gather. ms receives up to `count` values;
+ * returns the number of phases, or a negative error. Synchronises the stream
+ * of the last product. */
+int seasd_profile_enable(seasd_handle handle, int32_t enable);
+int seasd_profile_read(seasd_handle handle, double* ms, int32_t count);
+
+/* Short description of a return code (static storage). */
+const char* seasd_error_string(int32_t code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEASD_H */

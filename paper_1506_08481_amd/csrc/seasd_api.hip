@@ -1,0 +1,540 @@
+// seasd_api.hip - the C ABI declared in include/seasd.h: handle, configuration,
+// workspace, the mobility product and the GMRES far-field solve.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/seasd.h"
+#include "seasd_internal.h"
+#include "seasd_math.h"
+
+using namespace seasd;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t need) {
+        if (need <= bytes) return 0;
+        if (p) {
+            hipDeviceSynchronize();  // queued work may still read the old buffer
+            hipFree(p);
+        }
+        p = nullptr;
+        bytes = 0;
+        if (hipMalloc(&p, need) != hipSuccess) {
+            p = nullptr;
+            return SEASD_E_NOMEM;
+        }
+        bytes = need;
+        return 0;
+    }
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T* as() const {
+        return static_cast<T*>(p);
+    }
+};
+
+}  // namespace
+
+struct seasd_handle_s {
+    int device = 0;
+    seasd_config cfg{};
+    bool have_cfg = false;
+    // product workspace
+    DevBuf bin_of, counts, start, fill, perm, amax, err, sp, sa, sx, ybuf, rgrid, spec, twiddle;
+    int twiddle_M = 0;
+    // solver workspace
+    DevBuf V, w, z, u, r, hdev, partial, blocks, inv, coef, singular, one_pos, one_rad, one_x, one_y;
+    PhaseTimer timer;
+    hipStream_t last_stream = nullptr;
+};
+
+static int hip_ok(hipError_t e) { return e == hipSuccess ? 0 : SEASD_E_HIP; }
+
+extern "C" const char* seasd_error_string(int32_t code) {
+    switch (code) {
+        case SEASD_OK: return "success";
+        case SEASD_E_INVALID_ARG: return "invalid argument";
+        case SEASD_E_NONFINITE: return "non-finite position, radius or moment";
+        case SEASD_E_OVERLAP: return "overlapping spheres (r < a_i + a_j)";
+        case SEASD_E_CUTOFF: return "window or cut-off does not fit the cell";
+        case SEASD_E_SINGULAR: return "singular preconditioner block";
+        case SEASD_E_HIP: return "HIP runtime error";
+        case SEASD_E_NOMEM: return "device allocation failed";
+        case SEASD_E_UNSUPPORTED: return "unsupported request (only cubic cells)";
+        case SEASD_W_NOT_CONVERGED: return "solve did not reach the tolerance";
+        default: return "unknown code";
+    }
+}
+
+extern "C" int seasd_default_config(seasd_config* c) {
+    if (!c) return SEASD_E_INVALID_ARG;
+    std::memset(c, 0, sizeof(*c));
+    c->grid = 64;
+    c->P = 16;
+    c->m = 0.0;
+    c->xi = 0.5;
+    c->rc_factor = 4.0;
+    c->eta = 1.0;
+    c->precision = SEASD_FP64;
+    c->parts = SEASD_PARTS_ALL;
+    c->compressible = 1;
+    c->checks = 1;
+    c->tol = 1e-6;
+    c->max_iter = 1000;
+    c->restart = 50;
+    c->precond = SEASD_PRECOND_BLOCKDIAG;
+    return SEASD_OK;
+}
+
+extern "C" int seasd_create(seasd_handle* out, int32_t device) {
+    if (!out) return SEASD_E_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SEASD_E_HIP;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return SEASD_E_HIP;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return SEASD_E_HIP;
+    auto* h = new seasd_handle_s();
+    h->device = device;
+    seasd_default_config(&h->cfg);
+    h->have_cfg = true;
+    *out = h;
+    return SEASD_OK;
+}
+
+extern "C" int seasd_destroy(seasd_handle h) {
+    if (!h) return SEASD_OK;
+    hipSetDevice(h->device);
+    DevBuf* bufs[] = {&h->bin_of, &h->counts, &h->start, &h->fill, &h->perm, &h->amax, &h->err,
+                      &h->sp, &h->sa, &h->sx, &h->ybuf, &h->rgrid, &h->spec, &h->twiddle,
+                      &h->V, &h->w, &h->z, &h->u, &h->r, &h->hdev, &h->partial, &h->blocks,
+                      &h->inv, &h->coef, &h->singular, &h->one_pos, &h->one_rad, &h->one_x, &h->one_y};
+    for (DevBuf* b : bufs) b->release();
+    if (h->timer.created)
+        for (auto& e : h->timer.ev) hipEventDestroy(e);
+    delete h;
+    return SEASD_OK;
+}
+
+static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+extern "C" int seasd_set_config(seasd_handle h, const seasd_config* c) {
+    if (!h || !c) return SEASD_E_INVALID_ARG;
+    if (!pow2(c->grid) || c->grid < 8 || c->grid > 256) return SEASD_E_INVALID_ARG;
+    if (c->P < 4 || c->P > 32 || (c->P & 1) || c->P > c->grid) return SEASD_E_INVALID_ARG;
+    if (!(std::isfinite(c->m)) || !(c->xi > 0.0) || !std::isfinite(c->xi)) return SEASD_E_INVALID_ARG;
+    if (!(c->rc_factor > 1.0) || !std::isfinite(c->rc_factor)) return SEASD_E_INVALID_ARG;
+    if (!(c->eta > 0.0) || !std::isfinite(c->eta)) return SEASD_E_INVALID_ARG;
+    if (c->precision != SEASD_FP64 && c->precision != SEASD_FP32) return SEASD_E_INVALID_ARG;
+    if (c->parts < 0 || c->parts > SEASD_PARTS_ALL) return SEASD_E_INVALID_ARG;
+    if (c->restart < 1 || c->restart > 200 || c->max_iter < 1) return SEASD_E_INVALID_ARG;
+    if (!(c->tol > 0.0)) return SEASD_E_INVALID_ARG;
+    if (c->precond != SEASD_PRECOND_NONE && c->precond != SEASD_PRECOND_BLOCKDIAG) return SEASD_E_INVALID_ARG;
+    h->cfg = *c;
+    h->have_cfg = true;
+    return SEASD_OK;
+}
+
+static int cubic_edge(const double* box, double* L) {
+    if (!box) return SEASD_E_INVALID_ARG;
+    for (int i = 0; i < 9; ++i)
+        if (!std::isfinite(box[i])) return SEASD_E_INVALID_ARG;
+    const double l = box[0];
+    if (!(l > 0.0)) return SEASD_E_INVALID_ARG;
+    const double tol = 1e-12 * l;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const double v = box[3 * i + j];
+            if (i == j ? std::fabs(v - l) > tol : std::fabs(v) > tol) return SEASD_E_UNSUPPORTED;
+        }
+    *L = l;
+    return SEASD_OK;
+}
+
+// product workspace for n spheres on the configured grid
+static int ensure_product_ws(seasd_handle h, int64_t n) {
+    const int M = h->cfg.grid;
+    const int nb = M / 8;
+    const size_t nbins = (size_t)nb * nb * nb;
+    const size_t R = h->cfg.precision == SEASD_FP32 ? 4 : 8;
+    int rc = 0;
+    rc |= h->bin_of.ensure(sizeof(int) * n);
+    rc |= h->counts.ensure(sizeof(int) * nbins);
+    rc |= h->start.ensure(sizeof(int) * (nbins + 1));
+    rc |= h->fill.ensure(sizeof(int) * nbins);
+    rc |= h->perm.ensure(sizeof(int) * n);
+    rc |= h->amax.ensure(sizeof(unsigned long long));
+    rc |= h->err.ensure(sizeof(int));
+    rc |= h->sp.ensure(sizeof(double) * 3 * n);
+    rc |= h->sa.ensure(sizeof(double) * n);
+    rc |= h->sx.ensure(sizeof(double) * 12 * n);
+    rc |= h->ybuf.ensure(sizeof(double) * 12 * n);
+    if (h->cfg.parts & SEASD_PARTS_WAVE) {
+        rc |= h->rgrid.ensure(R * 4 * (size_t)M * M * M);
+        rc |= h->spec.ensure(R * 4 * (size_t)M * M * M);
+    } else {
+        rc |= h->rgrid.ensure(R * 4);
+    }
+    rc |= h->twiddle.ensure(sizeof(double) * M);
+    if (rc) return SEASD_E_NOMEM;
+    if (h->twiddle_M != M) {
+        std::vector<double> tw(M);
+        for (int j = 0; j < M / 2; ++j) {
+            const double a = 2.0 * kPi * j / M;
+            tw[2 * j] = std::cos(a);
+            tw[2 * j + 1] = std::sin(a);
+        }
+        if (hipMemcpy(h->twiddle.p, tw.data(), sizeof(double) * M, hipMemcpyHostToDevice) != hipSuccess)
+            return SEASD_E_HIP;
+        h->twiddle_M = M;
+    }
+    return SEASD_OK;
+}
+
+// queue one product; no synchronisation
+static int queue_apply(seasd_handle h, int64_t n, const double* pos, const double* radius, double L,
+                       const double* x, double* y, hipStream_t st, bool checks) {
+    const seasd_config& c = h->cfg;
+    int rc = ensure_product_ws(h, n);
+    if (rc) return rc;
+    ApplyArgs A{};
+    A.n = n;
+    A.pos = pos;
+    A.radius = radius;
+    A.x = x;
+    A.y = y;
+    A.L = L;
+    A.M = c.grid;
+    A.P = c.P;
+    A.nb = c.grid / 8;
+    A.binw = L / A.nb;
+    A.xi = c.xi;
+    A.rc_factor = c.rc_factor;
+    A.inv_eta = 1.0 / c.eta;
+    A.h = L / c.grid;
+    const double m = c.m > 0.0 ? c.m : std::sqrt(kPi * c.P);
+    A.tau = (c.P * A.h) * (c.P * A.h) / (8.0 * m * m);
+    A.alpha = 1.0 / (4.0 * A.tau);
+    A.cw = std::pow(4.0 * kPi * A.tau, -1.5);
+    A.parts = c.parts;
+    A.compressible = c.compressible;
+    A.checks = checks ? 1 : 0;
+    A.fp32 = c.precision == SEASD_FP32;
+    A.bin_of = h->bin_of.as<int>();
+    A.counts = h->counts.as<int>();
+    A.start = h->start.as<int>();
+    A.fill = h->fill.as<int>();
+    A.perm = h->perm.as<int>();
+    A.amax_bits = h->amax.as<unsigned long long>();
+    A.err = h->err.as<int>();
+    A.sp = h->sp.as<double>();
+    A.sa = h->sa.as<double>();
+    A.sx = h->sx.as<double>();
+    A.ybuf = h->ybuf.as<double>();
+    A.rgrid = h->rgrid.p;
+    A.spec = h->spec.p;
+    A.twiddle = h->twiddle.as<double>();
+    if (checks && hipMemsetAsync(A.err, 0, sizeof(int), st) != hipSuccess) return SEASD_E_HIP;
+    h->timer.reset();
+    if (launch_apply(A, st, &h->timer)) return SEASD_E_HIP;
+    h->last_stream = st;
+    return SEASD_OK;
+}
+
+static int read_err(seasd_handle h, hipStream_t st) {
+    int e = 0;
+    if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
+    if (hipMemcpy(&e, h->err.p, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return SEASD_E_HIP;
+    if (e & kErrNonfinite) return SEASD_E_NONFINITE;
+    if (e & kErrOverlap) return SEASD_E_OVERLAP;
+    if (e & kErrCutoff) return SEASD_E_CUTOFF;
+    return SEASD_OK;
+}
+
+extern "C" int seasd_mobility_apply(seasd_handle h, int64_t n, const double* pos, const double* radius,
+                                    const double* box, const double* x, double* y, void* stream) {
+    if (!h || n < 1 || n > (int64_t)1 << 28 || !pos || !radius || !x || !y) return SEASD_E_INVALID_ARG;
+    if (x == y) return SEASD_E_INVALID_ARG;
+    double L;
+    int rc = cubic_edge(box, &L);
+    if (rc) return rc;
+    if (hipSetDevice(h->device) != hipSuccess) return SEASD_E_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    rc = queue_apply(h, n, pos, radius, L, x, y, st, h->cfg.checks != 0);
+    if (rc) return rc;
+    if (h->cfg.checks) return read_err(h, st);
+    return SEASD_OK;
+}
+
+extern "C" int seasd_profile_enable(seasd_handle h, int32_t enable) {
+    if (!h) return SEASD_E_INVALID_ARG;
+    if (enable && !h->timer.created) {
+        if (hipSetDevice(h->device) != hipSuccess) return SEASD_E_HIP;
+        for (auto& e : h->timer.ev)
+            if (hipEventCreate(&e) != hipSuccess) return SEASD_E_HIP;
+        h->timer.created = true;
+    }
+    h->timer.enabled = enable != 0;
+    return SEASD_OK;
+}
+
+extern "C" int seasd_profile_read(seasd_handle h, double* ms, int32_t count) {
+    if (!h || !ms || count < 0) return SEASD_E_INVALID_ARG;
+    if (!h->timer.created) return SEASD_E_INVALID_ARG;
+    if (hipStreamSynchronize(h->last_stream) != hipSuccess) return SEASD_E_HIP;
+    std::vector<double> out(kNumPhases, 0.0);
+    for (int k = 0; k + 1 < h->timer.count; ++k) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, h->timer.ev[k], h->timer.ev[k + 1]) != hipSuccess) return SEASD_E_HIP;
+        if (h->timer.order[k] >= 0) out[h->timer.order[k]] += t;
+    }
+    for (int k = 0; k < count && k < kNumPhases; ++k) ms[k] = out[k];
+    return kNumPhases;
+}
+
+// ---------------------------------------------------------------------------
+// far-field solve
+
+// Single-sphere blocks M_ii(a) = self(a) + Q(a^2), Q quadratic in a^2: sample
+// the product on one sphere alone in the cell at three radii (12 unit inputs
+// each), remove the single-sphere self terms, fit the quadratic exactly.
+static int build_preconditioner(seasd_handle h, int64_t n, const double* radius, double L, hipStream_t st) {
+    int rc = 0;
+    rc |= h->coef.ensure(sizeof(double) * 3 * 144);
+    rc |= h->blocks.ensure(sizeof(double) * 144 * n);
+    rc |= h->inv.ensure(sizeof(double) * 144 * n);
+    rc |= h->singular.ensure(sizeof(int));
+    rc |= h->one_pos.ensure(sizeof(double) * 3);
+    rc |= h->one_rad.ensure(sizeof(double));
+    rc |= h->one_x.ensure(sizeof(double) * 12);
+    rc |= h->one_y.ensure(sizeof(double) * 12);
+    if (rc) return SEASD_E_NOMEM;
+    // radius range (host reduction; setup cost only)
+    std::vector<double> rad(n);
+    if (hipMemcpy(rad.data(), radius, sizeof(double) * n, hipMemcpyDeviceToHost) != hipSuccess) return SEASD_E_HIP;
+    double amin = rad[0], amax = rad[0];
+    for (double a : rad) {
+        if (!(a > 0.0) || !std::isfinite(a)) return SEASD_E_NONFINITE;
+        amin = std::fmin(amin, a);
+        amax = std::fmax(amax, a);
+    }
+    double samp[3] = {amin, 0.5 * (amin + amax), amax};
+    if (amax - amin < 1e-3 * amax) {
+        samp[0] = amin;
+        samp[1] = 1.25 * amin;
+        samp[2] = 1.5 * amin;
+    }
+    const double zero3[3] = {0.0, 0.0, 0.0};
+    if (hipMemcpy(h->one_pos.p, zero3, sizeof(zero3), hipMemcpyHostToDevice) != hipSuccess) return SEASD_E_HIP;
+    double Q[3][144];
+    const double eta = h->cfg.eta;
+    for (int s = 0; s < 3; ++s) {
+        if (hipMemcpy(h->one_rad.p, &samp[s], sizeof(double), hipMemcpyHostToDevice) != hipSuccess) return SEASD_E_HIP;
+        for (int b = 0; b < 12; ++b) {
+            double e[12] = {0};
+            e[b] = 1.0;
+            if (hipMemcpyAsync(h->one_x.p, e, sizeof(e), hipMemcpyHostToDevice, st) != hipSuccess) return SEASD_E_HIP;
+            rc = queue_apply(h, 1, h->one_pos.as<double>(), h->one_rad.as<double>(), L, h->one_x.as<double>(),
+                             h->one_y.as<double>(), st, false);
+            if (rc) return rc;
+            double col[12];
+            if (hipMemcpyAsync(col, h->one_y.p, sizeof(col), hipMemcpyDeviceToHost, st) != hipSuccess) return SEASD_E_HIP;
+            if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
+            for (int r = 0; r < 12; ++r) Q[s][12 * r + b] = col[r];
+        }
+        const double a = samp[s], a3 = a * a * a;
+        for (int c = 0; c < 3; ++c) Q[s][13 * c] -= 1.0 / (6.0 * kPi * eta * a);
+        for (int c = 3; c < 6; ++c) Q[s][13 * c] -= 1.0 / (8.0 * kPi * eta * a3);
+        for (int c = 6; c < 11; ++c) Q[s][13 * c] -= 3.0 / (20.0 * kPi * eta * a3);
+        Q[s][13 * 11] -= 3.0 / (16.0 * kPi * eta * a3);
+    }
+    // Q(A) = C0 + C1 A + C2 A^2 through the three samples (Lagrange form)
+    double A[3] = {samp[0] * samp[0], samp[1] * samp[1], samp[2] * samp[2]};
+    std::vector<double> coef(3 * 144, 0.0);
+    for (int s = 0; s < 3; ++s) {
+        const int p = (s + 1) % 3, q = (s + 2) % 3;
+        const double den = (A[s] - A[p]) * (A[s] - A[q]);
+        const double l0 = A[p] * A[q] / den, l1 = -(A[p] + A[q]) / den, l2 = 1.0 / den;
+        for (int e = 0; e < 144; ++e) {
+            coef[e] += l0 * Q[s][e];
+            coef[144 + e] += l1 * Q[s][e];
+            coef[288 + e] += l2 * Q[s][e];
+        }
+    }
+    if (hipMemcpy(h->coef.p, coef.data(), sizeof(double) * 3 * 144, hipMemcpyHostToDevice) != hipSuccess)
+        return SEASD_E_HIP;
+    if (launch_build_blocks(n, radius, h->coef.as<double>(), h->cfg.xi, eta, h->blocks.as<double>(), st))
+        return SEASD_E_HIP;
+    if (hipMemsetAsync(h->singular.p, 0, sizeof(int), st) != hipSuccess) return SEASD_E_HIP;
+    if (launch_block_invert(n, h->blocks.as<double>(), h->inv.as<double>(), h->singular.as<int>(), st))
+        return SEASD_E_HIP;
+    int sing = 0;
+    if (hipMemcpyAsync(&sing, h->singular.p, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return SEASD_E_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
+    return sing ? SEASD_E_SINGULAR : SEASD_OK;
+}
+
+static int dot_host(seasd_handle h, int64_t len, int k, const double* V, int64_t ld, const double* w,
+                    double* out_host, hipStream_t st) {
+    if (launch_dots(len, k, V, ld, w, h->partial.as<double>(), h->hdev.as<double>(), st)) return SEASD_E_HIP;
+    if (hipMemcpyAsync(out_host, h->hdev.p, sizeof(double) * k, hipMemcpyDeviceToHost, st) != hipSuccess)
+        return SEASD_E_HIP;
+    return hip_ok(hipStreamSynchronize(st));
+}
+
+extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos, const double* radius,
+                                    const double* box, const double* b, double* x, seasd_solve_stats* stats,
+                                    void* stream) {
+    if (!h || n < 1 || n > (int64_t)1 << 28 || !pos || !radius || !b || !x) return SEASD_E_INVALID_ARG;
+    double L;
+    int rc = cubic_edge(box, &L);
+    if (rc) return rc;
+    if (hipSetDevice(h->device) != hipSuccess) return SEASD_E_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    const seasd_config c = h->cfg;
+    const int m = c.restart;
+    const int64_t len = 12 * n;
+    seasd_solve_stats S{};
+    rc = 0;
+    rc |= h->V.ensure(sizeof(double) * len * (m + 1));
+    rc |= h->w.ensure(sizeof(double) * len);
+    rc |= h->z.ensure(sizeof(double) * len);
+    rc |= h->u.ensure(sizeof(double) * len);
+    rc |= h->r.ensure(sizeof(double) * len);
+    rc |= h->hdev.ensure(sizeof(double) * 256);
+    rc |= h->partial.ensure(sizeof(double) * 256 * 256);
+    if (rc) return SEASD_E_NOMEM;
+    double* V = h->V.as<double>();
+    double* w = h->w.as<double>();
+    double* z = h->z.as<double>();
+    double* u = h->u.as<double>();
+    double* r = h->r.as<double>();
+    const bool pc = c.precond == SEASD_PRECOND_BLOCKDIAG;
+    if (pc) {
+        rc = build_preconditioner(h, n, radius, L, st);
+        if (rc) return rc;
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    S.setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    // input checks on the first product only
+    auto apply = [&](const double* in, double* out, bool chk) -> int {
+        int e = queue_apply(h, n, pos, radius, L, in, out, st, chk);
+        if (e) return e;
+        ++S.matvecs;
+        return chk ? read_err(h, st) : SEASD_OK;
+    };
+    auto precond = [&](const double* in, double* out) -> int {
+        if (!pc) return hip_ok(hipMemcpyAsync(out, in, sizeof(double) * len, hipMemcpyDeviceToDevice, st));
+        return launch_block_apply(n, h->inv.as<double>(), in, out, st) ? SEASD_E_HIP : SEASD_OK;
+    };
+    double bnorm2 = 0.0;
+    rc = dot_host(h, len, 1, b, len, b, &bnorm2, st);
+    if (rc) return rc;
+    const double bnorm = std::sqrt(bnorm2);
+    if (bnorm == 0.0) {
+        hipMemsetAsync(x, 0, sizeof(double) * len, st);
+        hipStreamSynchronize(st);
+        S.converged = 1;
+        if (stats) *stats = S;
+        return SEASD_OK;
+    }
+    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), yv(m);
+    bool first = true;
+    double relres = 1.0;
+    int total = 0;
+    while (true) {
+        // r = b - M x
+        rc = apply(x, r, first && c.checks);
+        first = false;
+        if (rc) return rc;
+        if (launch_axpby(len, 1.0, b, -1.0, r, st)) return SEASD_E_HIP;
+        double rn2 = 0.0;
+        rc = dot_host(h, len, 1, r, len, r, &rn2, st);
+        if (rc) return rc;
+        const double beta = std::sqrt(rn2);
+        relres = beta / bnorm;
+        if (relres <= c.tol || total >= c.max_iter) break;
+        // v_0 = r / beta
+        if (launch_axpby(len, 1.0 / beta, r, 0.0, V, st)) return SEASD_E_HIP;
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int j = 0;
+        for (; j < m && total < c.max_iter; ++j, ++total) {
+            rc = precond(V + j * len, z);
+            if (rc) return rc;
+            rc = apply(z, w, false);
+            if (rc) return rc;
+            // classical Gram-Schmidt, twice
+            for (int q = 0; q <= j; ++q) H[q * m + j] = 0.0;
+            for (int pass = 0; pass < 2; ++pass) {
+                if (launch_dots(len, j + 1, V, len, w, h->partial.as<double>(), h->hdev.as<double>(), st))
+                    return SEASD_E_HIP;
+                if (launch_gemv_sub(len, j + 1, V, len, h->hdev.as<double>(), w, st)) return SEASD_E_HIP;
+                if (hipMemcpyAsync(hcol.data(), h->hdev.p, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st) !=
+                    hipSuccess)
+                    return SEASD_E_HIP;
+                if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
+                for (int q = 0; q <= j; ++q) H[q * m + j] += hcol[q];
+            }
+            double wn2 = 0.0;
+            rc = dot_host(h, len, 1, w, len, w, &wn2, st);
+            if (rc) return rc;
+            const double hn = std::sqrt(wn2);
+            H[(j + 1) * m + j] = hn;
+            if (hn > 0.0 && launch_axpby(len, 1.0 / hn, w, 0.0, V + (j + 1) * len, st)) return SEASD_E_HIP;
+            // Givens rotations on column j
+            for (int q = 0; q < j; ++q) {
+                const double a = H[q * m + j], bb = H[(q + 1) * m + j];
+                H[q * m + j] = cs[q] * a + sn[q] * bb;
+                H[(q + 1) * m + j] = -sn[q] * a + cs[q] * bb;
+            }
+            const double a = H[j * m + j], bb = H[(j + 1) * m + j];
+            const double den = std::hypot(a, bb);
+            cs[j] = den > 0 ? a / den : 1.0;
+            sn[j] = den > 0 ? bb / den : 0.0;
+            H[j * m + j] = den;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            if (std::fabs(g[j + 1]) / bnorm <= 0.5 * c.tol || hn == 0.0) {
+                ++j;
+                ++total;
+                break;
+            }
+        }
+        // y = H^-1 g (upper triangular j x j), x += P (V y)
+        for (int q = j - 1; q >= 0; --q) {
+            double s = g[q];
+            for (int k = q + 1; k < j; ++k) s -= H[q * m + k] * yv[k];
+            yv[q] = H[q * m + q] != 0.0 ? s / H[q * m + q] : 0.0;
+        }
+        if (hipMemcpyAsync(h->hdev.p, yv.data(), sizeof(double) * j, hipMemcpyHostToDevice, st) != hipSuccess)
+            return SEASD_E_HIP;
+        if (hipMemsetAsync(u, 0, sizeof(double) * len, st) != hipSuccess) return SEASD_E_HIP;
+        // u = -(-V y)
+        if (launch_gemv_sub(len, j, V, len, h->hdev.as<double>(), u, st)) return SEASD_E_HIP;
+        rc = precond(u, z);
+        if (rc) return rc;
+        if (launch_axpby(len, -1.0, z, 1.0, x, st)) return SEASD_E_HIP;
+        ++S.restarts;
+        if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
+    }
+    S.iterations = total;
+    S.true_residual = relres;
+    S.converged = relres <= c.tol ? 1 : 0;
+    S.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = S;
+    return S.converged ? SEASD_OK : SEASD_W_NOT_CONVERGED;
+}

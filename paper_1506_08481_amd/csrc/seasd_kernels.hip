@@ -1,0 +1,777 @@
+// seasd_kernels.hip - gfx950 kernels of the Spectral Ewald mobility product.
+//
+// Pipeline for y = M x (one call):
+//   bin      wrap centres into the cell, count spheres per bin (a bin is one
+//            8^3 tile of the grid), scan, scatter, order each bin by input
+//            index (deterministic), copy moments into binned order
+//   pair     real-space pair sum over neighbour bins + self terms (FP64)
+//   spread   tile-owner Gaussian spreading: one workgroup owns an 8^3 tile
+//            and accumulates every sphere whose window touches it, so no
+//            grid point is written by two workgroups (no atomics)
+//   fft_x_fwd, fft_y_fwd, fft_z_scale (forward z, k-space multiply, inverse
+//            z), fft_y_inv, fft_x_inv: 3-D transforms by line passes through LDS
+//   gather   one wavefront per sphere reads its window of the velocity and
+//            pressure grids, adds the pair/self part, writes y in input order
+//
+// Grid layouts (R = float or double):
+//   real grid  [z][y][x] of R4 = 4 interleaved real fields
+//              forward: (Hx, Hy, Hz, Hs)   inverse: (vx, vy, vz, p)
+//   spectrum   [z][y][qx < M/2] of C4 = 4 interleaved complex fields. The
+//              x transform of a real field is kept for qx in [0, M/2); the
+//              qx = M/2 plane is the Nyquist plane, which the method zeroes.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "seasd_math.h"
+#include "seasd_internal.h"
+
+namespace seasd {
+
+template <typename R>
+struct alignas(4 * sizeof(R)) R4 {
+    R x, y, z, w;
+};
+
+template <typename R>
+struct C1 {
+    R re, im;
+};
+
+template <typename R>
+__device__ inline C1<R> cmul(C1<R> a, C1<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+// ---------------------------------------------------------------------------
+// binning
+
+// coordinate wrapped into [0, L); the same expression is used for the bin and
+// for the binned copy so both always agree
+__device__ inline double wrap_coord(double p, double L) {
+    double w = p - L * floor(p / L);
+    return (w < L && w >= 0.0) ? w : 0.0;
+}
+
+__global__ void k_bin_count(int n, const double* __restrict__ pos, const double* __restrict__ rad,
+                            double L, int nb, double binw, int* __restrict__ bin_of,
+                            int* __restrict__ counts, unsigned long long* __restrict__ amax_bits,
+                            int* __restrict__ err) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double p[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+    double a = rad[i];
+    bool bad = !(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]) && isfinite(a)) || !(a > 0.0);
+    if (bad) {
+        atomicOr(err, kErrNonfinite);
+        p[0] = p[1] = p[2] = 0.0;
+        a = 1.0;
+    }
+    int b[3];
+    for (int d = 0; d < 3; ++d) {
+        double w = wrap_coord(p[d], L);
+        int k = (int)floor(w / binw);
+        b[d] = k < 0 ? 0 : (k >= nb ? nb - 1 : k);
+    }
+    int bin = (b[2] * nb + b[1]) * nb + b[0];
+    bin_of[i] = bin;
+    atomicAdd(&counts[bin], 1);
+    atomicMax(amax_bits, (unsigned long long)__double_as_longlong(a));
+}
+
+// exclusive scan of counts[0..nbins) into start[0..nbins], one workgroup
+__global__ void k_bin_scan(int nbins, const int* __restrict__ counts, int* __restrict__ start,
+                           int* __restrict__ fill) {
+    __shared__ int part[1024];
+    int t = threadIdx.x;
+    int per = (nbins + blockDim.x - 1) / blockDim.x;
+    int b0 = t * per, b1 = min(nbins, b0 + per);
+    int s = 0;
+    for (int b = b0; b < b1; ++b) s += counts[b];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+        int v = (t >= off) ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - s;
+    for (int b = b0; b < b1; ++b) {
+        start[b] = run;
+        fill[b] = 0;
+        run += counts[b];
+    }
+    if (t == blockDim.x - 1) start[nbins] = part[t];
+}
+
+__global__ void k_bin_scatter(int n, const int* __restrict__ bin_of, const int* __restrict__ start,
+                              int* __restrict__ fill, int* __restrict__ perm) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b = bin_of[i];
+    perm[start[b] + atomicAdd(&fill[b], 1)] = i;
+}
+
+// order each bin by input index so that every later sum runs in a fixed order
+__global__ void k_bin_order(int nbins, const int* __restrict__ start, int* __restrict__ perm) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbins) return;
+    int s0 = start[b], s1 = start[b + 1];
+    for (int i = s0 + 1; i < s1; ++i) {
+        int v = perm[i], j = i - 1;
+        while (j >= s0 && perm[j] > v) {
+            perm[j + 1] = perm[j];
+            --j;
+        }
+        perm[j + 1] = v;
+    }
+}
+
+// binned copies: wrapped centres, radii and moments (FP64)
+__global__ void k_bin_gather(int n, const int* __restrict__ perm, const double* __restrict__ pos,
+                             const double* __restrict__ rad, const double* __restrict__ x,
+                             double L, int compressible, double* __restrict__ sp,
+                             double* __restrict__ sa, double* __restrict__ sx,
+                             int* __restrict__ err) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int i = perm[s];
+    for (int d = 0; d < 3; ++d) {
+        double p = pos[3 * i + d];
+        sp[3 * s + d] = isfinite(p) ? wrap_coord(p, L) : 0.0;
+    }
+    double a = rad[i];
+    sa[s] = (isfinite(a) && a > 0.0) ? a : 1.0;
+    bool bad = false;
+    for (int c = 0; c < 12; ++c) {
+        double v = x[12 * (size_t)i + c];
+        if (!isfinite(v)) {
+            bad = true;
+            v = 0.0;
+        }
+        if (c == 11 && !compressible) v = 0.0;
+        sx[12 * (size_t)s + c] = v;
+    }
+    if (bad) atomicOr(err, kErrNonfinite);
+}
+
+// ---------------------------------------------------------------------------
+// real-space pair sum and self terms: one thread per sphere (binned order)
+
+__global__ void k_pair(int n, const double* __restrict__ sp, const double* __restrict__ sa,
+                       const double* __restrict__ sx, const int* __restrict__ start, int nb,
+                       double L, double binw, double xi, double rc_factor, double inv_eta,
+                       const unsigned long long* __restrict__ amax_bits, int parts, int checks,
+                       double* __restrict__ ybuf, int* __restrict__ err) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const double px = sp[3 * s], py = sp[3 * s + 1], pz = sp[3 * s + 2];
+    const double ai = sa[s];
+    double y[12];
+    for (int c = 0; c < 12; ++c) y[c] = 0.0;
+    if (parts & kPartsReal) {
+        const double amax = __longlong_as_double((long long)*amax_bits);
+        const double rcmax = rc_factor * (ai + amax);
+        int reach = (int)ceil(rcmax / binw);
+        if (reach > 2 * nb + 2) {  // cut-off beyond about two cell lengths: refuse
+            atomicOr(err, kErrCutoff);
+            reach = 2 * nb + 2;
+        }
+        const int bx = min(nb - 1, (int)(px / binw)), by = min(nb - 1, (int)(py / binw)),
+                  bz = min(nb - 1, (int)(pz / binw));
+        for (int oz = -reach; oz <= reach; ++oz) {
+            int cz = bz + oz;
+            int wz = (cz >= 0) ? cz / nb : -((-cz + nb - 1) / nb);
+            cz -= wz * nb;
+            for (int oy = -reach; oy <= reach; ++oy) {
+                int cy = by + oy;
+                int wy = (cy >= 0) ? cy / nb : -((-cy + nb - 1) / nb);
+                cy -= wy * nb;
+                for (int ox = -reach; ox <= reach; ++ox) {
+                    int cx = bx + ox;
+                    int wx = (cx >= 0) ? cx / nb : -((-cx + nb - 1) / nb);
+                    cx -= wx * nb;
+                    const int bin = (cz * nb + cy) * nb + cx;
+                    const double shx = wx * L, shy = wy * L, shz = wz * L;
+                    for (int j = start[bin]; j < start[bin + 1]; ++j) {
+                        if (j == s && wx == 0 && wy == 0 && wz == 0) continue;
+                        const double dx = px - (sp[3 * j] + shx);
+                        const double dy = py - (sp[3 * j + 1] + shy);
+                        const double dz = pz - (sp[3 * j + 2] + shz);
+                        const double r2 = dx * dx + dy * dy + dz * dz;
+                        const double aj = sa[j];
+                        const double rc = rc_factor * (ai + aj);
+                        if (r2 >= rc * rc) continue;
+                        if (checks && r2 < (ai + aj) * (ai + aj) * (1.0 - 1e-12)) atomicOr(err, kErrOverlap);
+                        double xj[12];
+                        for (int c = 0; c < 12; ++c) xj[c] = sx[12 * (size_t)j + c];
+                        pair_coupling<double>(dx, dy, dz, ai, aj, xi, inv_eta, xj, y);
+                    }
+                }
+            }
+        }
+    }
+    if (parts & kPartsSelf) {
+        double d4[4];
+        self_diag<double>(ai, xi, 1.0 / inv_eta, d4);
+        const double* xs = sx + 12 * (size_t)s;
+        for (int c = 0; c < 3; ++c) y[c] += d4[0] * xs[c];
+        for (int c = 3; c < 6; ++c) y[c] += d4[1] * xs[c];
+        for (int c = 6; c < 11; ++c) y[c] += d4[2] * xs[c];
+        y[11] += d4[3] * xs[11];
+    }
+    for (int c = 0; c < 12; ++c) ybuf[12 * (size_t)s + c] = y[c];
+}
+
+// ---------------------------------------------------------------------------
+// window helpers
+//
+// The window is the normalised Gaussian h(r) = (4 pi tau)^(-3/2) exp(-r^2/(4 tau))
+// with tau = (P h)^2/(8 m^2), i.e. exp(-m^2/2) at the support edge P h/2
+// (eqs. shape, theta-param written in Cartesian form for a cubic cell). It is
+// evaluated on P points per dimension starting at i0 = floor(x/h) - P/2 + 1.
+// 1-D factors exp(-alpha (d0 + k h)^2) use fast Gaussian gridding (eq.
+// fgg-exp), anchored at the window centre so the recurrences run over at most
+// P/2 steps.
+
+template <typename R>
+__device__ inline void fgg_factors(double d0, double h, double alpha, int P, R* out) {
+    const int kc = P / 2 - 1;               // d0 + kc h lies in (-h, 0]
+    const double dc = d0 + kc * h;
+    const double e0 = exp(-alpha * dc * dc);
+    const double up = exp(-2.0 * alpha * dc * h);  // ratio step k -> k+1 (before the k^2 term)
+    const double q = exp(-alpha * h * h);
+    // upward: k = kc + j, value = e0 * up^j * q^(j^2)
+    double v = e0, stp = up * q;                    // j=1 factor: up q^(1)
+    out[kc] = (R)e0;
+    const double q2 = q * q;
+    for (int k = kc + 1; k < P; ++k) {
+        v *= stp;
+        stp *= q2;
+        out[k] = (R)v;
+    }
+    // downward: k = kc - j, value = e0 * up^(-j) * q^(j^2)
+    v = e0;
+    stp = q / up;
+    for (int k = kc - 1; k >= 0; --k) {
+        v *= stp;
+        stp *= q2;
+        out[k] = (R)v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// spreading: one workgroup of 512 threads owns one 8^3 tile
+
+constexpr int kTile = 8;
+constexpr int kStage = 64;     // spheres staged per round
+constexpr int kMaxP = 32;
+
+template <typename R>
+struct SpreadStage {
+    R ex[kStage][kMaxP], ey[kStage][kMaxP], ez[kStage][kMaxP];
+    R d0[kStage][3];
+    int i0[kStage][3];
+    R F[kStage][3], T[kStage][3], S[kStage][6], s6[kStage], a2[kStage];
+};
+
+template <typename R>
+__global__ __launch_bounds__(512) void k_spread(
+    int n, const double* __restrict__ sp, const double* __restrict__ sa,
+    const double* __restrict__ sx, const int* __restrict__ start, int nb, int M, int P, double h,
+    double alpha, double cw, R4<R>* __restrict__ grid) {
+    __shared__ SpreadStage<R> st;
+    __shared__ int bins[125], pre[126];
+    __shared__ int nbins_used;
+    const int t = threadIdx.x;
+    const int tiles = M / kTile;
+    const int tx = blockIdx.x % tiles, ty = (blockIdx.x / tiles) % tiles, tz = blockIdx.x / (tiles * tiles);
+    const int lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
+    const int gx = tx * kTile + lx, gy = ty * kTile + ly, gz = tz * kTile + lz;
+    const int mask = M - 1;
+
+    // distinct bins whose spheres can reach this tile
+    const int reach = (P / 2 + kTile - 1) / kTile;
+    const int span = min(2 * reach + 1, nb);
+    if (t == 0) {
+        int c = 0;
+        for (int oz = 0; oz < span; ++oz)
+            for (int oy = 0; oy < span; ++oy)
+                for (int ox = 0; ox < span; ++ox) {
+                    int bx = (span == nb) ? ox : ((tx - reach + ox) % nb + nb) % nb;
+                    int by = (span == nb) ? oy : ((ty - reach + oy) % nb + nb) % nb;
+                    int bz = (span == nb) ? oz : ((tz - reach + oz) % nb + nb) % nb;
+                    bins[c++] = (bz * nb + by) * nb + bx;
+                }
+        nbins_used = c;
+        int run = 0;
+        for (int k = 0; k < c; ++k) {
+            pre[k] = run;
+            run += start[bins[k] + 1] - start[bins[k]];
+        }
+        pre[c] = run;
+    }
+    __syncthreads();
+    const int ncand = pre[nbins_used];
+    const R al = (R)alpha;
+    const R al2 = al * al, al3 = al2 * al;
+    const R hh = (R)h;
+    R acc[4] = {0, 0, 0, 0};
+    R cmp[4] = {0, 0, 0, 0};  // compensation (Neumaier) terms
+
+    for (int c0 = 0; c0 < ncand; c0 += kStage) {
+        if (t < kStage && c0 + t < ncand) {
+            const int c = c0 + t;
+            int k = 0;
+            while (pre[k + 1] <= c) ++k;
+            const int s = start[bins[k]] + (c - pre[k]);
+            const double a = sa[s];
+            for (int d = 0; d < 3; ++d) {
+                const double p = sp[3 * s + d];
+                const int i0 = (int)floor(p / h) - P / 2 + 1;
+                const double d0 = i0 * h - p;
+                st.i0[t][d] = i0;
+                st.d0[t][d] = (R)d0;
+                R* dst = (d == 0) ? st.ex[t] : (d == 1 ? st.ey[t] : st.ez[t]);
+                fgg_factors<R>(d0, h, alpha, P, dst);
+            }
+            const double* xs = sx + 12 * (size_t)s;
+            for (int d = 0; d < 3; ++d) {
+                st.F[t][d] = (R)xs[d];
+                st.T[t][d] = (R)xs[3 + d];
+            }
+            double S[6];
+            s5_to_sym<double>(xs + 6, S);
+            for (int d = 0; d < 6; ++d) st.S[t][d] = (R)S[d];
+            st.s6[t] = (R)(kSqrt3 * xs[11]);
+            st.a2[t] = (R)(a * a);
+        }
+        __syncthreads();
+        const int cnt = min(kStage, ncand - c0);
+        for (int q = 0; q < cnt; ++q) {
+            const int kx = (gx - st.i0[q][0]) & mask;
+            const int ky = (gy - st.i0[q][1]) & mask;
+            const int kz = (gz - st.i0[q][2]) & mask;
+            const bool in = (kx < P) && (ky < P) && (kz < P);
+            if (!__any(in)) continue;
+            if (!in) continue;
+            const R rx = st.d0[q][0] + kx * hh, ry = st.d0[q][1] + ky * hh, rz = st.d0[q][2] + kz * hh;
+            const R r2 = rx * rx + ry * ry + rz * rz;
+            const R w = (R)cw * st.ex[q][kx] * st.ey[q][ky] * st.ez[q][kz];
+            const R a2 = st.a2[q];
+            const R cF = w * (R(1) + a2 * (R(1) / R(6)) * (R(4) * al2 * r2 - R(6) * al));
+            const R cS = w * (R(2) * al - a2 * (R(1) / R(10)) * (R(20) * al2 - R(8) * al3 * r2));
+            const R cT = -al * w;
+            const R* F = st.F[q];
+            const R* T = st.T[q];
+            const R* S = st.S[q];
+            const R Srx = S[0] * rx + S[3] * ry + S[4] * rz;
+            const R Sry = S[3] * rx + S[1] * ry + S[5] * rz;
+            const R Srz = S[4] * rx + S[5] * ry + S[2] * rz;
+            R v[4];
+            v[0] = cF * F[0] + cT * (ry * T[2] - rz * T[1]) + cS * Srx;
+            v[1] = cF * F[1] + cT * (rz * T[0] - rx * T[2]) + cS * Sry;
+            v[2] = cF * F[2] + cT * (rx * T[1] - ry * T[0]) + cS * Srz;
+            v[3] = w * st.s6[q];
+            for (int c = 0; c < 4; ++c) {  // Neumaier summation
+                const R sum = acc[c] + v[c];
+                cmp[c] += (fabs(acc[c]) >= fabs(v[c])) ? ((acc[c] - sum) + v[c]) : ((v[c] - sum) + acc[c]);
+                acc[c] = sum;
+            }
+        }
+        __syncthreads();
+    }
+    R4<R> out;
+    out.x = acc[0] + cmp[0];
+    out.y = acc[1] + cmp[1];
+    out.z = acc[2] + cmp[2];
+    out.w = acc[3] + cmp[3];
+    grid[((size_t)gz * M + gy) * M + gx] = out;
+}
+
+// ---------------------------------------------------------------------------
+// FFT building block: radix-2 Stockham over `nlines` lines of length M held in
+// LDS (line-major), ping-ponging between a and b. tw[j] = exp(sgn 2 pi i j/M),
+// j < M/2. Returns the buffer that holds the result.
+
+template <typename R, int M>
+__device__ inline C1<R>* lds_fft(C1<R>* a, C1<R>* b, int nlines, const C1<R>* tw) {
+    constexpr int H = M / 2;
+    for (int p = 1; p < M; p <<= 1) {
+        const int tstride = H / p;
+        for (int e = threadIdx.x; e < nlines * H; e += blockDim.x) {
+            const int line = e / H, j = e - line * H;
+            const int k = j & (p - 1);
+            const C1<R> x0 = a[line * M + j];
+            const C1<R> x1 = cmul(tw[k * tstride], a[line * M + j + H]);
+            C1<R>* o = b + line * M + 2 * j - k;
+            o[0] = {x0.re + x1.re, x0.im + x1.im};
+            o[p] = {x0.re - x1.re, x0.im - x1.im};
+        }
+        __syncthreads();
+        C1<R>* tmp = a;
+        a = b;
+        b = tmp;
+    }
+    return a;
+}
+
+template <typename R, int M>
+__device__ inline void load_twiddles(C1<R>* tw, const double* __restrict__ twg, int sgn) {
+    for (int j = threadIdx.x; j < M / 2; j += blockDim.x) {
+        tw[j].re = (R)twg[2 * j];
+        tw[j].im = (R)(sgn * twg[2 * j + 1]);
+    }
+}
+
+// x pass, forward, real -> half spectrum. Two real fields share one complex
+// transform (A = f0 + i f1), separated with A(-q) = conj of the partner.
+template <typename R, int M, int LPB>
+__global__ __launch_bounds__(256) void k_fft_x_fwd(const R4<R>* __restrict__ in, C1<R>* __restrict__ out,
+                                                   const double* __restrict__ twg) {
+    __shared__ C1<R> buf[2][2 * LPB * M];
+    __shared__ C1<R> tw[M / 2];
+    load_twiddles<R, M>(tw, twg, +1);
+    const size_t line0 = (size_t)blockIdx.x * LPB;
+    for (int e = threadIdx.x; e < LPB * M; e += blockDim.x) {
+        const int l = e / M, x = e - l * M;
+        const R4<R> v = in[(line0 + l) * M + x];
+        buf[0][(2 * l) * M + x] = {v.x, v.y};
+        buf[0][(2 * l + 1) * M + x] = {v.z, v.w};
+    }
+    __syncthreads();
+    C1<R>* r = lds_fft<R, M>(buf[0], buf[1], 2 * LPB, tw);
+    for (int e = threadIdx.x; e < LPB * (M / 2); e += blockDim.x) {
+        const int l = e / (M / 2), q = e - l * (M / 2);
+        const int qn = (M - q) & (M - 1);
+        C1<R> o[4];
+        for (int g = 0; g < 2; ++g) {
+            const C1<R> A = r[(2 * l + g) * M + q];
+            const C1<R> B = r[(2 * l + g) * M + qn];  // A(-q)
+            // f0 = (A(q) + conj A(-q))/2,  f1 = -i (A(q) - conj A(-q))/2
+            o[2 * g] = {R(0.5) * (A.re + B.re), R(0.5) * (A.im - B.im)};
+            o[2 * g + 1] = {R(0.5) * (A.im + B.im), R(-0.5) * (A.re - B.re)};
+        }
+        C1<R>* dst = out + ((line0 + l) * (M / 2) + q) * 4;
+        for (int c = 0; c < 4; ++c) dst[c] = o[c];
+    }
+}
+
+// x pass, inverse, half spectrum -> real. The qx = M/2 plane is zero.
+template <typename R, int M, int LPB>
+__global__ __launch_bounds__(256) void k_fft_x_inv(const C1<R>* __restrict__ in, R4<R>* __restrict__ out,
+                                                   const double* __restrict__ twg) {
+    __shared__ C1<R> buf[2][2 * LPB * M];
+    __shared__ C1<R> tw[M / 2];
+    load_twiddles<R, M>(tw, twg, -1);
+    const size_t line0 = (size_t)blockIdx.x * LPB;
+    for (int e = threadIdx.x; e < LPB * M; e += blockDim.x) {
+        const int l = e / M, x = e - l * M;
+        for (int g = 0; g < 2; ++g) {
+            C1<R> A;
+            if (x == 0) {
+                const C1<R>* s = in + ((line0 + l) * (M / 2)) * 4 + 2 * g;
+                A = {s[0].re, s[1].re};
+            } else if (x < M / 2) {
+                const C1<R>* s = in + ((line0 + l) * (M / 2) + x) * 4 + 2 * g;
+                A = {s[0].re - s[1].im, s[0].im + s[1].re};       // G0 + i G1
+            } else if (x == M / 2) {
+                A = {R(0), R(0)};
+            } else {
+                const C1<R>* s = in + ((line0 + l) * (M / 2) + (M - x)) * 4 + 2 * g;
+                A = {s[0].re + s[1].im, s[1].re - s[0].im};       // conj G0 + i conj G1
+            }
+            buf[0][(2 * l + g) * M + x] = A;
+        }
+    }
+    __syncthreads();
+    C1<R>* r = lds_fft<R, M>(buf[0], buf[1], 2 * LPB, tw);
+    for (int e = threadIdx.x; e < LPB * M; e += blockDim.x) {
+        const int l = e / M, x = e - l * M;
+        const C1<R> A = r[(2 * l) * M + x], B = r[(2 * l + 1) * M + x];
+        out[(line0 + l) * M + x] = {A.re, A.im, B.re, B.im};
+    }
+}
+
+// y pass (either direction) on the half spectrum: a block owns W columns of
+// qx at one z; 4 fields per element -> 4W lines of length M.
+template <typename R, int M, int W>
+__global__ __launch_bounds__(256) void k_fft_y(C1<R>* __restrict__ data, const double* __restrict__ twg,
+                                               int sgn) {
+    __shared__ C1<R> buf[2][4 * W * M];
+    __shared__ C1<R> tw[M / 2];
+    load_twiddles<R, M>(tw, twg, sgn);
+    constexpr int HX = M / 2;
+    const int x0 = (blockIdx.x % (HX / W)) * W;
+    const int z = blockIdx.x / (HX / W);
+    for (int e = threadIdx.x; e < W * M * 4; e += blockDim.x) {
+        const int c = e & 3, w = (e >> 2) % W, y = (e >> 2) / W;
+        buf[0][(w * 4 + c) * M + y] = data[(((size_t)z * M + y) * HX + x0 + w) * 4 + c];
+    }
+    __syncthreads();
+    C1<R>* r = lds_fft<R, M>(buf[0], buf[1], 4 * W, tw);
+    for (int e = threadIdx.x; e < W * M * 4; e += blockDim.x) {
+        const int c = e & 3, w = (e >> 2) % W, y = (e >> 2) / W;
+        data[(((size_t)z * M + y) * HX + x0 + w) * 4 + c] = r[(w * 4 + c) * M + y];
+    }
+}
+
+struct KScale {
+    double twopi_over_L;   // k = (2 pi / L) q
+    double inv4xi2;        // 1 / (4 xi^2)
+    double two_tau;        // deconvolution exp(2 tau k^2)
+    double norm;           // 1/M^3 : grid-sum normalisation of forward x inverse
+    double inv_eta;
+};
+
+// z pass: forward z transform, k-space multiply (eq. wave-result with the
+// periodic Stokes propagator, the source flow and the pressure), inverse z
+// transform. A block owns W columns of qx at one qy.
+template <typename R, int M, int W>
+__global__ __launch_bounds__(256) void k_fft_z_scale(C1<R>* __restrict__ data,
+                                                     const double* __restrict__ twg, KScale ks) {
+    __shared__ C1<R> buf[2][4 * W * M];
+    __shared__ C1<R> twf[M / 2], twi[M / 2];
+    load_twiddles<R, M>(twf, twg, +1);
+    load_twiddles<R, M>(twi, twg, -1);
+    constexpr int HX = M / 2;
+    const int x0 = (blockIdx.x % (HX / W)) * W;
+    const int y = blockIdx.x / (HX / W);
+    const size_t zstride = (size_t)M * HX * 4;
+    for (int e = threadIdx.x; e < W * M * 4; e += blockDim.x) {
+        const int c = e & 3, w = (e >> 2) % W, z = (e >> 2) / W;
+        buf[0][(w * 4 + c) * M + z] = data[z * zstride + ((size_t)y * HX + x0 + w) * 4 + c];
+    }
+    __syncthreads();
+    C1<R>* a = lds_fft<R, M>(buf[0], buf[1], 4 * W, twf);
+    C1<R>* b = (a == buf[0]) ? buf[1] : buf[0];
+    const int qy = (y < M / 2) ? y : y - M;
+    for (int e = threadIdx.x; e < W * M; e += blockDim.x) {
+        const int w = e % W, z = e / W;
+        const int qx = x0 + w;
+        const int qz = (z < M / 2) ? z : z - M;
+        C1<R>* f0 = a + (w * 4 + 0) * M + z;
+        C1<R>* f1 = a + (w * 4 + 1) * M + z;
+        C1<R>* f2 = a + (w * 4 + 2) * M + z;
+        C1<R>* f3 = a + (w * 4 + 3) * M + z;
+        const bool zero = (qx == 0 && qy == 0 && qz == 0) || (y == M / 2) || (z == M / 2);
+        if (zero) {
+            *f0 = *f1 = *f2 = *f3 = {R(0), R(0)};
+            continue;
+        }
+        const double kx = ks.twopi_over_L * qx, ky = ks.twopi_over_L * qy, kz = ks.twopi_over_L * qz;
+        const double k2 = kx * kx + ky * ky + kz * kz;
+        const double ex = exp(k2 * (ks.two_tau - ks.inv4xi2)) * ks.norm / k2;
+        const R st = (R)(ks.inv_eta * (1.0 + k2 * ks.inv4xi2) * ex);   // Stokes, incl. 1/k^2
+        const R lp = (R)ex;                                              // Laplace 1/k^2
+        const R rkx = (R)kx, rky = (R)ky, rkz = (R)kz, ik2 = (R)(1.0 / k2);
+        const C1<R> h0 = *f0, h1 = *f1, h2 = *f2, h3 = *f3;
+        // k.f and the transverse projection
+        const C1<R> kf = {rkx * h0.re + rky * h1.re + rkz * h2.re, rkx * h0.im + rky * h1.im + rkz * h2.im};
+        const C1<R> pk = {kf.re * ik2, kf.im * ik2};
+        const R sq = R(0.25) * (R)ks.inv_eta * lp;   // source flow (i k)/(4 eta k^2)
+        // v = st (f - k (k.f)/k^2) + sq i k h3 ; i k h3 = k (-h3.im, h3.re)
+        *f0 = {st * (h0.re - rkx * pk.re) - sq * rkx * h3.im, st * (h0.im - rkx * pk.im) + sq * rkx * h3.re};
+        *f1 = {st * (h1.re - rky * pk.re) - sq * rky * h3.im, st * (h1.im - rky * pk.im) + sq * rky * h3.re};
+        *f2 = {st * (h2.re - rkz * pk.re) - sq * rkz * h3.im, st * (h2.im - rkz * pk.im) + sq * rkz * h3.re};
+        // p = i (k.f) / k^2
+        *f3 = {-lp * kf.im, lp * kf.re};
+    }
+    __syncthreads();
+    C1<R>* r = lds_fft<R, M>(a, b, 4 * W, twi);
+    for (int e = threadIdx.x; e < W * M * 4; e += blockDim.x) {
+        const int c = e & 3, w = (e >> 2) % W, z = (e >> 2) / W;
+        data[z * zstride + ((size_t)y * HX + x0 + w) * 4 + c] = r[(w * 4 + c) * M + z];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// gather: one wavefront per sphere (binned order); adds the pair/self part
+// and writes y in input order.
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_gather(
+    int n, const double* __restrict__ sp, const double* __restrict__ sa,
+    const int* __restrict__ perm, const R4<R>* __restrict__ grid, int M, int P, double h,
+    double alpha, double cwh3, double inv_eta, int parts, int compressible,
+    const double* __restrict__ ybuf, double* __restrict__ yout) {
+    constexpr int WPB = 4;
+    __shared__ R fac[WPB][3][kMaxP];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int s0 = blockIdx.x * WPB + wv;
+    const bool active = s0 < n;       // every wavefront reaches the barrier
+    const int s = active ? s0 : n - 1;
+    const int mask = M - 1;
+    int i0[3];
+    R d0[3];
+    for (int d = 0; d < 3; ++d) {
+        const double p = sp[3 * s + d];
+        i0[d] = (int)floor(p / h) - P / 2 + 1;
+        const double dd = i0[d] * h - p;
+        d0[d] = (R)dd;
+        if (lane < P) {
+            const double r = dd + lane * h;
+            fac[wv][d][lane] = (R)exp(-alpha * r * r);
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    double acc[13];
+    for (int c = 0; c < 13; ++c) acc[c] = 0.0;
+    if (parts & kPartsWave) {
+        const R al = (R)alpha, al2 = al * al, al3 = al2 * al, hh = (R)h;
+        const R a2 = (R)(sa[s] * sa[s]);
+        R ac[13], cp[13];
+        for (int c = 0; c < 13; ++c) ac[c] = cp[c] = R(0);
+        const int P2 = P * P;
+        for (int e = lane; e < P2; e += 64) {
+            const int kx = e % P, ky = e / P;
+            const R rx = d0[0] + kx * hh, ry = d0[1] + ky * hh;
+            const R wxy = (R)cwh3 * fac[wv][0][kx] * fac[wv][1][ky];
+            const int gx = (i0[0] + kx) & mask, gy = (i0[1] + ky) & mask;
+            for (int kz = 0; kz < P; ++kz) {
+                const int gz = (i0[2] + kz) & mask;
+                const R4<R> g = grid[((size_t)gz * M + gy) * M + gx];
+                const R rz = d0[2] + kz * hh;
+                const R r2 = rx * rx + ry * ry + rz * rz;
+                const R w = wxy * fac[wv][2][kz];
+                const R cU = w * (R(1) + a2 * (R(1) / R(6)) * (R(4) * al2 * r2 - R(6) * al));
+                const R cE = w * (R(2) * al - a2 * (R(1) / R(10)) * (R(20) * al2 - R(8) * al3 * r2));
+                const R cW = al * w;
+                R v[13];
+                v[0] = cU * g.x;
+                v[1] = cU * g.y;
+                v[2] = cU * g.z;
+                v[3] = cW * (ry * g.z - rz * g.y);
+                v[4] = cW * (rz * g.x - rx * g.z);
+                v[5] = cW * (rx * g.y - ry * g.x);
+                v[6] = cE * g.x * rx;
+                v[7] = cE * g.y * ry;
+                v[8] = cE * g.z * rz;
+                v[9] = cE * R(0.5) * (g.x * ry + g.y * rx);
+                v[10] = cE * R(0.5) * (g.x * rz + g.z * rx);
+                v[11] = cE * R(0.5) * (g.y * rz + g.z * ry);
+                v[12] = w * g.w;
+                for (int c = 0; c < 13; ++c) {
+                    const R sum = ac[c] + v[c];
+                    cp[c] += (fabs(ac[c]) >= fabs(v[c])) ? ((ac[c] - sum) + v[c]) : ((v[c] - sum) + ac[c]);
+                    ac[c] = sum;
+                }
+            }
+        }
+        for (int c = 0; c < 13; ++c) acc[c] = (double)ac[c] + (double)cp[c];
+        // wavefront reduction in FP64
+        for (int off = 32; off > 0; off >>= 1)
+            for (int c = 0; c < 13; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
+    }
+    if (lane == 0) {
+        const int i = perm[s];
+        double out[12];
+        const double* yb = ybuf + 12 * (size_t)s;
+        for (int c = 0; c < 6; ++c) out[c] = yb[c] + acc[c];
+        double e5[5];
+        sym_to_e5<double>(acc + 6, e5);
+        for (int c = 0; c < 5; ++c) out[6 + c] = yb[6 + c] + e5[c];
+        out[11] = yb[11] - inv_eta * (kSqrt3 / 4.0) * acc[12];
+        if (!compressible) out[11] = 0.0;
+        for (int c = 0; c < 12; ++c) yout[12 * (size_t)i + c] = out[c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers (declared in seasd_internal.h)
+
+template <typename R>
+static int launch_fft_chain_M(int M, void* rgrid, void* spec, const double* tw, const KScale& ks,
+                              hipStream_t st, PhaseTimer* tm);
+
+#define FFT_CASE(MM, LPB, W)                                                                            \
+    case MM: {                                                                                          \
+        const int lines = MM * MM;                                                                      \
+        tm->begin(kPhaseFftXFwd, st);                                                                   \
+        hipLaunchKernelGGL((k_fft_x_fwd<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,              \
+                           (const R4<R>*)rgrid, (C1<R>*)spec, tw);                                      \
+        tm->begin(kPhaseFftYFwd, st);                                                                   \
+        hipLaunchKernelGGL((k_fft_y<R, MM, W>), dim3((MM / 2 / W) * MM), dim3(256), 0, st,              \
+                           (C1<R>*)spec, tw, +1);                                                       \
+        tm->begin(kPhaseFftZ, st);                                                                      \
+        hipLaunchKernelGGL((k_fft_z_scale<R, MM, W>), dim3((MM / 2 / W) * MM), dim3(256), 0, st,        \
+                           (C1<R>*)spec, tw, ks);                                                       \
+        tm->begin(kPhaseFftYInv, st);                                                                   \
+        hipLaunchKernelGGL((k_fft_y<R, MM, W>), dim3((MM / 2 / W) * MM), dim3(256), 0, st,              \
+                           (C1<R>*)spec, tw, -1);                                                       \
+        tm->begin(kPhaseFftXInv, st);                                                                   \
+        hipLaunchKernelGGL((k_fft_x_inv<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,              \
+                           (const C1<R>*)spec, (R4<R>*)rgrid, tw);                                      \
+        break;                                                                                          \
+    }
+
+template <typename R>
+static int launch_fft_chain_M(int M, void* rgrid, void* spec, const double* tw, const KScale& ks,
+                              hipStream_t st, PhaseTimer* tm) {
+    constexpr bool dbl = sizeof(R) == 8;
+    switch (M) {
+        FFT_CASE(8, 8, 2)
+        FFT_CASE(16, 8, 2)
+        FFT_CASE(32, 4, 2)
+        FFT_CASE(64, 4, 2)
+        FFT_CASE(128, 2, (dbl ? 1 : 2))
+        FFT_CASE(256, 1, (dbl ? 1 : 2))
+        default:
+            return -1;
+    }
+    return 0;
+}
+
+int launch_apply(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
+    const int n = (int)A.n;
+    const int T = 256;
+    const int gb = (n + T - 1) / T;
+    const int nbins = A.nb * A.nb * A.nb;
+    tm->begin(kPhaseBin, st);
+    hipMemsetAsync(A.counts, 0, sizeof(int) * nbins, st);
+    hipMemsetAsync(A.amax_bits, 0, sizeof(unsigned long long), st);
+    hipLaunchKernelGGL(k_bin_count, dim3(gb), dim3(T), 0, st, n, A.pos, A.radius, A.L, A.nb, A.binw,
+                       A.bin_of, A.counts, A.amax_bits, A.err);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, nbins, A.counts, A.start, A.fill);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(gb), dim3(T), 0, st, n, A.bin_of, A.start, A.fill, A.perm);
+    hipLaunchKernelGGL(k_bin_order, dim3((nbins + T - 1) / T), dim3(T), 0, st, nbins, A.start, A.perm);
+    hipLaunchKernelGGL(k_bin_gather, dim3(gb), dim3(T), 0, st, n, A.perm, A.pos, A.radius, A.x, A.L,
+                       A.compressible, A.sp, A.sa, A.sx, A.err);
+    tm->begin(kPhasePair, st);
+    hipLaunchKernelGGL(k_pair, dim3(gb), dim3(T), 0, st, n, A.sp, A.sa, A.sx, A.start, A.nb, A.L, A.binw,
+                       A.xi, A.rc_factor, A.inv_eta, A.amax_bits, A.parts, A.checks, A.ybuf, A.err);
+    const bool wave = (A.parts & kPartsWave) != 0;
+    const int tiles = A.M / kTile;
+    KScale ks{2.0 * kPi / A.L, 1.0 / (4.0 * A.xi * A.xi), 2.0 * A.tau,
+              1.0 / ((double)A.M * A.M * A.M), A.inv_eta};
+    if (A.fp32) {
+        if (wave) {
+            tm->begin(kPhaseSpread, st);
+            hipLaunchKernelGGL((k_spread<float>), dim3(tiles * tiles * tiles), dim3(512), 0, st, n, A.sp,
+                               A.sa, A.sx, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
+                               (R4<float>*)A.rgrid);
+            if (launch_fft_chain_M<float>(A.M, A.rgrid, A.spec, A.twiddle, ks, st, tm)) return -1;
+        }
+        tm->begin(kPhaseGather, st);
+        hipLaunchKernelGGL((k_gather<float>), dim3((n + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa, A.perm,
+                           (const R4<float>*)A.rgrid, A.M, A.P, A.h, A.alpha, A.cw * A.h * A.h * A.h,
+                           A.inv_eta, A.parts, A.compressible, A.ybuf, A.y);
+    } else {
+        if (wave) {
+            tm->begin(kPhaseSpread, st);
+            hipLaunchKernelGGL((k_spread<double>), dim3(tiles * tiles * tiles), dim3(512), 0, st, n, A.sp,
+                               A.sa, A.sx, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
+                               (R4<double>*)A.rgrid);
+            if (launch_fft_chain_M<double>(A.M, A.rgrid, A.spec, A.twiddle, ks, st, tm)) return -1;
+        }
+        tm->begin(kPhaseGather, st);
+        hipLaunchKernelGGL((k_gather<double>), dim3((n + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa, A.perm,
+                           (const R4<double>*)A.rgrid, A.M, A.P, A.h, A.alpha, A.cw * A.h * A.h * A.h,
+                           A.inv_eta, A.parts, A.compressible, A.ybuf, A.y);
+    }
+    tm->end(st);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+}  // namespace seasd

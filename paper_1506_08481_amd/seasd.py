@@ -1,0 +1,222 @@
+"""Python binding of the C ABI in include/seasd.h (ctypes; marshalling only).
+
+Every step of the mobility product and of the far-field solve runs in the HIP
+library libseasd.so built by paper_1506_08481_amd.build. Importing this module
+when the library has not been built raises at once; there is no other
+implementation to fall back on.
+
+PyTorch is used for device memory and streams: the functions take CUDA/HIP
+tensors and pass their data pointers and torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libseasd.so")
+
+SEASD_OK = 0
+SEASD_E_INVALID_ARG = -1
+SEASD_E_NONFINITE = -2
+SEASD_E_OVERLAP = -3
+SEASD_E_CUTOFF = -4
+SEASD_E_SINGULAR = -5
+SEASD_E_HIP = -6
+SEASD_E_NOMEM = -7
+SEASD_E_UNSUPPORTED = -8
+SEASD_W_NOT_CONVERGED = 1
+
+SEASD_FP64, SEASD_FP32 = 0, 1
+SEASD_PARTS_REAL, SEASD_PARTS_WAVE, SEASD_PARTS_SELF, SEASD_PARTS_ALL = 1, 2, 4, 7
+SEASD_PRECOND_NONE, SEASD_PRECOND_BLOCKDIAG = 0, 1
+
+PHASES = ("bin", "pair", "spread", "fft_x_fwd", "fft_y_fwd", "fft_z_scale", "fft_y_inv", "fft_x_inv", "gather")
+
+# exported symbols of include/seasd.h
+SYMBOLS = ("seasd_create", "seasd_destroy", "seasd_default_config", "seasd_set_config",
+           "seasd_mobility_apply", "seasd_solve_farfield", "seasd_profile_enable",
+           "seasd_profile_read", "seasd_error_string")
+
+
+class seasd_config(ctypes.Structure):
+    _fields_ = [
+        ("grid", ctypes.c_int32),
+        ("P", ctypes.c_int32),
+        ("m", ctypes.c_double),
+        ("xi", ctypes.c_double),
+        ("rc_factor", ctypes.c_double),
+        ("eta", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("parts", ctypes.c_int32),
+        ("compressible", ctypes.c_int32),
+        ("checks", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("restart", ctypes.c_int32),
+        ("precond", ctypes.c_int32),
+    ]
+
+
+class seasd_solve_stats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32),
+        ("restarts", ctypes.c_int32),
+        ("matvecs", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("true_residual", ctypes.c_double),
+        ("setup_ms", ctypes.c_double),
+        ("solve_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SeasdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"seasd error {code}: {msg}")
+        self.code = code
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1506_08481_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    lib.seasd_create.argtypes = [ctypes.POINTER(vp), i32]
+    lib.seasd_destroy.argtypes = [vp]
+    lib.seasd_default_config.argtypes = [ctypes.POINTER(seasd_config)]
+    lib.seasd_set_config.argtypes = [vp, ctypes.POINTER(seasd_config)]
+    lib.seasd_mobility_apply.argtypes = [vp, i64, dp, dp, ctypes.POINTER(ctypes.c_double), dp, dp, vp]
+    lib.seasd_solve_farfield.argtypes = [vp, i64, dp, dp, ctypes.POINTER(ctypes.c_double), dp, dp,
+                                         ctypes.POINTER(seasd_solve_stats), vp]
+    lib.seasd_profile_enable.argtypes = [vp, i32]
+    lib.seasd_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32]
+    lib.seasd_error_string.argtypes = [i32]
+    lib.seasd_error_string.restype = ctypes.c_char_p
+    for name in SYMBOLS:
+        if name != "seasd_error_string":
+            getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+def _check(code: int, allow=(SEASD_OK,)) -> int:
+    if code not in allow:
+        raise SeasdError(code, lib().seasd_error_string(code).decode())
+    return code
+
+
+def default_config(**overrides) -> seasd_config:
+    c = seasd_config()
+    _check(lib().seasd_default_config(ctypes.byref(c)))
+    for k, v in overrides.items():
+        if not hasattr(c, k):
+            raise KeyError(k)
+        setattr(c, k, v)
+    return c
+
+
+def _box9(box) -> ctypes.Array:
+    vals = [float(v) for v in (box.T.reshape(-1) if hasattr(box, "T") else box)]
+    if len(vals) != 9:
+        raise ValueError("box needs 9 values")
+    return (ctypes.c_double * 9)(*vals)
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _require(t, shape_tail, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 device tensor")
+    if tuple(t.shape[1:]) != shape_tail:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}")
+
+
+class Seasd:
+    """Owns one seasd_handle. box: a 3x3 array whose columns are the lattice
+    vectors (or 9 numbers a1, a2, a3)."""
+
+    def __init__(self, device: int = 0, **config):
+        h = ctypes.c_void_p()
+        _check(lib().seasd_create(ctypes.byref(h), int(device)))
+        self.h = h
+        self.device = device
+        self.config = default_config(**config)
+        _check(lib().seasd_set_config(self.h, ctypes.byref(self.config)))
+
+    def set_config(self, **overrides):
+        for k, v in overrides.items():
+            setattr(self.config, k, v)
+        _check(lib().seasd_set_config(self.h, ctypes.byref(self.config)))
+
+    def seasd_mobility_apply(self, pos, radius, box, x, y=None, stream=None):
+        import torch
+        _require(pos, (3,), "pos")
+        _require(x, (12,), "x")
+        if radius.dim() != 1 or radius.dtype != torch.float64 or not radius.is_cuda:
+            raise TypeError("radius must be a 1-D float64 device tensor")
+        n = pos.shape[0]
+        if y is None:
+            y = torch.empty((n, 12), dtype=torch.float64, device=pos.device)
+        _check(lib().seasd_mobility_apply(self.h, n, pos.data_ptr(), radius.data_ptr(), _box9(box),
+                                          x.data_ptr(), y.data_ptr(), ctypes.c_void_p(_stream_ptr(stream))))
+        return y
+
+    apply = seasd_mobility_apply
+
+    def seasd_solve_farfield(self, pos, radius, box, b, x0=None, stream=None):
+        import torch
+        _require(pos, (3,), "pos")
+        _require(b, (12,), "b")
+        n = pos.shape[0]
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        st = seasd_solve_stats()
+        code = lib().seasd_solve_farfield(self.h, n, pos.data_ptr(), radius.data_ptr(), _box9(box),
+                                          b.data_ptr(), x.data_ptr(), ctypes.byref(st),
+                                          ctypes.c_void_p(_stream_ptr(stream)))
+        _check(code, allow=(SEASD_OK, SEASD_W_NOT_CONVERGED))
+        return x, st.as_dict()
+
+    solve = seasd_solve_farfield
+
+    def profile(self, enable: bool = True):
+        _check(lib().seasd_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        buf = (ctypes.c_double * len(PHASES))()
+        n = lib().seasd_profile_read(self.h, buf, len(PHASES))
+        if n < 0:
+            _check(n)
+        return {PHASES[i]: buf[i] for i in range(len(PHASES))}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().seasd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def default_m(P: int) -> float:
+    return math.sqrt(math.pi * P)

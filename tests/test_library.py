@@ -1,0 +1,61 @@
+"""Host-side checks of the C-ABI library: it loads, exports every symbol that
+include/seasd.h declares, and the binding's structures match the header.
+No GPU is touched."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1506_08481_amd import seasd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "seasd.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(seasd_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_header_symbols():
+    if not os.path.exists(seasd.LIB_PATH):
+        pytest.skip("libseasd.so not built")
+    lib = ctypes.CDLL(seasd.LIB_PATH)
+    declared = _header_functions()
+    assert declared, "no declarations parsed"
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(seasd.SYMBOLS)
+
+
+def _header_struct_fields(name):
+    src = open(os.path.join(ROOT, "include", "seasd.h")).read()
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), src, re.S).group(1)
+    fields = []
+    for line in body.splitlines():
+        line = line.split("/*")[0].strip()
+        if not line:
+            continue
+        typ, rest = line.split(None, 1)
+        for f in rest.rstrip(";").split(","):
+            fields.append((typ, f.strip()))
+    return fields
+
+
+@pytest.mark.parametrize("cname,pyclass", [("seasd_config", seasd.seasd_config),
+                                           ("seasd_solve_stats", seasd.seasd_solve_stats)])
+def test_binding_struct_layout_matches_header(cname, pyclass):
+    cmap = {"int32_t": ctypes.c_int32, "double": ctypes.c_double}
+    hdr = _header_struct_fields(cname)
+    assert [f for _, f in hdr] == [f for f, _ in pyclass._fields_]
+    for (typ, f), (pf, pt) in zip(hdr, pyclass._fields_):
+        assert cmap[typ] is pt, f
+
+
+def test_default_config_and_validation_on_host():
+    # seasd_default_config and the error strings touch no device state
+    if not os.path.exists(seasd.LIB_PATH):
+        pytest.skip("libseasd.so not built")
+    c = seasd.default_config()
+    assert c.grid == 64 and c.P == 16 and c.rc_factor == 4.0 and c.precision == seasd.SEASD_FP64
+    assert seasd.lib().seasd_error_string(seasd.SEASD_E_OVERLAP).decode().startswith("overlapping")
