@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Throughput of the Spectral Ewald grand-mobility product on one MI355X.
+
+Workload: N = 100,000 monodisperse spheres (a = 1) at volume fraction 0.4 in a
+periodic cube (L = 101.55), random non-overlapping placement; moments x drawn
+i.i.d. N(0, 1); grid 256^3; spreading, FFTs and gather in FP32, pair sum in
+FP64. One step = one full product y = M x (binning, real-space pair sum,
+spreading, five FFT passes with the k-space multiply, gather), inputs resident
+in HBM. Parameters (xi, r_c, P, m) are chosen among a few candidates as the
+fastest one whose relative error against the FP64 GPU product is below 1e-6.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+
+# (xi, rc_factor, P, m / sqrt(pi P))
+CANDIDATES = [
+    (0.7, 3.5, 14, 0.95),
+    (0.8, 3.0, 16, 0.85),
+    (0.7, 3.5, 16, 0.95),
+]
+REF = (0.7, 3.5, 18, 0.95)   # FP64 reference product (SE error ~1e-8)
+
+
+def phase_cost(phase, n, M, P, s_bytes, pairs):
+    """Algorithmic bytes and flops of one launch of a phase (see the design notes):
+    FFT passes read and write the 4-field grid once: 8 M^3 s bytes; spreading
+    writes the grid once (4 M^3 s) and reads the binned particles (16 doubles
+    each); gather reads the grid once (4 M^3 s) and the particles; their flops
+    are 48 (spread) and 60 (gather) per window point and sphere; the pair sum
+    costs about 700 FP64 flops per pair within the cut-off."""
+    g = M ** 3
+    if phase.startswith("fft"):
+        return {"bytes": 8 * g * s_bytes, "flops": 0.0}
+    if phase == "spread":
+        return {"bytes": 4 * g * s_bytes + n * 16 * 8, "flops": 48.0 * n * P ** 3}
+    if phase == "gather":
+        return {"bytes": 4 * g * s_bytes + n * 28 * 8, "flops": 60.0 * n * P ** 3}
+    if phase == "pair":
+        return {"bytes": n * 28 * 8, "flops": 700.0 * pairs}
+    return {"bytes": n * 64, "flops": 0.0}
+
+
+def count_pairs(pos, rad, L, rc_factor):
+    from scipy.spatial import cKDTree
+    tree = cKDTree(np.mod(pos, L), boxsize=L)
+    rmax = rc_factor * 2.0 * float(rad.max())
+    pr = tree.query_pairs(rmax, output_type="ndarray")
+    d = pos[pr[:, 0]] - pos[pr[:, 1]]
+    d -= L * np.round(d / L)
+    r = np.linalg.norm(d, axis=1)
+    keep = r < rc_factor * (rad[pr[:, 0]] + rad[pr[:, 1]])
+    return 2 * int(np.count_nonzero(keep))   # ordered pairs
+
+
+def cpu_baseline(seconds_hint=20.0):
+    """The FP64 oracle timed on a bounded sample of the same kind of workload:
+    a full product for N = 300 spheres at phi = 0.4, single-threaded, then
+    scaled to N = 100,000 by the N^(3/2) cost of a classical Ewald sum."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import ewald
+    from paper_1506_08481_amd import workloads as wl
+    n_s = 300
+    s = wl.monodisperse(n_s, 0.4, 31)
+    x = wl.force_moments(n_s, 32)
+    with threadpool_limits(limits=1):
+        p = ewald.converged_params(s.box, s.radius, xi=0.5, tol_exp=6.5)
+        t0 = time.perf_counter()
+        ewald.apply(s.pos, s.radius, s.box, x, p)
+        dt = time.perf_counter() - t0
+    scale = (100000.0 / n_s) ** 1.5
+    return {"value": 1.0 / (dt * scale), "unit": "matvecs/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full oracle product (converged classical Ewald, FP64, numpy) for N={n_s} "
+                      f"at phi=0.4 took {dt:.2f} s on 1 thread; scaled to N=100000 by (N/{n_s})^1.5 "
+                      f"= x{scale:.0f}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n", type=int, default=100000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1506_08481_amd import seasd
+    from paper_1506_08481_amd import workloads as wl
+
+    t_setup = time.time()
+    s = wl.config_large(n=args.n)
+    x = wl.force_moments(s.n, 3001)
+    dev = torch.device("cuda:0")
+    P_ = torch.as_tensor(s.pos, device=dev)
+    R_ = torch.as_tensor(s.radius, device=dev)
+    X_ = torch.as_tensor(x, device=dev)
+    M = 256
+    print(f"setup: N={s.n} L={s.L:.3f} placement {time.time() - t_setup:.1f}s", file=sys.stderr, flush=True)
+
+    def engine(cand, precision):
+        xi, rcf, P, mf = cand
+        return seasd.Seasd(0, grid=M, P=P, m=mf * math.sqrt(math.pi * P), xi=xi, rc_factor=rcf,
+                           precision=precision, checks=0)
+
+    ref_eng = engine(REF, seasd.SEASD_FP64)
+    ref_eng.set_config(checks=1)
+    yref = ref_eng.apply(P_, R_, s.box, X_).clone()
+    ref_eng.close()
+    torch.cuda.synchronize()
+
+    # candidate selection: fastest with |y - y_fp64| / |y_fp64| <= 1e-6
+    best = None
+    tune = []
+    for cand in CANDIDATES:
+        eng = engine(cand, seasd.SEASD_FP32)
+        y = eng.apply(P_, R_, s.box, X_)
+        torch.cuda.synchronize()
+        err = float(torch.linalg.norm(y - yref) / torch.linalg.norm(yref))
+        t0 = time.perf_counter()
+        for _ in range(5):
+            eng.apply(P_, R_, s.box, X_, y)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / 5 * 1e3
+        tune.append({"xi": cand[0], "rc_factor": cand[1], "P": cand[2], "m": round(cand[3] * math.sqrt(math.pi * cand[2]), 3),
+                     "err_vs_fp64": err, "ms": ms})
+        print(f"candidate {cand}: err {err:.2e} {ms:.3f} ms", file=sys.stderr, flush=True)
+        if err <= 1e-6 and (best is None or ms < best[1]):
+            best = (cand, ms, err)
+        eng.close()
+    if best is None:
+        best = (CANDIDATES[-1], None, None)
+    cand = best[0]
+    eng = engine(cand, seasd.SEASD_FP32)
+    y = torch.empty_like(X_)
+    for _ in range(args.warmup):
+        eng.apply(P_, R_, s.box, X_, y)
+    torch.cuda.synchronize()
+    eng.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        eng.apply(P_, R_, s.box, X_, y)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    phases = eng.profile_read()
+    eng.profile(False)
+    err = float(torch.linalg.norm(y - yref) / torch.linalg.norm(yref))
+    ms_per_step = elapsed / args.steps * 1e3
+
+    pairs = count_pairs(s.pos, s.radius, s.L, cand[1])
+    kernel_phases = [k for k in seasd.PHASES if k != "bin"]
+    dom = max(kernel_phases, key=lambda k: phases[k])
+    cost = phase_cost(dom, s.n, M, cand[2], 4, pairs)
+    t_dom = phases[dom] * 1e-3
+    if dom == "pair":
+        roof = {"bound": "alu", "achieved": cost["flops"] / t_dom / 1e12, "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s"}
+    elif cost["flops"] / PEAK_FP32_TFLOPS / 1e12 > cost["bytes"] / PEAK_HBM_GBS / 1e9:
+        roof = {"bound": "alu", "achieved": cost["flops"] / t_dom / 1e12, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": cost["bytes"] / t_dom / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["kernel_ms"] = phases[dom]
+
+    out = {
+        "metric": "M·F matvecs/s at N=1e5, phi=0.4, 1e-6 err",
+        "value": 1e3 / ms_per_step,
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "monodisperse spheres N=100000 phi=0.4, grid 256^3, FP32 spread/FFT/gather, "
+                               "FP64 pair sum", "N": s.n, "L": s.L, "grid": M,
+                   "xi": cand[0], "rc_factor": cand[1], "P": cand[2],
+                   "m": cand[3] * math.sqrt(math.pi * cand[2])},
+        "rel_err_vs_fp64_gpu": err,
+        "phases_ms": {k: round(v, 5) for k, v in phases.items()},
+        "tuning": tune,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -152,13 +152,22 @@ int seasd_mobility_apply(seasd_handle handle, int64_t n,
                          const double* pos, const double* radius, const double* box,
                          const double* x, double* y, void* stream);
 
-/* Far-field solve M x = b for all 12n unknowns (Sec. 4.1, eq. HI-ff with no
- * near-field resistance), by right-preconditioned restarted GMRES in FP64 on
- * the device, with the block-diagonal far-field preconditioner of Sec. 4.2
- * (each sphere's 12x12 block with its own periodic images, inverted in FP64).
- *   b      device [n][12] right-hand side
- *   x      device [n][12] in: initial guess, out: solution
- *   stats  host, may be NULL
+/* Far-field solve (Sec. 4.1, eq. HI-ff with no near-field resistance) by
+ * right-preconditioned restarted GMRES in FP64 on the device, with the
+ * block-diagonal far-field preconditioner of Sec. 4.2 (each sphere's 11x11
+ * incompressible block with its own periodic images, inverted in FP64).
+ * The pressure moments follow the paper's one-way coupling (Sec. 2.3): only
+ * the part of each pressure moment fixed by its own trace equation,
+ * s_self = b_trace / m_self, drives source flows while F, T, S are solved;
+ * the interaction part comes afterwards from the pressure Faxen law:
+ *   A f = b_f - C s_self,   s = (b_trace - D f) / m_self,
+ * with A the 11x11 incompressible block of M, C its source-flow column and D
+ * its pressure row. With compressible = 0 the trace is dropped (s = 0).
+ *   b      device [n][12] right-hand side (U, W, E, e)
+ *   x      device [n][12] in: initial guess for F, T, S (trace ignored),
+ *          out: solution
+ *   stats  host, may be NULL; true_residual is ||b' - A f|| / ||b'|| of the
+ *          incompressible system (b' = b_f - C s_self) from a fresh product
  * Synchronises `stream`. Returns SEASD_W_NOT_CONVERGED if max_iter was reached
  * with the true residual above tol (x then holds the last iterate), and the
  * errors of seasd_mobility_apply or SEASD_E_SINGULAR. */
@@ -166,12 +175,16 @@ int seasd_solve_farfield(seasd_handle handle, int64_t n,
                          const double* pos, const double* radius, const double* box,
                          const double* b, double* x, seasd_solve_stats* stats, void* stream);
 
-/* Per-phase timing of the most recent mobility product, recorded with HIP
- * events on the call's stream when enabled (off by default, costs one event
- * pair per phase). Phases, in order: bin, pair, spread, fft_x_fwd, fft_y_fwd,
- * fft_z_scale, fft_y_inv, fft_x_inv, gather. ms receives up to `count` values;
- * returns the number of phases, or a negative error. Synchronises the stream
- * of the last product. */
+/* Per-phase timing of mobility products, recorded with HIP events on each
+ * call's stream while enabled (off by default; one event per phase, no
+ * synchronisation). Phases, in order: bin, pair, spread, fft_x_fwd,
+ * fft_y_fwd, fft_z_scale, fft_y_inv, fft_x_inv, gather.
+ * seasd_profile_enable(h, 1) starts a new recording (also discarding any
+ * unread one); seasd_profile_read synchronises the stream of the last
+ * product, writes the average duration in ms of each phase over the products
+ * recorded since then into ms[0..8], the number of those products into ms[9]
+ * (when count > 9), starts a new recording and returns the number of phases
+ * (9), or a negative error. */
 int seasd_profile_enable(seasd_handle handle, int32_t enable);
 int seasd_profile_read(seasd_handle handle, double* ms, int32_t count);
 

@@ -52,9 +52,11 @@ struct seasd_handle_s {
     bool have_cfg = false;
     // product workspace
     DevBuf bin_of, counts, start, fill, perm, amax, err, sp, sa, sx, ybuf, rgrid, spec, twiddle;
+    DevBuf ncount, noff, list, total;
+    int64_t geom_n = -1;      // spheres in the geometry currently held in the workspace
     int twiddle_M = 0;
     // solver workspace
-    DevBuf V, w, z, u, r, hdev, partial, blocks, inv, coef, singular, one_pos, one_rad, one_x, one_y;
+    DevBuf V, w, z, u, r, bred, hdev, partial, blocks, inv, coef, singular, one_pos, one_rad, one_x, one_y;
     PhaseTimer timer;
     hipStream_t last_stream = nullptr;
 };
@@ -118,11 +120,11 @@ extern "C" int seasd_destroy(seasd_handle h) {
     hipSetDevice(h->device);
     DevBuf* bufs[] = {&h->bin_of, &h->counts, &h->start, &h->fill, &h->perm, &h->amax, &h->err,
                       &h->sp, &h->sa, &h->sx, &h->ybuf, &h->rgrid, &h->spec, &h->twiddle,
-                      &h->V, &h->w, &h->z, &h->u, &h->r, &h->hdev, &h->partial, &h->blocks,
+                      &h->ncount, &h->noff, &h->list, &h->total,
+                      &h->V, &h->w, &h->z, &h->u, &h->r, &h->bred, &h->hdev, &h->partial, &h->blocks,
                       &h->inv, &h->coef, &h->singular, &h->one_pos, &h->one_rad, &h->one_x, &h->one_y};
     for (DevBuf* b : bufs) b->release();
-    if (h->timer.created)
-        for (auto& e : h->timer.ev) hipEventDestroy(e);
+    h->timer.destroy();
     delete h;
     return SEASD_OK;
 }
@@ -180,6 +182,9 @@ static int ensure_product_ws(seasd_handle h, int64_t n) {
     rc |= h->sa.ensure(sizeof(double) * n);
     rc |= h->sx.ensure(sizeof(double) * 12 * n);
     rc |= h->ybuf.ensure(sizeof(double) * 12 * n);
+    rc |= h->ncount.ensure(sizeof(int) * n);
+    rc |= h->noff.ensure(sizeof(int) * (n + 1));
+    rc |= h->list.ensure(sizeof(int2) * 1024);
     if (h->cfg.parts & SEASD_PARTS_WAVE) {
         rc |= h->rgrid.ensure(R * 4 * (size_t)M * M * M);
         rc |= h->spec.ensure(R * 4 * (size_t)M * M * M);
@@ -202,13 +207,10 @@ static int ensure_product_ws(seasd_handle h, int64_t n) {
     return SEASD_OK;
 }
 
-// queue one product; no synchronisation
-static int queue_apply(seasd_handle h, int64_t n, const double* pos, const double* radius, double L,
-                       const double* x, double* y, hipStream_t st, bool checks) {
+static void fill_args(seasd_handle h, ApplyArgs& A, int64_t n, const double* pos, const double* radius, double L,
+                      const double* x, double* y, bool checks, int compressible) {
     const seasd_config& c = h->cfg;
-    int rc = ensure_product_ws(h, n);
-    if (rc) return rc;
-    ApplyArgs A{};
+    A = ApplyArgs{};
     A.n = n;
     A.pos = pos;
     A.radius = radius;
@@ -228,7 +230,7 @@ static int queue_apply(seasd_handle h, int64_t n, const double* pos, const doubl
     A.alpha = 1.0 / (4.0 * A.tau);
     A.cw = std::pow(4.0 * kPi * A.tau, -1.5);
     A.parts = c.parts;
-    A.compressible = c.compressible;
+    A.compressible = compressible;
     A.checks = checks ? 1 : 0;
     A.fp32 = c.precision == SEASD_FP32;
     A.bin_of = h->bin_of.as<int>();
@@ -236,6 +238,9 @@ static int queue_apply(seasd_handle h, int64_t n, const double* pos, const doubl
     A.start = h->start.as<int>();
     A.fill = h->fill.as<int>();
     A.perm = h->perm.as<int>();
+    A.ncount = h->ncount.as<int>();
+    A.noff = h->noff.as<int>();
+    A.list = h->list.as<int2>();
     A.amax_bits = h->amax.as<unsigned long long>();
     A.err = h->err.as<int>();
     A.sp = h->sp.as<double>();
@@ -245,9 +250,37 @@ static int queue_apply(seasd_handle h, int64_t n, const double* pos, const doubl
     A.rgrid = h->rgrid.p;
     A.spec = h->spec.p;
     A.twiddle = h->twiddle.as<double>();
+}
+
+// Queue one product. With reuse_geometry the binning and neighbour list of the
+// previous call (same spheres) are kept and only the moments are re-binned.
+// Building a geometry waits once for the neighbour total (one 4-byte copy) to
+// size the list; everything else is queued without synchronisation.
+static int queue_apply(seasd_handle h, int64_t n, const double* pos, const double* radius, double L,
+                       const double* x, double* y, hipStream_t st, bool checks, bool reuse_geometry = false,
+                       int compressible = -1) {
+    if (compressible < 0) compressible = h->cfg.compressible;
+    int rc = ensure_product_ws(h, n);
+    if (rc) return rc;
+    ApplyArgs A;
+    fill_args(h, A, n, pos, radius, L, x, y, checks, compressible);
     if (checks && hipMemsetAsync(A.err, 0, sizeof(int), st) != hipSuccess) return SEASD_E_HIP;
-    h->timer.reset();
-    if (launch_apply(A, st, &h->timer)) return SEASD_E_HIP;
+    h->timer.start_product();
+    if (reuse_geometry && h->geom_n == n) {
+        if (launch_moments(A, st)) return SEASD_E_HIP;
+    } else {
+        h->geom_n = -1;
+        if (launch_geometry(A, st, &h->timer)) return SEASD_E_HIP;
+        int total = 0;
+        if (hipMemcpyAsync(&total, A.noff + n, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return SEASD_E_HIP;
+        if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
+        if (total < 0) return SEASD_E_CUTOFF;
+        if (h->list.ensure(sizeof(int2) * ((size_t)total + 1))) return SEASD_E_NOMEM;
+        A.list = h->list.as<int2>();
+        if (launch_pairlist(A, st)) return SEASD_E_HIP;
+        h->geom_n = n;
+    }
+    if (launch_compute(A, st, &h->timer)) return SEASD_E_HIP;
     h->last_stream = st;
     return SEASD_OK;
 }
@@ -279,27 +312,32 @@ extern "C" int seasd_mobility_apply(seasd_handle h, int64_t n, const double* pos
 
 extern "C" int seasd_profile_enable(seasd_handle h, int32_t enable) {
     if (!h) return SEASD_E_INVALID_ARG;
-    if (enable && !h->timer.created) {
-        if (hipSetDevice(h->device) != hipSuccess) return SEASD_E_HIP;
-        for (auto& e : h->timer.ev)
-            if (hipEventCreate(&e) != hipSuccess) return SEASD_E_HIP;
-        h->timer.created = true;
-    }
+    if (hipSetDevice(h->device) != hipSuccess) return SEASD_E_HIP;
     h->timer.enabled = enable != 0;
+    h->timer.products = 0;
     return SEASD_OK;
 }
 
 extern "C" int seasd_profile_read(seasd_handle h, double* ms, int32_t count) {
     if (!h || !ms || count < 0) return SEASD_E_INVALID_ARG;
-    if (!h->timer.created) return SEASD_E_INVALID_ARG;
-    if (hipStreamSynchronize(h->last_stream) != hipSuccess) return SEASD_E_HIP;
-    std::vector<double> out(kNumPhases, 0.0);
-    for (int k = 0; k + 1 < h->timer.count; ++k) {
-        float t = 0.f;
-        if (hipEventElapsedTime(&t, h->timer.ev[k], h->timer.ev[k + 1]) != hipSuccess) return SEASD_E_HIP;
-        if (h->timer.order[k] >= 0) out[h->timer.order[k]] += t;
+    if (hipSetDevice(h->device) != hipSuccess) return SEASD_E_HIP;
+    if (h->timer.products > 0 && hipStreamSynchronize(h->last_stream) != hipSuccess) return SEASD_E_HIP;
+    std::vector<double> out(kNumPhases + 1, 0.0);
+    const int np = h->timer.products;
+    constexpr int S = PhaseTimer::kSlots;
+    for (int p = 0; p < np; ++p) {
+        for (int k = 0; k + 1 < h->timer.used[p]; ++k) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, h->timer.ev[p * S + k], h->timer.ev[p * S + k + 1]) != hipSuccess)
+                return SEASD_E_HIP;
+            const int ph = h->timer.order[p * S + k];
+            if (ph >= 0) out[ph] += t;
+        }
     }
-    for (int k = 0; k < count && k < kNumPhases; ++k) ms[k] = out[k];
+    for (int k = 0; k < kNumPhases; ++k) out[k] = np ? out[k] / np : 0.0;
+    out[kNumPhases] = np;
+    for (int k = 0; k < count && k <= kNumPhases; ++k) ms[k] = out[k];
+    h->timer.products = 0;
     return kNumPhases;
 }
 
@@ -413,6 +451,7 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
     rc |= h->z.ensure(sizeof(double) * len);
     rc |= h->u.ensure(sizeof(double) * len);
     rc |= h->r.ensure(sizeof(double) * len);
+    rc |= h->bred.ensure(sizeof(double) * len);
     rc |= h->hdev.ensure(sizeof(double) * 256);
     rc |= h->partial.ensure(sizeof(double) * 256 * 256);
     if (rc) return SEASD_E_NOMEM;
@@ -421,17 +460,20 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
     double* z = h->z.as<double>();
     double* u = h->u.as<double>();
     double* r = h->r.as<double>();
+    double* bred = h->bred.as<double>();
     const bool pc = c.precond == SEASD_PRECOND_BLOCKDIAG;
-    if (pc) {
+    if (pc) {  // before the geometry: its single-sphere products use the shared workspace
         rc = build_preconditioner(h, n, radius, L, st);
         if (rc) return rc;
     }
     auto t1 = std::chrono::steady_clock::now();
     S.setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-    // input checks on the first product only
-    auto apply = [&](const double* in, double* out, bool chk) -> int {
-        int e = queue_apply(h, n, pos, radius, L, in, out, st, chk);
+    bool have_geometry = false;
+    // product with the incompressible components only (trace input and output zeroed)
+    auto apply11 = [&](const double* in, double* out, bool chk) -> int {
+        int e = queue_apply(h, n, pos, radius, L, in, out, st, chk, have_geometry, 0);
         if (e) return e;
+        have_geometry = true;
         ++S.matvecs;
         return chk ? read_err(h, st) : SEASD_OK;
     };
@@ -439,34 +481,44 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
         if (!pc) return hip_ok(hipMemcpyAsync(out, in, sizeof(double) * len, hipMemcpyDeviceToDevice, st));
         return launch_block_apply(n, h->inv.as<double>(), in, out, st) ? SEASD_E_HIP : SEASD_OK;
     };
+    // One-way pressure-moment coupling (Sec. 2.3 and 4.1): only the part of
+    // each pressure moment fixed by its own trace equation, s_self = b_trace /
+    // M_self, drives source flows in the solve; the interaction part follows
+    // from the pressure Faxen law once F, T, S are known.
+    if (c.compressible) {
+        if (launch_trace_op(n, 0, radius, c.eta, b, nullptr, z, st)) return SEASD_E_HIP;
+        rc = queue_apply(h, n, pos, radius, L, z, w, st, c.checks != 0, false, 1);
+        if (rc) return rc;
+        ++S.matvecs;
+        if (c.checks && (rc = read_err(h, st))) return rc;
+        if (launch_trace_op(n, 1, radius, c.eta, b, w, bred, st)) return SEASD_E_HIP;
+    } else {
+        if (hipMemsetAsync(w, 0, sizeof(double) * len, st) != hipSuccess) return SEASD_E_HIP;
+        if (launch_trace_op(n, 1, radius, c.eta, b, w, bred, st)) return SEASD_E_HIP;
+    }
     double bnorm2 = 0.0;
-    rc = dot_host(h, len, 1, b, len, b, &bnorm2, st);
+    rc = dot_host(h, len, 1, bred, len, bred, &bnorm2, st);
     if (rc) return rc;
     const double bnorm = std::sqrt(bnorm2);
-    if (bnorm == 0.0) {
-        hipMemsetAsync(x, 0, sizeof(double) * len, st);
-        hipStreamSynchronize(st);
-        S.converged = 1;
-        if (stats) *stats = S;
-        return SEASD_OK;
-    }
     std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), yv(m);
     bool first = true;
-    double relres = 1.0;
+    double relres = 0.0;
     int total = 0;
-    while (true) {
-        // r = b - M x
-        rc = apply(x, r, first && c.checks);
+    if (bnorm == 0.0) {
+        if (hipMemsetAsync(x, 0, sizeof(double) * len, st) != hipSuccess) return SEASD_E_HIP;
+    }
+    while (bnorm > 0.0) {
+        // r = b' - A x  (A: incompressible block)
+        rc = apply11(x, r, first && c.checks && !c.compressible);
         first = false;
         if (rc) return rc;
-        if (launch_axpby(len, 1.0, b, -1.0, r, st)) return SEASD_E_HIP;
+        if (launch_axpby(len, 1.0, bred, -1.0, r, st)) return SEASD_E_HIP;
         double rn2 = 0.0;
         rc = dot_host(h, len, 1, r, len, r, &rn2, st);
         if (rc) return rc;
         const double beta = std::sqrt(rn2);
         relres = beta / bnorm;
         if (relres <= c.tol || total >= c.max_iter) break;
-        // v_0 = r / beta
         if (launch_axpby(len, 1.0 / beta, r, 0.0, V, st)) return SEASD_E_HIP;
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
@@ -474,7 +526,7 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
         for (; j < m && total < c.max_iter; ++j, ++total) {
             rc = precond(V + j * len, z);
             if (rc) return rc;
-            rc = apply(z, w, false);
+            rc = apply11(z, w, false);
             if (rc) return rc;
             // classical Gram-Schmidt, twice
             for (int q = 0; q <= j; ++q) H[q * m + j] = 0.0;
@@ -516,21 +568,32 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
         }
         // y = H^-1 g (upper triangular j x j), x += P (V y)
         for (int q = j - 1; q >= 0; --q) {
-            double s = g[q];
-            for (int k = q + 1; k < j; ++k) s -= H[q * m + k] * yv[k];
-            yv[q] = H[q * m + q] != 0.0 ? s / H[q * m + q] : 0.0;
+            double sum = g[q];
+            for (int k = q + 1; k < j; ++k) sum -= H[q * m + k] * yv[k];
+            yv[q] = H[q * m + q] != 0.0 ? sum / H[q * m + q] : 0.0;
         }
         if (hipMemcpyAsync(h->hdev.p, yv.data(), sizeof(double) * j, hipMemcpyHostToDevice, st) != hipSuccess)
             return SEASD_E_HIP;
         if (hipMemsetAsync(u, 0, sizeof(double) * len, st) != hipSuccess) return SEASD_E_HIP;
-        // u = -(-V y)
-        if (launch_gemv_sub(len, j, V, len, h->hdev.as<double>(), u, st)) return SEASD_E_HIP;
+        if (launch_gemv_sub(len, j, V, len, h->hdev.as<double>(), u, st)) return SEASD_E_HIP;   // u = -V y
         rc = precond(u, z);
         if (rc) return rc;
         if (launch_axpby(len, -1.0, z, 1.0, x, st)) return SEASD_E_HIP;
         ++S.restarts;
         if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
     }
+    // pressure moments from the pressure Faxen law: s = M_self^-1 (b_trace - p-coupling(F, S))
+    if (launch_trace_op(n, 1, radius, c.eta, x, nullptr, z, st)) return SEASD_E_HIP;   // z = (F, T, S, 0)
+    if (c.compressible) {
+        rc = queue_apply(h, n, pos, radius, L, z, w, st, false, have_geometry, 1);
+        if (rc) return rc;
+        ++S.matvecs;
+        if (launch_trace_op(n, 1, radius, c.eta, z, nullptr, x, st)) return SEASD_E_HIP;
+        if (launch_trace_op(n, 2, radius, c.eta, b, w, x, st)) return SEASD_E_HIP;
+    } else if (hipMemcpyAsync(x, z, sizeof(double) * len, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+        return SEASD_E_HIP;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
     S.iterations = total;
     S.true_residual = relres;
     S.converged = relres <= c.tol ? 1 : 0;

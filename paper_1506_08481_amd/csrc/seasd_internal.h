@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace seasd {
 
 constexpr int kPartsReal = 1, kPartsWave = 2, kPartsSelf = 4;
@@ -22,30 +24,48 @@ enum Phase {
     kNumPhases
 };
 
-// Records one HIP event at the start of each phase on the launching stream
-// when enabled; the duration of a phase is the time to the next event.
+// When enabled, records one HIP event at the start of each phase (and one at
+// the end) of every product on the launching stream, without synchronising.
+// Event sets are kept per product until read, so a run of back-to-back
+// products can be timed phase by phase.
 struct PhaseTimer {
+    static constexpr int kSlots = kNumPhases + 1;
     bool enabled = false;
-    hipEvent_t ev[kNumPhases + 1] = {};
-    int order[kNumPhases + 1];
-    int count = 0;
-    bool created = false;
-    void reset() { count = 0; }
-    void begin(int phase, hipStream_t st) {
+    std::vector<hipEvent_t> ev;     // kSlots per recorded product
+    std::vector<int> order;         // phase of each slot (-1: end marker)
+    std::vector<int> used;          // slots used per product
+    int products = 0;
+    void start_product() {
         if (!enabled) return;
-        if (count <= kNumPhases) {
-            order[count] = phase;
-            hipEventRecord(ev[count], st);
-            ++count;
+        ++products;
+        if ((int)used.size() < products) {
+            used.push_back(0);
+            for (int k = 0; k < kSlots; ++k) {
+                hipEvent_t e;
+                hipEventCreate(&e);
+                ev.push_back(e);
+                order.push_back(-1);
+            }
         }
+        used[products - 1] = 0;
     }
-    void end(hipStream_t st) {
-        if (!enabled) return;
-        if (count <= kNumPhases) {
-            order[count] = -1;
-            hipEventRecord(ev[count], st);
-            ++count;
-        }
+    void mark(int phase, hipStream_t st) {
+        if (!enabled || products == 0) return;
+        int& u = used[products - 1];
+        if (u >= kSlots) return;
+        const int slot = (products - 1) * kSlots + u;
+        order[slot] = phase;
+        hipEventRecord(ev[slot], st);
+        ++u;
+    }
+    void begin(int phase, hipStream_t st) { mark(phase, st); }
+    void end(hipStream_t st) { mark(-1, st); }
+    void destroy() {
+        for (auto e : ev) hipEventDestroy(e);
+        ev.clear();
+        order.clear();
+        used.clear();
+        products = 0;
     }
 };
 
@@ -64,6 +84,9 @@ struct ApplyArgs {
     int* start;
     int* fill;
     int* perm;
+    int* ncount;     // [n] neighbours per binned sphere
+    int* noff;       // [n+1] their exclusive scan
+    int2* list;      // neighbour entries (j, packed image shift)
     unsigned long long* amax_bits;
     int* err;
     double* sp;
@@ -75,7 +98,10 @@ struct ApplyArgs {
     const double* twiddle;
 };
 
-int launch_apply(const ApplyArgs& a, hipStream_t st, PhaseTimer* tm);
+int launch_geometry(const ApplyArgs& a, hipStream_t st, PhaseTimer* tm);
+int launch_pairlist(const ApplyArgs& a, hipStream_t st);
+int launch_moments(const ApplyArgs& a, hipStream_t st);
+int launch_compute(const ApplyArgs& a, hipStream_t st, PhaseTimer* tm);
 
 // GMRES / preconditioner helpers (seasd_solver.hip)
 int launch_block_apply(int64_t n, const double* blocks, const double* v, double* z, hipStream_t st);
@@ -85,6 +111,8 @@ int launch_dots(int64_t len, int k, const double* V, int64_t ld, const double* w
 int launch_gemv_sub(int64_t len, int k, const double* V, int64_t ld, const double* h, double* w,
                     hipStream_t st);
 int launch_axpby(int64_t len, double a, const double* x, double b, double* y, hipStream_t st);
+int launch_trace_op(int64_t n, int mode, const double* radius, double eta, const double* b, const double* in,
+                    double* out, hipStream_t st);
 int launch_build_blocks(int64_t n, const double* radius, const double* coef, double xi, double eta,
                         double* blocks, hipStream_t st);
 

@@ -156,59 +156,136 @@ __global__ void k_bin_gather(int n, const int* __restrict__ perm, const double* 
 }
 
 // ---------------------------------------------------------------------------
-// real-space pair sum and self terms: one thread per sphere (binned order)
+// real-space pair sum and self terms (FP64)
+//
+// Pass 1 counts, per sphere, the sources (sphere j and lattice image) within
+// r_c = rc_factor (a_i + a_j); pass 2, after a scan, writes them as
+// (j, image code) entries; pass 3 evaluates the couplings along each list, so
+// no lane spends the heavy pair arithmetic on a candidate outside the cut-off.
 
-__global__ void k_pair(int n, const double* __restrict__ sp, const double* __restrict__ sa,
-                       const double* __restrict__ sx, const int* __restrict__ start, int nb,
-                       double L, double binw, double xi, double rc_factor, double inv_eta,
-                       const unsigned long long* __restrict__ amax_bits, int parts, int checks,
-                       double* __restrict__ ybuf, int* __restrict__ err) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline int floordiv(int c, int nb) { return (c >= 0) ? c / nb : -((-c + nb - 1) / nb); }
+
+// visit every (j, image) within the cut-off of binned sphere s; f(j, code) per hit
+template <typename F>
+__device__ inline void for_each_neighbour(int s, const double* __restrict__ sp, const double* __restrict__ sa,
+                                          const int* __restrict__ start, int nb, double L, double binw,
+                                          double rc_factor, double amax, int checks, int* __restrict__ err,
+                                          F&& f) {
+    const double px = sp[3 * s], py = sp[3 * s + 1], pz = sp[3 * s + 2];
+    const double ai = sa[s];
+    const double rcmax = rc_factor * (ai + amax);
+    int reach = (int)ceil(rcmax / binw);
+    if (reach > 3 * nb + 2) {  // cut-off beyond about three cell lengths: refuse
+        atomicOr(err, kErrCutoff);
+        reach = 3 * nb + 2;
+    }
+    const int bx = min(nb - 1, (int)(px / binw)), by = min(nb - 1, (int)(py / binw)),
+              bz = min(nb - 1, (int)(pz / binw));
+    for (int oz = -reach; oz <= reach; ++oz) {
+        int cz = bz + oz;
+        const int wz = floordiv(cz, nb);
+        cz -= wz * nb;
+        for (int oy = -reach; oy <= reach; ++oy) {
+            int cy = by + oy;
+            const int wy = floordiv(cy, nb);
+            cy -= wy * nb;
+            for (int ox = -reach; ox <= reach; ++ox) {
+                int cx = bx + ox;
+                const int wx = floordiv(cx, nb);
+                cx -= wx * nb;
+                const int bin = (cz * nb + cy) * nb + cx;
+                const int code = ((wz + 512) << 20) | ((wy + 512) << 10) | (wx + 512);
+                for (int j = start[bin]; j < start[bin + 1]; ++j) {
+                    if (j == s && wx == 0 && wy == 0 && wz == 0) continue;
+                    const double dx = px - (sp[3 * j] + wx * L);
+                    const double dy = py - (sp[3 * j + 1] + wy * L);
+                    const double dz = pz - (sp[3 * j + 2] + wz * L);
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    const double aj = sa[j];
+                    const double rc = rc_factor * (ai + aj);
+                    if (r2 >= rc * rc) continue;
+                    if (checks && r2 < (ai + aj) * (ai + aj) * (1.0 - 1e-12)) atomicOr(err, kErrOverlap);
+                    f(j, code);
+                }
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pair_count(int n, const double* __restrict__ sp,
+                                                    const double* __restrict__ sa, const int* __restrict__ start,
+                                                    int nb, double L, double binw, double rc_factor,
+                                                    const unsigned long long* __restrict__ amax_bits, int checks,
+                                                    int* __restrict__ ncount, int* __restrict__ err) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const double amax = __longlong_as_double((long long)*amax_bits);
+    int c = 0;
+    for_each_neighbour(s, sp, sa, start, nb, L, binw, rc_factor, amax, checks, err, [&](int, int) { ++c; });
+    ncount[s] = c;
+}
+
+__global__ __launch_bounds__(256) void k_pair_fill(int n, const double* __restrict__ sp,
+                                                   const double* __restrict__ sa, const int* __restrict__ start,
+                                                   int nb, double L, double binw, double rc_factor,
+                                                   const unsigned long long* __restrict__ amax_bits,
+                                                   const int* __restrict__ noff, int2* __restrict__ list,
+                                                   int* __restrict__ err) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const double amax = __longlong_as_double((long long)*amax_bits);
+    int k = noff[s];
+    for_each_neighbour(s, sp, sa, start, nb, L, binw, rc_factor, amax, 0, err,
+                       [&](int j, int code) { list[k++] = make_int2(j, code); });
+}
+
+// exclusive scan of n counts with one workgroup of 1024 threads
+__global__ __launch_bounds__(1024) void k_scan_counts(int n, const int* __restrict__ cnt, int* __restrict__ off) {
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    const int per = (n + 1023) / 1024;
+    const int b0 = min(n, t * per), b1 = min(n, b0 + per);
+    int s = 0;
+    for (int b = b0; b < b1; ++b) s += cnt[b];
+    part[t] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int v = (t >= o) ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - s;
+    for (int b = b0; b < b1; ++b) {
+        off[b] = run;
+        run += cnt[b];
+    }
+    if (t == 1023) off[n] = part[t];
+}
+
+__global__ __launch_bounds__(128) void k_pair_eval(int n, const double* __restrict__ sp,
+                                                   const double* __restrict__ sa, const double* __restrict__ sx,
+                                                   const int* __restrict__ noff, const int2* __restrict__ list,
+                                                   double L, double xi, double inv_eta, int parts,
+                                                   double* __restrict__ ybuf) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const double px = sp[3 * s], py = sp[3 * s + 1], pz = sp[3 * s + 2];
     const double ai = sa[s];
     double y[12];
     for (int c = 0; c < 12; ++c) y[c] = 0.0;
     if (parts & kPartsReal) {
-        const double amax = __longlong_as_double((long long)*amax_bits);
-        const double rcmax = rc_factor * (ai + amax);
-        int reach = (int)ceil(rcmax / binw);
-        if (reach > 2 * nb + 2) {  // cut-off beyond about two cell lengths: refuse
-            atomicOr(err, kErrCutoff);
-            reach = 2 * nb + 2;
-        }
-        const int bx = min(nb - 1, (int)(px / binw)), by = min(nb - 1, (int)(py / binw)),
-                  bz = min(nb - 1, (int)(pz / binw));
-        for (int oz = -reach; oz <= reach; ++oz) {
-            int cz = bz + oz;
-            int wz = (cz >= 0) ? cz / nb : -((-cz + nb - 1) / nb);
-            cz -= wz * nb;
-            for (int oy = -reach; oy <= reach; ++oy) {
-                int cy = by + oy;
-                int wy = (cy >= 0) ? cy / nb : -((-cy + nb - 1) / nb);
-                cy -= wy * nb;
-                for (int ox = -reach; ox <= reach; ++ox) {
-                    int cx = bx + ox;
-                    int wx = (cx >= 0) ? cx / nb : -((-cx + nb - 1) / nb);
-                    cx -= wx * nb;
-                    const int bin = (cz * nb + cy) * nb + cx;
-                    const double shx = wx * L, shy = wy * L, shz = wz * L;
-                    for (int j = start[bin]; j < start[bin + 1]; ++j) {
-                        if (j == s && wx == 0 && wy == 0 && wz == 0) continue;
-                        const double dx = px - (sp[3 * j] + shx);
-                        const double dy = py - (sp[3 * j + 1] + shy);
-                        const double dz = pz - (sp[3 * j + 2] + shz);
-                        const double r2 = dx * dx + dy * dy + dz * dz;
-                        const double aj = sa[j];
-                        const double rc = rc_factor * (ai + aj);
-                        if (r2 >= rc * rc) continue;
-                        if (checks && r2 < (ai + aj) * (ai + aj) * (1.0 - 1e-12)) atomicOr(err, kErrOverlap);
-                        double xj[12];
-                        for (int c = 0; c < 12; ++c) xj[c] = sx[12 * (size_t)j + c];
-                        pair_coupling<double>(dx, dy, dz, ai, aj, xi, inv_eta, xj, y);
-                    }
-                }
-            }
+        const int k1 = noff[s + 1];
+        for (int k = noff[s]; k < k1; ++k) {
+            const int2 e = list[k];
+            const int j = e.x;
+            const int wx = (e.y & 1023) - 512, wy = ((e.y >> 10) & 1023) - 512, wz = ((e.y >> 20) & 1023) - 512;
+            const double dx = px - (sp[3 * j] + wx * L);
+            const double dy = py - (sp[3 * j + 1] + wy * L);
+            const double dz = pz - (sp[3 * j + 2] + wz * L);
+            double xj[12];
+            for (int c = 0; c < 12; ++c) xj[c] = sx[12 * (size_t)j + c];
+            pair_coupling<double>(dx, dy, dz, ai, sa[j], xi, inv_eta, xj, y);
         }
     }
     if (parts & kPartsSelf) {
@@ -723,7 +800,8 @@ static int launch_fft_chain_M(int M, void* rgrid, void* spec, const double* tw, 
     return 0;
 }
 
-int launch_apply(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
+// binning, neighbour counts and their scan; the total is noff[n]
+int launch_geometry(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     const int n = (int)A.n;
     const int T = 256;
     const int gb = (n + T - 1) / T;
@@ -738,9 +816,39 @@ int launch_apply(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     hipLaunchKernelGGL(k_bin_order, dim3((nbins + T - 1) / T), dim3(T), 0, st, nbins, A.start, A.perm);
     hipLaunchKernelGGL(k_bin_gather, dim3(gb), dim3(T), 0, st, n, A.perm, A.pos, A.radius, A.x, A.L,
                        A.compressible, A.sp, A.sa, A.sx, A.err);
+    if (A.parts & kPartsReal) {
+        hipLaunchKernelGGL(k_pair_count, dim3(gb), dim3(T), 0, st, n, A.sp, A.sa, A.start, A.nb, A.L, A.binw,
+                           A.rc_factor, A.amax_bits, A.checks, A.ncount, A.err);
+        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, n, A.ncount, A.noff);
+    } else {
+        hipMemsetAsync(A.noff, 0, sizeof(int) * (n + 1), st);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// neighbour list (needs a list of at least noff[n] entries)
+int launch_pairlist(const ApplyArgs& A, hipStream_t st) {
+    const int n = (int)A.n;
+    if (!(A.parts & kPartsReal)) return 0;
+    hipLaunchKernelGGL(k_pair_fill, dim3((n + 255) / 256), dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb, A.L,
+                       A.binw, A.rc_factor, A.amax_bits, A.noff, A.list, A.err);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// moments into binned order (used when the geometry is reused for a new x)
+int launch_moments(const ApplyArgs& A, hipStream_t st) {
+    const int n = (int)A.n;
+    hipLaunchKernelGGL(k_bin_gather, dim3((n + 255) / 256), dim3(256), 0, st, n, A.perm, A.pos, A.radius, A.x,
+                       A.L, A.compressible, A.sp, A.sa, A.sx, A.err);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// pair sum, wave-space part and gather on an existing geometry
+int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
+    const int n = (int)A.n;
     tm->begin(kPhasePair, st);
-    hipLaunchKernelGGL(k_pair, dim3(gb), dim3(T), 0, st, n, A.sp, A.sa, A.sx, A.start, A.nb, A.L, A.binw,
-                       A.xi, A.rc_factor, A.inv_eta, A.amax_bits, A.parts, A.checks, A.ybuf, A.err);
+    hipLaunchKernelGGL(k_pair_eval, dim3((n + 127) / 128), dim3(128), 0, st, n, A.sp, A.sa, A.sx, A.noff,
+                       A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
     const bool wave = (A.parts & kPartsWave) != 0;
     const int tiles = A.M / kTile;
     KScale ks{2.0 * kPi / A.L, 1.0 / (4.0 * A.xi * A.xi), 2.0 * A.tau,

@@ -63,7 +63,7 @@ __global__ void k_gemv_sub(int64_t len, int k, const double* __restrict__ V, int
 __global__ void k_axpby(int64_t len, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= len) return;
-    y[i] = a * x[i] + b * y[i];
+    y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];  // b = 0: y may be uninitialised
 }
 
 // z_i = B_i v_i with B_i a 12x12 block per sphere (row-major)
@@ -95,6 +95,33 @@ __global__ void k_build_blocks(int64_t n, const double* __restrict__ radius, con
     for (int c = 3; c < 6; ++c) b[13 * c] += 1.0 / (8.0 * pi * eta * a * A);
     for (int c = 6; c < 11; ++c) b[13 * c] += 3.0 / (20.0 * pi * eta * a * A);
     b[13 * 11] += 3.0 / (16.0 * pi * eta * a * A);
+    // the far-field solve runs on the 11 incompressible components: the trace
+    // row and column are replaced by the identity
+    for (int c = 0; c < 12; ++c) b[12 * 11 + c] = b[12 * c + 11] = 0.0;
+    b[13 * 11] = 1.0;
+}
+
+// Pressure-moment steps of the one-way compressible solve (Sec. 2.3, 4.1):
+//   mode 0: out = (0,...,0, s_self) with s_self = (16/3) pi eta a^3 b_trace
+//   mode 1: out = (b - in) on the 11 incompressible components (in = NULL: b), 0 on the trace
+//   mode 2: out_trace = (16/3) pi eta a^3 (b_trace - in_trace)
+__global__ void k_trace_op(int64_t n, int mode, const double* __restrict__ radius, double eta,
+                           const double* __restrict__ b, const double* __restrict__ in, double* __restrict__ out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double a = radius[i];
+    const double d = 16.0 / 3.0 * 3.14159265358979323846 * eta * a * a * a;
+    const double* bi = b + 12 * i;
+    double* o = out + 12 * i;
+    if (mode == 0) {
+        for (int c = 0; c < 11; ++c) o[c] = 0.0;
+        o[11] = d * bi[11];
+    } else if (mode == 1) {
+        for (int c = 0; c < 11; ++c) o[c] = in ? bi[c] - in[12 * i + c] : bi[c];
+        o[11] = 0.0;
+    } else {
+        o[11] = d * (bi[11] - in[12 * i + 11]);
+    }
 }
 
 // inverse of each 12x12 block by Gauss-Jordan elimination with partial pivoting
@@ -172,6 +199,12 @@ int launch_block_apply(int64_t n, const double* blocks, const double* v, double*
 int launch_build_blocks(int64_t n, const double* radius, const double* coef, double /*xi*/, double eta,
                         double* blocks, hipStream_t st) {
     hipLaunchKernelGGL(k_build_blocks, dim3(grid1(n, 128)), dim3(128), 0, st, n, radius, coef, eta, blocks);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_trace_op(int64_t n, int mode, const double* radius, double eta, const double* b, const double* in,
+                    double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_trace_op, dim3(grid1(n, 256)), dim3(256), 0, st, n, mode, radius, eta, b, in, out);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

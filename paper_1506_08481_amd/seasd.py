@@ -200,11 +200,15 @@ class Seasd:
         _check(lib().seasd_profile_enable(self.h, 1 if enable else 0))
 
     def profile_read(self) -> dict:
-        buf = (ctypes.c_double * len(PHASES))()
-        n = lib().seasd_profile_read(self.h, buf, len(PHASES))
+        """Average ms per phase over the products since the last read, plus
+        the number of products under the key 'products'."""
+        buf = (ctypes.c_double * (len(PHASES) + 1))()
+        n = lib().seasd_profile_read(self.h, buf, len(PHASES) + 1)
         if n < 0:
             _check(n)
-        return {PHASES[i]: buf[i] for i in range(len(PHASES))}
+        out = {PHASES[i]: buf[i] for i in range(len(PHASES))}
+        out["products"] = int(buf[len(PHASES)])
+        return out
 
     def close(self):
         if getattr(self, "h", None):

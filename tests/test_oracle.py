@@ -306,3 +306,19 @@ def test_pair_image_correction_tends_to_hasimoto():
         corr = -HASIMOTO_SC / (6 * math.pi * L)
         # remaining terms are O(r^2/L^3)
         assert np.allclose(diff, corr * np.eye(3), rtol=0, atol=60.0 / L ** 3)
+
+
+def test_one_way_solve_satisfies_its_equations(dense8):
+    # f solves the incompressible rows with only the self part of the pressure
+    # moments as sources; the trace rows then hold exactly (pressure Faxen law)
+    s, M = dense8
+    n = s.n
+    B = M.reshape(n, 12, n, 12)
+    b = wl.force_moments(n, 5)
+    x = solve.one_way_solve(s.pos, s.radius, s.box, b, ewald.converged_params(s.box, s.radius, xi=0.8))
+    y = (M @ x.reshape(-1)).reshape(n, 12)
+    assert np.allclose(y[:, 11], b[:, 11], rtol=0, atol=1e-12)          # trace rows exact
+    m_self = np.array([B[i, 11, i, 11] for i in range(n)])
+    s_int = x[:, 11] - b[:, 11] / m_self                                # interaction part
+    feedback = np.einsum("iajb,jb->ia", B[:, :11, :, 11:12], s_int[:, None])
+    assert np.allclose(y[:, :11] - feedback, b[:, :11], rtol=0, atol=1e-11)
