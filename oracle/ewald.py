@@ -244,11 +244,13 @@ def real_part(pos, rad, box, x, params: EwaldParams, targets=None) -> np.ndarray
     return out
 
 
-def wave_part(pos, rad, box, x, params: EwaldParams, targets=None, kblock: int = 4096) -> np.ndarray:
+def wave_part(pos, rad, box, x, params: EwaldParams, targets=None, kblock: int | None = None) -> np.ndarray:
     """(1/V) sum over the k-set of exp(-i k.r_i) K(k) sum_j exp(i k.r_j) x_j,
     including j = i (the wave-space self term is removed in self_part)."""
     N = pos.shape[0]
     tgt = np.arange(N) if targets is None else np.asarray(targets)
+    if kblock is None:  # keep the [N, kblock] phase arrays near 2e7 entries
+        kblock = int(max(16, min(4096, 2e7 // max(N, 1))))
     V = abs(np.linalg.det(box))
     syms = block_symbols(params.eta)
     kv = k_vectors(box, params)

@@ -52,7 +52,7 @@ struct seasd_handle_s {
     bool have_cfg = false;
     // product workspace
     DevBuf bin_of, counts, start, fill, perm, amax, err, sp, sa, sx, ybuf, rgrid, spec, twiddle;
-    DevBuf ncount, noff, list, total;
+    DevBuf ncount, noff, list, total, wi0, wmom, wfac;
     int64_t geom_n = -1;      // spheres in the geometry currently held in the workspace
     int twiddle_M = 0;
     // solver workspace
@@ -120,7 +120,7 @@ extern "C" int seasd_destroy(seasd_handle h) {
     hipSetDevice(h->device);
     DevBuf* bufs[] = {&h->bin_of, &h->counts, &h->start, &h->fill, &h->perm, &h->amax, &h->err,
                       &h->sp, &h->sa, &h->sx, &h->ybuf, &h->rgrid, &h->spec, &h->twiddle,
-                      &h->ncount, &h->noff, &h->list, &h->total,
+                      &h->ncount, &h->noff, &h->list, &h->total, &h->wi0, &h->wmom, &h->wfac,
                       &h->V, &h->w, &h->z, &h->u, &h->r, &h->bred, &h->hdev, &h->partial, &h->blocks,
                       &h->inv, &h->coef, &h->singular, &h->one_pos, &h->one_rad, &h->one_x, &h->one_y};
     for (DevBuf* b : bufs) b->release();
@@ -185,22 +185,25 @@ static int ensure_product_ws(seasd_handle h, int64_t n) {
     rc |= h->ncount.ensure(sizeof(int) * n);
     rc |= h->noff.ensure(sizeof(int) * (n + 1));
     rc |= h->list.ensure(sizeof(int2) * 1024);
+    rc |= h->wi0.ensure(sizeof(int) * 4 * n);
+    rc |= h->wmom.ensure(R * 20 * n);
+    rc |= h->wfac.ensure(R * 3 * h->cfg.P * n);
     if (h->cfg.parts & SEASD_PARTS_WAVE) {
         rc |= h->rgrid.ensure(R * 4 * (size_t)M * M * M);
         rc |= h->spec.ensure(R * 4 * (size_t)M * M * M);
     } else {
         rc |= h->rgrid.ensure(R * 4);
     }
-    rc |= h->twiddle.ensure(sizeof(double) * M);
+    rc |= h->twiddle.ensure(sizeof(double) * 2 * M);
     if (rc) return SEASD_E_NOMEM;
     if (h->twiddle_M != M) {
-        std::vector<double> tw(M);
-        for (int j = 0; j < M / 2; ++j) {
+        std::vector<double> tw(2 * M);
+        for (int j = 0; j < M; ++j) {
             const double a = 2.0 * kPi * j / M;
             tw[2 * j] = std::cos(a);
             tw[2 * j + 1] = std::sin(a);
         }
-        if (hipMemcpy(h->twiddle.p, tw.data(), sizeof(double) * M, hipMemcpyHostToDevice) != hipSuccess)
+        if (hipMemcpy(h->twiddle.p, tw.data(), sizeof(double) * 2 * M, hipMemcpyHostToDevice) != hipSuccess)
             return SEASD_E_HIP;
         h->twiddle_M = M;
     }
@@ -247,6 +250,9 @@ static void fill_args(seasd_handle h, ApplyArgs& A, int64_t n, const double* pos
     A.sa = h->sa.as<double>();
     A.sx = h->sx.as<double>();
     A.ybuf = h->ybuf.as<double>();
+    A.wi0 = h->wi0.p;
+    A.wmom = h->wmom.p;
+    A.wfac = h->wfac.p;
     A.rgrid = h->rgrid.p;
     A.spec = h->spec.p;
     A.twiddle = h->twiddle.as<double>();

@@ -93,6 +93,9 @@ struct ApplyArgs {
     double* sa;
     double* sx;
     double* ybuf;
+    void* wi0;       // [n] int4 window anchors
+    void* wmom;      // [n][20] R moments and offsets
+    void* wfac;      // [n][3P] R window factors
     void* rgrid;
     void* spec;
     const double* twiddle;

@@ -45,6 +45,38 @@ __device__ inline C1<R> cmul(C1<R> a, C1<R> b) {
 // ---------------------------------------------------------------------------
 // binning
 
+// Bins are numbered along a Morton (Z-order) curve, so that spheres that are
+// consecutive in binned order sit in compact 3-D blocks (cache locality for
+// the pair sum, spreading and gather). nb is a power of two.
+__host__ __device__ inline unsigned spread_bits3(unsigned v) {
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+__host__ __device__ inline int bin_id(int bx, int by, int bz) {
+    return (int)(spread_bits3((unsigned)bx) | (spread_bits3((unsigned)by) << 1) | (spread_bits3((unsigned)bz) << 2));
+}
+__host__ __device__ inline unsigned compact_bits3(unsigned v) {
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030c30c3u;
+    v = (v | (v >> 4)) & 0x0300f00fu;
+    v = (v | (v >> 8)) & 0x030000ffu;
+    v = (v | (v >> 16)) & 0x000003ffu;
+    return v;
+}
+
+// Workgroups are handed to the 8 XCDs round-robin; renumber them so that each
+// XCD runs one contiguous range of work items (its L2 then sees a compact
+// region of the grid and of the sphere data).
+__device__ inline int xcd_block(int b, int nblk) {
+    const int per = nblk / 8, rem = nblk % 8;
+    const int k = b % 8, idx = b / 8;
+    return k * per + min(k, rem) + idx;
+}
+
 // coordinate wrapped into [0, L); the same expression is used for the bin and
 // for the binned copy so both always agree
 __device__ inline double wrap_coord(double p, double L) {
@@ -72,7 +104,7 @@ __global__ void k_bin_count(int n, const double* __restrict__ pos, const double*
         int k = (int)floor(w / binw);
         b[d] = k < 0 ? 0 : (k >= nb ? nb - 1 : k);
     }
-    int bin = (b[2] * nb + b[1]) * nb + b[0];
+    int bin = bin_id(b[0], b[1], b[2]);
     bin_of[i] = bin;
     atomicAdd(&counts[bin], 1);
     atomicMax(amax_bits, (unsigned long long)__double_as_longlong(a));
@@ -193,7 +225,7 @@ __device__ inline void for_each_neighbour(int s, const double* __restrict__ sp, 
                 int cx = bx + ox;
                 const int wx = floordiv(cx, nb);
                 cx -= wx * nb;
-                const int bin = (cz * nb + cy) * nb + cx;
+                const int bin = bin_id(cx, cy, cz);
                 const int code = ((wz + 512) << 20) | ((wy + 512) << 10) | (wx + 512);
                 for (int j = start[bin]; j < start[bin + 1]; ++j) {
                     if (j == s && wx == 0 && wy == 0 && wz == 0) continue;
@@ -301,70 +333,113 @@ __global__ __launch_bounds__(128) void k_pair_eval(int n, const double* __restri
 }
 
 // ---------------------------------------------------------------------------
-// window helpers
+// window records
 //
 // The window is the normalised Gaussian h(r) = (4 pi tau)^(-3/2) exp(-r^2/(4 tau))
 // with tau = (P h)^2/(8 m^2), i.e. exp(-m^2/2) at the support edge P h/2
 // (eqs. shape, theta-param written in Cartesian form for a cubic cell). It is
 // evaluated on P points per dimension starting at i0 = floor(x/h) - P/2 + 1.
-// 1-D factors exp(-alpha (d0 + k h)^2) use fast Gaussian gridding (eq.
-// fgg-exp), anchored at the window centre so the recurrences run over at most
-// P/2 steps.
+// One record per sphere (binned order) holds i0, the offset d0 = i0 h - x, the
+// 1-D factors exp(-alpha (d0 + k h)^2) and the moments; spreading and gather
+// both read it. The factors use fast Gaussian gridding (eq. fgg-exp), anchored
+// at the window centre so the recurrences run over at most P/2 steps, in FP64.
 
-template <typename R>
-__device__ inline void fgg_factors(double d0, double h, double alpha, int P, R* out) {
+constexpr int kTile = 8;
+constexpr int kMaxP = 32;
+constexpr int kMomStride = 20;  // d0[3], a2, F[3], T[3], S[6], sqrt3 s6, pad[3]
+
+__device__ inline void fgg_factors(double d0, double h, double alpha, int P, double* out) {
     const int kc = P / 2 - 1;               // d0 + kc h lies in (-h, 0]
     const double dc = d0 + kc * h;
     const double e0 = exp(-alpha * dc * dc);
-    const double up = exp(-2.0 * alpha * dc * h);  // ratio step k -> k+1 (before the k^2 term)
-    const double q = exp(-alpha * h * h);
-    // upward: k = kc + j, value = e0 * up^j * q^(j^2)
-    double v = e0, stp = up * q;                    // j=1 factor: up q^(1)
-    out[kc] = (R)e0;
+    const double up = exp(-2.0 * alpha * dc * h);  // exp(-2 alpha dc h)^j
+    const double q = exp(-alpha * h * h);          // exp(-alpha h^2)^(j^2)
     const double q2 = q * q;
+    double v = e0, stp = up * q;
+    out[kc] = e0;
     for (int k = kc + 1; k < P; ++k) {
         v *= stp;
         stp *= q2;
-        out[k] = (R)v;
+        out[k] = v;
     }
-    // downward: k = kc - j, value = e0 * up^(-j) * q^(j^2)
     v = e0;
     stp = q / up;
     for (int k = kc - 1; k >= 0; --k) {
         v *= stp;
         stp *= q2;
-        out[k] = (R)v;
+        out[k] = v;
     }
 }
 
-// ---------------------------------------------------------------------------
-// spreading: one workgroup of 512 threads owns one 8^3 tile
+template <typename R>
+__global__ __launch_bounds__(256) void k_window(int n, const double* __restrict__ sp, const double* __restrict__ sa,
+                                                const double* __restrict__ sx, int P, double h, double alpha,
+                                                int4* __restrict__ wi0, R* __restrict__ wmom, R* __restrict__ wfac) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int i0[3];
+    R* mom = wmom + (size_t)kMomStride * s;
+    R* fac = wfac + (size_t)3 * P * s;
+    double f[kMaxP];
+    for (int d = 0; d < 3; ++d) {
+        const double p = sp[3 * s + d];
+        i0[d] = (int)floor(p / h) - P / 2 + 1;
+        const double d0 = i0[d] * h - p;
+        mom[d] = (R)d0;
+        fgg_factors(d0, h, alpha, P, f);
+        for (int k = 0; k < P; ++k) fac[d * P + k] = (R)f[k];
+    }
+    wi0[s] = make_int4(i0[0], i0[1], i0[2], 0);
+    const double a = sa[s];
+    const double* xs = sx + 12 * (size_t)s;
+    mom[3] = (R)(a * a);
+    for (int d = 0; d < 3; ++d) {
+        mom[4 + d] = (R)xs[d];
+        mom[7 + d] = (R)xs[3 + d];
+    }
+    double S[6];
+    s5_to_sym<double>(xs + 6, S);
+    for (int d = 0; d < 6; ++d) mom[10 + d] = (R)S[d];
+    mom[16] = (R)(kSqrt3 * xs[11]);
+    mom[17] = mom[18] = mom[19] = R(0);
+}
 
-constexpr int kTile = 8;
+// ---------------------------------------------------------------------------
+// spreading: one workgroup of 256 threads owns one 8^3 tile; each thread owns
+// the two points (x, y, z) and (x, y, z + 4) of the tile
+
 constexpr int kStage = 64;     // spheres staged per round
-constexpr int kMaxP = 32;
 
 template <typename R>
 struct SpreadStage {
-    R ex[kStage][kMaxP], ey[kStage][kMaxP], ez[kStage][kMaxP];
-    R d0[kStage][3];
     int i0[kStage][3];
-    R F[kStage][3], T[kStage][3], S[kStage][6], s6[kStage], a2[kStage];
+    R mom[kStage][kMomStride];
+    R fac[kStage][3 * kMaxP];
 };
 
 template <typename R>
-__global__ __launch_bounds__(512) void k_spread(
-    int n, const double* __restrict__ sp, const double* __restrict__ sa,
-    const double* __restrict__ sx, const int* __restrict__ start, int nb, int M, int P, double h,
-    double alpha, double cw, R4<R>* __restrict__ grid) {
+__device__ inline void neumaier(R& acc, R& cmp, R v) {
+    const R sum = acc + v;
+    cmp += (fabs(acc) >= fabs(v)) ? ((acc - sum) + v) : ((v - sum) + acc);
+    acc = sum;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_spread(
+    int n, const int4* __restrict__ wi0, const R* __restrict__ wmom, const R* __restrict__ wfac,
+    const int* __restrict__ start, int nb, int M, int P, double h, double alpha, double cw,
+    R4<R>* __restrict__ grid) {
     __shared__ SpreadStage<R> st;
     __shared__ int bins[125], pre[126];
     __shared__ int nbins_used;
     const int t = threadIdx.x;
     const int tiles = M / kTile;
-    const int tx = blockIdx.x % tiles, ty = (blockIdx.x / tiles) % tiles, tz = blockIdx.x / (tiles * tiles);
+    const int ntiles = tiles * tiles * tiles;
+    // Morton-ordered tiles, contiguous per XCD
+    const unsigned tcode = (unsigned)xcd_block(blockIdx.x, ntiles);
+    const int tx = (int)compact_bits3(tcode), ty = (int)compact_bits3(tcode >> 1), tz = (int)compact_bits3(tcode >> 2);
     const int lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
-    const int gx = tx * kTile + lx, gy = ty * kTile + ly, gz = tz * kTile + lz;
+    const int gx = tx * kTile + lx, gy = ty * kTile + ly, gz0 = tz * kTile + lz, gz1 = gz0 + 4;
     const int mask = M - 1;
 
     // distinct bins whose spheres can reach this tile
@@ -378,7 +453,7 @@ __global__ __launch_bounds__(512) void k_spread(
                     int bx = (span == nb) ? ox : ((tx - reach + ox) % nb + nb) % nb;
                     int by = (span == nb) ? oy : ((ty - reach + oy) % nb + nb) % nb;
                     int bz = (span == nb) ? oz : ((tz - reach + oz) % nb + nb) % nb;
-                    bins[c++] = (bz * nb + by) * nb + bx;
+                    bins[c++] = bin_id(bx, by, bz);
                 }
         nbins_used = c;
         int run = 0;
@@ -390,112 +465,152 @@ __global__ __launch_bounds__(512) void k_spread(
     }
     __syncthreads();
     const int ncand = pre[nbins_used];
-    const R al = (R)alpha;
-    const R al2 = al * al, al3 = al2 * al;
-    const R hh = (R)h;
-    R acc[4] = {0, 0, 0, 0};
-    R cmp[4] = {0, 0, 0, 0};  // compensation (Neumaier) terms
+    const R al = (R)alpha, al2 = al * al, al3 = al2 * al;
+    const R hh = (R)h, cwr = (R)cw;
+    const R i6 = R(1) / R(6), i10 = R(1) / R(10);
+    R acc[2][4], cmp[2][4];
+    for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 4; ++c) acc[a][c] = cmp[a][c] = R(0);
+    const int fl = 3 * P;
 
     for (int c0 = 0; c0 < ncand; c0 += kStage) {
-        if (t < kStage && c0 + t < ncand) {
-            const int c = c0 + t;
+        const int cnt = min(kStage, ncand - c0);
+        // stage records: thread t copies record slices (coalesced per sphere)
+        for (int e = t; e < cnt; e += 256) {
+            const int c = c0 + e;
             int k = 0;
             while (pre[k + 1] <= c) ++k;
-            const int s = start[bins[k]] + (c - pre[k]);
-            const double a = sa[s];
-            for (int d = 0; d < 3; ++d) {
-                const double p = sp[3 * s + d];
-                const int i0 = (int)floor(p / h) - P / 2 + 1;
-                const double d0 = i0 * h - p;
-                st.i0[t][d] = i0;
-                st.d0[t][d] = (R)d0;
-                R* dst = (d == 0) ? st.ex[t] : (d == 1 ? st.ey[t] : st.ez[t]);
-                fgg_factors<R>(d0, h, alpha, P, dst);
-            }
-            const double* xs = sx + 12 * (size_t)s;
-            for (int d = 0; d < 3; ++d) {
-                st.F[t][d] = (R)xs[d];
-                st.T[t][d] = (R)xs[3 + d];
-            }
-            double S[6];
-            s5_to_sym<double>(xs + 6, S);
-            for (int d = 0; d < 6; ++d) st.S[t][d] = (R)S[d];
-            st.s6[t] = (R)(kSqrt3 * xs[11]);
-            st.a2[t] = (R)(a * a);
+            const int sidx = start[bins[k]] + (c - pre[k]);
+            const int4 v = wi0[sidx];
+            st.i0[e][0] = v.x;
+            st.i0[e][1] = v.y;
+            st.i0[e][2] = v.z;
+            // remember the sphere index in the (unused) pad of mom
+            reinterpret_cast<int*>(&st.mom[e][17])[0] = sidx;
         }
         __syncthreads();
-        const int cnt = min(kStage, ncand - c0);
+        for (int e = t; e < cnt * kMomStride; e += 256) {
+            const int q = e / kMomStride, k = e - q * kMomStride;
+            if (k >= 17) continue;
+            const int sidx = reinterpret_cast<const int*>(&st.mom[q][17])[0];
+            st.mom[q][k] = wmom[(size_t)kMomStride * sidx + k];
+        }
+        for (int e = t; e < cnt * fl; e += 256) {
+            const int q = e / fl, k = e - q * fl;
+            const int sidx = reinterpret_cast<const int*>(&st.mom[q][17])[0];
+            st.fac[q][k] = wfac[(size_t)fl * sidx + k];
+        }
+        __syncthreads();
         for (int q = 0; q < cnt; ++q) {
             const int kx = (gx - st.i0[q][0]) & mask;
             const int ky = (gy - st.i0[q][1]) & mask;
-            const int kz = (gz - st.i0[q][2]) & mask;
-            const bool in = (kx < P) && (ky < P) && (kz < P);
-            if (!__any(in)) continue;
-            if (!in) continue;
-            const R rx = st.d0[q][0] + kx * hh, ry = st.d0[q][1] + ky * hh, rz = st.d0[q][2] + kz * hh;
-            const R r2 = rx * rx + ry * ry + rz * rz;
-            const R w = (R)cw * st.ex[q][kx] * st.ey[q][ky] * st.ez[q][kz];
-            const R a2 = st.a2[q];
-            const R cF = w * (R(1) + a2 * (R(1) / R(6)) * (R(4) * al2 * r2 - R(6) * al));
-            const R cS = w * (R(2) * al - a2 * (R(1) / R(10)) * (R(20) * al2 - R(8) * al3 * r2));
-            const R cT = -al * w;
-            const R* F = st.F[q];
-            const R* T = st.T[q];
-            const R* S = st.S[q];
-            const R Srx = S[0] * rx + S[3] * ry + S[4] * rz;
-            const R Sry = S[3] * rx + S[1] * ry + S[5] * rz;
-            const R Srz = S[4] * rx + S[5] * ry + S[2] * rz;
-            R v[4];
-            v[0] = cF * F[0] + cT * (ry * T[2] - rz * T[1]) + cS * Srx;
-            v[1] = cF * F[1] + cT * (rz * T[0] - rx * T[2]) + cS * Sry;
-            v[2] = cF * F[2] + cT * (rx * T[1] - ry * T[0]) + cS * Srz;
-            v[3] = w * st.s6[q];
-            for (int c = 0; c < 4; ++c) {  // Neumaier summation
-                const R sum = acc[c] + v[c];
-                cmp[c] += (fabs(acc[c]) >= fabs(v[c])) ? ((acc[c] - sum) + v[c]) : ((v[c] - sum) + acc[c]);
-                acc[c] = sum;
+            const int kz0 = (gz0 - st.i0[q][2]) & mask;
+            const int kz1 = (gz1 - st.i0[q][2]) & mask;
+            const bool inxy = (kx < P) && (ky < P);
+            const bool in0 = inxy && (kz0 < P), in1 = inxy && (kz1 < P);
+            if (!__any(in0 || in1)) continue;
+            if (!(in0 || in1)) continue;
+            const R* mo = st.mom[q];
+            const R* fa = st.fac[q];
+            const R rx = mo[0] + kx * hh, ry = mo[1] + ky * hh;
+            const R wxy = cwr * fa[kx] * fa[P + ky];
+            const R a2 = mo[3];
+            const R F0 = mo[4], F1 = mo[5], F2 = mo[6], T0 = mo[7], T1 = mo[8], T2 = mo[9];
+            const R S0 = mo[10], S1 = mo[11], S2 = mo[12], S3 = mo[13], S4 = mo[14], S5 = mo[15];
+            const R sq = mo[16];
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const bool in = p ? in1 : in0;
+                if (!in) continue;
+                const int kz = p ? kz1 : kz0;
+                const R rz = mo[2] + kz * hh;
+                const R r2 = rx * rx + ry * ry + rz * rz;
+                const R w = wxy * fa[2 * P + kz];
+                const R cF = w * (R(1) + a2 * i6 * (R(4) * al2 * r2 - R(6) * al));
+                const R cS = w * (R(2) * al - a2 * i10 * (R(20) * al2 - R(8) * al3 * r2));
+                const R cT = -al * w;
+                const R Srx = S0 * rx + S3 * ry + S4 * rz;
+                const R Sry = S3 * rx + S1 * ry + S5 * rz;
+                const R Srz = S4 * rx + S5 * ry + S2 * rz;
+                neumaier(acc[p][0], cmp[p][0], cF * F0 + cT * (ry * T2 - rz * T1) + cS * Srx);
+                neumaier(acc[p][1], cmp[p][1], cF * F1 + cT * (rz * T0 - rx * T2) + cS * Sry);
+                neumaier(acc[p][2], cmp[p][2], cF * F2 + cT * (rx * T1 - ry * T0) + cS * Srz);
+                neumaier(acc[p][3], cmp[p][3], w * sq);
             }
         }
         __syncthreads();
     }
-    R4<R> out;
-    out.x = acc[0] + cmp[0];
-    out.y = acc[1] + cmp[1];
-    out.z = acc[2] + cmp[2];
-    out.w = acc[3] + cmp[3];
-    grid[((size_t)gz * M + gy) * M + gx] = out;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        R4<R> out;
+        out.x = acc[p][0] + cmp[p][0];
+        out.y = acc[p][1] + cmp[p][1];
+        out.z = acc[p][2] + cmp[p][2];
+        out.w = acc[p][3] + cmp[p][3];
+        grid[((size_t)(p ? gz1 : gz0) * M + gy) * M + gx] = out;
+    }
 }
 
 // ---------------------------------------------------------------------------
-// FFT building block: radix-2 Stockham over `nlines` lines of length M held in
-// LDS (line-major), ping-ponging between a and b. tw[j] = exp(sgn 2 pi i j/M),
-// j < M/2. Returns the buffer that holds the result.
+// FFT building block: Stockham autosort transform over `nlines` lines of
+// length M held in LDS (line-major), ping-ponging between a and b: one
+// radix-2 stage when log2 M is odd, then radix-4 stages. tw[j] =
+// exp(sgn 2 pi i j/M), j < M. Returns the buffer that holds the result.
+
+template <typename R>
+__device__ inline C1<R> cadd(C1<R> a, C1<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ inline C1<R> csub(C1<R> a, C1<R> b) { return {a.re - b.re, a.im - b.im}; }
+// multiply by sgn*i
+template <typename R>
+__device__ inline C1<R> cmuli(C1<R> a, int sgn) { return sgn > 0 ? C1<R>{-a.im, a.re} : C1<R>{a.im, -a.re}; }
 
 template <typename R, int M>
-__device__ inline C1<R>* lds_fft(C1<R>* a, C1<R>* b, int nlines, const C1<R>* tw) {
-    constexpr int H = M / 2;
-    for (int p = 1; p < M; p <<= 1) {
-        const int tstride = H / p;
+__device__ inline C1<R>* lds_fft(C1<R>* a, C1<R>* b, int nlines, const C1<R>* tw, int sgn) {
+    constexpr int LOG = (M <= 1) ? 0 : 31 - __builtin_clz(M);
+    int p = 1;
+    if (LOG & 1) {  // radix-2 stage
+        constexpr int H = M / 2;
         for (int e = threadIdx.x; e < nlines * H; e += blockDim.x) {
             const int line = e / H, j = e - line * H;
-            const int k = j & (p - 1);
             const C1<R> x0 = a[line * M + j];
-            const C1<R> x1 = cmul(tw[k * tstride], a[line * M + j + H]);
-            C1<R>* o = b + line * M + 2 * j - k;
-            o[0] = {x0.re + x1.re, x0.im + x1.im};
-            o[p] = {x0.re - x1.re, x0.im - x1.im};
+            const C1<R> x1 = a[line * M + j + H];
+            C1<R>* o = b + line * M + 2 * j;
+            o[0] = cadd(x0, x1);
+            o[1] = csub(x0, x1);
         }
         __syncthreads();
-        C1<R>* tmp = a;
-        a = b;
-        b = tmp;
+        C1<R>* tmp = a; a = b; b = tmp;
+        p = 2;
+    }
+    constexpr int Q = M / 4;
+    for (; p < M; p <<= 2) {
+        const int tstride = M / (4 * p);
+        for (int e = threadIdx.x; e < nlines * Q; e += blockDim.x) {
+            const int line = e / Q, j = e - line * Q;
+            const int k = j & (p - 1);
+            const C1<R>* in = a + line * M + j;
+            const C1<R> x0 = in[0];
+            const C1<R> x1 = cmul(tw[(k * tstride) & (M - 1)], in[Q]);
+            const C1<R> x2 = cmul(tw[(2 * k * tstride) & (M - 1)], in[2 * Q]);
+            const C1<R> x3 = cmul(tw[(3 * k * tstride) & (M - 1)], in[3 * Q]);
+            const C1<R> s02 = cadd(x0, x2), d02 = csub(x0, x2);
+            const C1<R> s13 = cadd(x1, x3), d13 = cmuli(csub(x1, x3), sgn);
+            C1<R>* o = b + line * M + 4 * (j - k) + k;
+            o[0] = cadd(s02, s13);
+            o[p] = cadd(d02, d13);
+            o[2 * p] = csub(s02, s13);
+            o[3 * p] = csub(d02, d13);
+        }
+        __syncthreads();
+        C1<R>* tmp = a; a = b; b = tmp;
     }
     return a;
 }
 
 template <typename R, int M>
 __device__ inline void load_twiddles(C1<R>* tw, const double* __restrict__ twg, int sgn) {
-    for (int j = threadIdx.x; j < M / 2; j += blockDim.x) {
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
         tw[j].re = (R)twg[2 * j];
         tw[j].im = (R)(sgn * twg[2 * j + 1]);
     }
@@ -507,7 +622,7 @@ template <typename R, int M, int LPB>
 __global__ __launch_bounds__(256) void k_fft_x_fwd(const R4<R>* __restrict__ in, C1<R>* __restrict__ out,
                                                    const double* __restrict__ twg) {
     __shared__ C1<R> buf[2][2 * LPB * M];
-    __shared__ C1<R> tw[M / 2];
+    __shared__ C1<R> tw[M];
     load_twiddles<R, M>(tw, twg, +1);
     const size_t line0 = (size_t)blockIdx.x * LPB;
     for (int e = threadIdx.x; e < LPB * M; e += blockDim.x) {
@@ -517,7 +632,7 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd(const R4<R>* __restrict__ in,
         buf[0][(2 * l + 1) * M + x] = {v.z, v.w};
     }
     __syncthreads();
-    C1<R>* r = lds_fft<R, M>(buf[0], buf[1], 2 * LPB, tw);
+    C1<R>* r = lds_fft<R, M>(buf[0], buf[1], 2 * LPB, tw, +1);
     for (int e = threadIdx.x; e < LPB * (M / 2); e += blockDim.x) {
         const int l = e / (M / 2), q = e - l * (M / 2);
         const int qn = (M - q) & (M - 1);
@@ -539,7 +654,7 @@ template <typename R, int M, int LPB>
 __global__ __launch_bounds__(256) void k_fft_x_inv(const C1<R>* __restrict__ in, R4<R>* __restrict__ out,
                                                    const double* __restrict__ twg) {
     __shared__ C1<R> buf[2][2 * LPB * M];
-    __shared__ C1<R> tw[M / 2];
+    __shared__ C1<R> tw[M];
     load_twiddles<R, M>(tw, twg, -1);
     const size_t line0 = (size_t)blockIdx.x * LPB;
     for (int e = threadIdx.x; e < LPB * M; e += blockDim.x) {
@@ -562,7 +677,7 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(const C1<R>* __restrict__ in,
         }
     }
     __syncthreads();
-    C1<R>* r = lds_fft<R, M>(buf[0], buf[1], 2 * LPB, tw);
+    C1<R>* r = lds_fft<R, M>(buf[0], buf[1], 2 * LPB, tw, -1);
     for (int e = threadIdx.x; e < LPB * M; e += blockDim.x) {
         const int l = e / M, x = e - l * M;
         const C1<R> A = r[(2 * l) * M + x], B = r[(2 * l + 1) * M + x];
@@ -576,7 +691,7 @@ template <typename R, int M, int W>
 __global__ __launch_bounds__(256) void k_fft_y(C1<R>* __restrict__ data, const double* __restrict__ twg,
                                                int sgn) {
     __shared__ C1<R> buf[2][4 * W * M];
-    __shared__ C1<R> tw[M / 2];
+    __shared__ C1<R> tw[M];
     load_twiddles<R, M>(tw, twg, sgn);
     constexpr int HX = M / 2;
     const int x0 = (blockIdx.x % (HX / W)) * W;
@@ -586,7 +701,7 @@ __global__ __launch_bounds__(256) void k_fft_y(C1<R>* __restrict__ data, const d
         buf[0][(w * 4 + c) * M + y] = data[(((size_t)z * M + y) * HX + x0 + w) * 4 + c];
     }
     __syncthreads();
-    C1<R>* r = lds_fft<R, M>(buf[0], buf[1], 4 * W, tw);
+    C1<R>* r = lds_fft<R, M>(buf[0], buf[1], 4 * W, tw, sgn);
     for (int e = threadIdx.x; e < W * M * 4; e += blockDim.x) {
         const int c = e & 3, w = (e >> 2) % W, y = (e >> 2) / W;
         data[(((size_t)z * M + y) * HX + x0 + w) * 4 + c] = r[(w * 4 + c) * M + y];
@@ -608,7 +723,7 @@ template <typename R, int M, int W>
 __global__ __launch_bounds__(256) void k_fft_z_scale(C1<R>* __restrict__ data,
                                                      const double* __restrict__ twg, KScale ks) {
     __shared__ C1<R> buf[2][4 * W * M];
-    __shared__ C1<R> twf[M / 2], twi[M / 2];
+    __shared__ C1<R> twf[M], twi[M];
     load_twiddles<R, M>(twf, twg, +1);
     load_twiddles<R, M>(twi, twg, -1);
     constexpr int HX = M / 2;
@@ -620,7 +735,7 @@ __global__ __launch_bounds__(256) void k_fft_z_scale(C1<R>* __restrict__ data,
         buf[0][(w * 4 + c) * M + z] = data[z * zstride + ((size_t)y * HX + x0 + w) * 4 + c];
     }
     __syncthreads();
-    C1<R>* a = lds_fft<R, M>(buf[0], buf[1], 4 * W, twf);
+    C1<R>* a = lds_fft<R, M>(buf[0], buf[1], 4 * W, twf, +1);
     C1<R>* b = (a == buf[0]) ? buf[1] : buf[0];
     const int qy = (y < M / 2) ? y : y - M;
     for (int e = threadIdx.x; e < W * M; e += blockDim.x) {
@@ -655,7 +770,7 @@ __global__ __launch_bounds__(256) void k_fft_z_scale(C1<R>* __restrict__ data,
         *f3 = {-lp * kf.im, lp * kf.re};
     }
     __syncthreads();
-    C1<R>* r = lds_fft<R, M>(a, b, 4 * W, twi);
+    C1<R>* r = lds_fft<R, M>(a, b, 4 * W, twi, -1);
     for (int e = threadIdx.x; e < W * M * 4; e += blockDim.x) {
         const int c = e & 3, w = (e >> 2) % W, z = (e >> 2) / W;
         data[z * zstride + ((size_t)y * HX + x0 + w) * 4 + c] = r[(w * 4 + c) * M + z];
@@ -663,81 +778,73 @@ __global__ __launch_bounds__(256) void k_fft_z_scale(C1<R>* __restrict__ data,
 }
 
 // ---------------------------------------------------------------------------
-// gather: one wavefront per sphere (binned order); adds the pair/self part
-// and writes y in input order.
+// gather: one wavefront per sphere (binned order, contiguous per XCD); each
+// lane owns some (x, y) columns of the window and sums them over z in R, the
+// column sums are added with Neumaier compensation and the wavefront reduces
+// in FP64. Adds the pair/self part and writes y in input order.
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_gather(
-    int n, const double* __restrict__ sp, const double* __restrict__ sa,
+    int n, const int4* __restrict__ wi0, const R* __restrict__ wmom, const R* __restrict__ wfac,
     const int* __restrict__ perm, const R4<R>* __restrict__ grid, int M, int P, double h,
     double alpha, double cwh3, double inv_eta, int parts, int compressible,
     const double* __restrict__ ybuf, double* __restrict__ yout) {
     constexpr int WPB = 4;
-    __shared__ R fac[WPB][3][kMaxP];
+    __shared__ R fac[WPB][3 * kMaxP];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int s0 = blockIdx.x * WPB + wv;
+    const int nblk = (n + WPB - 1) / WPB;
+    const int s0 = xcd_block(blockIdx.x, nblk) * WPB + wv;
     const bool active = s0 < n;       // every wavefront reaches the barrier
     const int s = active ? s0 : n - 1;
     const int mask = M - 1;
-    int i0[3];
-    R d0[3];
-    for (int d = 0; d < 3; ++d) {
-        const double p = sp[3 * s + d];
-        i0[d] = (int)floor(p / h) - P / 2 + 1;
-        const double dd = i0[d] * h - p;
-        d0[d] = (R)dd;
-        if (lane < P) {
-            const double r = dd + lane * h;
-            fac[wv][d][lane] = (R)exp(-alpha * r * r);
-        }
-    }
+    const int fl = 3 * P;
+    for (int k = lane; k < fl; k += 64) fac[wv][k] = wfac[(size_t)fl * s + k];
     __syncthreads();
     if (!active) return;
+    const int4 i0 = wi0[s];
+    const R* mo = wmom + (size_t)kMomStride * s;
+    const R d0x = mo[0], d0y = mo[1], d0z = mo[2], a2 = mo[3];
     double acc[13];
     for (int c = 0; c < 13; ++c) acc[c] = 0.0;
     if (parts & kPartsWave) {
         const R al = (R)alpha, al2 = al * al, al3 = al2 * al, hh = (R)h;
-        const R a2 = (R)(sa[s] * sa[s]);
+        const R i6 = R(1) / R(6), i10 = R(1) / R(10);
         R ac[13], cp[13];
         for (int c = 0; c < 13; ++c) ac[c] = cp[c] = R(0);
         const int P2 = P * P;
         for (int e = lane; e < P2; e += 64) {
             const int kx = e % P, ky = e / P;
-            const R rx = d0[0] + kx * hh, ry = d0[1] + ky * hh;
-            const R wxy = (R)cwh3 * fac[wv][0][kx] * fac[wv][1][ky];
-            const int gx = (i0[0] + kx) & mask, gy = (i0[1] + ky) & mask;
+            const R rx = d0x + kx * hh, ry = d0y + ky * hh;
+            const R wxy = (R)cwh3 * fac[wv][kx] * fac[wv][P + ky];
+            const int gx = (i0.x + kx) & mask, gy = (i0.y + ky) & mask;
+            R col[13];
+            for (int c = 0; c < 13; ++c) col[c] = R(0);
             for (int kz = 0; kz < P; ++kz) {
-                const int gz = (i0[2] + kz) & mask;
+                const int gz = (i0.z + kz) & mask;
                 const R4<R> g = grid[((size_t)gz * M + gy) * M + gx];
-                const R rz = d0[2] + kz * hh;
+                const R rz = d0z + kz * hh;
                 const R r2 = rx * rx + ry * ry + rz * rz;
-                const R w = wxy * fac[wv][2][kz];
-                const R cU = w * (R(1) + a2 * (R(1) / R(6)) * (R(4) * al2 * r2 - R(6) * al));
-                const R cE = w * (R(2) * al - a2 * (R(1) / R(10)) * (R(20) * al2 - R(8) * al3 * r2));
+                const R w = wxy * fac[wv][2 * P + kz];
+                const R cU = w * (R(1) + a2 * i6 * (R(4) * al2 * r2 - R(6) * al));
+                const R cE = w * (R(2) * al - a2 * i10 * (R(20) * al2 - R(8) * al3 * r2));
                 const R cW = al * w;
-                R v[13];
-                v[0] = cU * g.x;
-                v[1] = cU * g.y;
-                v[2] = cU * g.z;
-                v[3] = cW * (ry * g.z - rz * g.y);
-                v[4] = cW * (rz * g.x - rx * g.z);
-                v[5] = cW * (rx * g.y - ry * g.x);
-                v[6] = cE * g.x * rx;
-                v[7] = cE * g.y * ry;
-                v[8] = cE * g.z * rz;
-                v[9] = cE * R(0.5) * (g.x * ry + g.y * rx);
-                v[10] = cE * R(0.5) * (g.x * rz + g.z * rx);
-                v[11] = cE * R(0.5) * (g.y * rz + g.z * ry);
-                v[12] = w * g.w;
-                for (int c = 0; c < 13; ++c) {
-                    const R sum = ac[c] + v[c];
-                    cp[c] += (fabs(ac[c]) >= fabs(v[c])) ? ((ac[c] - sum) + v[c]) : ((v[c] - sum) + ac[c]);
-                    ac[c] = sum;
-                }
+                col[0] += cU * g.x;
+                col[1] += cU * g.y;
+                col[2] += cU * g.z;
+                col[3] += cW * (ry * g.z - rz * g.y);
+                col[4] += cW * (rz * g.x - rx * g.z);
+                col[5] += cW * (rx * g.y - ry * g.x);
+                col[6] += cE * g.x * rx;
+                col[7] += cE * g.y * ry;
+                col[8] += cE * g.z * rz;
+                col[9] += cE * R(0.5) * (g.x * ry + g.y * rx);
+                col[10] += cE * R(0.5) * (g.x * rz + g.z * rx);
+                col[11] += cE * R(0.5) * (g.y * rz + g.z * ry);
+                col[12] += w * g.w;
             }
+            for (int c = 0; c < 13; ++c) neumaier(ac[c], cp[c], col[c]);
         }
         for (int c = 0; c < 13; ++c) acc[c] = (double)ac[c] + (double)cp[c];
-        // wavefront reduction in FP64
         for (int off = 32; off > 0; off >>= 1)
             for (int c = 0; c < 13; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
     }
@@ -789,11 +896,11 @@ static int launch_fft_chain_M(int M, void* rgrid, void* spec, const double* tw, 
     constexpr bool dbl = sizeof(R) == 8;
     switch (M) {
         FFT_CASE(8, 8, 2)
-        FFT_CASE(16, 8, 2)
-        FFT_CASE(32, 4, 2)
-        FFT_CASE(64, 4, 2)
-        FFT_CASE(128, 2, (dbl ? 1 : 2))
-        FFT_CASE(256, 1, (dbl ? 1 : 2))
+        FFT_CASE(16, 8, (dbl ? 2 : 4))
+        FFT_CASE(32, 4, (dbl ? 2 : 4))
+        FFT_CASE(64, 4, (dbl ? 2 : 4))
+        FFT_CASE(128, 2, (dbl ? 2 : 4))
+        FFT_CASE(256, 1, (dbl ? 1 : 4))
         default:
             return -1;
     }
@@ -853,30 +960,37 @@ int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     const int tiles = A.M / kTile;
     KScale ks{2.0 * kPi / A.L, 1.0 / (4.0 * A.xi * A.xi), 2.0 * A.tau,
               1.0 / ((double)A.M * A.M * A.M), A.inv_eta};
+    const int gw = (n + 255) / 256;
+    const int gg = (n + 3) / 4;
+    const double cwh3 = A.cw * A.h * A.h * A.h;
     if (A.fp32) {
+        tm->begin(kPhaseSpread, st);
+        hipLaunchKernelGGL((k_window<float>), dim3(gw), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.P, A.h, A.alpha,
+                           (int4*)A.wi0, (float*)A.wmom, (float*)A.wfac);
         if (wave) {
-            tm->begin(kPhaseSpread, st);
-            hipLaunchKernelGGL((k_spread<float>), dim3(tiles * tiles * tiles), dim3(512), 0, st, n, A.sp,
-                               A.sa, A.sx, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
-                               (R4<float>*)A.rgrid);
+            hipLaunchKernelGGL((k_spread<float>), dim3(tiles * tiles * tiles), dim3(256), 0, st, n,
+                               (const int4*)A.wi0, (const float*)A.wmom, (const float*)A.wfac, A.start, A.nb, A.M,
+                               A.P, A.h, A.alpha, A.cw, (R4<float>*)A.rgrid);
             if (launch_fft_chain_M<float>(A.M, A.rgrid, A.spec, A.twiddle, ks, st, tm)) return -1;
         }
         tm->begin(kPhaseGather, st);
-        hipLaunchKernelGGL((k_gather<float>), dim3((n + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa, A.perm,
-                           (const R4<float>*)A.rgrid, A.M, A.P, A.h, A.alpha, A.cw * A.h * A.h * A.h,
-                           A.inv_eta, A.parts, A.compressible, A.ybuf, A.y);
+        hipLaunchKernelGGL((k_gather<float>), dim3(gg), dim3(256), 0, st, n, (const int4*)A.wi0,
+                           (const float*)A.wmom, (const float*)A.wfac, A.perm, (const R4<float>*)A.rgrid, A.M, A.P,
+                           A.h, A.alpha, cwh3, A.inv_eta, A.parts, A.compressible, A.ybuf, A.y);
     } else {
+        tm->begin(kPhaseSpread, st);
+        hipLaunchKernelGGL((k_window<double>), dim3(gw), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.P, A.h, A.alpha,
+                           (int4*)A.wi0, (double*)A.wmom, (double*)A.wfac);
         if (wave) {
-            tm->begin(kPhaseSpread, st);
-            hipLaunchKernelGGL((k_spread<double>), dim3(tiles * tiles * tiles), dim3(512), 0, st, n, A.sp,
-                               A.sa, A.sx, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
-                               (R4<double>*)A.rgrid);
+            hipLaunchKernelGGL((k_spread<double>), dim3(tiles * tiles * tiles), dim3(256), 0, st, n,
+                               (const int4*)A.wi0, (const double*)A.wmom, (const double*)A.wfac, A.start, A.nb,
+                               A.M, A.P, A.h, A.alpha, A.cw, (R4<double>*)A.rgrid);
             if (launch_fft_chain_M<double>(A.M, A.rgrid, A.spec, A.twiddle, ks, st, tm)) return -1;
         }
         tm->begin(kPhaseGather, st);
-        hipLaunchKernelGGL((k_gather<double>), dim3((n + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa, A.perm,
-                           (const R4<double>*)A.rgrid, A.M, A.P, A.h, A.alpha, A.cw * A.h * A.h * A.h,
-                           A.inv_eta, A.parts, A.compressible, A.ybuf, A.y);
+        hipLaunchKernelGGL((k_gather<double>), dim3(gg), dim3(256), 0, st, n, (const int4*)A.wi0,
+                           (const double*)A.wmom, (const double*)A.wfac, A.perm, (const R4<double>*)A.rgrid, A.M,
+                           A.P, A.h, A.alpha, cwh3, A.inv_eta, A.parts, A.compressible, A.ybuf, A.y);
     }
     tm->end(st);
     return hipGetLastError() == hipSuccess ? 0 : -2;
