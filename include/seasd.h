@@ -188,6 +188,51 @@ int seasd_solve_farfield(seasd_handle handle, int64_t n,
 int seasd_profile_enable(seasd_handle handle, int32_t enable);
 int seasd_profile_read(seasd_handle handle, double* ms, int32_t count);
 
+/* ---- many independent suspensions -------------------------------------------
+ * Autotuner: parameters for one suspension of n spheres (radii a_min..a_max)
+ * in a cubic cell of edge L, aiming at a global relative error of `target`
+ * (1e-6 or looser) in the given precision. It picks the grid M (a power of
+ * two with spacing L/M near 0.4 a_max, 32..256; the bins are 8^3 tiles of
+ * that grid), xi from the grid spacing so that the k-space tail
+ * exp(-k_max^2/(4 xi^2)) stays fixed, the real-space cut-off factor so that
+ * xi r_c is fixed for the smallest pair, and the window (P, m) from accuracy
+ * scans of the method against the oracle (Sec. 5.1). Other fields take the
+ * defaults. */
+int seasd_autotune(int64_t n, double L, double a_min, double a_max, double target, int32_t precision,
+                   seasd_config* cfg);
+
+typedef struct seasd_batch_s* seasd_batch;
+
+/* Plan for nsys independent suspensions (cubic cells), all sphere arrays
+ * concatenated: suspension k owns spheres offsets[k] .. offsets[k+1]-1.
+ *   offsets  host [nsys+1], offsets[0] = 0, increasing
+ *   pos      device [N][3], radius device [N] (N = offsets[nsys]); read during
+ *            this call only (the plan keeps binned copies)
+ *   boxes    host [nsys][9] lattice vectors (cubic)
+ *   per_sys  host [nsys] configurations, or NULL to autotune each suspension
+ *            for `target` with the handle's precision
+ * Builds every suspension's geometry (binning, neighbour lists) and captures
+ * the product phases of all of them into one hipGraph (suspensions spread
+ * over 8 streams that fork from and join `stream`). Synchronises `stream`.
+ * The plan holds its own workspace; destroy it with seasd_batch_destroy. */
+int seasd_batch_create(seasd_handle handle, int32_t nsys, const int64_t* offsets, const double* pos,
+                       const double* radius, const double* boxes, const seasd_config* per_sys, double target,
+                       seasd_batch* plan, void* stream);
+
+/* y = M x for every suspension of the plan with one graph launch on `stream`:
+ * x, y device [N][12] (concatenated like the positions). Asynchronous. */
+int seasd_batch_apply(seasd_batch plan, const double* x, double* y, void* stream);
+
+/* Per-suspension configuration chosen for the plan (host out[nsys]). */
+int seasd_batch_configs(seasd_batch plan, seasd_config* out);
+
+int seasd_batch_destroy(seasd_batch plan);
+
+/* One-shot batched product: create a plan, apply it once, destroy it. */
+int seasd_mobility_apply_batched(seasd_handle handle, int32_t nsys, const int64_t* offsets,
+                                 const double* pos, const double* radius, const double* boxes,
+                                 const seasd_config* per_sys, const double* x, double* y, void* stream);
+
 /* Short description of a return code (static storage). */
 const char* seasd_error_string(int32_t code);
 

@@ -2,6 +2,7 @@
 // workspace, the mobility product and the GMRES far-field solve.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -52,7 +53,8 @@ struct seasd_handle_s {
     bool have_cfg = false;
     // product workspace
     DevBuf bin_of, counts, start, fill, perm, amax, err, sp, sa, sx, ybuf, rgrid, spec, twiddle;
-    DevBuf ncount, noff, list, total, wi0, wmom, wfac;
+    DevBuf ncount, maxcount, list, total, wrec, scan_tmp;
+    int cap = 64;             // neighbour-list slots per sphere, grown on demand
     int64_t geom_n = -1;      // spheres in the geometry currently held in the workspace
     int twiddle_M = 0;
     // solver workspace
@@ -120,7 +122,7 @@ extern "C" int seasd_destroy(seasd_handle h) {
     hipSetDevice(h->device);
     DevBuf* bufs[] = {&h->bin_of, &h->counts, &h->start, &h->fill, &h->perm, &h->amax, &h->err,
                       &h->sp, &h->sa, &h->sx, &h->ybuf, &h->rgrid, &h->spec, &h->twiddle,
-                      &h->ncount, &h->noff, &h->list, &h->total, &h->wi0, &h->wmom, &h->wfac,
+                      &h->ncount, &h->maxcount, &h->list, &h->total, &h->wrec, &h->scan_tmp,
                       &h->V, &h->w, &h->z, &h->u, &h->r, &h->bred, &h->hdev, &h->partial, &h->blocks,
                       &h->inv, &h->coef, &h->singular, &h->one_pos, &h->one_rad, &h->one_x, &h->one_y};
     for (DevBuf* b : bufs) b->release();
@@ -183,11 +185,9 @@ static int ensure_product_ws(seasd_handle h, int64_t n) {
     rc |= h->sx.ensure(sizeof(double) * 12 * n);
     rc |= h->ybuf.ensure(sizeof(double) * 12 * n);
     rc |= h->ncount.ensure(sizeof(int) * n);
-    rc |= h->noff.ensure(sizeof(int) * (n + 1));
-    rc |= h->list.ensure(sizeof(int2) * 1024);
-    rc |= h->wi0.ensure(sizeof(int) * 4 * n);
-    rc |= h->wmom.ensure(R * 20 * n);
-    rc |= h->wfac.ensure(R * 3 * h->cfg.P * n);
+    rc |= h->maxcount.ensure(sizeof(int));
+    rc |= h->scan_tmp.ensure(sizeof(int) * (((size_t)std::max<int64_t>(n, (int64_t)nbins) + 2047) / 2048 + 2));
+    rc |= h->wrec.ensure(R * (24 + 3 * h->cfg.P) * n);
     if (h->cfg.parts & SEASD_PARTS_WAVE) {
         rc |= h->rgrid.ensure(R * 4 * (size_t)M * M * M);
         rc |= h->spec.ensure(R * 4 * (size_t)M * M * M);
@@ -241,8 +241,10 @@ static void fill_args(seasd_handle h, ApplyArgs& A, int64_t n, const double* pos
     A.start = h->start.as<int>();
     A.fill = h->fill.as<int>();
     A.perm = h->perm.as<int>();
+    A.scan_tmp = h->scan_tmp.as<int>();
     A.ncount = h->ncount.as<int>();
-    A.noff = h->noff.as<int>();
+    A.maxcount = h->maxcount.as<int>();
+    A.cap = h->cap;
     A.list = h->list.as<int2>();
     A.amax_bits = h->amax.as<unsigned long long>();
     A.err = h->err.as<int>();
@@ -250,9 +252,7 @@ static void fill_args(seasd_handle h, ApplyArgs& A, int64_t n, const double* pos
     A.sa = h->sa.as<double>();
     A.sx = h->sx.as<double>();
     A.ybuf = h->ybuf.as<double>();
-    A.wi0 = h->wi0.p;
-    A.wmom = h->wmom.p;
-    A.wfac = h->wfac.p;
+    A.wrec = h->wrec.p;
     A.rgrid = h->rgrid.p;
     A.spec = h->spec.p;
     A.twiddle = h->twiddle.as<double>();
@@ -260,8 +260,9 @@ static void fill_args(seasd_handle h, ApplyArgs& A, int64_t n, const double* pos
 
 // Queue one product. With reuse_geometry the binning and neighbour list of the
 // previous call (same spheres) are kept and only the moments are re-binned.
-// Building a geometry waits once for the neighbour total (one 4-byte copy) to
-// size the list; everything else is queued without synchronisation.
+// Building a geometry waits once for the largest neighbour count (one 4-byte
+// copy) to confirm the list fit its slots; everything else is queued without
+// synchronisation.
 static int queue_apply(seasd_handle h, int64_t n, const double* pos, const double* radius, double L,
                        const double* x, double* y, hipStream_t st, bool checks, bool reuse_geometry = false,
                        int compressible = -1) {
@@ -277,13 +278,19 @@ static int queue_apply(seasd_handle h, int64_t n, const double* pos, const doubl
     } else {
         h->geom_n = -1;
         if (launch_geometry(A, st, &h->timer)) return SEASD_E_HIP;
-        int total = 0;
-        if (hipMemcpyAsync(&total, A.noff + n, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return SEASD_E_HIP;
-        if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
-        if (total < 0) return SEASD_E_CUTOFF;
-        if (h->list.ensure(sizeof(int2) * ((size_t)total + 1))) return SEASD_E_NOMEM;
-        A.list = h->list.as<int2>();
-        if (launch_pairlist(A, st)) return SEASD_E_HIP;
+        for (int attempt = 0; attempt < 3; ++attempt) {
+            if (h->list.ensure(sizeof(int2) * (size_t)h->cap * n)) return SEASD_E_NOMEM;
+            A.list = h->list.as<int2>();
+            A.cap = h->cap;
+            if (launch_pairlist(A, st)) return SEASD_E_HIP;
+            if (!(A.parts & kPartsReal)) break;
+            int mx = 0;
+            if (hipMemcpyAsync(&mx, A.maxcount, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+                return SEASD_E_HIP;
+            if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
+            if (mx <= h->cap) break;
+            h->cap = mx + mx / 4 + 8;     // rare: grow and list again
+        }
         h->geom_n = n;
     }
     if (launch_compute(A, st, &h->timer)) return SEASD_E_HIP;
@@ -606,4 +613,209 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
     S.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = S;
     return S.converged ? SEASD_OK : SEASD_W_NOT_CONVERGED;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner and batched products
+
+extern "C" int seasd_autotune(int64_t n, double L, double a_min, double a_max, double target, int32_t precision,
+                              seasd_config* cfg) {
+    if (!cfg || n < 1 || !(L > 0.0) || !(a_min > 0.0) || !(a_max >= a_min) || !(target > 0.0))
+        return SEASD_E_INVALID_ARG;
+    seasd_default_config(cfg);
+    cfg->precision = precision;
+    cfg->checks = 0;
+    // grid: spacing near 0.4 a_max (the scans below were taken at h = 0.39-0.40)
+    int M = 32;
+    while (M < 256 && L / M > 0.42 * a_max) M *= 2;
+    const double h = L / M;
+    // Measured at h/a = 0.39-0.40 against the converged oracle (FP64 window
+    // error; FP32 adds ~5e-7): (xi a, rc_factor, P, m/sqrt(pi P)) =
+    //   (0.8, 3.0, 16, 0.85) -> 4.6e-7,  (0.7, 3.5, 16, 0.95) -> 6.6e-8,
+    //   (0.7, 3.5, 14, 0.95) -> 4.6e-7,  (0.6, 3.5, 12, 0.95) -> 3.7e-6.
+    // xi scales as 1/h (fixed k-space tail); xi r_c is held for the smallest
+    // pair (r_c = rc_factor * 2 a_min), as in the scans with a = 1.
+    double xi_h, rcx, mf;
+    int P;
+    if (target >= 1e-5) { xi_h = 0.6 * 0.397; rcx = 0.6 * 3.5; P = 12; mf = 0.95; }
+    else if (target >= 1e-6 || precision == SEASD_FP32) { xi_h = 0.8 * 0.397; rcx = 0.8 * 3.0; P = 16; mf = 0.85; }
+    else { xi_h = 0.7 * 0.397; rcx = 0.7 * 3.5; P = 16; mf = 0.95; }
+    cfg->grid = M;
+    cfg->xi = xi_h / h;
+    cfg->rc_factor = std::max(1.5, rcx / (cfg->xi * a_min));
+    cfg->P = std::min(P, M);
+    cfg->m = mf * std::sqrt(kPi * cfg->P);
+    return SEASD_OK;
+}
+
+struct seasd_batch_s {
+    int device = 0;
+    int nsys = 0;
+    std::vector<int64_t> off;
+    std::vector<double> L;
+    std::vector<seasd_handle> sub;
+    std::vector<seasd_config> cfg;
+    DevBuf pos, rad, xin, yout;
+    hipStream_t streams[8] = {};
+    hipEvent_t fork = nullptr, join[8] = {};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" int seasd_batch_destroy(seasd_batch b) {
+    if (!b) return SEASD_OK;
+    hipSetDevice(b->device);
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    for (auto& e : b->join)
+        if (e) hipEventDestroy(e);
+    if (b->fork) hipEventDestroy(b->fork);
+    for (auto& st : b->streams)
+        if (st) hipStreamDestroy(st);
+    for (auto h : b->sub) seasd_destroy(h);
+    b->pos.release();
+    b->rad.release();
+    b->xin.release();
+    b->yout.release();
+    delete b;
+    return SEASD_OK;
+}
+
+extern "C" int seasd_batch_create(seasd_handle h, int32_t nsys, const int64_t* offsets, const double* pos,
+                                  const double* radius, const double* boxes, const seasd_config* per_sys,
+                                  double target, seasd_batch* out, void* stream) {
+    if (!h || !out || nsys < 1 || !offsets || !pos || !radius || !boxes) return SEASD_E_INVALID_ARG;
+    *out = nullptr;
+    if (offsets[0] != 0) return SEASD_E_INVALID_ARG;
+    for (int k = 0; k < nsys; ++k)
+        if (offsets[k + 1] <= offsets[k]) return SEASD_E_INVALID_ARG;
+    if (!per_sys && !(target > 0.0)) return SEASD_E_INVALID_ARG;
+    if (hipSetDevice(h->device) != hipSuccess) return SEASD_E_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    auto* b = new seasd_batch_s();
+    b->device = h->device;
+    b->nsys = nsys;
+    b->off.assign(offsets, offsets + nsys + 1);
+    const int64_t N = offsets[nsys];
+    int rc = 0;
+    auto fail = [&](int code) {
+        seasd_batch_destroy(b);
+        return code;
+    };
+    for (int k = 0; k < nsys; ++k) {
+        double Lk;
+        if ((rc = cubic_edge(boxes + 9 * k, &Lk))) return fail(rc);
+        b->L.push_back(Lk);
+    }
+    if (b->pos.ensure(sizeof(double) * 3 * N) || b->rad.ensure(sizeof(double) * N) ||
+        b->xin.ensure(sizeof(double) * 12 * N) || b->yout.ensure(sizeof(double) * 12 * N))
+        return fail(SEASD_E_NOMEM);
+    if (hipMemcpyAsync(b->pos.p, pos, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(b->rad.p, radius, sizeof(double) * N, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemsetAsync(b->xin.p, 0, sizeof(double) * 12 * N, st) != hipSuccess)
+        return fail(SEASD_E_HIP);
+    std::vector<double> rad(N);
+    if (hipMemcpyAsync(rad.data(), radius, sizeof(double) * N, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(SEASD_E_HIP);
+    // per-suspension handles, configurations and geometries
+    for (int k = 0; k < nsys; ++k) {
+        const int64_t n = offsets[k + 1] - offsets[k];
+        seasd_config c;
+        if (per_sys) {
+            c = per_sys[k];
+        } else {
+            double amax = 0.0, amin = rad[offsets[k]];
+            for (int64_t i = offsets[k]; i < offsets[k + 1]; ++i) {
+                amax = std::max(amax, rad[i]);
+                amin = std::min(amin, rad[i]);
+            }
+            if ((rc = seasd_autotune(n, b->L[k], amin, amax, target, h->cfg.precision, &c))) return fail(rc);
+            c.eta = h->cfg.eta;
+            c.compressible = h->cfg.compressible;
+        }
+        c.checks = 0;
+        seasd_handle sh = nullptr;
+        if ((rc = seasd_create(&sh, h->device))) return fail(rc);
+        b->sub.push_back(sh);
+        if ((rc = seasd_set_config(sh, &c))) return fail(rc);
+        b->cfg.push_back(c);
+        const int64_t o = offsets[k];
+        rc = queue_apply(sh, n, b->pos.as<double>() + 3 * o, b->rad.as<double>() + o, b->L[k],
+                         b->xin.as<double>() + 12 * o, b->yout.as<double>() + 12 * o, st, false);
+        if (rc) return fail(rc);
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(SEASD_E_HIP);
+    // capture: fork to 8 streams, one product per suspension, join
+    for (auto& s8 : b->streams)
+        if (hipStreamCreateWithFlags(&s8, hipStreamNonBlocking) != hipSuccess) return fail(SEASD_E_HIP);
+    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) return fail(SEASD_E_HIP);
+    for (auto& e : b->join)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(SEASD_E_HIP);
+    hipStream_t cap = b->streams[0];
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return fail(SEASD_E_HIP);
+    bool ok = hipEventRecord(b->fork, cap) == hipSuccess;
+    for (int k = 1; k < 8 && ok; ++k) ok = hipStreamWaitEvent(b->streams[k], b->fork, 0) == hipSuccess;
+    // heaviest suspensions first, round-robin over the streams
+    std::vector<int> order(nsys);
+    for (int k = 0; k < nsys; ++k) order[k] = k;
+    std::sort(order.begin(), order.end(), [&](int a, int c) {
+        const double wa = (double)b->cfg[a].grid * b->cfg[a].grid * b->cfg[a].grid + 50.0 * (offsets[a + 1] - offsets[a]);
+        const double wc = (double)b->cfg[c].grid * b->cfg[c].grid * b->cfg[c].grid + 50.0 * (offsets[c + 1] - offsets[c]);
+        return wa > wc;
+    });
+    for (int r = 0; r < nsys && ok; ++r) {
+        const int k = order[r];
+        const int64_t n = offsets[k + 1] - offsets[k], o = offsets[k];
+        rc = queue_apply(b->sub[k], n, b->pos.as<double>() + 3 * o, b->rad.as<double>() + o, b->L[k],
+                         b->xin.as<double>() + 12 * o, b->yout.as<double>() + 12 * o, b->streams[r % 8], false,
+                         true);
+        ok = rc == SEASD_OK;
+    }
+    for (int k = 1; k < 8 && ok; ++k) {
+        ok = hipEventRecord(b->join[k], b->streams[k]) == hipSuccess &&
+             hipStreamWaitEvent(cap, b->join[k], 0) == hipSuccess;
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cap, &g);
+    if (!ok || ec != hipSuccess || !g) {
+        if (g) hipGraphDestroy(g);
+        return fail(rc ? rc : SEASD_E_HIP);
+    }
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) return fail(SEASD_E_HIP);
+    *out = b;
+    return SEASD_OK;
+}
+
+extern "C" int seasd_batch_apply(seasd_batch b, const double* x, double* y, void* stream) {
+    if (!b || !x || !y || x == y) return SEASD_E_INVALID_ARG;
+    if (hipSetDevice(b->device) != hipSuccess) return SEASD_E_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = b->off[b->nsys];
+    if (hipMemcpyAsync(b->xin.p, x, sizeof(double) * 12 * N, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return SEASD_E_HIP;
+    if (hipGraphLaunch(b->exec, st) != hipSuccess) return SEASD_E_HIP;
+    if (hipMemcpyAsync(y, b->yout.p, sizeof(double) * 12 * N, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return SEASD_E_HIP;
+    return SEASD_OK;
+}
+
+extern "C" int seasd_batch_configs(seasd_batch b, seasd_config* out) {
+    if (!b || !out) return SEASD_E_INVALID_ARG;
+    for (int k = 0; k < b->nsys; ++k) out[k] = b->cfg[k];
+    return SEASD_OK;
+}
+
+extern "C" int seasd_mobility_apply_batched(seasd_handle h, int32_t nsys, const int64_t* offsets,
+                                            const double* pos, const double* radius, const double* boxes,
+                                            const seasd_config* per_sys, const double* x, double* y,
+                                            void* stream) {
+    seasd_batch b = nullptr;
+    int rc = seasd_batch_create(h, nsys, offsets, pos, radius, boxes, per_sys, 1e-6, &b, stream);
+    if (rc) return rc;
+    rc = seasd_batch_apply(b, x, y, stream);
+    if (rc == SEASD_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = SEASD_E_HIP;
+    seasd_batch_destroy(b);
+    return rc;
 }

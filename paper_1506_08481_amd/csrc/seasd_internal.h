@@ -84,18 +84,18 @@ struct ApplyArgs {
     int* start;
     int* fill;
     int* perm;
+    int* scan_tmp;   // block sums of the device scans
     int* ncount;     // [n] neighbours per binned sphere
-    int* noff;       // [n+1] their exclusive scan
-    int2* list;      // neighbour entries (j, packed image shift)
+    int* maxcount;   // largest entry of ncount
+    int cap;         // list slots per sphere
+    int2* list;      // [n][cap] neighbour entries (j, packed image shift)
     unsigned long long* amax_bits;
     int* err;
     double* sp;
     double* sa;
     double* sx;
     double* ybuf;
-    void* wi0;       // [n] int4 window anchors
-    void* wmom;      // [n][20] R moments and offsets
-    void* wfac;      // [n][3P] R window factors
+    void* wrec;      // [n][24 + 3P] R window records
     void* rgrid;
     void* spec;
     const double* twiddle;

@@ -110,30 +110,100 @@ __global__ void k_bin_count(int n, const double* __restrict__ pos, const double*
     atomicMax(amax_bits, (unsigned long long)__double_as_longlong(a));
 }
 
-// exclusive scan of counts[0..nbins) into start[0..nbins], one workgroup
-__global__ void k_bin_scan(int nbins, const int* __restrict__ counts, int* __restrict__ start,
-                           int* __restrict__ fill) {
-    __shared__ int part[1024];
-    int t = threadIdx.x;
-    int per = (nbins + blockDim.x - 1) / blockDim.x;
-    int b0 = t * per, b1 = min(nbins, b0 + per);
+// Device-wide exclusive scan of int counts: each workgroup of 256 threads
+// owns 2048 consecutive entries (coalesced loads through LDS); block sums are
+// scanned by one workgroup and added back. out has n + 1 entries (total last).
+constexpr int kScanItems = 8;
+constexpr int kScanChunk = 256 * kScanItems;
+
+__device__ inline int block_exclusive_scan(int v, int* sh, int& total) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int u = (t >= o) ? sh[t - o] : 0;
+        __syncthreads();
+        sh[t] += u;
+        __syncthreads();
+    }
+    total = sh[255];
+    const int incl = sh[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(int n, const int* __restrict__ in, int* __restrict__ partial) {
+    __shared__ int sh[256];
+    const int base = blockIdx.x * kScanChunk;
     int s = 0;
-    for (int b = b0; b < b1; ++b) s += counts[b];
+    for (int k = 0; k < kScanItems; ++k) {
+        const int i = base + k * 256 + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    int total;
+    block_exclusive_scan(s, sh, total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(int nb, int* __restrict__ partial) {
+    __shared__ int part[1024];
+    const int t = threadIdx.x;
+    const int per = (nb + 1023) / 1024;
+    const int b0 = min(nb, t * per), b1 = min(nb, b0 + per);
+    int s = 0;
+    for (int b = b0; b < b1; ++b) s += partial[b];
     part[t] = s;
     __syncthreads();
-    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-        int v = (t >= off) ? part[t - off] : 0;
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int v = (t >= o) ? part[t - o] : 0;
         __syncthreads();
         part[t] += v;
         __syncthreads();
     }
     int run = part[t] - s;
     for (int b = b0; b < b1; ++b) {
-        start[b] = run;
-        fill[b] = 0;
-        run += counts[b];
+        const int v = partial[b];
+        partial[b] = run;
+        run += v;
     }
-    if (t == blockDim.x - 1) start[nbins] = part[t];
+    if (t == 1023) partial[nb] = part[t];
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(int n, const int* __restrict__ in, const int* __restrict__ partial,
+                                                    int* __restrict__ out) {
+    __shared__ int tile[kScanChunk];
+    __shared__ int sh[256];
+    const int base = blockIdx.x * kScanChunk;
+    for (int k = 0; k < kScanItems; ++k) {
+        const int i = base + k * 256 + threadIdx.x;
+        tile[k * 256 + threadIdx.x] = (i < n) ? in[i] : 0;
+    }
+    __syncthreads();
+    int v[kScanItems], s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = tile[threadIdx.x * kScanItems + k];
+        s += v[k];
+    }
+    int total;
+    int run = block_exclusive_scan(s, sh, total) + partial[blockIdx.x];
+    for (int k = 0; k < kScanItems; ++k) {
+        tile[threadIdx.x * kScanItems + k] = run;
+        run += v[k];
+    }
+    __syncthreads();
+    for (int k = 0; k < kScanItems; ++k) {
+        const int i = base + k * 256 + threadIdx.x;
+        if (i < n) out[i] = tile[k * 256 + threadIdx.x];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = partial[gridDim.x];
+}
+
+static int launch_scan(int n, const int* in, int* out, int* partial, hipStream_t st) {
+    const int nb = (n + kScanChunk - 1) / kScanChunk;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(256), 0, st, n, in, partial);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, nb, partial);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(256), 0, st, n, in, partial, out);
+    return 0;
 }
 
 __global__ void k_bin_scatter(int n, const int* __restrict__ bin_of, const int* __restrict__ start,
@@ -244,60 +314,31 @@ __device__ inline void for_each_neighbour(int s, const double* __restrict__ sp, 
     }
 }
 
-__global__ __launch_bounds__(256) void k_pair_count(int n, const double* __restrict__ sp,
-                                                    const double* __restrict__ sa, const int* __restrict__ start,
-                                                    int nb, double L, double binw, double rc_factor,
-                                                    const unsigned long long* __restrict__ amax_bits, int checks,
-                                                    int* __restrict__ ncount, int* __restrict__ err) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const double amax = __longlong_as_double((long long)*amax_bits);
-    int c = 0;
-    for_each_neighbour(s, sp, sa, start, nb, L, binw, rc_factor, amax, checks, err, [&](int, int) { ++c; });
-    ncount[s] = c;
-}
-
+// One pass: every sphere lists its neighbours into its own slot of `cap`
+// entries (in visiting order), stores the full count and raises the running
+// maximum; the host grows cap and repeats the pass if the maximum exceeded it.
 __global__ __launch_bounds__(256) void k_pair_fill(int n, const double* __restrict__ sp,
                                                    const double* __restrict__ sa, const int* __restrict__ start,
                                                    int nb, double L, double binw, double rc_factor,
-                                                   const unsigned long long* __restrict__ amax_bits,
-                                                   const int* __restrict__ noff, int2* __restrict__ list,
-                                                   int* __restrict__ err) {
+                                                   const unsigned long long* __restrict__ amax_bits, int checks,
+                                                   int cap, int* __restrict__ ncount, int* __restrict__ maxcount,
+                                                   int2* __restrict__ list, int* __restrict__ err) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const double amax = __longlong_as_double((long long)*amax_bits);
-    int k = noff[s];
-    for_each_neighbour(s, sp, sa, start, nb, L, binw, rc_factor, amax, 0, err,
-                       [&](int j, int code) { list[k++] = make_int2(j, code); });
-}
-
-// exclusive scan of n counts with one workgroup of 1024 threads
-__global__ __launch_bounds__(1024) void k_scan_counts(int n, const int* __restrict__ cnt, int* __restrict__ off) {
-    __shared__ int part[1024];
-    const int t = threadIdx.x;
-    const int per = (n + 1023) / 1024;
-    const int b0 = min(n, t * per), b1 = min(n, b0 + per);
-    int s = 0;
-    for (int b = b0; b < b1; ++b) s += cnt[b];
-    part[t] = s;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const int v = (t >= o) ? part[t - o] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int run = part[t] - s;
-    for (int b = b0; b < b1; ++b) {
-        off[b] = run;
-        run += cnt[b];
-    }
-    if (t == 1023) off[n] = part[t];
+    int2* dst = list + (size_t)cap * s;
+    int k = 0;
+    for_each_neighbour(s, sp, sa, start, nb, L, binw, rc_factor, amax, checks, err, [&](int j, int code) {
+        if (k < cap) dst[k] = make_int2(j, code);
+        ++k;
+    });
+    ncount[s] = k;
+    atomicMax(maxcount, k);
 }
 
 __global__ __launch_bounds__(128) void k_pair_eval(int n, const double* __restrict__ sp,
                                                    const double* __restrict__ sa, const double* __restrict__ sx,
-                                                   const int* __restrict__ noff, const int2* __restrict__ list,
+                                                   const int* __restrict__ ncount, int cap, const int2* __restrict__ list,
                                                    double L, double xi, double inv_eta, int parts,
                                                    double* __restrict__ ybuf) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -307,8 +348,8 @@ __global__ __launch_bounds__(128) void k_pair_eval(int n, const double* __restri
     double y[12];
     for (int c = 0; c < 12; ++c) y[c] = 0.0;
     if (parts & kPartsReal) {
-        const int k1 = noff[s + 1];
-        for (int k = noff[s]; k < k1; ++k) {
+        const int k0 = cap * s, k1 = k0 + min(ncount[s], cap);
+        for (int k = k0; k < k1; ++k) {
             const int2 e = list[k];
             const int j = e.x;
             const int wx = (e.y & 1023) - 512, wy = ((e.y >> 10) & 1023) - 512, wz = ((e.y >> 20) & 1023) - 512;
@@ -346,7 +387,15 @@ __global__ __launch_bounds__(128) void k_pair_eval(int n, const double* __restri
 
 constexpr int kTile = 8;
 constexpr int kMaxP = 32;
-constexpr int kMomStride = 20;  // d0[3], a2, F[3], T[3], S[6], sqrt3 s6, pad[3]
+// record layout (R units): [0..2] i0 (int bits), [3] d1, [4..6] d0, [7] a^2,
+// [8..10] F, [11..13] T, [14..19] S (xx yy zz xy xz yz), [20] sqrt3 s6,
+// [21] c0, [22] c1, [23] e0, [24 ..] factors x[P], y[P], z[P].
+// With w the window value at squared distance r2, the Faxen-weighted window
+// (1 + a^2 lap/6) h is w (c0 + c1 r2) and -(d/dr)(1 + a^2 lap/10) h / r is
+// w (e0 + d1 r2): c0 = 1 - a^2 alpha, c1 = (2/3) a^2 alpha^2,
+// e0 = 2 alpha - 2 a^2 alpha^2, d1 = 0.8 a^2 alpha^3.
+constexpr int kRecHead = 24;
+__host__ __device__ inline int rec_stride(int P) { return kRecHead + 3 * P; }
 
 __device__ inline void fgg_factors(double d0, double h, double alpha, int P, double* out) {
     const int kc = P / 2 - 1;               // d0 + kc h lies in (-h, 0]
@@ -372,50 +421,58 @@ __device__ inline void fgg_factors(double d0, double h, double alpha, int P, dou
 }
 
 template <typename R>
+__device__ inline int rec_i0(const R* rec, int d) {
+    if constexpr (sizeof(R) == 4) return __float_as_int(rec[d]);
+    else return (int)__double_as_longlong(rec[d]);
+}
+
+template <typename R>
 __global__ __launch_bounds__(256) void k_window(int n, const double* __restrict__ sp, const double* __restrict__ sa,
                                                 const double* __restrict__ sx, int P, double h, double alpha,
-                                                int4* __restrict__ wi0, R* __restrict__ wmom, R* __restrict__ wfac) {
+                                                R* __restrict__ rec_out) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    int i0[3];
-    R* mom = wmom + (size_t)kMomStride * s;
-    R* fac = wfac + (size_t)3 * P * s;
+    R* rec = rec_out + (size_t)rec_stride(P) * s;
     double f[kMaxP];
     for (int d = 0; d < 3; ++d) {
         const double p = sp[3 * s + d];
-        i0[d] = (int)floor(p / h) - P / 2 + 1;
-        const double d0 = i0[d] * h - p;
-        mom[d] = (R)d0;
+        const int i0 = (int)floor(p / h) - P / 2 + 1;
+        const double d0 = i0 * h - p;
+        if constexpr (sizeof(R) == 4) rec[d] = __int_as_float(i0);
+        else rec[d] = __longlong_as_double((long long)i0);
+        rec[4 + d] = (R)d0;
         fgg_factors(d0, h, alpha, P, f);
-        for (int k = 0; k < P; ++k) fac[d * P + k] = (R)f[k];
+        for (int k = 0; k < P; ++k) rec[kRecHead + d * P + k] = (R)f[k];
     }
-    wi0[s] = make_int4(i0[0], i0[1], i0[2], 0);
     const double a = sa[s];
+    const double a2 = a * a;
     const double* xs = sx + 12 * (size_t)s;
-    mom[3] = (R)(a * a);
+    rec[3] = (R)(0.8 * a2 * alpha * alpha * alpha);
+    rec[7] = (R)a2;
+    rec[21] = (R)(1.0 - a2 * alpha);
+    rec[22] = (R)(2.0 / 3.0 * a2 * alpha * alpha);
+    rec[23] = (R)(2.0 * alpha - 2.0 * a2 * alpha * alpha);
     for (int d = 0; d < 3; ++d) {
-        mom[4 + d] = (R)xs[d];
-        mom[7 + d] = (R)xs[3 + d];
+        rec[8 + d] = (R)xs[d];
+        rec[11 + d] = (R)xs[3 + d];
     }
     double S[6];
     s5_to_sym<double>(xs + 6, S);
-    for (int d = 0; d < 6; ++d) mom[10 + d] = (R)S[d];
-    mom[16] = (R)(kSqrt3 * xs[11]);
-    mom[17] = mom[18] = mom[19] = R(0);
+    for (int d = 0; d < 6; ++d) rec[14 + d] = (R)S[d];
+    rec[20] = (R)(kSqrt3 * xs[11]);
 }
 
 // ---------------------------------------------------------------------------
-// spreading: one workgroup of 256 threads owns one 8^3 tile; each thread owns
-// the two points (x, y, z) and (x, y, z + 4) of the tile
+// spreading: one workgroup of 256 threads owns one 8^3 tile. The tile is cut
+// into eight 4^3 sub-blocks; wavefront w owns sub-blocks w and w + 4 (one
+// point per lane in each), so a wavefront skips a sphere whose window misses
+// its sub-block. The spheres that can reach the tile are listed once in LDS,
+// their records are staged 32 at a time, and every point accumulates its sum
+// in registers with Neumaier compensation: each grid point is written by
+// exactly one lane, with no atomics.
 
-constexpr int kStage = 64;     // spheres staged per round
-
-template <typename R>
-struct SpreadStage {
-    int i0[kStage][3];
-    R mom[kStage][kMomStride];
-    R fac[kStage][3 * kMaxP];
-};
+constexpr int kStage = 32;     // spheres staged per round
+constexpr int kMaxCand = 2048; // candidate list held in LDS
 
 template <typename R>
 __device__ inline void neumaier(R& acc, R& cmp, R v) {
@@ -426,33 +483,40 @@ __device__ inline void neumaier(R& acc, R& cmp, R v) {
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_spread(
-    int n, const int4* __restrict__ wi0, const R* __restrict__ wmom, const R* __restrict__ wfac,
-    const int* __restrict__ start, int nb, int M, int P, double h, double alpha, double cw,
-    R4<R>* __restrict__ grid) {
-    __shared__ SpreadStage<R> st;
+    int n, const R* __restrict__ recs, const int* __restrict__ start, int nb, int M, int P, double h,
+    double alpha, double cw, R4<R>* __restrict__ grid) {
+    __shared__ R st[kStage * (kRecHead + 3 * kMaxP)];
+    __shared__ int cand[kMaxCand];
     __shared__ int bins[125], pre[126];
     __shared__ int nbins_used;
     const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
     const int tiles = M / kTile;
     const int ntiles = tiles * tiles * tiles;
-    // Morton-ordered tiles, contiguous per XCD
     const unsigned tcode = (unsigned)xcd_block(blockIdx.x, ntiles);
     const int tx = (int)compact_bits3(tcode), ty = (int)compact_bits3(tcode >> 1), tz = (int)compact_bits3(tcode >> 2);
-    const int lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
-    const int gx = tx * kTile + lx, gy = ty * kTile + ly, gz0 = tz * kTile + lz, gz1 = gz0 + 4;
+    // sub-block b (0..7) at offset (b&1, (b>>1)&1, b>>2) * 4; lane -> point inside
+    const int ox = lane & 3, oy = (lane >> 2) & 3, oz = lane >> 4;
+    int gx[2], gy[2], gz[2];
+    for (int p = 0; p < 2; ++p) {
+        const int b = wv + 4 * p;
+        gx[p] = tx * kTile + (b & 1) * 4 + ox;
+        gy[p] = ty * kTile + ((b >> 1) & 1) * 4 + oy;
+        gz[p] = tz * kTile + (b >> 2) * 4 + oz;
+    }
     const int mask = M - 1;
+    const int RS = rec_stride(P);
 
-    // distinct bins whose spheres can reach this tile
     const int reach = (P / 2 + kTile - 1) / kTile;
     const int span = min(2 * reach + 1, nb);
     if (t == 0) {
         int c = 0;
-        for (int oz = 0; oz < span; ++oz)
-            for (int oy = 0; oy < span; ++oy)
-                for (int ox = 0; ox < span; ++ox) {
-                    int bx = (span == nb) ? ox : ((tx - reach + ox) % nb + nb) % nb;
-                    int by = (span == nb) ? oy : ((ty - reach + oy) % nb + nb) % nb;
-                    int bz = (span == nb) ? oz : ((tz - reach + oz) % nb + nb) % nb;
+        for (int kz = 0; kz < span; ++kz)
+            for (int ky = 0; ky < span; ++ky)
+                for (int kx = 0; kx < span; ++kx) {
+                    const int bx = (span == nb) ? kx : ((tx - reach + kx) % nb + nb) % nb;
+                    const int by = (span == nb) ? ky : ((ty - reach + ky) % nb + nb) % nb;
+                    const int bz = (span == nb) ? kz : ((tz - reach + kz) % nb + nb) % nb;
                     bins[c++] = bin_id(bx, by, bz);
                 }
         nbins_used = c;
@@ -465,80 +529,70 @@ __global__ __launch_bounds__(256) void k_spread(
     }
     __syncthreads();
     const int ncand = pre[nbins_used];
-    const R al = (R)alpha, al2 = al * al, al3 = al2 * al;
+    const R al = (R)alpha;
     const R hh = (R)h, cwr = (R)cw;
-    const R i6 = R(1) / R(6), i10 = R(1) / R(10);
     R acc[2][4], cmp[2][4];
     for (int a = 0; a < 2; ++a)
         for (int c = 0; c < 4; ++c) acc[a][c] = cmp[a][c] = R(0);
-    const int fl = 3 * P;
-
-    for (int c0 = 0; c0 < ncand; c0 += kStage) {
-        const int cnt = min(kStage, ncand - c0);
-        // stage records: thread t copies record slices (coalesced per sphere)
-        for (int e = t; e < cnt; e += 256) {
-            const int c = c0 + e;
-            int k = 0;
-            while (pre[k + 1] <= c) ++k;
-            const int sidx = start[bins[k]] + (c - pre[k]);
-            const int4 v = wi0[sidx];
-            st.i0[e][0] = v.x;
-            st.i0[e][1] = v.y;
-            st.i0[e][2] = v.z;
-            // remember the sphere index in the (unused) pad of mom
-            reinterpret_cast<int*>(&st.mom[e][17])[0] = sidx;
+    // both points of a lane share x and y; their z differ by 4
+    for (int cbase = 0; cbase < ncand; cbase += kMaxCand) {
+        const int clen = min(kMaxCand, ncand - cbase);
+        // list this chunk of candidates: one bin per thread
+        for (int k = t; k < nbins_used; k += 256) {
+            const int b0 = max(pre[k], cbase), b1 = min(pre[k + 1], cbase + clen);
+            const int s0 = start[bins[k]] + (b0 - pre[k]);
+            for (int c = b0; c < b1; ++c) cand[c - cbase] = s0 + (c - b0);
         }
         __syncthreads();
-        for (int e = t; e < cnt * kMomStride; e += 256) {
-            const int q = e / kMomStride, k = e - q * kMomStride;
-            if (k >= 17) continue;
-            const int sidx = reinterpret_cast<const int*>(&st.mom[q][17])[0];
-            st.mom[q][k] = wmom[(size_t)kMomStride * sidx + k];
-        }
-        for (int e = t; e < cnt * fl; e += 256) {
-            const int q = e / fl, k = e - q * fl;
-            const int sidx = reinterpret_cast<const int*>(&st.mom[q][17])[0];
-            st.fac[q][k] = wfac[(size_t)fl * sidx + k];
-        }
-        __syncthreads();
-        for (int q = 0; q < cnt; ++q) {
-            const int kx = (gx - st.i0[q][0]) & mask;
-            const int ky = (gy - st.i0[q][1]) & mask;
-            const int kz0 = (gz0 - st.i0[q][2]) & mask;
-            const int kz1 = (gz1 - st.i0[q][2]) & mask;
-            const bool inxy = (kx < P) && (ky < P);
-            const bool in0 = inxy && (kz0 < P), in1 = inxy && (kz1 < P);
-            if (!__any(in0 || in1)) continue;
-            if (!(in0 || in1)) continue;
-            const R* mo = st.mom[q];
-            const R* fa = st.fac[q];
-            const R rx = mo[0] + kx * hh, ry = mo[1] + ky * hh;
-            const R wxy = cwr * fa[kx] * fa[P + ky];
-            const R a2 = mo[3];
-            const R F0 = mo[4], F1 = mo[5], F2 = mo[6], T0 = mo[7], T1 = mo[8], T2 = mo[9];
-            const R S0 = mo[10], S1 = mo[11], S2 = mo[12], S3 = mo[13], S4 = mo[14], S5 = mo[15];
-            const R sq = mo[16];
-#pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                const bool in = p ? in1 : in0;
-                if (!in) continue;
-                const int kz = p ? kz1 : kz0;
-                const R rz = mo[2] + kz * hh;
-                const R r2 = rx * rx + ry * ry + rz * rz;
-                const R w = wxy * fa[2 * P + kz];
-                const R cF = w * (R(1) + a2 * i6 * (R(4) * al2 * r2 - R(6) * al));
-                const R cS = w * (R(2) * al - a2 * i10 * (R(20) * al2 - R(8) * al3 * r2));
-                const R cT = -al * w;
-                const R Srx = S0 * rx + S3 * ry + S4 * rz;
-                const R Sry = S3 * rx + S1 * ry + S5 * rz;
-                const R Srz = S4 * rx + S5 * ry + S2 * rz;
-                neumaier(acc[p][0], cmp[p][0], cF * F0 + cT * (ry * T2 - rz * T1) + cS * Srx);
-                neumaier(acc[p][1], cmp[p][1], cF * F1 + cT * (rz * T0 - rx * T2) + cS * Sry);
-                neumaier(acc[p][2], cmp[p][2], cF * F2 + cT * (rx * T1 - ry * T0) + cS * Srz);
-                neumaier(acc[p][3], cmp[p][3], w * sq);
+        for (int c0 = 0; c0 < clen; c0 += kStage) {
+            const int cnt = min(kStage, clen - c0);
+            // stage records (contiguous per sphere)
+            for (int e = t; e < cnt * RS; e += 256) {
+                const int q = e / RS, k = e - q * RS;
+                st[q * RS + k] = recs[(size_t)RS * cand[c0 + q] + k];
             }
+            __syncthreads();
+            R part[2][4];  // this round's contributions, plain sums
+            for (int a = 0; a < 2; ++a)
+                for (int c = 0; c < 4; ++c) part[a][c] = R(0);
+            for (int q = 0; q < cnt; ++q) {
+                const R* rc = st + q * RS;
+                const int i0x = rec_i0(rc, 0), i0y = rec_i0(rc, 1), i0z = rec_i0(rc, 2);
+                bool in[2];
+                int kx[2], ky[2], kz[2];
+                for (int p = 0; p < 2; ++p) {
+                    kx[p] = (gx[p] - i0x) & mask;
+                    ky[p] = (gy[p] - i0y) & mask;
+                    kz[p] = (gz[p] - i0z) & mask;
+                    in[p] = (kx[p] < P) && (ky[p] < P) && (kz[p] < P);
+                }
+                if (!__any(in[0] || in[1])) continue;
+                const R F0 = rc[8], F1 = rc[9], F2 = rc[10], T0 = rc[11], T1 = rc[12], T2 = rc[13];
+                const R S0 = rc[14], S1 = rc[15], S2 = rc[16], S3 = rc[17], S4 = rc[18], S5 = rc[19];
+                const R sq = rc[20], c0 = rc[21], c1 = rc[22], e0 = rc[23], d1 = rc[3];
+                const R* fa = rc + kRecHead;
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    if (!in[p]) continue;
+                    const R rx = rc[4] + kx[p] * hh, ry = rc[5] + ky[p] * hh, rz = rc[6] + kz[p] * hh;
+                    const R r2 = rx * rx + ry * ry + rz * rz;
+                    const R w = cwr * fa[kx[p]] * fa[P + ky[p]] * fa[2 * P + kz[p]];
+                    const R cF = w * (c0 + c1 * r2);
+                    const R cS = w * (e0 + d1 * r2);
+                    const R cT = -al * w;
+                    const R Srx = S0 * rx + S3 * ry + S4 * rz;
+                    const R Sry = S3 * rx + S1 * ry + S5 * rz;
+                    const R Srz = S4 * rx + S5 * ry + S2 * rz;
+                    part[p][0] += cF * F0 + cT * (ry * T2 - rz * T1) + cS * Srx;
+                    part[p][1] += cF * F1 + cT * (rz * T0 - rx * T2) + cS * Sry;
+                    part[p][2] += cF * F2 + cT * (rx * T1 - ry * T0) + cS * Srz;
+                    part[p][3] += w * sq;
+                }
+            }
+            for (int a = 0; a < 2; ++a)
+                for (int c = 0; c < 4; ++c) neumaier(acc[a][c], cmp[a][c], part[a][c]);
+            __syncthreads();
         }
-        __syncthreads();
     }
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
@@ -547,7 +601,7 @@ __global__ __launch_bounds__(256) void k_spread(
         out.y = acc[p][1] + cmp[p][1];
         out.z = acc[p][2] + cmp[p][2];
         out.w = acc[p][3] + cmp[p][3];
-        grid[((size_t)(p ? gz1 : gz0) * M + gy) * M + gx] = out;
+        grid[((size_t)gz[p] * M + gy[p]) * M + gx[p]] = out;
     }
 }
 
@@ -785,8 +839,7 @@ __global__ __launch_bounds__(256) void k_fft_z_scale(C1<R>* __restrict__ data,
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_gather(
-    int n, const int4* __restrict__ wi0, const R* __restrict__ wmom, const R* __restrict__ wfac,
-    const int* __restrict__ perm, const R4<R>* __restrict__ grid, int M, int P, double h,
+    int n, const R* __restrict__ recs, const int* __restrict__ perm, const R4<R>* __restrict__ grid, int M, int P, double h,
     double alpha, double cwh3, double inv_eta, int parts, int compressible,
     const double* __restrict__ ybuf, double* __restrict__ yout) {
     constexpr int WPB = 4;
@@ -798,17 +851,17 @@ __global__ __launch_bounds__(256) void k_gather(
     const int s = active ? s0 : n - 1;
     const int mask = M - 1;
     const int fl = 3 * P;
-    for (int k = lane; k < fl; k += 64) fac[wv][k] = wfac[(size_t)fl * s + k];
+    const R* rc = recs + (size_t)rec_stride(P) * s;
+    for (int k = lane; k < fl; k += 64) fac[wv][k] = rc[kRecHead + k];
     __syncthreads();
     if (!active) return;
-    const int4 i0 = wi0[s];
-    const R* mo = wmom + (size_t)kMomStride * s;
-    const R d0x = mo[0], d0y = mo[1], d0z = mo[2], a2 = mo[3];
+    const int4 i0 = make_int4(rec_i0(rc, 0), rec_i0(rc, 1), rec_i0(rc, 2), 0);
+    const R d0x = rc[4], d0y = rc[5], d0z = rc[6];
+    const R c0 = rc[21], c1 = rc[22], e0 = rc[23], d1 = rc[3];
     double acc[13];
     for (int c = 0; c < 13; ++c) acc[c] = 0.0;
     if (parts & kPartsWave) {
-        const R al = (R)alpha, al2 = al * al, al3 = al2 * al, hh = (R)h;
-        const R i6 = R(1) / R(6), i10 = R(1) / R(10);
+        const R al = (R)alpha, hh = (R)h;
         R ac[13], cp[13];
         for (int c = 0; c < 13; ++c) ac[c] = cp[c] = R(0);
         const int P2 = P * P;
@@ -825,8 +878,8 @@ __global__ __launch_bounds__(256) void k_gather(
                 const R rz = d0z + kz * hh;
                 const R r2 = rx * rx + ry * ry + rz * rz;
                 const R w = wxy * fac[wv][2 * P + kz];
-                const R cU = w * (R(1) + a2 * i6 * (R(4) * al2 * r2 - R(6) * al));
-                const R cE = w * (R(2) * al - a2 * i10 * (R(20) * al2 - R(8) * al3 * r2));
+                const R cU = w * (c0 + c1 * r2);
+                const R cE = w * (e0 + d1 * r2);
                 const R cW = al * w;
                 col[0] += cU * g.x;
                 col[1] += cU * g.y;
@@ -907,7 +960,7 @@ static int launch_fft_chain_M(int M, void* rgrid, void* spec, const double* tw, 
     return 0;
 }
 
-// binning, neighbour counts and their scan; the total is noff[n]
+// binning: bins, their scan, binned copies of centres, radii and moments
 int launch_geometry(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     const int n = (int)A.n;
     const int T = 256;
@@ -918,27 +971,24 @@ int launch_geometry(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     hipMemsetAsync(A.amax_bits, 0, sizeof(unsigned long long), st);
     hipLaunchKernelGGL(k_bin_count, dim3(gb), dim3(T), 0, st, n, A.pos, A.radius, A.L, A.nb, A.binw,
                        A.bin_of, A.counts, A.amax_bits, A.err);
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, nbins, A.counts, A.start, A.fill);
+    launch_scan(nbins, A.counts, A.start, A.scan_tmp, st);
+    hipMemsetAsync(A.fill, 0, sizeof(int) * nbins, st);
     hipLaunchKernelGGL(k_bin_scatter, dim3(gb), dim3(T), 0, st, n, A.bin_of, A.start, A.fill, A.perm);
     hipLaunchKernelGGL(k_bin_order, dim3((nbins + T - 1) / T), dim3(T), 0, st, nbins, A.start, A.perm);
     hipLaunchKernelGGL(k_bin_gather, dim3(gb), dim3(T), 0, st, n, A.perm, A.pos, A.radius, A.x, A.L,
                        A.compressible, A.sp, A.sa, A.sx, A.err);
-    if (A.parts & kPartsReal) {
-        hipLaunchKernelGGL(k_pair_count, dim3(gb), dim3(T), 0, st, n, A.sp, A.sa, A.start, A.nb, A.L, A.binw,
-                           A.rc_factor, A.amax_bits, A.checks, A.ncount, A.err);
-        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, n, A.ncount, A.noff);
-    } else {
-        hipMemsetAsync(A.noff, 0, sizeof(int) * (n + 1), st);
-    }
+    if (!(A.parts & kPartsReal)) hipMemsetAsync(A.ncount, 0, sizeof(int) * n, st);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-// neighbour list (needs a list of at least noff[n] entries)
+// neighbour list into slots of A.cap entries; *A.maxcount receives the
+// largest count (the list is complete when it does not exceed A.cap)
 int launch_pairlist(const ApplyArgs& A, hipStream_t st) {
     const int n = (int)A.n;
     if (!(A.parts & kPartsReal)) return 0;
+    hipMemsetAsync(A.maxcount, 0, sizeof(int), st);
     hipLaunchKernelGGL(k_pair_fill, dim3((n + 255) / 256), dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb, A.L,
-                       A.binw, A.rc_factor, A.amax_bits, A.noff, A.list, A.err);
+                       A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount, A.maxcount, A.list, A.err);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -954,8 +1004,8 @@ int launch_moments(const ApplyArgs& A, hipStream_t st) {
 int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     const int n = (int)A.n;
     tm->begin(kPhasePair, st);
-    hipLaunchKernelGGL(k_pair_eval, dim3((n + 127) / 128), dim3(128), 0, st, n, A.sp, A.sa, A.sx, A.noff,
-                       A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
+    hipLaunchKernelGGL(k_pair_eval, dim3((n + 127) / 128), dim3(128), 0, st, n, A.sp, A.sa, A.sx, A.ncount,
+                       A.cap, A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
     const bool wave = (A.parts & kPartsWave) != 0;
     const int tiles = A.M / kTile;
     KScale ks{2.0 * kPi / A.L, 1.0 / (4.0 * A.xi * A.xi), 2.0 * A.tau,
@@ -966,30 +1016,28 @@ int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     if (A.fp32) {
         tm->begin(kPhaseSpread, st);
         hipLaunchKernelGGL((k_window<float>), dim3(gw), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.P, A.h, A.alpha,
-                           (int4*)A.wi0, (float*)A.wmom, (float*)A.wfac);
+                           (float*)A.wrec);
         if (wave) {
             hipLaunchKernelGGL((k_spread<float>), dim3(tiles * tiles * tiles), dim3(256), 0, st, n,
-                               (const int4*)A.wi0, (const float*)A.wmom, (const float*)A.wfac, A.start, A.nb, A.M,
-                               A.P, A.h, A.alpha, A.cw, (R4<float>*)A.rgrid);
+                               (const float*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
+                               (R4<float>*)A.rgrid);
             if (launch_fft_chain_M<float>(A.M, A.rgrid, A.spec, A.twiddle, ks, st, tm)) return -1;
         }
         tm->begin(kPhaseGather, st);
-        hipLaunchKernelGGL((k_gather<float>), dim3(gg), dim3(256), 0, st, n, (const int4*)A.wi0,
-                           (const float*)A.wmom, (const float*)A.wfac, A.perm, (const R4<float>*)A.rgrid, A.M, A.P,
+        hipLaunchKernelGGL((k_gather<float>), dim3(gg), dim3(256), 0, st, n, (const float*)A.wrec, A.perm, (const R4<float>*)A.rgrid, A.M, A.P,
                            A.h, A.alpha, cwh3, A.inv_eta, A.parts, A.compressible, A.ybuf, A.y);
     } else {
         tm->begin(kPhaseSpread, st);
         hipLaunchKernelGGL((k_window<double>), dim3(gw), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.P, A.h, A.alpha,
-                           (int4*)A.wi0, (double*)A.wmom, (double*)A.wfac);
+                           (double*)A.wrec);
         if (wave) {
             hipLaunchKernelGGL((k_spread<double>), dim3(tiles * tiles * tiles), dim3(256), 0, st, n,
-                               (const int4*)A.wi0, (const double*)A.wmom, (const double*)A.wfac, A.start, A.nb,
-                               A.M, A.P, A.h, A.alpha, A.cw, (R4<double>*)A.rgrid);
+                               (const double*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
+                               (R4<double>*)A.rgrid);
             if (launch_fft_chain_M<double>(A.M, A.rgrid, A.spec, A.twiddle, ks, st, tm)) return -1;
         }
         tm->begin(kPhaseGather, st);
-        hipLaunchKernelGGL((k_gather<double>), dim3(gg), dim3(256), 0, st, n, (const int4*)A.wi0,
-                           (const double*)A.wmom, (const double*)A.wfac, A.perm, (const R4<double>*)A.rgrid, A.M,
+        hipLaunchKernelGGL((k_gather<double>), dim3(gg), dim3(256), 0, st, n, (const double*)A.wrec, A.perm, (const R4<double>*)A.rgrid, A.M,
                            A.P, A.h, A.alpha, cwh3, A.inv_eta, A.parts, A.compressible, A.ybuf, A.y);
     }
     tm->end(st);

@@ -37,7 +37,9 @@ PHASES = ("bin", "pair", "spread", "fft_x_fwd", "fft_y_fwd", "fft_z_scale", "fft
 # exported symbols of include/seasd.h
 SYMBOLS = ("seasd_create", "seasd_destroy", "seasd_default_config", "seasd_set_config",
            "seasd_mobility_apply", "seasd_solve_farfield", "seasd_profile_enable",
-           "seasd_profile_read", "seasd_error_string")
+           "seasd_profile_read", "seasd_error_string", "seasd_autotune", "seasd_batch_create",
+           "seasd_batch_apply", "seasd_batch_configs", "seasd_batch_destroy",
+           "seasd_mobility_apply_batched")
 
 
 class seasd_config(ctypes.Structure):
@@ -94,6 +96,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                          ctypes.POINTER(seasd_solve_stats), vp]
     lib.seasd_profile_enable.argtypes = [vp, i32]
     lib.seasd_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32]
+    lib.seasd_autotune.argtypes = [i64, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, i32,
+                                    ctypes.POINTER(seasd_config)]
+    lib.seasd_batch_create.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), dp, dp, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(vp), vp]
+    lib.seasd_batch_apply.argtypes = [vp, dp, dp, vp]
+    lib.seasd_batch_configs.argtypes = [vp, ctypes.POINTER(seasd_config)]
+    lib.seasd_batch_destroy.argtypes = [vp]
+    lib.seasd_mobility_apply_batched.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), dp, dp,
+                                                 ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, dp, dp, vp]
     lib.seasd_error_string.argtypes = [i32]
     lib.seasd_error_string.restype = ctypes.c_char_p
     for name in SYMBOLS:
@@ -213,6 +224,61 @@ class Seasd:
     def close(self):
         if getattr(self, "h", None):
             lib().seasd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def seasd_autotune(n: int, L: float, a_min: float, a_max: float, target: float = 1e-6,
+                   precision: int = SEASD_FP32) -> seasd_config:
+    c = seasd_config()
+    _check(lib().seasd_autotune(int(n), float(L), float(a_min), float(a_max), float(target), int(precision),
+                                ctypes.byref(c)))
+    return c
+
+
+class Batch:
+    """A plan for many independent suspensions (concatenated sphere arrays)
+    whose products run as one hipGraph launch."""
+
+    def __init__(self, eng: "Seasd", offsets, pos, radius, boxes, per_sys=None, target: float = 1e-6,
+                 stream=None):
+        _require(pos, (3,), "pos")
+        nsys = len(offsets) - 1
+        off = (ctypes.c_int64 * (nsys + 1))(*[int(v) for v in offsets])
+        bx = [float(v) for b in boxes for v in (b.T.reshape(-1) if hasattr(b, "T") else b)]
+        boxes9 = (ctypes.c_double * (9 * nsys))(*bx)
+        cfgs = None
+        if per_sys is not None:
+            cfgs = (seasd_config * nsys)(*per_sys)
+        h = ctypes.c_void_p()
+        _check(lib().seasd_batch_create(eng.h, nsys, off, pos.data_ptr(), radius.data_ptr(), boxes9,
+                                        ctypes.cast(cfgs, ctypes.c_void_p) if cfgs is not None else None,
+                                        float(target), ctypes.byref(h), ctypes.c_void_p(_stream_ptr(stream))))
+        self.h = h
+        self.nsys = nsys
+        self.n = int(offsets[-1])
+
+    def apply(self, x, y=None, stream=None):
+        import torch
+        _require(x, (12,), "x")
+        if y is None:
+            y = torch.empty_like(x)
+        _check(lib().seasd_batch_apply(self.h, x.data_ptr(), y.data_ptr(), ctypes.c_void_p(_stream_ptr(stream))))
+        return y
+
+    def configs(self):
+        out = (seasd_config * self.nsys)()
+        _check(lib().seasd_batch_configs(self.h, out))
+        return list(out)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().seasd_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):
