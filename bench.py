@@ -92,6 +92,128 @@ def cpu_baseline(seconds_hint=20.0):
                       f"= x{scale:.0f}"}
 
 
+def _place_batch(k, seed):
+    from paper_1506_08481_amd import workloads as wl
+    rng = np.random.default_rng(seed + k)
+    n = int(np.exp(rng.uniform(np.log(500), np.log(8000))))
+    phi = float(rng.uniform(0.1, 0.45))
+    return wl.lognormal(n, phi, seed + 1000 + k)
+
+
+def bench_batch(args):
+    """256 independent suspensions, N log-uniform in [500, 8000], radii
+    lognormal (median 1, sigma 0.2), phi uniform in [0.1, 0.45], each with its
+    own cell and grid; all products in one hipGraph launch, FP32, autotuned."""
+    import multiprocessing as mp
+
+    import torch
+
+    from paper_1506_08481_amd import seasd
+    from paper_1506_08481_amd import workloads as wl
+    nsys = 256
+    t0 = time.time()
+    with mp.get_context("fork").Pool(min(8, os.cpu_count() or 1)) as pool:
+        sus = pool.starmap(_place_batch, [(k, 4000) for k in range(nsys)])
+    offs = np.concatenate([[0], np.cumsum([s.n for s in sus])])
+    pos = np.concatenate([s.pos for s in sus])
+    rad = np.concatenate([s.radius for s in sus])
+    x = wl.force_moments(int(offs[-1]), 4001)
+    print(f"setup: {nsys} suspensions, {offs[-1]} spheres, placement {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    eng = seasd.Seasd(0, precision=seasd.SEASD_FP32, checks=0)
+    t0 = time.time()
+    plan = seasd.Batch(eng, offs, torch.as_tensor(pos, device=dev), torch.as_tensor(rad, device=dev),
+                       [s.box for s in sus], target=1e-6)
+    t_plan = time.time() - t0
+    X = torch.as_tensor(x, device=dev)
+    Y = torch.empty_like(X)
+    for _ in range(args.warmup):
+        plan.apply(X, Y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.apply(X, Y)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    cfgs = plan.configs()
+    grids = {}
+    for c in cfgs:
+        grids[c.grid] = grids.get(c.grid, 0) + 1
+    out = {"metric": "batched sphere-products/s (256 suspensions, one graph launch)",
+           "value": float(offs[-1]) / dt, "unit": "sphere-products/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "256 suspensions, N log-uniform [500, 8000], radii lognormal(1, 0.2), "
+                                  "phi U[0.1, 0.45], autotuned FP32", "spheres": int(offs[-1]),
+                      "grids": {str(k): v for k, v in sorted(grids.items())}},
+           "plan_build_s": t_plan}
+    plan.close()
+    eng.close()
+    print(json.dumps(out))
+
+
+def bench_solve(args):
+    """N = 10,000 bidisperse spheres (radii 1 and 2, equal volume fraction per
+    species, phi = 0.3), grid 128^3, FP64, right-hand side N(0, 1): far-field
+    GMRES solve to relative residual 1e-8 with and without the block-diagonal
+    preconditioner."""
+    import torch
+
+    from paper_1506_08481_amd import seasd
+    from paper_1506_08481_amd import workloads as wl
+    s = wl.config_bidisperse_solve()
+    b = wl.force_moments(s.n, 2001)
+    dev = torch.device("cuda:0")
+    P_, R_, B_ = (torch.as_tensor(a, device=dev) for a in (s.pos, s.radius, b))
+    c = seasd.seasd_autotune(s.n, s.L, 1.0, 2.0, 1e-8, seasd.SEASD_FP64)
+    res = {}
+    for name, pc in (("blockdiag", seasd.SEASD_PRECOND_BLOCKDIAG), ("none", seasd.SEASD_PRECOND_NONE)):
+        eng = seasd.Seasd(0, grid=128, P=c.P, m=c.m, xi=c.xi, rc_factor=c.rc_factor, precision=seasd.SEASD_FP64,
+                          tol=1e-8, restart=50, max_iter=1500, precond=pc, checks=1)
+        eng.solve(P_, R_, s.box, B_)   # warm-up (allocation, code load)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st = eng.solve(P_, R_, s.box, B_)
+        torch.cuda.synchronize()
+        st["wall_s"] = time.perf_counter() - t0
+        res[name] = st
+        eng.close()
+    out = {"metric": "far-field solve time, N=1e4 bidisperse phi=0.3, tol 1e-8",
+           "value": res["blockdiag"]["wall_s"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": res["blockdiag"]["wall_s"] * 1e3, "higher_is_better": False, "scaling": "strong",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "bidisperse N=10000 (radii 1, 2) phi=0.3 grid 128^3 FP64 GMRES(50) tol 1e-8",
+                      "xi": c.xi, "rc_factor": c.rc_factor, "P": c.P, "m": c.m},
+           "solves": res}
+    print(json.dumps(out))
+
+
+def pmc_probe(args):
+    """Products of the benchmark workload followed by a plain device copy of
+    256 MiB (torch), for calibrating HBM byte counters."""
+    import torch
+
+    from paper_1506_08481_amd import seasd
+    from paper_1506_08481_amd import workloads as wl
+    s = wl.config_large(n=args.n)
+    x = wl.force_moments(s.n, 3001)
+    dev = torch.device("cuda:0")
+    P_, R_, X_ = (torch.as_tensor(a, device=dev) for a in (s.pos, s.radius, x))
+    xi, rcf, P, mf = CANDIDATES[1]
+    eng = seasd.Seasd(0, grid=256, P=P, m=mf * math.sqrt(math.pi * P), xi=xi, rc_factor=rcf,
+                      precision=seasd.SEASD_FP32, checks=0)
+    y = torch.empty_like(X_)
+    for _ in range(3):
+        eng.apply(P_, R_, s.box, X_, y)
+    a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)   # 256 MiB
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "done", "copy_bytes_each_way": a.numel() * 4}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,10 +221,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=100000)
+    ap.add_argument("--workload", choices=["large", "solve", "batch"], default="large")
+    ap.add_argument("--pmc-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
+    if args.pmc_probe:
+        return pmc_probe(args)
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "solve":
+        return bench_solve(args)
 
     import torch
 

@@ -91,6 +91,8 @@ extern "C" {
 typedef struct seasd_config {
     int32_t grid;           /* M, grid points per dimension: power of two, 8..512            */
     int32_t P;              /* window support in grid points per dimension: even, 4..min(M,32) */
+    int32_t tile;           /* spreading tile = bin edge in grid points: 4, 8, or 0 (auto:    */
+                            /* 4 below M = 128, else 8)                                      */
     double  m;              /* window shape parameter (eq. theta-param); <= 0: sqrt(pi P)   */
     double  xi;             /* Ewald splitting parameter, Beenakker convention (Sec. 2.2)   */
     double  rc_factor;      /* real-space cut-off r_c = rc_factor (a_i + a_j), > 1           */
@@ -195,7 +197,8 @@ int seasd_profile_read(seasd_handle handle, double* ms, int32_t count);
  * two with spacing L/M near 0.4 a_max, 32..256; the bins are 8^3 tiles of
  * that grid), xi from the grid spacing so that the k-space tail
  * exp(-k_max^2/(4 xi^2)) stays fixed, the real-space cut-off factor so that
- * xi r_c is fixed for the smallest pair, and the window (P, m) from accuracy
+ * xi r_c is fixed for a pair of spheres of radius a_min (the batch planner
+ * passes the 10th-percentile radius), and the window (P, m) from accuracy
  * scans of the method against the oracle (Sec. 5.1). Other fields take the
  * defaults. */
 int seasd_autotune(int64_t n, double L, double a_min, double a_max, double target, int32_t precision,

@@ -137,6 +137,7 @@ extern "C" int seasd_set_config(seasd_handle h, const seasd_config* c) {
     if (!h || !c) return SEASD_E_INVALID_ARG;
     if (!pow2(c->grid) || c->grid < 8 || c->grid > 256) return SEASD_E_INVALID_ARG;
     if (c->P < 4 || c->P > 32 || (c->P & 1) || c->P > c->grid) return SEASD_E_INVALID_ARG;
+    if (c->tile != 0 && c->tile != 4 && c->tile != 8) return SEASD_E_INVALID_ARG;
     if (!(std::isfinite(c->m)) || !(c->xi > 0.0) || !std::isfinite(c->xi)) return SEASD_E_INVALID_ARG;
     if (!(c->rc_factor > 1.0) || !std::isfinite(c->rc_factor)) return SEASD_E_INVALID_ARG;
     if (!(c->eta > 0.0) || !std::isfinite(c->eta)) return SEASD_E_INVALID_ARG;
@@ -167,9 +168,13 @@ static int cubic_edge(const double* box, double* L) {
 }
 
 // product workspace for n spheres on the configured grid
+// spreading tile (= bin) edge in grid points: the configured one, or 4 for
+// grids below 128 (more workgroups) and 8 from 128 up
+static int tile_of(const seasd_config& c) { return c.tile ? c.tile : (c.grid < 128 ? 4 : 8); }
+
 static int ensure_product_ws(seasd_handle h, int64_t n) {
     const int M = h->cfg.grid;
-    const int nb = M / 8;
+    const int nb = M / tile_of(h->cfg);
     const size_t nbins = (size_t)nb * nb * nb;
     const size_t R = h->cfg.precision == SEASD_FP32 ? 4 : 8;
     int rc = 0;
@@ -222,7 +227,8 @@ static void fill_args(seasd_handle h, ApplyArgs& A, int64_t n, const double* pos
     A.L = L;
     A.M = c.grid;
     A.P = c.P;
-    A.nb = c.grid / 8;
+    A.tile = tile_of(c);
+    A.nb = c.grid / A.tile;
     A.binw = L / A.nb;
     A.xi = c.xi;
     A.rc_factor = c.rc_factor;
@@ -725,12 +731,11 @@ extern "C" int seasd_batch_create(seasd_handle h, int32_t nsys, const int64_t* o
         if (per_sys) {
             c = per_sys[k];
         } else {
-            double amax = 0.0, amin = rad[offsets[k]];
-            for (int64_t i = offsets[k]; i < offsets[k + 1]; ++i) {
-                amax = std::max(amax, rad[i]);
-                amin = std::min(amin, rad[i]);
-            }
-            if ((rc = seasd_autotune(n, b->L[k], amin, amax, target, h->cfg.precision, &c))) return fail(rc);
+            // the real-space tail is held for pairs of 10th-percentile spheres
+            std::vector<double> rk(rad.begin() + offsets[k], rad.begin() + offsets[k + 1]);
+            std::sort(rk.begin(), rk.end());
+            const double asmall = rk[(size_t)(0.1 * (rk.size() - 1))], amax = rk.back();
+            if ((rc = seasd_autotune(n, b->L[k], asmall, amax, target, h->cfg.precision, &c))) return fail(rc);
             c.eta = h->cfg.eta;
             c.compressible = h->cfg.compressible;
         }

@@ -77,7 +77,7 @@ struct ApplyArgs {
     double* y;
     double L, binw, xi, rc_factor, inv_eta;
     double h, alpha, tau, cw;
-    int M, P, nb, parts, compressible, checks, fp32;
+    int M, P, nb, tile, parts, compressible, checks, fp32;
     // workspace
     int* bin_of;
     int* counts;

@@ -323,7 +323,7 @@ __global__ __launch_bounds__(256) void k_pair_fill(int n, const double* __restri
                                                    const unsigned long long* __restrict__ amax_bits, int checks,
                                                    int cap, int* __restrict__ ncount, int* __restrict__ maxcount,
                                                    int2* __restrict__ list, int* __restrict__ err) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const double amax = __longlong_as_double((long long)*amax_bits);
     int2* dst = list + (size_t)cap * s;
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(128) void k_pair_eval(int n, const double* __restri
                                                    const int* __restrict__ ncount, int cap, const int2* __restrict__ list,
                                                    double L, double xi, double inv_eta, int parts,
                                                    double* __restrict__ ybuf) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const double px = sp[3 * s], py = sp[3 * s + 1], pz = sp[3 * s + 2];
     const double ai = sa[s];
@@ -385,7 +385,6 @@ __global__ __launch_bounds__(128) void k_pair_eval(int n, const double* __restri
 // both read it. The factors use fast Gaussian gridding (eq. fgg-exp), anchored
 // at the window centre so the recurrences run over at most P/2 steps, in FP64.
 
-constexpr int kTile = 8;
 constexpr int kMaxP = 32;
 // record layout (R units): [0..2] i0 (int bits), [3] d1, [4..6] d0, [7] a^2,
 // [8..10] F, [11..13] T, [14..19] S (xx yy zz xy xz yz), [20] sqrt3 s6,
@@ -481,33 +480,37 @@ __device__ inline void neumaier(R& acc, R& cmp, R v) {
     acc = sum;
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_spread(
+template <typename R, int TILE>
+__global__ __launch_bounds__(TILE == 8 ? 256 : 64) void k_spread(
     int n, const R* __restrict__ recs, const int* __restrict__ start, int nb, int M, int P, double h,
     double alpha, double cw, R4<R>* __restrict__ grid) {
+    constexpr int NT = TILE == 8 ? 256 : 64;   // threads per workgroup
+    constexpr int NPT = TILE == 8 ? 2 : 1;     // points per lane
+    constexpr int MAXB = 729;                  // (2 reach + 1)^3 for reach <= 4
     __shared__ R st[kStage * (kRecHead + 3 * kMaxP)];
     __shared__ int cand[kMaxCand];
-    __shared__ int bins[125], pre[126];
+    __shared__ int bins[MAXB], pre[MAXB + 1];
     __shared__ int nbins_used;
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
-    const int tiles = M / kTile;
+    const int tiles = M / TILE;
     const int ntiles = tiles * tiles * tiles;
     const unsigned tcode = (unsigned)xcd_block(blockIdx.x, ntiles);
     const int tx = (int)compact_bits3(tcode), ty = (int)compact_bits3(tcode >> 1), tz = (int)compact_bits3(tcode >> 2);
-    // sub-block b (0..7) at offset (b&1, (b>>1)&1, b>>2) * 4; lane -> point inside
+    // 4^3 sub-blocks: sub-block b at offset (b&1, (b>>1)&1, b>>2) * 4; wavefront
+    // w owns sub-blocks w and w + 4 of an 8^3 tile (the single one of a 4^3 tile)
     const int ox = lane & 3, oy = (lane >> 2) & 3, oz = lane >> 4;
-    int gx[2], gy[2], gz[2];
-    for (int p = 0; p < 2; ++p) {
+    int gx[NPT], gy[NPT], gz[NPT];
+    for (int p = 0; p < NPT; ++p) {
         const int b = wv + 4 * p;
-        gx[p] = tx * kTile + (b & 1) * 4 + ox;
-        gy[p] = ty * kTile + ((b >> 1) & 1) * 4 + oy;
-        gz[p] = tz * kTile + (b >> 2) * 4 + oz;
+        gx[p] = tx * TILE + (b & 1) * 4 * (TILE / 8) + ox;
+        gy[p] = ty * TILE + ((b >> 1) & 1) * 4 * (TILE / 8) + oy;
+        gz[p] = tz * TILE + (b >> 2) * 4 * (TILE / 8) + oz;
     }
     const int mask = M - 1;
     const int RS = rec_stride(P);
 
-    const int reach = (P / 2 + kTile - 1) / kTile;
+    const int reach = (P / 2 + TILE - 1) / TILE;
     const int span = min(2 * reach + 1, nb);
     if (t == 0) {
         int c = 0;
@@ -531,14 +534,13 @@ __global__ __launch_bounds__(256) void k_spread(
     const int ncand = pre[nbins_used];
     const R al = (R)alpha;
     const R hh = (R)h, cwr = (R)cw;
-    R acc[2][4], cmp[2][4];
-    for (int a = 0; a < 2; ++a)
+    R acc[NPT][4], cmp[NPT][4];
+    for (int a = 0; a < NPT; ++a)
         for (int c = 0; c < 4; ++c) acc[a][c] = cmp[a][c] = R(0);
-    // both points of a lane share x and y; their z differ by 4
+
     for (int cbase = 0; cbase < ncand; cbase += kMaxCand) {
         const int clen = min(kMaxCand, ncand - cbase);
-        // list this chunk of candidates: one bin per thread
-        for (int k = t; k < nbins_used; k += 256) {
+        for (int k = t; k < nbins_used; k += NT) {
             const int b0 = max(pre[k], cbase), b1 = min(pre[k + 1], cbase + clen);
             const int s0 = start[bins[k]] + (b0 - pre[k]);
             for (int c = b0; c < b1; ++c) cand[c - cbase] = s0 + (c - b0);
@@ -546,33 +548,34 @@ __global__ __launch_bounds__(256) void k_spread(
         __syncthreads();
         for (int c0 = 0; c0 < clen; c0 += kStage) {
             const int cnt = min(kStage, clen - c0);
-            // stage records (contiguous per sphere)
-            for (int e = t; e < cnt * RS; e += 256) {
+            for (int e = t; e < cnt * RS; e += NT) {
                 const int q = e / RS, k = e - q * RS;
                 st[q * RS + k] = recs[(size_t)RS * cand[c0 + q] + k];
             }
             __syncthreads();
-            R part[2][4];  // this round's contributions, plain sums
-            for (int a = 0; a < 2; ++a)
+            R part[NPT][4];  // this round's contributions, plain sums
+            for (int a = 0; a < NPT; ++a)
                 for (int c = 0; c < 4; ++c) part[a][c] = R(0);
             for (int q = 0; q < cnt; ++q) {
                 const R* rc = st + q * RS;
                 const int i0x = rec_i0(rc, 0), i0y = rec_i0(rc, 1), i0z = rec_i0(rc, 2);
-                bool in[2];
-                int kx[2], ky[2], kz[2];
-                for (int p = 0; p < 2; ++p) {
+                bool in[NPT];
+                int kx[NPT], ky[NPT], kz[NPT];
+                bool any = false;
+                for (int p = 0; p < NPT; ++p) {
                     kx[p] = (gx[p] - i0x) & mask;
                     ky[p] = (gy[p] - i0y) & mask;
                     kz[p] = (gz[p] - i0z) & mask;
                     in[p] = (kx[p] < P) && (ky[p] < P) && (kz[p] < P);
+                    any = any || in[p];
                 }
-                if (!__any(in[0] || in[1])) continue;
+                if (!__any(any)) continue;
                 const R F0 = rc[8], F1 = rc[9], F2 = rc[10], T0 = rc[11], T1 = rc[12], T2 = rc[13];
                 const R S0 = rc[14], S1 = rc[15], S2 = rc[16], S3 = rc[17], S4 = rc[18], S5 = rc[19];
                 const R sq = rc[20], c0 = rc[21], c1 = rc[22], e0 = rc[23], d1 = rc[3];
                 const R* fa = rc + kRecHead;
 #pragma unroll
-                for (int p = 0; p < 2; ++p) {
+                for (int p = 0; p < NPT; ++p) {
                     if (!in[p]) continue;
                     const R rx = rc[4] + kx[p] * hh, ry = rc[5] + ky[p] * hh, rz = rc[6] + kz[p] * hh;
                     const R r2 = rx * rx + ry * ry + rz * rz;
@@ -589,13 +592,13 @@ __global__ __launch_bounds__(256) void k_spread(
                     part[p][3] += w * sq;
                 }
             }
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < NPT; ++a)
                 for (int c = 0; c < 4; ++c) neumaier(acc[a][c], cmp[a][c], part[a][c]);
             __syncthreads();
         }
     }
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
+    for (int p = 0; p < NPT; ++p) {
         R4<R> out;
         out.x = acc[p][0] + cmp[p][0];
         out.y = acc[p][1] + cmp[p][1];
@@ -1007,7 +1010,7 @@ int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     hipLaunchKernelGGL(k_pair_eval, dim3((n + 127) / 128), dim3(128), 0, st, n, A.sp, A.sa, A.sx, A.ncount,
                        A.cap, A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
     const bool wave = (A.parts & kPartsWave) != 0;
-    const int tiles = A.M / kTile;
+    const int tiles = A.M / A.tile;
     KScale ks{2.0 * kPi / A.L, 1.0 / (4.0 * A.xi * A.xi), 2.0 * A.tau,
               1.0 / ((double)A.M * A.M * A.M), A.inv_eta};
     const int gw = (n + 255) / 256;
@@ -1018,9 +1021,14 @@ int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
         hipLaunchKernelGGL((k_window<float>), dim3(gw), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.P, A.h, A.alpha,
                            (float*)A.wrec);
         if (wave) {
-            hipLaunchKernelGGL((k_spread<float>), dim3(tiles * tiles * tiles), dim3(256), 0, st, n,
-                               (const float*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
-                               (R4<float>*)A.rgrid);
+            if (A.tile == 8)
+                hipLaunchKernelGGL((k_spread<float, 8>), dim3(tiles * tiles * tiles), dim3(256), 0, st, n,
+                                   (const float*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
+                                   (R4<float>*)A.rgrid);
+            else
+                hipLaunchKernelGGL((k_spread<float, 4>), dim3(tiles * tiles * tiles), dim3(64), 0, st, n,
+                                   (const float*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
+                                   (R4<float>*)A.rgrid);
             if (launch_fft_chain_M<float>(A.M, A.rgrid, A.spec, A.twiddle, ks, st, tm)) return -1;
         }
         tm->begin(kPhaseGather, st);
@@ -1031,9 +1039,14 @@ int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
         hipLaunchKernelGGL((k_window<double>), dim3(gw), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.P, A.h, A.alpha,
                            (double*)A.wrec);
         if (wave) {
-            hipLaunchKernelGGL((k_spread<double>), dim3(tiles * tiles * tiles), dim3(256), 0, st, n,
-                               (const double*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
-                               (R4<double>*)A.rgrid);
+            if (A.tile == 8)
+                hipLaunchKernelGGL((k_spread<double, 8>), dim3(tiles * tiles * tiles), dim3(256), 0, st, n,
+                                   (const double*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
+                                   (R4<double>*)A.rgrid);
+            else
+                hipLaunchKernelGGL((k_spread<double, 4>), dim3(tiles * tiles * tiles), dim3(64), 0, st, n,
+                                   (const double*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
+                                   (R4<double>*)A.rgrid);
             if (launch_fft_chain_M<double>(A.M, A.rgrid, A.spec, A.twiddle, ks, st, tm)) return -1;
         }
         tm->begin(kPhaseGather, st);

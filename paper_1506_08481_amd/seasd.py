@@ -46,6 +46,7 @@ class seasd_config(ctypes.Structure):
     _fields_ = [
         ("grid", ctypes.c_int32),
         ("P", ctypes.c_int32),
+        ("tile", ctypes.c_int32),
         ("m", ctypes.c_double),
         ("xi", ctypes.c_double),
         ("rc_factor", ctypes.c_double),
