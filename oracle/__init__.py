@@ -12,5 +12,8 @@ Contents:
              converged mode and split-diagnostic modes.
   solve    - dense far-field solve and block-diagonal preconditioner blocks
              (Sec. 4.2) for small N.
+  mpnn     - the project's learned preconditioner network on top of those
+             blocks (not in the paper): forward, loss and backward in FP64,
+             with optional bfloat16 rounding of matrix-product operands.
 """
-from . import symbols, ewald  # noqa: F401
+from . import symbols, ewald, solve, mpnn  # noqa: F401
