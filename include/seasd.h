@@ -74,7 +74,10 @@ extern "C" {
 #define SEASD_E_HIP            -6   /* a HIP runtime call failed                */
 #define SEASD_E_NOMEM          -7   /* workspace allocation failed              */
 #define SEASD_E_UNSUPPORTED    -8   /* valid request this build does not handle */
+#define SEASD_E_FORMAT         -9   /* weights file missing, wrong or corrupt   */
 #define SEASD_W_NOT_CONVERGED   1   /* solve stopped at max_iter above tol      */
+#define SEASD_W_PRECOND_FALLBACK 2  /* learned preconditioner rejected; the     */
+                                    /* block-diagonal one was used instead      */
 
 /* ---- configuration --------------------------------------------------------- */
 #define SEASD_FP64 0
@@ -87,6 +90,9 @@ extern "C" {
 
 #define SEASD_PRECOND_NONE      0
 #define SEASD_PRECOND_BLOCKDIAG 1   /* per-sphere inverse of the self block (Sec. 4.2) */
+#define SEASD_PRECOND_LEARNED   2   /* block-diagonal one rescaled by the attached     */
+                                    /* network, plus its initial guess (see below)     */
+#define SEASD_PRECOND_LEARNED_GUESS 3 /* block-diagonal blocks, the network's guess   */
 
 typedef struct seasd_config {
     int32_t grid;           /* M, grid points per dimension: power of two, 8..512            */
@@ -117,6 +123,9 @@ typedef struct seasd_solve_stats {
     double  true_residual;   /* ||b - M x|| / ||b|| from a fresh product at exit     */
     double  setup_ms;        /* preconditioner construction                          */
     double  solve_ms;        /* total wall time of the call                          */
+    int32_t precond_used;    /* SEASD_PRECOND_* actually applied                     */
+    int32_t guess_used;      /* 1 if the learned initial guess was kept              */
+    double  initial_residual;/* ||b' - A x0|| / ||b'|| of the starting iterate       */
 } seasd_solve_stats;
 
 typedef struct seasd_handle_s* seasd_handle;
@@ -194,8 +203,8 @@ int seasd_profile_read(seasd_handle handle, double* ms, int32_t count);
  * Autotuner: parameters for one suspension of n spheres (radii a_min..a_max)
  * in a cubic cell of edge L, aiming at a global relative error of `target`
  * (1e-6 or looser) in the given precision. It picks the grid M (a power of
- * two with spacing L/M near 0.4 a_max, 32..256; the bins are 8^3 tiles of
- * that grid), xi from the grid spacing so that the k-space tail
+ * two with spacing L/M near 0.4 a_max, 32..256; the bins are tiles of 4^3
+ * grid points below M = 128 and of 8^3 from 128 up), xi from the grid spacing so that the k-space tail
  * exp(-k_max^2/(4 xi^2)) stays fixed, the real-space cut-off factor so that
  * xi r_c is fixed for a pair of spheres of radius a_min (the batch planner
  * passes the 10th-percentile radius), and the window (P, m) from accuracy
@@ -235,6 +244,89 @@ int seasd_batch_destroy(seasd_batch plan);
 int seasd_mobility_apply_batched(seasd_handle handle, int32_t nsys, const int64_t* offsets,
                                  const double* pos, const double* radius, const double* boxes,
                                  const seasd_config* per_sys, const double* x, double* y, void* stream);
+
+/* ---- learned preconditioner (not in the paper) ------------------------------
+ * A two-layer message-passing network on the neighbour graph (edges between
+ * spheres closer than 2 (a_i + a_j)) that works on top of the block-diagonal
+ * preconditioner of Sec. 4.2. For every sphere it predicts three
+ * log-scalings o_i (force, torque, stresslet groups) that turn the inverse
+ * block B_i into S_i B_i S_i, S_i = diag(exp(o_i / 2)); for every edge it
+ * predicts 15 coefficients of the rotation-covariant 11x11 maps that a pair
+ * direction allows, giving the initial guess
+ *   x0_i = S_i B_i S_i b_i + sum_j sigma_i * Q(c_ij, u_ij) (sigma_j * b_j),
+ * sigma = sqrt(diag B). Node features: degree, neighbour crowding, size
+ * ratios; edge features: r/(a_i+a_j), its inverse powers, log(a_j/a_i),
+ * a_j/(a_i+a_j). Hidden width 64. Dense layers run on the matrix cores with
+ * BF16 operands and FP32 accumulation; the initial guess and the rescaled
+ * blocks are FP64. Training minimises the relative residual of the guess,
+ * ||b' - A x0||^2 / ||b'||^2, over far-field problems (configuration and
+ * right-hand side), with the method's own product supplying A.
+ * A network object lives on one device; it holds FP32 master weights, their
+ * BF16 copies, the Adam moments and the activations of the last
+ * configuration it saw. Not thread safe. */
+typedef struct seasd_net_s* seasd_net;
+
+/* Create a network on `device` with random weights from `seed` (uniform
+ * He-style ranges, zero biases, output layers scaled by 0.01 so that a fresh
+ * network reproduces the block-diagonal preconditioner closely). */
+int seasd_net_create(seasd_net* net, int32_t device, uint64_t seed);
+int seasd_net_destroy(seasd_net net);
+
+/* Number of FP32 parameters (the flat layout: W_in[16][64], b_in[64], then
+ * per layer W_uv[64][128], W_e[16][64], b_a[64], W_m[64][64], b_m[64],
+ * W_h[128][64], b_h[64], then W_o[64][16], b_o[16], W_c[64][16], b_c[16];
+ * weights row-major as [fan_in][fan_out]). */
+int64_t seasd_net_param_count(void);
+
+/* Copy the FP32 master weights to / from a host array of exactly
+ * seasd_net_param_count() floats (set also refreshes the BF16 copies). */
+int seasd_net_get_params(seasd_net net, float* host, int64_t count);
+int seasd_net_set_params(seasd_net net, const float* host, int64_t count);
+
+/* Weights file: magic "SEASDNET", version 1, parameter count, Adam step, FP32
+ * weights and both Adam moments, FNV-1a 64-bit checksum of all preceding
+ * bytes. load returns SEASD_E_FORMAT for a missing, truncated, mismatched or
+ * corrupt file and leaves the network unchanged. */
+int seasd_net_save(seasd_net net, const char* path);
+int seasd_net_load(seasd_net net, const char* path);
+
+/* One configuration and 1 <= nrhs <= 4096 right-hand sides:
+ *   b      device [nrhs][n][12] right-hand sides (trace component ignored)
+ *   x0     device [nrhs][n][12] initial guesses out (trace 0), or NULL
+ *   loss   host, or NULL: the training loss, the mean over right-hand sides
+ *          of ||b' - A x0||^2 / ||b'||^2, with b' the incompressible
+ *          components of b and A the 11x11 incompressible block of M
+ *          applied by this library's own product (the handle's
+ *          configuration); the relative residual is what GMRES reduces
+ *   grad   host [seasd_net_param_count()] gradient of the loss, or NULL
+ * The gradient with respect to x0 is -2 A (b' - A x0) / (nrhs ||b'||^2), so
+ * each right-hand side costs two products when loss or grad is asked for.
+ * The block-diagonal blocks are built as in seasd_solve_farfield.
+ * Synchronises. Errors as seasd_solve_farfield, and SEASD_E_CUTOFF when
+ * 8 a_max >= L (edge cut-off beyond half the cell). */
+int seasd_net_loss_grad(seasd_handle handle, seasd_net net, int64_t n, const double* pos, const double* radius,
+                        const double* box, int32_t nrhs, const double* b, double* x0, double* loss, float* grad,
+                        void* stream);
+
+/* Loss and gradient as above followed by one Adam step (beta 0.9 / 0.999,
+ * eps 1e-8, learning rate lr) on the device. */
+int seasd_net_train_step(seasd_handle handle, seasd_net net, int64_t n, const double* pos, const double* radius,
+                         const double* box, int32_t nrhs, const double* b, float lr, double* loss, void* stream);
+
+/* Attach a network for solves with precond = SEASD_PRECOND_LEARNED or
+ * SEASD_PRECOND_LEARNED_GUESS (NULL detaches; the handle does not own it).
+ * Such a solve builds the graph, runs the network once and starts GMRES from
+ * the network's x0 (overwriting the caller's guess); with
+ * SEASD_PRECOND_LEARNED it also replaces the block-diagonal blocks by S B S,
+ * with SEASD_PRECOND_LEARNED_GUESS it keeps them. It falls
+ * back to the block-diagonal blocks and a zero guess, and returns
+ * SEASD_W_PRECOND_FALLBACK if the solve otherwise converged, when an output
+ * is non-finite or a scaling is beyond e^8; and it drops the guess (zero
+ * start, guess_used = 0) when its true residual exceeds ||b'||. */
+int seasd_precond_attach(seasd_handle handle, seasd_net net);
+
+/* Load a weights file into a network owned by the handle and attach it. */
+int seasd_precond_load(seasd_handle handle, const char* path);
 
 /* Short description of a return code (static storage). */
 const char* seasd_error_string(int32_t code);

@@ -31,7 +31,10 @@ Definitions (edges i -> j, i != j, minimum image, |r_ij| < 2 (a_i + a_j)):
   c_ij   = m_ij W_c + b_c (c_ij[0:15]: coefficients of the 15 structures)
   sigma_i[c] = sqrt(B_i[c, c]),  s_i[c] = exp(o_i[group(c)] / 2)  (c < 11)
   x0_i   = s_i * B_i (s_i * b_i) + sum_j sigma_i * (sum_k c_ijk T_k(u_ij)) (sigma_j * b_j)
-  loss   = mean over (rhs, i, c < 11) of ((x0 - x*) / sigma^2)^2
+  loss   = mean over right-hand sides of ||b' - A x0||^2 / ||b'||^2 (the
+           relative residual of the guess, A the 11x11 incompressible block
+           of the mobility); an error loss against solutions x*,
+           mean ((x0 - x*) / sigma^2)^2, is also provided
 The T_k are the 15 rotation-covariant 11x11 maps between (F, T, S) and
 (U, Omega, E) that a direction u allows (structures()).
 """
@@ -188,38 +191,73 @@ def forward(theta, fn, fe, g, bf=True):
     return act
 
 
-def x0_and_loss(o, c, g, Binv, b, xstar=None):
-    """x0 for every right-hand side and, with x*, the loss and its gradient
-    with respect to o and c. Binv: [n, 12, 12]; b, x*: [nrhs, n, 12]."""
-    n = g["n"]
-    src, dst = g["src"], g["dst"]
+def _pieces(o, c, g, Binv):
     B = Binv[:, :11, :11]
     sig = np.sqrt(np.einsum("ncc->nc", B))
     s = np.exp(0.5 * o[:, GROUP])                          # [n, 11]
-    Tk = np.stack([structures(u) for u in g["u"]]) if len(src) else np.zeros((0, 15, 11, 11))
+    Tk = np.stack([structures(u) for u in g["u"]]) if len(g["src"]) else np.zeros((0, 15, 11, 11))
+    return B, sig, s, Tk
+
+
+def x0_apply(o, c, g, Binv, b):
+    """x0 for every right-hand side; Binv: [n, 12, 12]; b: [nrhs, n, 12]."""
+    src, dst = g["src"], g["dst"]
+    B, sig, s, Tk = _pieces(o, c, g, Binv)
     Q = np.einsum("ek,ekab->eab", c[:, :15], Tk)           # [E, 11, 11]
-    nrhs = b.shape[0]
-    x0 = np.zeros((nrhs, n, 12))
-    loss, do, dc = 0.0, np.zeros_like(o), np.zeros_like(c)
-    cnt = nrhs * n * 11
-    for q in range(nrhs):
+    x0 = np.zeros(b.shape[:2] + (12,))
+    for q in range(b.shape[0]):
         bq = b[q, :, :11]
-        Bsb = np.einsum("nab,nb->na", B, s * bq)
-        y = s * Bsb
-        wj = sig[dst] * bq[dst]
-        y_e = sig[src] * np.einsum("eab,eb->ea", Q, wj)
+        y = s * np.einsum("nab,nb->na", B, s * bq)
+        y_e = sig[src] * np.einsum("eab,eb->ea", Q, sig[dst] * bq[dst])
         np.add.at(y, src, y_e)
         x0[q, :, :11] = y
-        if xstar is None:
-            continue
-        eps = (y - xstar[q, :, :11]) / sig ** 2
-        loss += float((eps ** 2).sum()) / cnt
-        gq = 2.0 * eps / sig ** 2 / cnt                    # dL/dx0
+    return x0
+
+
+def x0_vjp(o, c, g, Binv, b, gx):
+    """Gradients with respect to o and c of sum(gx * x0)."""
+    src, dst = g["src"], g["dst"]
+    B, sig, s, Tk = _pieces(o, c, g, Binv)
+    do, dc = np.zeros_like(o), np.zeros_like(c)
+    for q in range(b.shape[0]):
+        bq, gq = b[q, :, :11], gx[q, :, :11]
+        Bsb = np.einsum("nab,nb->na", B, s * bq)
         dLds = gq * Bsb + bq * np.einsum("nba,nb->na", B, s * gq)
         np.add.at(do.T, GROUP, (0.5 * s * dLds).T)
-        t = sig[src] * gq[src]
-        dc[:, :15] += np.einsum("ea,ekab,eb->ek", t, Tk, wj)
-    return x0, loss, do, dc
+        dc[:, :15] += np.einsum("ea,ekab,eb->ek", sig[src] * gq[src], Tk, sig[dst] * bq[dst])
+    return do, dc
+
+
+def x0_and_loss(o, c, g, Binv, b, xstar=None):
+    """x0 and, with x*, the error loss mean(((x0 - x*) / sigma^2)^2) and its
+    gradient with respect to o and c."""
+    x0 = x0_apply(o, c, g, Binv, b)
+    if xstar is None:
+        return x0, 0.0, np.zeros_like(o), np.zeros_like(c)
+    sig2 = np.einsum("ncc->nc", Binv[:, :11, :11])
+    cnt = b.shape[0] * g["n"] * 11
+    eps = (x0[..., :11] - xstar[..., :11]) / sig2
+    gx = np.zeros_like(x0)
+    gx[..., :11] = 2.0 * eps / sig2 / cnt
+    do, dc = x0_vjp(o, c, g, Binv, b, gx)
+    return x0, float((eps ** 2).sum()) / cnt, do, dc
+
+
+def residual_loss(x0, b, Aop):
+    """mean over right-hand sides of ||b' - A x0||^2 / ||b'||^2 (b' = b on the
+    11 incompressible components) and its gradient with respect to x0 (A
+    symmetric). Aop maps [n, 12] (trace ignored) to [n, 11]."""
+    nrhs = b.shape[0]
+    loss, gx = 0.0, np.zeros_like(x0)
+    for q in range(nrhs):
+        bq = b[q, :, :11]
+        nb2 = float((bq ** 2).sum())
+        r = bq - Aop(x0[q])
+        loss += float((r ** 2).sum()) / nb2 / nrhs
+        rr = np.zeros_like(x0[q])
+        rr[:, :11] = r
+        gx[q, :, :11] = -2.0 * Aop(rr) / nb2 / nrhs
+    return loss, gx
 
 
 def backward(theta, fn, fe, g, act, do, dc, bf=True):
@@ -258,11 +296,25 @@ def backward(theta, fn, fe, g, act, do, dc, bf=True):
 
 
 def loss_grad(theta, pos, rad, L, Binv, b, xstar, bf=True):
-    """Loss, flat gradient and x0 for one configuration and nrhs pairs (b, x*)."""
+    """Error loss, flat gradient and x0 for one configuration and nrhs pairs
+    (b, x*)."""
     g = graph(pos, rad, L)
     fn, fe = features(g, rad)
     act = forward(theta, fn, fe, g, bf)
     x0, loss, do, dc = x0_and_loss(act["o"], act["c"], g, Binv, b, xstar)
+    grad = backward(theta, fn, fe, g, act, do, dc, bf)
+    return loss, grad, x0
+
+
+def residual_loss_grad(theta, pos, rad, L, Binv, b, Aop, bf=True):
+    """The training loss: relative residual of the guess, mean over right-hand
+    sides of ||b' - A x0||^2 / ||b'||^2, its flat gradient and x0."""
+    g = graph(pos, rad, L)
+    fn, fe = features(g, rad)
+    act = forward(theta, fn, fe, g, bf)
+    x0 = x0_apply(act["o"], act["c"], g, Binv, b)
+    loss, gx = residual_loss(x0, b, Aop)
+    do, dc = x0_vjp(act["o"], act["c"], g, Binv, b, gx)
     grad = backward(theta, fn, fe, g, act, do, dc, bf)
     return loss, grad, x0
 

@@ -10,42 +10,11 @@
 
 #include "../../include/seasd.h"
 #include "seasd_internal.h"
+#include "seasd_learn.h"
 #include "seasd_math.h"
 
 using namespace seasd;
 
-namespace {
-
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    int ensure(size_t need) {
-        if (need <= bytes) return 0;
-        if (p) {
-            hipDeviceSynchronize();  // queued work may still read the old buffer
-            hipFree(p);
-        }
-        p = nullptr;
-        bytes = 0;
-        if (hipMalloc(&p, need) != hipSuccess) {
-            p = nullptr;
-            return SEASD_E_NOMEM;
-        }
-        bytes = need;
-        return 0;
-    }
-    void release() {
-        if (p) hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    template <typename T>
-    T* as() const {
-        return static_cast<T*>(p);
-    }
-};
-
-}  // namespace
 
 struct seasd_handle_s {
     int device = 0;
@@ -59,6 +28,14 @@ struct seasd_handle_s {
     int twiddle_M = 0;
     // solver workspace
     DevBuf V, w, z, u, r, bred, hdev, partial, blocks, inv, coef, singular, one_pos, one_rad, one_x, one_y;
+    // block-diagonal fit cache: (a_min, a_max, L, grid, P, m, xi, rc_factor, eta, precision, tile)
+    double pc_key[11] = {0};
+    bool pc_valid = false;
+    double pc_amax = 0.0;
+    // learned preconditioner
+    seasd_net net = nullptr;       // attached (not owned)
+    seasd_net own_net = nullptr;   // loaded by seasd_precond_load
+    DevBuf inv2, bad, lx0, lg, lb, lax, lres;
     PhaseTimer timer;
     hipStream_t last_stream = nullptr;
 };
@@ -76,7 +53,9 @@ extern "C" const char* seasd_error_string(int32_t code) {
         case SEASD_E_HIP: return "HIP runtime error";
         case SEASD_E_NOMEM: return "device allocation failed";
         case SEASD_E_UNSUPPORTED: return "unsupported request (only cubic cells)";
+        case SEASD_E_FORMAT: return "weights file missing, mismatched or failing its checksum";
         case SEASD_W_NOT_CONVERGED: return "solve did not reach the tolerance";
+        case SEASD_W_PRECOND_FALLBACK: return "learned preconditioner rejected, block-diagonal used";
         default: return "unknown code";
     }
 }
@@ -124,8 +103,10 @@ extern "C" int seasd_destroy(seasd_handle h) {
                       &h->sp, &h->sa, &h->sx, &h->ybuf, &h->rgrid, &h->spec, &h->twiddle,
                       &h->ncount, &h->maxcount, &h->list, &h->total, &h->wrec, &h->scan_tmp,
                       &h->V, &h->w, &h->z, &h->u, &h->r, &h->bred, &h->hdev, &h->partial, &h->blocks,
-                      &h->inv, &h->coef, &h->singular, &h->one_pos, &h->one_rad, &h->one_x, &h->one_y};
+                      &h->inv, &h->coef, &h->singular, &h->one_pos, &h->one_rad, &h->one_x, &h->one_y,
+                      &h->inv2, &h->bad, &h->lx0, &h->lg, &h->lb, &h->lax, &h->lres};
     for (DevBuf* b : bufs) b->release();
+    if (h->own_net) seasd_net_destroy(h->own_net);
     h->timer.destroy();
     delete h;
     return SEASD_OK;
@@ -145,7 +126,7 @@ extern "C" int seasd_set_config(seasd_handle h, const seasd_config* c) {
     if (c->parts < 0 || c->parts > SEASD_PARTS_ALL) return SEASD_E_INVALID_ARG;
     if (c->restart < 1 || c->restart > 200 || c->max_iter < 1) return SEASD_E_INVALID_ARG;
     if (!(c->tol > 0.0)) return SEASD_E_INVALID_ARG;
-    if (c->precond != SEASD_PRECOND_NONE && c->precond != SEASD_PRECOND_BLOCKDIAG) return SEASD_E_INVALID_ARG;
+    if (c->precond < SEASD_PRECOND_NONE || c->precond > SEASD_PRECOND_LEARNED_GUESS) return SEASD_E_INVALID_ARG;
     h->cfg = *c;
     h->have_cfg = true;
     return SEASD_OK;
@@ -386,52 +367,62 @@ static int build_preconditioner(seasd_handle h, int64_t n, const double* radius,
         amin = std::fmin(amin, a);
         amax = std::fmax(amax, a);
     }
-    double samp[3] = {amin, 0.5 * (amin + amax), amax};
-    if (amax - amin < 1e-3 * amax) {
-        samp[0] = amin;
-        samp[1] = 1.25 * amin;
-        samp[2] = 1.5 * amin;
-    }
-    const double zero3[3] = {0.0, 0.0, 0.0};
-    if (hipMemcpy(h->one_pos.p, zero3, sizeof(zero3), hipMemcpyHostToDevice) != hipSuccess) return SEASD_E_HIP;
-    double Q[3][144];
-    const double eta = h->cfg.eta;
-    for (int s = 0; s < 3; ++s) {
-        if (hipMemcpy(h->one_rad.p, &samp[s], sizeof(double), hipMemcpyHostToDevice) != hipSuccess) return SEASD_E_HIP;
-        for (int b = 0; b < 12; ++b) {
-            double e[12] = {0};
-            e[b] = 1.0;
-            if (hipMemcpyAsync(h->one_x.p, e, sizeof(e), hipMemcpyHostToDevice, st) != hipSuccess) return SEASD_E_HIP;
-            rc = queue_apply(h, 1, h->one_pos.as<double>(), h->one_rad.as<double>(), L, h->one_x.as<double>(),
-                             h->one_y.as<double>(), st, false);
-            if (rc) return rc;
-            double col[12];
-            if (hipMemcpyAsync(col, h->one_y.p, sizeof(col), hipMemcpyDeviceToHost, st) != hipSuccess) return SEASD_E_HIP;
-            if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
-            for (int r = 0; r < 12; ++r) Q[s][12 * r + b] = col[r];
+    h->pc_amax = amax;
+    const seasd_config& cf = h->cfg;
+    const double key[11] = {amin, amax, L, (double)cf.grid, (double)cf.P, cf.m, cf.xi, cf.rc_factor, cf.eta,
+                            (double)cf.precision, (double)cf.tile};
+    const bool cached = h->pc_valid && std::memcmp(key, h->pc_key, sizeof(key)) == 0;
+    if (!cached) {
+        h->pc_valid = false;
+        double samp[3] = {amin, 0.5 * (amin + amax), amax};
+        if (amax - amin < 1e-3 * amax) {
+            samp[0] = amin;
+            samp[1] = 1.25 * amin;
+            samp[2] = 1.5 * amin;
         }
-        const double a = samp[s], a3 = a * a * a;
-        for (int c = 0; c < 3; ++c) Q[s][13 * c] -= 1.0 / (6.0 * kPi * eta * a);
-        for (int c = 3; c < 6; ++c) Q[s][13 * c] -= 1.0 / (8.0 * kPi * eta * a3);
-        for (int c = 6; c < 11; ++c) Q[s][13 * c] -= 3.0 / (20.0 * kPi * eta * a3);
-        Q[s][13 * 11] -= 3.0 / (16.0 * kPi * eta * a3);
-    }
-    // Q(A) = C0 + C1 A + C2 A^2 through the three samples (Lagrange form)
-    double A[3] = {samp[0] * samp[0], samp[1] * samp[1], samp[2] * samp[2]};
-    std::vector<double> coef(3 * 144, 0.0);
-    for (int s = 0; s < 3; ++s) {
-        const int p = (s + 1) % 3, q = (s + 2) % 3;
-        const double den = (A[s] - A[p]) * (A[s] - A[q]);
-        const double l0 = A[p] * A[q] / den, l1 = -(A[p] + A[q]) / den, l2 = 1.0 / den;
-        for (int e = 0; e < 144; ++e) {
-            coef[e] += l0 * Q[s][e];
-            coef[144 + e] += l1 * Q[s][e];
-            coef[288 + e] += l2 * Q[s][e];
+        const double zero3[3] = {0.0, 0.0, 0.0};
+        if (hipMemcpy(h->one_pos.p, zero3, sizeof(zero3), hipMemcpyHostToDevice) != hipSuccess) return SEASD_E_HIP;
+        double Q[3][144];
+        const double eta = h->cfg.eta;
+        for (int s = 0; s < 3; ++s) {
+            if (hipMemcpy(h->one_rad.p, &samp[s], sizeof(double), hipMemcpyHostToDevice) != hipSuccess) return SEASD_E_HIP;
+            for (int b = 0; b < 12; ++b) {
+                double e[12] = {0};
+                e[b] = 1.0;
+                if (hipMemcpyAsync(h->one_x.p, e, sizeof(e), hipMemcpyHostToDevice, st) != hipSuccess) return SEASD_E_HIP;
+                rc = queue_apply(h, 1, h->one_pos.as<double>(), h->one_rad.as<double>(), L, h->one_x.as<double>(),
+                                 h->one_y.as<double>(), st, false);
+                if (rc) return rc;
+                double col[12];
+                if (hipMemcpyAsync(col, h->one_y.p, sizeof(col), hipMemcpyDeviceToHost, st) != hipSuccess) return SEASD_E_HIP;
+                if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
+                for (int r = 0; r < 12; ++r) Q[s][12 * r + b] = col[r];
+            }
+            const double a = samp[s], a3 = a * a * a;
+            for (int c = 0; c < 3; ++c) Q[s][13 * c] -= 1.0 / (6.0 * kPi * eta * a);
+            for (int c = 3; c < 6; ++c) Q[s][13 * c] -= 1.0 / (8.0 * kPi * eta * a3);
+            for (int c = 6; c < 11; ++c) Q[s][13 * c] -= 3.0 / (20.0 * kPi * eta * a3);
+            Q[s][13 * 11] -= 3.0 / (16.0 * kPi * eta * a3);
         }
+        // Q(A) = C0 + C1 A + C2 A^2 through the three samples (Lagrange form)
+        double A[3] = {samp[0] * samp[0], samp[1] * samp[1], samp[2] * samp[2]};
+        std::vector<double> coef(3 * 144, 0.0);
+        for (int s = 0; s < 3; ++s) {
+            const int p = (s + 1) % 3, q = (s + 2) % 3;
+            const double den = (A[s] - A[p]) * (A[s] - A[q]);
+            const double l0 = A[p] * A[q] / den, l1 = -(A[p] + A[q]) / den, l2 = 1.0 / den;
+            for (int e = 0; e < 144; ++e) {
+                coef[e] += l0 * Q[s][e];
+                coef[144 + e] += l1 * Q[s][e];
+                coef[288 + e] += l2 * Q[s][e];
+            }
+        }
+        if (hipMemcpy(h->coef.p, coef.data(), sizeof(double) * 3 * 144, hipMemcpyHostToDevice) != hipSuccess)
+            return SEASD_E_HIP;
+        std::memcpy(h->pc_key, key, sizeof(key));
+        h->pc_valid = true;
     }
-    if (hipMemcpy(h->coef.p, coef.data(), sizeof(double) * 3 * 144, hipMemcpyHostToDevice) != hipSuccess)
-        return SEASD_E_HIP;
-    if (launch_build_blocks(n, radius, h->coef.as<double>(), h->cfg.xi, eta, h->blocks.as<double>(), st))
+    if (launch_build_blocks(n, radius, h->coef.as<double>(), h->cfg.xi, h->cfg.eta, h->blocks.as<double>(), st))
         return SEASD_E_HIP;
     if (hipMemsetAsync(h->singular.p, 0, sizeof(int), st) != hipSuccess) return SEASD_E_HIP;
     if (launch_block_invert(n, h->blocks.as<double>(), h->inv.as<double>(), h->singular.as<int>(), st))
@@ -448,6 +439,60 @@ static int dot_host(seasd_handle h, int64_t len, int k, const double* V, int64_t
     if (hipMemcpyAsync(out_host, h->hdev.p, sizeof(double) * k, hipMemcpyDeviceToHost, st) != hipSuccess)
         return SEASD_E_HIP;
     return hip_ok(hipStreamSynchronize(st));
+}
+
+// Binning of the given configuration into the product workspace (no
+// neighbour list: the next product rebuilds its geometry). x: any valid
+// [n][12] array (gathered along, unused).
+static int prepare_geometry(seasd_handle h, int64_t n, const double* pos, const double* radius, double L,
+                            const double* x, hipStream_t st, ApplyArgs& A) {
+    int rc = ensure_product_ws(h, n);
+    if (rc) return rc;
+    fill_args(h, A, n, pos, radius, L, x, nullptr, h->cfg.checks != 0, 0);
+    if (hipMemsetAsync(A.err, 0, sizeof(int), st) != hipSuccess) return SEASD_E_HIP;
+    PhaseTimer off;
+    h->geom_n = -1;
+    if (launch_geometry(A, st, &off)) return SEASD_E_HIP;
+    if (h->cfg.checks) return read_err(h, st);
+    return SEASD_OK;
+}
+
+// Learned part of a solve or a training step: graph and forward pass of the
+// attached network on the binned configuration in A.
+static int learned_forward(seasd_handle h, seasd_net net, double L, const ApplyArgs& A, hipStream_t st) {
+    if (net_device(net) != h->device) return SEASD_E_INVALID_ARG;
+    if (!(L > 4.0 * kEdgeCut * h->pc_amax)) return SEASD_E_CUTOFF;   // edges reach below L/2
+    if (hipMemsetAsync(A.err, 0, sizeof(int), st) != hipSuccess) return SEASD_E_HIP;
+    int rc = net_build_graph(net, A, st);
+    if (rc) return rc;
+    if ((rc = read_err(h, st))) return rc;   // a missing reverse edge reads as a cut-off failure
+    return net_forward(net, st);
+}
+
+// Rescaled blocks into h->inv2 and the initial guess x0 for b; *fallback = 1
+// when the network output is rejected.
+static int learned_setup(seasd_handle h, int64_t n, const double* pos, const double* radius, double L,
+                         const double* b, double* x0, bool geometry_current, hipStream_t st, int* fallback) {
+    ApplyArgs A;
+    int rc;
+    if (geometry_current) {
+        fill_args(h, A, n, pos, radius, L, b, nullptr, false, 0);
+    } else if ((rc = prepare_geometry(h, n, pos, radius, L, b, st, A))) {
+        return rc;
+    }
+    if ((rc = learned_forward(h, h->net, L, A, st))) return rc;
+    if (h->inv2.ensure(sizeof(double) * 144 * n) || h->bad.ensure(sizeof(int))) return SEASD_E_NOMEM;
+    if (hipMemsetAsync(h->bad.p, 0, sizeof(int), st) != hipSuccess) return SEASD_E_HIP;
+    if ((rc = net_learned_blocks(h->net, h->inv.as<double>(), h->perm.as<int>(), h->inv2.as<double>(),
+                                 h->bad.as<int>(), st)))
+        return rc;
+    if ((rc = net_x0(h->net, h->inv.as<double>(), h->perm.as<int>(), 1, b, nullptr, x0, st))) return rc;
+    if ((rc = check_finite(12 * n, x0, h->bad.as<int>(), st))) return rc;
+    int bad = 0;
+    if (hipMemcpyAsync(&bad, h->bad.p, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return SEASD_E_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
+    *fallback = bad ? 1 : 0;
+    return SEASD_OK;
 }
 
 extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos, const double* radius,
@@ -480,7 +525,9 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
     double* u = h->u.as<double>();
     double* r = h->r.as<double>();
     double* bred = h->bred.as<double>();
-    const bool pc = c.precond == SEASD_PRECOND_BLOCKDIAG;
+    const bool pc = c.precond != SEASD_PRECOND_NONE;
+    const bool learned = c.precond == SEASD_PRECOND_LEARNED || c.precond == SEASD_PRECOND_LEARNED_GUESS;
+    if (learned && !h->net) return SEASD_E_INVALID_ARG;
     if (pc) {  // before the geometry: its single-sphere products use the shared workspace
         rc = build_preconditioner(h, n, radius, L, st);
         if (rc) return rc;
@@ -496,9 +543,10 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
         ++S.matvecs;
         return chk ? read_err(h, st) : SEASD_OK;
     };
+    const double* pc_blocks = h->inv.as<double>();
     auto precond = [&](const double* in, double* out) -> int {
         if (!pc) return hip_ok(hipMemcpyAsync(out, in, sizeof(double) * len, hipMemcpyDeviceToDevice, st));
-        return launch_block_apply(n, h->inv.as<double>(), in, out, st) ? SEASD_E_HIP : SEASD_OK;
+        return launch_block_apply(n, pc_blocks, in, out, st) ? SEASD_E_HIP : SEASD_OK;
     };
     // One-way pressure-moment coupling (Sec. 2.3 and 4.1): only the part of
     // each pressure moment fixed by its own trace equation, s_self = b_trace /
@@ -515,10 +563,25 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
         if (hipMemsetAsync(w, 0, sizeof(double) * len, st) != hipSuccess) return SEASD_E_HIP;
         if (launch_trace_op(n, 1, radius, c.eta, b, w, bred, st)) return SEASD_E_HIP;
     }
+    // learned preconditioner: rescaled blocks and the network's initial guess
+    int fallback = 0, guess = 0;
+    if (learned) {
+        auto tl = std::chrono::steady_clock::now();
+        rc = learned_setup(h, n, pos, radius, L, bred, x, c.compressible != 0, st, &fallback);
+        if (rc) return rc;
+        if (fallback) {
+            if (hipMemsetAsync(x, 0, sizeof(double) * len, st) != hipSuccess) return SEASD_E_HIP;
+        } else {
+            if (c.precond == SEASD_PRECOND_LEARNED) pc_blocks = h->inv2.as<double>();
+            guess = 1;
+        }
+        S.setup_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tl).count();
+    }
     double bnorm2 = 0.0;
     rc = dot_host(h, len, 1, bred, len, bred, &bnorm2, st);
     if (rc) return rc;
     const double bnorm = std::sqrt(bnorm2);
+    bool first_cycle = true;
     std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), yv(m);
     bool first = true;
     double relres = 0.0;
@@ -537,6 +600,17 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
         if (rc) return rc;
         const double beta = std::sqrt(rn2);
         relres = beta / bnorm;
+        if (first_cycle) {
+            first_cycle = false;
+            S.initial_residual = relres;
+            if (guess && relres > 1.0) {   // the guess is worse than zero: drop it
+                guess = 0;
+                if (hipMemsetAsync(x, 0, sizeof(double) * len, st) != hipSuccess) return SEASD_E_HIP;
+                S.initial_residual = 1.0;
+                if (launch_axpby(len, 1.0, bred, 0.0, r, st)) return SEASD_E_HIP;
+                relres = 1.0;
+            }
+        }
         if (relres <= c.tol || total >= c.max_iter) break;
         if (launch_axpby(len, 1.0 / beta, r, 0.0, V, st)) return SEASD_E_HIP;
         std::fill(g.begin(), g.end(), 0.0);
@@ -617,8 +691,120 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
     S.true_residual = relres;
     S.converged = relres <= c.tol ? 1 : 0;
     S.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    S.precond_used = learned && !fallback ? c.precond : c.precond == SEASD_PRECOND_NONE ? 0 : 1;
+    S.guess_used = guess;
     if (stats) *stats = S;
-    return S.converged ? SEASD_OK : SEASD_W_NOT_CONVERGED;
+    if (!S.converged) return SEASD_W_NOT_CONVERGED;
+    return fallback ? SEASD_W_PRECOND_FALLBACK : SEASD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned preconditioner: attach, load, loss / gradient and training steps
+
+extern "C" int seasd_precond_attach(seasd_handle h, seasd_net net) {
+    if (!h) return SEASD_E_INVALID_ARG;
+    h->net = net;
+    return SEASD_OK;
+}
+
+extern "C" int seasd_precond_load(seasd_handle h, const char* path) {
+    if (!h || !path) return SEASD_E_INVALID_ARG;
+    seasd_net net = nullptr;
+    int rc = seasd_net_create(&net, h->device, 0);
+    if (rc) return rc;
+    if ((rc = seasd_net_load(net, path))) {
+        seasd_net_destroy(net);
+        return rc;
+    }
+    if (h->own_net) {
+        if (h->net == h->own_net) h->net = nullptr;
+        seasd_net_destroy(h->own_net);
+    }
+    h->own_net = net;
+    h->net = net;
+    return SEASD_OK;
+}
+
+// Network guess for nrhs right-hand sides and, when asked, the training loss
+// (mean relative residual ||b' - A x0||^2 / ||b'||^2 with the method's own
+// product), its gradient and an Adam step. The gradient with respect to x0 is
+// -2 A (b' - A x0) / (nrhs ||b'||^2) (A symmetric), so each right-hand side
+// costs two products.
+static int net_step(seasd_handle h, seasd_net net, int64_t n, const double* pos, const double* radius,
+                    const double* box, int32_t nrhs, const double* b, double* x0, double* loss, float* grad,
+                    bool adam, float lr, void* stream) {
+    if (!h || !net || n < 1 || n > (int64_t)1 << 26 || !pos || !radius || !b || nrhs < 1 || nrhs > 4096)
+        return SEASD_E_INVALID_ARG;
+    double L;
+    int rc = cubic_edge(box, &L);
+    if (rc) return rc;
+    if (hipSetDevice(h->device) != hipSuccess) return SEASD_E_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = build_preconditioner(h, n, radius, L, st))) return rc;
+    ApplyArgs A;
+    if ((rc = prepare_geometry(h, n, pos, radius, L, b, st, A))) return rc;
+    if ((rc = learned_forward(h, net, L, A, st))) return rc;
+    const int64_t len = 12 * n;
+    rc = 0;
+    rc |= h->lx0.ensure(sizeof(double) * len * nrhs);
+    rc |= h->lg.ensure(sizeof(double) * len * nrhs);
+    rc |= h->lb.ensure(sizeof(double) * len);
+    rc |= h->lax.ensure(sizeof(double) * len);
+    rc |= h->lres.ensure(sizeof(double) * len);
+    rc |= h->hdev.ensure(sizeof(double) * 256);
+    rc |= h->partial.ensure(sizeof(double) * 256 * 256);
+    if (rc) return SEASD_E_NOMEM;
+    double* X0 = h->lx0.as<double>();
+    double* G = h->lg.as<double>();
+    double* bq = h->lb.as<double>();
+    double* ax = h->lax.as<double>();
+    double* res = h->lres.as<double>();
+    const double* inv = h->inv.as<double>();
+    if ((rc = net_x0(net, inv, h->perm.as<int>(), nrhs, b, nullptr, X0, st))) return rc;
+    if (x0 && hipMemcpyAsync(x0, X0, sizeof(double) * len * nrhs, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return SEASD_E_HIP;
+    if (loss || grad || adam) {
+        double total = 0.0;
+        bool geometry = false;
+        for (int q = 0; q < nrhs; ++q) {
+            // b' (trace dropped), r = b' - A x0, g = -2 A r / (nrhs |b'|^2)
+            if (launch_trace_op(n, 1, radius, h->cfg.eta, b + q * len, nullptr, bq, st)) return SEASD_E_HIP;
+            if ((rc = queue_apply(h, n, pos, radius, L, X0 + q * len, ax, st, false, geometry, 0))) return rc;
+            geometry = true;
+            if (launch_axpby(len, 1.0, bq, 0.0, res, st) || launch_axpby(len, -1.0, ax, 1.0, res, st))
+                return SEASD_E_HIP;
+            double rr = 0.0, bb = 0.0;
+            if ((rc = dot_host(h, len, 1, res, len, res, &rr, st))) return rc;
+            if ((rc = dot_host(h, len, 1, bq, len, bq, &bb, st))) return rc;
+            if (!(bb > 0.0)) return SEASD_E_INVALID_ARG;
+            total += rr / bb / nrhs;
+            if (grad || adam) {
+                if ((rc = queue_apply(h, n, pos, radius, L, res, ax, st, false, true, 0))) return rc;
+                if (launch_axpby(len, -2.0 / (nrhs * bb), ax, 0.0, G + q * len, st)) return SEASD_E_HIP;
+            }
+        }
+        if (loss) *loss = total;
+        if (grad || adam) {
+            if ((rc = net_x0(net, inv, h->perm.as<int>(), nrhs, b, G, nullptr, st))) return rc;
+            if ((rc = net_backward(net, st))) return rc;
+            if (grad && (rc = net_grads_to_host(net, grad, seasd_net_param_count(), st))) return rc;
+            if (adam && (rc = net_adam(net, lr, st))) return rc;
+        }
+    }
+    return hip_ok(hipStreamSynchronize(st));
+}
+
+extern "C" int seasd_net_loss_grad(seasd_handle h, seasd_net net, int64_t n, const double* pos, const double* radius,
+                                   const double* box, int32_t nrhs, const double* b, double* x0, double* loss,
+                                   float* grad, void* stream) {
+    return net_step(h, net, n, pos, radius, box, nrhs, b, x0, loss, grad, false, 0.f, stream);
+}
+
+extern "C" int seasd_net_train_step(seasd_handle h, seasd_net net, int64_t n, const double* pos,
+                                    const double* radius, const double* box, int32_t nrhs, const double* b, float lr,
+                                    double* loss, void* stream) {
+    if (!(lr > 0.f) || !std::isfinite(lr)) return SEASD_E_INVALID_ARG;
+    return net_step(h, net, n, pos, radius, box, nrhs, b, nullptr, loss, nullptr, true, lr, stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -69,6 +69,36 @@ struct PhaseTimer {
     }
 };
 
+// device buffer that only grows
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t need) {   // 0, or -7 (SEASD_E_NOMEM) when the allocation fails
+        if (need <= bytes) return 0;
+        if (p) {
+            hipDeviceSynchronize();  // queued work may still read the old buffer
+            hipFree(p);
+        }
+        p = nullptr;
+        bytes = 0;
+        if (hipMalloc(&p, need) != hipSuccess) {
+            p = nullptr;
+            return -7;
+        }
+        bytes = need;
+        return 0;
+    }
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T* as() const {
+        return static_cast<T*>(p);
+    }
+};
+
 struct ApplyArgs {
     int64_t n;
     const double* pos;
@@ -118,5 +148,13 @@ int launch_trace_op(int64_t n, int mode, const double* radius, double eta, const
                     double* out, hipStream_t st);
 int launch_build_blocks(int64_t n, const double* radius, const double* coef, double xi, double eta,
                         double* blocks, hipStream_t st);
+
+// neighbour graph of the learned preconditioner (seasd_kernels.hip): edges
+// s -> j between binned spheres with |r| < cut (a_s + a_j). Count pass: deg
+// and rowptr (n + 1 entries, exclusive scan); fill pass: edge arrays, reverse
+// edge index, edge and node features (16 floats each).
+int launch_edge_count(const ApplyArgs& a, double cut, int* deg, int* rowptr, hipStream_t st);
+int launch_edge_fill(const ApplyArgs& a, double cut, const int* rowptr, int* esrc, int* edst, int* erev,
+                     float4* geo, float* fe, float* fn, hipStream_t st);
 
 }  // namespace seasd

@@ -374,6 +374,91 @@ __global__ __launch_bounds__(128) void k_pair_eval(int n, const double* __restri
 }
 
 // ---------------------------------------------------------------------------
+// neighbour graph of the learned preconditioner: directed edges s -> j between
+// binned spheres closer than cut (a_s + a_j), rows in binned order, each row
+// in the (deterministic) visiting order of for_each_neighbour
+
+__global__ __launch_bounds__(256) void k_edge_count(int n, const double* __restrict__ sp,
+                                                    const double* __restrict__ sa, const int* __restrict__ start,
+                                                    int nb, double L, double binw, double cut,
+                                                    const unsigned long long* __restrict__ amax_bits,
+                                                    int* __restrict__ deg, int* __restrict__ err) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const double amax = __longlong_as_double((long long)*amax_bits);
+    int k = 0;
+    for_each_neighbour(s, sp, sa, start, nb, L, binw, cut, amax, 0, err, [&](int, int) { ++k; });
+    deg[s] = k;
+}
+
+__global__ __launch_bounds__(256) void k_edge_fill(int n, const double* __restrict__ sp,
+                                                   const double* __restrict__ sa, const int* __restrict__ start,
+                                                   int nb, double L, double binw, double cut,
+                                                   const unsigned long long* __restrict__ amax_bits,
+                                                   const int* __restrict__ rowptr, int* __restrict__ esrc,
+                                                   int* __restrict__ edst, float4* __restrict__ geo,
+                                                   float* __restrict__ fe, int* __restrict__ err) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const double amax = __longlong_as_double((long long)*amax_bits);
+    const double px = sp[3 * s], py = sp[3 * s + 1], pz = sp[3 * s + 2], ai = sa[s];
+    int e = rowptr[s];
+    const int e1 = rowptr[s + 1];
+    for_each_neighbour(s, sp, sa, start, nb, L, binw, cut, amax, 0, err, [&](int j, int code) {
+        if (e >= e1) return;   // the count pass bounds the row
+        const int wx = (code & 1023) - 512, wy = ((code >> 10) & 1023) - 512, wz = ((code >> 20) & 1023) - 512;
+        const double dx = sp[3 * j] + wx * L - px, dy = sp[3 * j + 1] + wy * L - py, dz = sp[3 * j + 2] + wz * L - pz;
+        const double r = sqrt(dx * dx + dy * dy + dz * dz), aj = sa[j];
+        const double rho = r / (ai + aj);
+        esrc[e] = s;
+        edst[e] = j;
+        geo[e] = make_float4((float)(dx / r), (float)(dy / r), (float)(dz / r), (float)r);
+        float* f = fe + 16 * (size_t)e;
+        f[0] = (float)rho;
+        f[1] = (float)(1.0 / rho);
+        f[2] = (float)(1.0 / (rho * rho * rho));
+        f[3] = (float)log(aj / ai);
+        f[4] = (float)(aj / (ai + aj));
+        for (int k = 5; k < 16; ++k) f[k] = 0.f;
+        ++e;
+    });
+}
+
+// reverse edge (j -> s) of every edge s -> j, and the node features
+__global__ __launch_bounds__(256) void k_edge_rev(int n, const double* __restrict__ sa, const int* __restrict__ rowptr,
+                                                  const int* __restrict__ edst, const float4* __restrict__ geo,
+                                                  int* __restrict__ erev, float* __restrict__ fn,
+                                                  int* __restrict__ err) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int e0 = rowptr[s], e1 = rowptr[s + 1];
+    const double ai = sa[s];
+    double sr3 = 0.0, sl3 = 0.0, slog = 0.0;
+    for (int e = e0; e < e1; ++e) {
+        const int j = edst[e];
+        int rev = -1;
+        for (int q = rowptr[j]; q < rowptr[j + 1]; ++q)
+            if (edst[q] == s) {
+                rev = q;
+                break;
+            }
+        if (rev < 0) atomicOr(err, kErrCutoff);
+        erev[e] = rev < 0 ? e : rev;
+        const double aj = sa[j], rho = (double)geo[e].w / (ai + aj), lam = aj / ai;
+        sr3 += 1.0 / (rho * rho * rho);
+        sl3 += lam * lam * lam;
+        slog += log(lam);
+    }
+    const int deg = e1 - e0;
+    float* f = fn + 16 * (size_t)s;
+    f[0] = (float)(deg / 16.0);
+    f[1] = (float)(sr3 / 16.0);
+    f[2] = (float)(log1p(sl3) / 4.0);
+    f[3] = (float)(deg > 0 ? slog / deg : 0.0);
+    for (int k = 4; k < 16; ++k) f[k] = 0.f;
+}
+
+// ---------------------------------------------------------------------------
 // window records
 //
 // The window is the normalised Gaussian h(r) = (4 pi tau)^(-3/2) exp(-r^2/(4 tau))
@@ -992,6 +1077,24 @@ int launch_pairlist(const ApplyArgs& A, hipStream_t st) {
     hipMemsetAsync(A.maxcount, 0, sizeof(int), st);
     hipLaunchKernelGGL(k_pair_fill, dim3((n + 255) / 256), dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb, A.L,
                        A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount, A.maxcount, A.list, A.err);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int launch_edge_count(const ApplyArgs& A, double cut, int* deg, int* rowptr, hipStream_t st) {
+    const int n = (int)A.n;
+    hipLaunchKernelGGL(k_edge_count, dim3((n + 255) / 256), dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb, A.L,
+                       A.binw, cut, A.amax_bits, deg, A.err);
+    launch_scan(n, deg, rowptr, A.scan_tmp, st);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int launch_edge_fill(const ApplyArgs& A, double cut, const int* rowptr, int* esrc, int* edst, int* erev,
+                     float4* geo, float* fe, float* fn, hipStream_t st) {
+    const int n = (int)A.n;
+    hipLaunchKernelGGL(k_edge_fill, dim3((n + 255) / 256), dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb, A.L,
+                       A.binw, cut, A.amax_bits, rowptr, esrc, edst, geo, fe, A.err);
+    hipLaunchKernelGGL(k_edge_rev, dim3((n + 255) / 256), dim3(256), 0, st, n, A.sa, rowptr, edst, geo, erev, fn,
+                       A.err);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

@@ -26,11 +26,13 @@ SEASD_E_SINGULAR = -5
 SEASD_E_HIP = -6
 SEASD_E_NOMEM = -7
 SEASD_E_UNSUPPORTED = -8
+SEASD_E_FORMAT = -9
 SEASD_W_NOT_CONVERGED = 1
+SEASD_W_PRECOND_FALLBACK = 2
 
 SEASD_FP64, SEASD_FP32 = 0, 1
 SEASD_PARTS_REAL, SEASD_PARTS_WAVE, SEASD_PARTS_SELF, SEASD_PARTS_ALL = 1, 2, 4, 7
-SEASD_PRECOND_NONE, SEASD_PRECOND_BLOCKDIAG = 0, 1
+SEASD_PRECOND_NONE, SEASD_PRECOND_BLOCKDIAG, SEASD_PRECOND_LEARNED, SEASD_PRECOND_LEARNED_GUESS = 0, 1, 2, 3
 
 PHASES = ("bin", "pair", "spread", "fft_x_fwd", "fft_y_fwd", "fft_z_scale", "fft_y_inv", "fft_x_inv", "gather")
 
@@ -39,7 +41,9 @@ SYMBOLS = ("seasd_create", "seasd_destroy", "seasd_default_config", "seasd_set_c
            "seasd_mobility_apply", "seasd_solve_farfield", "seasd_profile_enable",
            "seasd_profile_read", "seasd_error_string", "seasd_autotune", "seasd_batch_create",
            "seasd_batch_apply", "seasd_batch_configs", "seasd_batch_destroy",
-           "seasd_mobility_apply_batched")
+           "seasd_mobility_apply_batched", "seasd_net_create", "seasd_net_destroy", "seasd_net_param_count",
+           "seasd_net_get_params", "seasd_net_set_params", "seasd_net_save", "seasd_net_load",
+           "seasd_net_loss_grad", "seasd_net_train_step", "seasd_precond_attach", "seasd_precond_load")
 
 
 class seasd_config(ctypes.Structure):
@@ -71,6 +75,9 @@ class seasd_solve_stats(ctypes.Structure):
         ("true_residual", ctypes.c_double),
         ("setup_ms", ctypes.c_double),
         ("solve_ms", ctypes.c_double),
+        ("precond_used", ctypes.c_int32),
+        ("guess_used", ctypes.c_int32),
+        ("initial_residual", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -106,11 +113,26 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.seasd_batch_destroy.argtypes = [vp]
     lib.seasd_mobility_apply_batched.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), dp, dp,
                                                  ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, dp, dp, vp]
+    lib.seasd_net_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_uint64]
+    lib.seasd_net_destroy.argtypes = [vp]
+    lib.seasd_net_param_count.argtypes = []
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.seasd_net_get_params.argtypes = [vp, fp, i64]
+    lib.seasd_net_set_params.argtypes = [vp, fp, i64]
+    lib.seasd_net_save.argtypes = [vp, ctypes.c_char_p]
+    lib.seasd_net_load.argtypes = [vp, ctypes.c_char_p]
+    lib.seasd_net_loss_grad.argtypes = [vp, vp, i64, dp, dp, ctypes.POINTER(ctypes.c_double), i32, dp, dp,
+                                        ctypes.POINTER(ctypes.c_double), fp, vp]
+    lib.seasd_net_train_step.argtypes = [vp, vp, i64, dp, dp, ctypes.POINTER(ctypes.c_double), i32, dp,
+                                         ctypes.c_float, ctypes.POINTER(ctypes.c_double), vp]
+    lib.seasd_precond_attach.argtypes = [vp, vp]
+    lib.seasd_precond_load.argtypes = [vp, ctypes.c_char_p]
     lib.seasd_error_string.argtypes = [i32]
     lib.seasd_error_string.restype = ctypes.c_char_p
     for name in SYMBOLS:
         if name != "seasd_error_string":
             getattr(lib, name).restype = ctypes.c_int
+    lib.seasd_net_param_count.restype = ctypes.c_int64
     return lib
 
 
@@ -203,10 +225,24 @@ class Seasd:
         code = lib().seasd_solve_farfield(self.h, n, pos.data_ptr(), radius.data_ptr(), _box9(box),
                                           b.data_ptr(), x.data_ptr(), ctypes.byref(st),
                                           ctypes.c_void_p(_stream_ptr(stream)))
-        _check(code, allow=(SEASD_OK, SEASD_W_NOT_CONVERGED))
-        return x, st.as_dict()
+        _check(code, allow=(SEASD_OK, SEASD_W_NOT_CONVERGED, SEASD_W_PRECOND_FALLBACK))
+        out = st.as_dict()
+        out["code"] = code
+        return x, out
 
     solve = seasd_solve_farfield
+
+    def seasd_precond_attach(self, net):
+        """Use `net` for solves with precond=SEASD_PRECOND_LEARNED (None detaches)."""
+        _check(lib().seasd_precond_attach(self.h, net.h if net is not None else None))
+        self._net = net   # keep it alive while attached
+
+    attach = seasd_precond_attach
+
+    def seasd_precond_load(self, path: str):
+        _check(lib().seasd_precond_load(self.h, os.fsencode(path)))
+
+    precond_load = seasd_precond_load
 
     def profile(self, enable: bool = True):
         _check(lib().seasd_profile_enable(self.h, 1 if enable else 0))
@@ -225,6 +261,79 @@ class Seasd:
     def close(self):
         if getattr(self, "h", None):
             lib().seasd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Net:
+    """The learned preconditioner network (seasd_net)."""
+
+    def __init__(self, device: int = 0, seed: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().seasd_net_create(ctypes.byref(h), int(device), ctypes.c_uint64(int(seed))))
+        self.h = h
+        self.count = int(lib().seasd_net_param_count())
+
+    def params(self):
+        import numpy as np
+        out = np.zeros(self.count, dtype=np.float32)
+        _check(lib().seasd_net_get_params(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), self.count))
+        return out
+
+    def set_params(self, values):
+        import numpy as np
+        v = np.ascontiguousarray(values, dtype=np.float32)
+        if v.size != self.count:
+            raise ValueError(f"need {self.count} parameters, got {v.size}")
+        _check(lib().seasd_net_set_params(self.h, v.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), self.count))
+
+    def save(self, path: str):
+        _check(lib().seasd_net_save(self.h, os.fsencode(path)))
+
+    def load(self, path: str):
+        _check(lib().seasd_net_load(self.h, os.fsencode(path)))
+
+    def seasd_net_loss_grad(self, eng: "Seasd", pos, radius, box, b, want_loss=True, want_grad=False,
+                            stream=None):
+        """b: [nrhs, n, 12] (or [n, 12]) float64 device tensor. Returns
+        (loss, grad, x0): the mean relative residual of the guesses, its
+        gradient (numpy float32) and the guesses."""
+        import numpy as np
+        import torch
+        if b.dim() == 2:
+            b = b.unsqueeze(0)
+        nrhs, n = int(b.shape[0]), int(b.shape[1])
+        x0 = torch.empty_like(b)
+        loss = ctypes.c_double(0.0)
+        grad = np.zeros(self.count, dtype=np.float32) if want_grad else None
+        _check(lib().seasd_net_loss_grad(
+            eng.h, self.h, n, pos.data_ptr(), radius.data_ptr(), _box9(box), nrhs, b.data_ptr(), x0.data_ptr(),
+            ctypes.byref(loss) if want_loss else None,
+            grad.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if grad is not None else None,
+            ctypes.c_void_p(_stream_ptr(stream))))
+        return (loss.value if want_loss else None), grad, x0
+
+    loss_grad = seasd_net_loss_grad
+
+    def seasd_net_train_step(self, eng: "Seasd", pos, radius, box, b, lr: float, stream=None) -> float:
+        if b.dim() == 2:
+            b = b.unsqueeze(0)
+        loss = ctypes.c_double(0.0)
+        _check(lib().seasd_net_train_step(eng.h, self.h, int(b.shape[1]), pos.data_ptr(), radius.data_ptr(),
+                                          _box9(box), int(b.shape[0]), b.data_ptr(), ctypes.c_float(lr),
+                                          ctypes.byref(loss), ctypes.c_void_p(_stream_ptr(stream))))
+        return loss.value
+
+    train_step = seasd_net_train_step
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().seasd_net_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _header_functions():
     src = open(os.path.join(ROOT, "include", "seasd.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(seasd_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|const char\*)\s+(seasd_\w+)\s*\(", src, re.M)))
 
 
 def test_library_exports_header_symbols():

@@ -77,6 +77,32 @@ def test_gradient_matches_finite_differences():
         assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * loss), (name, fd, an)
 
 
+def test_residual_loss_gradient_matches_finite_differences():
+    pos, rad = _system(6)
+    n = len(rad)
+    rng = np.random.default_rng(8)
+    G = rng.standard_normal((11 * n, 11 * n))
+    Amat = G @ G.T / (11 * n) + np.eye(11 * n)
+
+    def Aop(v):
+        return (Amat @ v[:, :11].reshape(-1)).reshape(n, 11)
+
+    theta = mpnn.init_params(5, head_scale=0.3)
+    B = _aniso_blocks(rad, 9)
+    b = rng.standard_normal((2, n, 12))
+    loss, grad, x0 = mpnn.residual_loss_grad(theta, pos, rad, 8.0, B, b, Aop, bf=False)
+    # the loss is what it says
+    want = np.mean([np.sum((b[q, :, :11] - Aop(x0[q])) ** 2) / np.sum(b[q, :, :11] ** 2) for q in range(2)])
+    assert abs(loss - want) < 1e-12 * want
+    for k in range(4):
+        d = rng.standard_normal(theta.size)
+        eps = 1e-6
+        lp = mpnn.residual_loss_grad(theta + eps * d, pos, rad, 8.0, B, b, Aop, bf=False)[0]
+        lm = mpnn.residual_loss_grad(theta - eps * d, pos, rad, 8.0, B, b, Aop, bf=False)[0]
+        fd = (lp - lm) / (2 * eps)
+        assert abs(fd - grad @ d) <= 1e-6 * max(abs(grad @ d), 1e-3 * loss)
+
+
 def _rep(R):
     """11x11 action of rotation R on (F, T, S-coordinates)."""
     Y = traceless_basis()
