@@ -126,6 +126,7 @@ typedef struct seasd_solve_stats {
     int32_t precond_used;    /* SEASD_PRECOND_* actually applied                     */
     int32_t guess_used;      /* 1 if the learned initial guess was kept              */
     double  initial_residual;/* ||b' - A x0|| / ||b'|| of the starting iterate       */
+    double  guess_scale;     /* alpha applied to the learned guess (0: dropped)      */
 } seasd_solve_stats;
 
 typedef struct seasd_handle_s* seasd_handle;
@@ -321,8 +322,10 @@ int seasd_net_train_step(seasd_handle handle, seasd_net net, int64_t n, const do
  * with SEASD_PRECOND_LEARNED_GUESS it keeps them. It falls
  * back to the block-diagonal blocks and a zero guess, and returns
  * SEASD_W_PRECOND_FALLBACK if the solve otherwise converged, when an output
- * is non-finite or a scaling is beyond e^8; and it drops the guess (zero
- * start, guess_used = 0) when its true residual exceeds ||b'||. */
+ * is non-finite or a scaling is beyond e^8. The true residual judges the
+ * guess: GMRES starts from alpha x0 with alpha = argmin ||b' - alpha A x0||
+ * (one product), so the starting residual never exceeds ||b'||; alpha <= 0
+ * drops the guess (guess_used = 0). */
 int seasd_precond_attach(seasd_handle handle, seasd_net net);
 
 /* Load a weights file into a network owned by the handle and attach it. */

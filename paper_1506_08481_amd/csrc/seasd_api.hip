@@ -598,20 +598,31 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
         double rn2 = 0.0;
         rc = dot_host(h, len, 1, r, len, r, &rn2, st);
         if (rc) return rc;
-        const double beta = std::sqrt(rn2);
-        relres = beta / bnorm;
-        if (first_cycle) {
+        relres = std::sqrt(rn2) / bnorm;
+        if (first_cycle && guess) {
+            // the true residual judges the guess: scale it by the alpha that
+            // minimises ||b' - alpha A x0|| (A x0 = b' - r), dropping it when
+            // alpha <= 0
             first_cycle = false;
-            S.initial_residual = relres;
-            if (guess && relres > 1.0) {   // the guess is worse than zero: drop it
-                guess = 0;
-                if (hipMemsetAsync(x, 0, sizeof(double) * len, st) != hipSuccess) return SEASD_E_HIP;
-                S.initial_residual = 1.0;
-                if (launch_axpby(len, 1.0, bred, 0.0, r, st)) return SEASD_E_HIP;
-                relres = 1.0;
-            }
+            if (launch_axpby(len, 1.0, bred, 0.0, u, st) || launch_axpby(len, -1.0, r, 1.0, u, st))
+                return SEASD_E_HIP;
+            double ba = 0.0, aa = 0.0;
+            if ((rc = dot_host(h, len, 1, bred, len, u, &ba, st))) return rc;
+            if ((rc = dot_host(h, len, 1, u, len, u, &aa, st))) return rc;
+            const double alpha = (aa > 0.0 && ba > 0.0) ? ba / aa : 0.0;
+            if (alpha == 0.0) guess = 0;
+            // x = alpha x0, r = b' - alpha A x0
+            if (launch_axpby(len, alpha, x, 0.0, z, st) ||
+                hipMemcpyAsync(x, z, sizeof(double) * len, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                launch_axpby(len, 1.0, bred, 0.0, r, st) || launch_axpby(len, -alpha, u, 1.0, r, st))
+                return SEASD_E_HIP;
+            if ((rc = dot_host(h, len, 1, r, len, r, &rn2, st))) return rc;
+            relres = std::sqrt(rn2) / bnorm;
+            S.guess_scale = alpha;
         }
+        if (S.initial_residual == 0.0) S.initial_residual = relres;
         if (relres <= c.tol || total >= c.max_iter) break;
+        const double beta = relres * bnorm;
         if (launch_axpby(len, 1.0 / beta, r, 0.0, V, st)) return SEASD_E_HIP;
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;

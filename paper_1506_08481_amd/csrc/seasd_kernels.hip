@@ -572,8 +572,12 @@ __global__ __launch_bounds__(TILE == 8 ? 256 : 64) void k_spread(
     constexpr int NT = TILE == 8 ? 256 : 64;   // threads per workgroup
     constexpr int NPT = TILE == 8 ? 2 : 1;     // points per lane
     constexpr int MAXB = 729;                  // (2 reach + 1)^3 for reach <= 4
-    __shared__ R st[kStage * (kRecHead + 3 * kMaxP)];
-    __shared__ int cand[kMaxCand];
+    // a 64-lane workgroup stages fewer records, keeping LDS per workgroup
+    // small enough for several workgroups per CU
+    constexpr int STAGE = TILE == 8 ? kStage : kStage / 2;
+    constexpr int MAXC = TILE == 8 ? kMaxCand : kMaxCand / 2;
+    __shared__ R st[STAGE * (kRecHead + 3 * kMaxP)];
+    __shared__ int cand[MAXC];
     __shared__ int bins[MAXB], pre[MAXB + 1];
     __shared__ int nbins_used;
     const int t = threadIdx.x;
@@ -623,16 +627,16 @@ __global__ __launch_bounds__(TILE == 8 ? 256 : 64) void k_spread(
     for (int a = 0; a < NPT; ++a)
         for (int c = 0; c < 4; ++c) acc[a][c] = cmp[a][c] = R(0);
 
-    for (int cbase = 0; cbase < ncand; cbase += kMaxCand) {
-        const int clen = min(kMaxCand, ncand - cbase);
+    for (int cbase = 0; cbase < ncand; cbase += MAXC) {
+        const int clen = min(MAXC, ncand - cbase);
         for (int k = t; k < nbins_used; k += NT) {
             const int b0 = max(pre[k], cbase), b1 = min(pre[k + 1], cbase + clen);
             const int s0 = start[bins[k]] + (b0 - pre[k]);
             for (int c = b0; c < b1; ++c) cand[c - cbase] = s0 + (c - b0);
         }
         __syncthreads();
-        for (int c0 = 0; c0 < clen; c0 += kStage) {
-            const int cnt = min(kStage, clen - c0);
+        for (int c0 = 0; c0 < clen; c0 += STAGE) {
+            const int cnt = min(STAGE, clen - c0);
             for (int e = t; e < cnt * RS; e += NT) {
                 const int q = e / RS, k = e - q * RS;
                 st[q * RS + k] = recs[(size_t)RS * cand[c0 + q] + k];

@@ -475,12 +475,31 @@ __global__ void k_nonfinite(int64_t len, const double* __restrict__ x, int* __re
     if (t < len && !isfinite(x[t])) atomicOr(bad, 1);
 }
 
-// Adam on the FP32 master copy, then the BF16 copies W and W^T of every weight
+// squared 2-norm of the gradient (one workgroup, fixed order)
+__global__ __launch_bounds__(256) void k_sqnorm(int64_t P, const float* __restrict__ g, float* __restrict__ out) {
+    __shared__ float red[256];
+    float s = 0.f;
+    for (int64_t i = threadIdx.x; i < P; i += 256) s += g[i] * g[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// Adam on the FP32 master copy with the gradient clipped to 2-norm <= clip
+// (a non-finite gradient skips the step), then the BF16 copies W and W^T of
+// every weight
 __global__ void k_adam(int64_t P, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m1,
-                       float* __restrict__ m2, float lr, float b1, float b2, float eps, float bc1, float bc2) {
+                       float* __restrict__ m2, const float* __restrict__ sqnorm, float clip, float lr, float b1,
+                       float b2, float eps, float bc1, float bc2) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P) return;
-    const float gi = g[i];
+    const float nrm = sqrtf(*sqnorm);
+    if (!isfinite(nrm)) return;
+    const float gi = g[i] * (nrm > clip ? clip / nrm : 1.f);
     const float a = b1 * m1[i] + (1.f - b1) * gi;
     const float v = b2 * m2[i] + (1.f - b2) * gi * gi;
     m1[i] = a;
@@ -512,6 +531,7 @@ using namespace seasd;
 namespace {
 
 constexpr int kH = 64;
+constexpr float kClip = 1.0f;   // gradient 2-norm bound of an Adam step
 
 struct Layout {
     int64_t W_in, b_in, W_uv[2], W_e[2], b_a[2], W_m[2], b_m[2], W_h[2], b_h[2], W_o, b_o, W_c, b_c, total;
@@ -582,7 +602,7 @@ struct seasd_net_s {
     // activations
     DevBuf h0, uv[2], a[2], m[2], g[2], r[2], hl[2], o, c;
     // backward workspace
-    DevBuf dO, dC, dh, dh2, dhg, duv, dzn, dze, dze2, partial, bad;
+    DevBuf dO, dC, dh, dh2, dhg, duv, dzn, dze, dze2, partial, bad, gnorm;
 };
 
 namespace seasd {
@@ -784,9 +804,12 @@ int net_adam(seasd_net net, float lr, hipStream_t st) {
     net->step += 1;
     const float b1 = 0.9f, b2 = 0.999f;
     const float bc1 = 1.f - std::pow(b1, (float)net->step), bc2 = 1.f - std::pow(b2, (float)net->step);
+    if (net->gnorm.ensure(sizeof(float))) return SEASD_E_NOMEM;
+    hipLaunchKernelGGL(k_sqnorm, dim3(1), dim3(256), 0, st, net->lay.total, net->grads.as<float>(),
+                       net->gnorm.as<float>());
     hipLaunchKernelGGL(k_adam, dim3(grid1(net->lay.total, 256)), dim3(256), 0, st, net->lay.total,
-                       net->params.as<float>(), net->grads.as<float>(), net->mom1.as<float>(), net->mom2.as<float>(), lr,
-                       b1, b2, 1e-8f, bc1, bc2);
+                       net->params.as<float>(), net->grads.as<float>(), net->mom1.as<float>(), net->mom2.as<float>(),
+                       net->gnorm.as<float>(), kClip, lr, b1, b2, 1e-8f, bc1, bc2);
     net->bf_dirty = true;
     return hipGetLastError() == hipSuccess ? net_pack(net, st) : SEASD_E_HIP;
 }
@@ -881,7 +904,7 @@ extern "C" int seasd_net_destroy(seasd_net net) {
                       &net->h0, &net->uv[0], &net->uv[1], &net->a[0], &net->a[1], &net->m[0], &net->m[1],
                       &net->g[0], &net->g[1], &net->r[0], &net->r[1], &net->hl[0], &net->hl[1], &net->o, &net->c,
                       &net->dO, &net->dC, &net->dh, &net->dh2, &net->dhg, &net->duv, &net->dzn, &net->dze,
-                      &net->dze2, &net->partial, &net->bad};
+                      &net->dze2, &net->partial, &net->bad, &net->gnorm};
     for (DevBuf* b : bufs) b->release();
     delete net;
     return SEASD_OK;

@@ -78,6 +78,7 @@ class seasd_solve_stats(ctypes.Structure):
         ("precond_used", ctypes.c_int32),
         ("guess_used", ctypes.c_int32),
         ("initial_residual", ctypes.c_double),
+        ("guess_scale", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -146,6 +147,14 @@ def lib() -> ctypes.CDLL:
     return _LIB
 
 
+def _torch_first():
+    """Let torch bring up its HIP runtime before the library touches the
+    device: torch may carry its own copy of the runtime, which does not start
+    once the system copy has claimed the device in this process."""
+    import torch
+    torch.cuda.init()
+
+
 def _check(code: int, allow=(SEASD_OK,)) -> int:
     if code not in allow:
         raise SeasdError(code, lib().seasd_error_string(code).decode())
@@ -188,6 +197,7 @@ class Seasd:
     vectors (or 9 numbers a1, a2, a3)."""
 
     def __init__(self, device: int = 0, **config):
+        _torch_first()
         h = ctypes.c_void_p()
         _check(lib().seasd_create(ctypes.byref(h), int(device)))
         self.h = h
@@ -274,6 +284,7 @@ class Net:
     """The learned preconditioner network (seasd_net)."""
 
     def __init__(self, device: int = 0, seed: int = 0):
+        _torch_first()
         h = ctypes.c_void_p()
         _check(lib().seasd_net_create(ctypes.byref(h), int(device), ctypes.c_uint64(int(seed))))
         self.h = h

@@ -67,7 +67,7 @@ class ProblemPool:
         self.pool.join()
 
 
-def train(net, problems: ProblemPool, epochs: int = 12, nrhs: int = 8, lr: float = 2e-3, seed: int = 11,
+def train(net, problems: ProblemPool, epochs: int = 12, nrhs: int = 8, lr: float = 5e-4, seed: int = 11,
           log=None):
     """Train `net` in place on the configurations `problems` delivers; returns
     the loss history (one entry per step)."""
@@ -173,7 +173,7 @@ def main():
     ap.add_argument("--configs", type=int, default=96)
     ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--nrhs", type=int, default=8)
-    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--lr", type=float, default=5e-4)
     ap.add_argument("--seed", type=int, default=11)
     args = ap.parse_args()
     problems = ProblemPool(args.configs, args.seed)   # before the GPU is touched

@@ -32,8 +32,8 @@ def large():
 def _sample_error(cfg, precision, large):
     from paper_1506_08481_amd import seasd
     s, (P_, R_, X_), tg, yo = large
-    xi, rcf, P, mf = cfg
-    eng = seasd.Seasd(0, grid=256, P=P, m=mf * math.sqrt(math.pi * P), xi=xi, rc_factor=rcf,
+    xi, rcf, P, mf, tile = cfg
+    eng = seasd.Seasd(0, grid=256, P=P, m=mf * math.sqrt(math.pi * P), xi=xi, rc_factor=rcf, tile=tile,
                       precision=precision, checks=1)
     y = eng.apply(P_, R_, s.box, X_).cpu().numpy()
     eng.close()
@@ -51,7 +51,7 @@ def test_large_fp64_reference(large):
     assert err < 5e-8
 
 
-@pytest.mark.parametrize("k", [0, 1, 2])
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
 def test_large_fp32_candidates(large, k):
     """Each FP32 configuration the benchmark may time holds the 1e-6 target
     on the sample (a factor 2 above it for the 64-sphere sampling spread)."""
