@@ -555,7 +555,7 @@ __global__ __launch_bounds__(256) void k_window(int n, const double* __restrict_
 // in registers with Neumaier compensation: each grid point is written by
 // exactly one lane, with no atomics.
 
-constexpr int kStage = 32;     // spheres staged per round
+constexpr int kStage = 16;     // spheres staged per round
 constexpr int kMaxCand = 2048; // candidate list held in LDS
 
 template <typename R>
@@ -565,12 +565,19 @@ __device__ inline void neumaier(R& acc, R& cmp, R v) {
     acc = sum;
 }
 
+// wavefronts per workgroup of an 8^3 tile (each lane owns 8 / kSpreadWaves points)
+constexpr int kSpreadWaves = 4;
+
+template <int TILE>
+constexpr int spread_threads() { return TILE == 8 ? 64 * kSpreadWaves : 64; }
+
 template <typename R, int TILE>
-__global__ __launch_bounds__(TILE == 8 ? 256 : 64) void k_spread(
+__global__ __launch_bounds__(spread_threads<TILE>()) void k_spread(
     int n, const R* __restrict__ recs, const int* __restrict__ start, int nb, int M, int P, double h,
     double alpha, double cw, R4<R>* __restrict__ grid) {
-    constexpr int NT = TILE == 8 ? 256 : 64;   // threads per workgroup
-    constexpr int NPT = TILE == 8 ? 2 : 1;     // points per lane
+    constexpr int NT = spread_threads<TILE>();  // threads per workgroup
+    constexpr int NW = NT / 64;                 // wavefronts
+    constexpr int NPT = 8 / (TILE == 8 ? NW : 8);   // points per lane
     constexpr int MAXB = 729;                  // (2 reach + 1)^3 for reach <= 4
     // a 64-lane workgroup stages fewer records, keeping LDS per workgroup
     // small enough for several workgroups per CU
@@ -587,11 +594,11 @@ __global__ __launch_bounds__(TILE == 8 ? 256 : 64) void k_spread(
     const unsigned tcode = (unsigned)xcd_block(blockIdx.x, ntiles);
     const int tx = (int)compact_bits3(tcode), ty = (int)compact_bits3(tcode >> 1), tz = (int)compact_bits3(tcode >> 2);
     // 4^3 sub-blocks: sub-block b at offset (b&1, (b>>1)&1, b>>2) * 4; wavefront
-    // w owns sub-blocks w and w + 4 of an 8^3 tile (the single one of a 4^3 tile)
+    // w owns sub-blocks w, w + NW, ... of an 8^3 tile (the single one of a 4^3 tile)
     const int ox = lane & 3, oy = (lane >> 2) & 3, oz = lane >> 4;
     int gx[NPT], gy[NPT], gz[NPT];
     for (int p = 0; p < NPT; ++p) {
-        const int b = wv + 4 * p;
+        const int b = wv + NW * p;
         gx[p] = tx * TILE + (b & 1) * 4 * (TILE / 8) + ox;
         gy[p] = ty * TILE + ((b >> 1) & 1) * 4 * (TILE / 8) + oy;
         gz[p] = tz * TILE + (b >> 2) * 4 * (TILE / 8) + oz;
@@ -964,9 +971,16 @@ __global__ __launch_bounds__(256) void k_gather(
             const int gx = (i0.x + kx) & mask, gy = (i0.y + ky) & mask;
             R col[13];
             for (int c = 0; c < 13; ++c) col[c] = R(0);
-            for (int kz = 0; kz < P; ++kz) {
-                const int gz = (i0.z + kz) & mask;
-                const R4<R> g = grid[((size_t)gz * M + gy) * M + gx];
+            const R4<R>* colp = grid + (size_t)gy * M + gx;
+            const size_t zs = (size_t)M * M;
+            // P is even: two grid loads in flight per step, several steps unrolled
+#pragma unroll 4
+            for (int kz2 = 0; kz2 < P; kz2 += 2) {
+              const R4<R> gpair[2] = {colp[(size_t)((i0.z + kz2) & mask) * zs],
+                                      colp[(size_t)((i0.z + kz2 + 1) & mask) * zs]};
+              for (int hz = 0; hz < 2; ++hz) {
+                const int kz = kz2 + hz;
+                const R4<R> g = gpair[hz];
                 const R rz = d0z + kz * hh;
                 const R r2 = rx * rx + ry * ry + rz * rz;
                 const R w = wxy * fac[wv][2 * P + kz];
@@ -986,6 +1000,7 @@ __global__ __launch_bounds__(256) void k_gather(
                 col[10] += cE * R(0.5) * (g.x * rz + g.z * rx);
                 col[11] += cE * R(0.5) * (g.y * rz + g.z * ry);
                 col[12] += w * g.w;
+              }
             }
             for (int c = 0; c < 13; ++c) neumaier(ac[c], cp[c], col[c]);
         }
@@ -1045,7 +1060,7 @@ static int launch_fft_chain_M(int M, void* rgrid, void* spec, const double* tw, 
         FFT_CASE(32, 4, (dbl ? 2 : 4))
         FFT_CASE(64, 4, (dbl ? 2 : 4))
         FFT_CASE(128, 2, (dbl ? 2 : 4))
-        FFT_CASE(256, 1, (dbl ? 1 : 4))
+        FFT_CASE(256, 2, (dbl ? 1 : 2))
         default:
             return -1;
     }
@@ -1129,7 +1144,7 @@ int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
                            (float*)A.wrec);
         if (wave) {
             if (A.tile == 8)
-                hipLaunchKernelGGL((k_spread<float, 8>), dim3(tiles * tiles * tiles), dim3(256), 0, st, n,
+                hipLaunchKernelGGL((k_spread<float, 8>), dim3(tiles * tiles * tiles), dim3(spread_threads<8>()), 0, st, n,
                                    (const float*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
                                    (R4<float>*)A.rgrid);
             else
@@ -1147,7 +1162,7 @@ int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
                            (double*)A.wrec);
         if (wave) {
             if (A.tile == 8)
-                hipLaunchKernelGGL((k_spread<double, 8>), dim3(tiles * tiles * tiles), dim3(256), 0, st, n,
+                hipLaunchKernelGGL((k_spread<double, 8>), dim3(tiles * tiles * tiles), dim3(spread_threads<8>()), 0, st, n,
                                    (const double*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
                                    (R4<double>*)A.rgrid);
             else

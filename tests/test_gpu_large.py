@@ -51,7 +51,7 @@ def test_large_fp64_reference(large):
     assert err < 5e-8
 
 
-@pytest.mark.parametrize("k", [0, 1, 2, 3])
+@pytest.mark.parametrize("k", [0, 1])
 def test_large_fp32_candidates(large, k):
     """Each FP32 configuration the benchmark may time holds the 1e-6 target
     on the sample (a factor 2 above it for the 64-sphere sampling spread)."""
