@@ -37,20 +37,33 @@ CANDIDATES = [
 REF = (0.7, 3.5, 18, 0.95, 8)   # FP64 reference product (SE error ~1e-8)
 
 
+# HBM bytes per launch measured with the byte counters (FETCH_SIZE x 2.0 +
+# WRITE_SIZE x 1.0; the factors come from a 2 GiB elementwise kernel of known
+# traffic profiled in the same runs), for the kernel versions and the
+# configuration (phase, grid, P, tile) recorded in
+# profiles/product_n100000_phi0.4_grid256_traffic.md. Any other configuration
+# reports null.
+MEASURED_TRAFFIC = {
+    ("spread", 256, 16, 8): 323.1e6,
+    ("gather", 256, 16, 8): 1432.1e6,
+}
+
+
 def phase_cost(phase, n, M, P, s_bytes, pairs):
-    """Algorithmic bytes and flops of one launch of a phase (see the design notes):
-    FFT passes read and write the 4-field grid once: 8 M^3 s bytes; spreading
-    writes the grid once (4 M^3 s) and reads the binned particles (16 doubles
-    each); gather reads the grid once (4 M^3 s) and the particles; their flops
-    are 48 (spread) and 60 (gather) per window point and sphere; the pair sum
-    costs about 700 FP64 flops per pair within the cut-off."""
+    """Algorithmic bytes and flops of one launch of a phase: FFT passes read
+    and write the 4-field grid once, 8 M^3 s bytes; spreading writes the grid
+    once (4 M^3 s) and reads the binned particles (16 doubles each); gather
+    reads the grid once (4 M^3 s) and the particles (28 doubles); flops per
+    (sphere, window point) as the kernels evaluate them: 65 for spreading
+    (offset, r^2, window weight, the force, torque and stresslet terms) and 62
+    for gather; the pair sum costs about 700 FP64 flops per pair within r_c."""
     g = M ** 3
     if phase.startswith("fft"):
         return {"bytes": 8 * g * s_bytes, "flops": 0.0}
     if phase == "spread":
-        return {"bytes": 4 * g * s_bytes + n * 16 * 8, "flops": 48.0 * n * P ** 3}
+        return {"bytes": 4 * g * s_bytes + n * 16 * 8, "flops": 65.0 * n * P ** 3}
     if phase == "gather":
-        return {"bytes": 4 * g * s_bytes + n * 28 * 8, "flops": 60.0 * n * P ** 3}
+        return {"bytes": 4 * g * s_bytes + n * 28 * 8, "flops": 62.0 * n * P ** 3}
     if phase == "pair":
         return {"bytes": n * 28 * 8, "flops": 700.0 * pairs}
     return {"bytes": n * 64, "flops": 0.0}
@@ -369,7 +382,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": cost["bytes"] / t_dom / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = MEASURED_TRAFFIC.get((dom, M, cand[2], cand[4]))
     roof["kernel"] = dom
     roof["kernel_ms"] = phases[dom]
 
