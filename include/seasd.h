@@ -204,8 +204,10 @@ int seasd_profile_read(seasd_handle handle, double* ms, int32_t count);
  * Autotuner: parameters for one suspension of n spheres (radii a_min..a_max)
  * in a cubic cell of edge L, aiming at a global relative error of `target`
  * (1e-6 or looser) in the given precision. It picks the grid M (a power of
- * two with spacing L/M near 0.4 a_max, 32..256; the bins are tiles of 4^3
- * grid points below M = 128 and of 8^3 from 128 up), xi from the grid spacing so that the k-space tail
+ * two, 32..256: for targets of 1e-6 or looser the finest with spacing
+ * L/M >= 0.21 a_max, below which the window's Faxen terms lose accuracy;
+ * for tighter targets the spacing nearest 0.4 a_max; the bins are tiles of
+ * 4^3 grid points below M = 128 and of 8^3 from 128 up), xi from the grid spacing so that the k-space tail
  * exp(-k_max^2/(4 xi^2)) stays fixed, the real-space cut-off factor so that
  * xi r_c is fixed for a pair of spheres of radius a_min (the batch planner
  * passes the 10th-percentile radius), and the window (P, m) from accuracy

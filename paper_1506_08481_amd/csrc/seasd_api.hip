@@ -828,9 +828,19 @@ extern "C" int seasd_autotune(int64_t n, double L, double a_min, double a_max, d
     seasd_default_config(cfg);
     cfg->precision = precision;
     cfg->checks = 0;
-    // grid: spacing near 0.4 a_max (the scans below were taken at h = 0.39-0.40)
+    // grid: xi follows the spacing (below), so a finer grid shortens the
+    // real-space cut-off and the pair sum shrinks as h^3 while the FFTs grow
+    // as M^3 log M; the Faxen terms of the window lose accuracy once h falls
+    // below about 0.2 a_max (measured FP32 errors against converged FP64
+    // products at h/a_max = 0.85, 0.42, 0.27, 0.21, 0.17, 0.14: 1.2e-7,
+    // 2.1e-7, 4.1e-7, 5.9e-7, 1.9e-6, 3.8e-6). For 1e-6 targets take the
+    // finest grid with h >= 0.21 a_max; tighter targets keep h near 0.4 a_max.
     int M = 32;
-    while (M < 256 && L / M > 0.42 * a_max) M *= 2;
+    if (target >= 1e-6) {
+        while (M < 256 && L / (2 * M) >= 0.21 * a_max) M *= 2;
+    } else {
+        while (M < 256 && L / M > 0.42 * a_max) M *= 2;
+    }
     const double h = L / M;
     // Measured at h/a = 0.39-0.40 against the converged oracle (FP64 window
     // error; FP32 adds ~5e-7): (xi a, rc_factor, P, m/sqrt(pi P)) =

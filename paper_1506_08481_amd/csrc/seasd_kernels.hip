@@ -20,6 +20,8 @@
 //              x transform of a real field is kept for qx in [0, M/2); the
 //              qx = M/2 plane is the Nyquist plane, which the method zeroes.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 #include "seasd_math.h"
@@ -265,6 +267,10 @@ __global__ void k_bin_gather(int n, const int* __restrict__ perm, const double* 
 // (j, image code) entries; pass 3 evaluates the couplings along each list, so
 // no lane spends the heavy pair arithmetic on a candidate outside the cut-off.
 
+// below this many spheres the neighbour list and the pair sum use one
+// wavefront per sphere (one thread per sphere would leave most CUs idle)
+constexpr int kWaveSpheres = 32768;
+
 __device__ inline int floordiv(int c, int nb) { return (c >= 0) ? c / nb : -((-c + nb - 1) / nb); }
 
 // visit every (j, image) within the cut-off of binned sphere s; f(j, code) per hit
@@ -336,6 +342,91 @@ __global__ __launch_bounds__(256) void k_pair_fill(int n, const double* __restri
     atomicMax(maxcount, k);
 }
 
+// The same list with one wavefront per sphere, for suspensions too small to
+// fill the chip with one thread per sphere: lane l takes bins l, l + 64, ... of the
+// (2 reach + 1)^3 neighbour bins in the visiting order of for_each_neighbour,
+// counts its hits, a wavefront prefix sum gives every lane its first slot and
+// a second sweep over the lane's bin writes the entries, so the list comes out
+// in the same order as the serial search.
+__global__ __launch_bounds__(256) void k_pair_fill_wave(int n, const double* __restrict__ sp,
+                                                        const double* __restrict__ sa, const int* __restrict__ start,
+                                                        int nb, double L, double binw, double rc_factor,
+                                                        const unsigned long long* __restrict__ amax_bits, int checks,
+                                                        int cap, int* __restrict__ ncount, int* __restrict__ maxcount,
+                                                        int2* __restrict__ list, int* __restrict__ err) {
+    const int lane = threadIdx.x & 63;
+    const int s = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    if (s >= n) return;   // whole wavefronts only; the kernel has no barrier
+    const double amax = __longlong_as_double((long long)*amax_bits);
+    const double px = sp[3 * s], py = sp[3 * s + 1], pz = sp[3 * s + 2];
+    const double ai = sa[s];
+    int reach = (int)ceil(rc_factor * (ai + amax) / binw);
+    if (reach > 3 * nb + 2) {
+        if (lane == 0) atomicOr(err, kErrCutoff);
+        reach = 3 * nb + 2;
+    }
+    const int span = 2 * reach + 1, nbins = span * span * span;
+    const int bx = min(nb - 1, (int)(px / binw)), by = min(nb - 1, (int)(py / binw)),
+              bz = min(nb - 1, (int)(pz / binw));
+    int2* dst = list + (size_t)cap * s;
+    int total = 0;
+    for (int base = 0; base < nbins; base += 64) {
+        const int q = base + lane;
+        int j0 = 0, j1 = 0, code = 0;
+        double ox = 0.0, oy = 0.0, oz = 0.0;
+        bool self_bin = false;
+        if (q < nbins) {
+            const int kx = q % span - reach, ky = (q / span) % span - reach, kz = q / (span * span) - reach;
+            int cx = bx + kx, cy = by + ky, cz = bz + kz;
+            const int wx = floordiv(cx, nb), wy = floordiv(cy, nb), wz = floordiv(cz, nb);
+            cx -= wx * nb;
+            cy -= wy * nb;
+            cz -= wz * nb;
+            const int bin = bin_id(cx, cy, cz);
+            j0 = start[bin];
+            j1 = start[bin + 1];
+            code = ((wz + 512) << 20) | ((wy + 512) << 10) | (wx + 512);
+            ox = wx * L;
+            oy = wy * L;
+            oz = wz * L;
+            self_bin = wx == 0 && wy == 0 && wz == 0;
+        }
+        int cnt = 0;
+        for (int j = j0; j < j1; ++j) {
+            if (j == s && self_bin) continue;
+            const double dx = px - (sp[3 * j] + ox), dy = py - (sp[3 * j + 1] + oy), dz = pz - (sp[3 * j + 2] + oz);
+            const double r2 = dx * dx + dy * dy + dz * dz, aj = sa[j];
+            const double rc = rc_factor * (ai + aj);
+            if (r2 >= rc * rc) continue;
+            if (checks && r2 < (ai + aj) * (ai + aj) * (1.0 - 1e-12)) atomicOr(err, kErrOverlap);
+            ++cnt;
+        }
+        int incl = cnt;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += v;
+        }
+        int k = total + incl - cnt;
+        if (cnt > 0) {
+            for (int j = j0; j < j1; ++j) {
+                if (j == s && self_bin) continue;
+                const double dx = px - (sp[3 * j] + ox), dy = py - (sp[3 * j + 1] + oy),
+                             dz = pz - (sp[3 * j + 2] + oz);
+                const double r2 = dx * dx + dy * dy + dz * dz, aj = sa[j];
+                const double rc = rc_factor * (ai + aj);
+                if (r2 >= rc * rc) continue;
+                if (k < cap) dst[k] = make_int2(j, code);
+                ++k;
+            }
+        }
+        total += __shfl(incl, 63, 64);
+    }
+    if (lane == 0) {
+        ncount[s] = total;
+        atomicMax(maxcount, total);
+    }
+}
+
 __global__ __launch_bounds__(128) void k_pair_eval(int n, const double* __restrict__ sp,
                                                    const double* __restrict__ sa, const double* __restrict__ sx,
                                                    const int* __restrict__ ncount, int cap, const int2* __restrict__ list,
@@ -361,6 +452,50 @@ __global__ __launch_bounds__(128) void k_pair_eval(int n, const double* __restri
             pair_coupling<double>(dx, dy, dz, ai, sa[j], xi, inv_eta, xj, y);
         }
     }
+    if (parts & kPartsSelf) {
+        double d4[4];
+        self_diag<double>(ai, xi, 1.0 / inv_eta, d4);
+        const double* xs = sx + 12 * (size_t)s;
+        for (int c = 0; c < 3; ++c) y[c] += d4[0] * xs[c];
+        for (int c = 3; c < 6; ++c) y[c] += d4[1] * xs[c];
+        for (int c = 6; c < 11; ++c) y[c] += d4[2] * xs[c];
+        y[11] += d4[3] * xs[11];
+    }
+    for (int c = 0; c < 12; ++c) ybuf[12 * (size_t)s + c] = y[c];
+}
+
+// Pair sum with one wavefront per sphere (small suspensions): lane l
+// evaluates list entries l, l + 64, ...; the 12 partial sums are reduced
+// across the wavefront in a fixed butterfly order.
+__global__ __launch_bounds__(256) void k_pair_eval_wave(int n, const double* __restrict__ sp,
+                                                        const double* __restrict__ sa, const double* __restrict__ sx,
+                                                        const int* __restrict__ ncount, int cap,
+                                                        const int2* __restrict__ list, double L, double xi,
+                                                        double inv_eta, int parts, double* __restrict__ ybuf) {
+    const int lane = threadIdx.x & 63;
+    const int s = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    if (s >= n) return;   // whole wavefronts only; the kernel has no barrier
+    const double px = sp[3 * s], py = sp[3 * s + 1], pz = sp[3 * s + 2];
+    const double ai = sa[s];
+    double y[12];
+    for (int c = 0; c < 12; ++c) y[c] = 0.0;
+    if (parts & kPartsReal) {
+        const int k0 = cap * s, k1 = k0 + min(ncount[s], cap);
+        for (int k = k0 + lane; k < k1; k += 64) {
+            const int2 e = list[k];
+            const int j = e.x;
+            const int wx = (e.y & 1023) - 512, wy = ((e.y >> 10) & 1023) - 512, wz = ((e.y >> 20) & 1023) - 512;
+            const double dx = px - (sp[3 * j] + wx * L);
+            const double dy = py - (sp[3 * j + 1] + wy * L);
+            const double dz = pz - (sp[3 * j + 2] + wz * L);
+            double xj[12];
+            for (int c = 0; c < 12; ++c) xj[c] = sx[12 * (size_t)j + c];
+            pair_coupling<double>(dx, dy, dz, ai, sa[j], xi, inv_eta, xj, y);
+        }
+        for (int off = 32; off > 0; off >>= 1)
+            for (int c = 0; c < 12; ++c) y[c] += __shfl_xor(y[c], off, 64);
+    }
+    if (lane != 0) return;
     if (parts & kPartsSelf) {
         double d4[4];
         self_diag<double>(ai, xi, 1.0 / inv_eta, d4);
@@ -769,33 +904,47 @@ __device__ inline void load_twiddles(C1<R>* tw, const double* __restrict__ twg, 
     }
 }
 
+// Arithmetic type of the FFT passes: the grid and spectrum are stored in R,
+// the butterflies run in FftT<R> (FP64 also for an FP32 grid when
+// kFftCompute64, which removes the transforms' rounding from the FP32 error
+// budget at twice the LDS per line).
+constexpr bool kFftCompute64 = false;
+template <typename R>
+struct FftT {
+    using type = typename std::conditional<kFftCompute64, double, R>::type;
+};
+
+template <typename T, typename R>
+__device__ inline C1<T> up(C1<R> a) { return C1<T>{(T)a.re, (T)a.im}; }
+
 // x pass, forward, real -> half spectrum. Two real fields share one complex
 // transform (A = f0 + i f1), separated with A(-q) = conj of the partner.
 template <typename R, int M, int LPB>
 __global__ __launch_bounds__(256) void k_fft_x_fwd(const R4<R>* __restrict__ in, C1<R>* __restrict__ out,
                                                    const double* __restrict__ twg) {
-    __shared__ C1<R> buf[2][2 * LPB * M];
-    __shared__ C1<R> tw[M];
-    load_twiddles<R, M>(tw, twg, +1);
+    using T = typename FftT<R>::type;
+    __shared__ C1<T> buf[2][2 * LPB * M];
+    __shared__ C1<T> tw[M];
+    load_twiddles<T, M>(tw, twg, +1);
     const size_t line0 = (size_t)blockIdx.x * LPB;
     for (int e = threadIdx.x; e < LPB * M; e += blockDim.x) {
         const int l = e / M, x = e - l * M;
         const R4<R> v = in[(line0 + l) * M + x];
-        buf[0][(2 * l) * M + x] = {v.x, v.y};
-        buf[0][(2 * l + 1) * M + x] = {v.z, v.w};
+        buf[0][(2 * l) * M + x] = {(T)v.x, (T)v.y};
+        buf[0][(2 * l + 1) * M + x] = {(T)v.z, (T)v.w};
     }
     __syncthreads();
-    C1<R>* r = lds_fft<R, M>(buf[0], buf[1], 2 * LPB, tw, +1);
+    C1<T>* r = lds_fft<T, M>(buf[0], buf[1], 2 * LPB, tw, +1);
     for (int e = threadIdx.x; e < LPB * (M / 2); e += blockDim.x) {
         const int l = e / (M / 2), q = e - l * (M / 2);
         const int qn = (M - q) & (M - 1);
         C1<R> o[4];
         for (int g = 0; g < 2; ++g) {
-            const C1<R> A = r[(2 * l + g) * M + q];
-            const C1<R> B = r[(2 * l + g) * M + qn];  // A(-q)
+            const C1<T> A = r[(2 * l + g) * M + q];
+            const C1<T> B = r[(2 * l + g) * M + qn];  // A(-q)
             // f0 = (A(q) + conj A(-q))/2,  f1 = -i (A(q) - conj A(-q))/2
-            o[2 * g] = {R(0.5) * (A.re + B.re), R(0.5) * (A.im - B.im)};
-            o[2 * g + 1] = {R(0.5) * (A.im + B.im), R(-0.5) * (A.re - B.re)};
+            o[2 * g] = {(R)(T(0.5) * (A.re + B.re)), (R)(T(0.5) * (A.im - B.im))};
+            o[2 * g + 1] = {(R)(T(0.5) * (A.im + B.im)), (R)(T(-0.5) * (A.re - B.re))};
         }
         C1<R>* dst = out + ((line0 + l) * (M / 2) + q) * 4;
         for (int c = 0; c < 4; ++c) dst[c] = o[c];
@@ -806,35 +955,36 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd(const R4<R>* __restrict__ in,
 template <typename R, int M, int LPB>
 __global__ __launch_bounds__(256) void k_fft_x_inv(const C1<R>* __restrict__ in, R4<R>* __restrict__ out,
                                                    const double* __restrict__ twg) {
-    __shared__ C1<R> buf[2][2 * LPB * M];
-    __shared__ C1<R> tw[M];
-    load_twiddles<R, M>(tw, twg, -1);
+    using T = typename FftT<R>::type;
+    __shared__ C1<T> buf[2][2 * LPB * M];
+    __shared__ C1<T> tw[M];
+    load_twiddles<T, M>(tw, twg, -1);
     const size_t line0 = (size_t)blockIdx.x * LPB;
     for (int e = threadIdx.x; e < LPB * M; e += blockDim.x) {
         const int l = e / M, x = e - l * M;
         for (int g = 0; g < 2; ++g) {
-            C1<R> A;
+            C1<T> A;
             if (x == 0) {
                 const C1<R>* s = in + ((line0 + l) * (M / 2)) * 4 + 2 * g;
-                A = {s[0].re, s[1].re};
+                A = {(T)s[0].re, (T)s[1].re};
             } else if (x < M / 2) {
                 const C1<R>* s = in + ((line0 + l) * (M / 2) + x) * 4 + 2 * g;
-                A = {s[0].re - s[1].im, s[0].im + s[1].re};       // G0 + i G1
+                A = {(T)s[0].re - (T)s[1].im, (T)s[0].im + (T)s[1].re};       // G0 + i G1
             } else if (x == M / 2) {
-                A = {R(0), R(0)};
+                A = {T(0), T(0)};
             } else {
                 const C1<R>* s = in + ((line0 + l) * (M / 2) + (M - x)) * 4 + 2 * g;
-                A = {s[0].re + s[1].im, s[1].re - s[0].im};       // conj G0 + i conj G1
+                A = {(T)s[0].re + (T)s[1].im, (T)s[1].re - (T)s[0].im};       // conj G0 + i conj G1
             }
             buf[0][(2 * l + g) * M + x] = A;
         }
     }
     __syncthreads();
-    C1<R>* r = lds_fft<R, M>(buf[0], buf[1], 2 * LPB, tw, -1);
+    C1<T>* r = lds_fft<T, M>(buf[0], buf[1], 2 * LPB, tw, -1);
     for (int e = threadIdx.x; e < LPB * M; e += blockDim.x) {
         const int l = e / M, x = e - l * M;
-        const C1<R> A = r[(2 * l) * M + x], B = r[(2 * l + 1) * M + x];
-        out[(line0 + l) * M + x] = {A.re, A.im, B.re, B.im};
+        const C1<T> A = r[(2 * l) * M + x], B = r[(2 * l + 1) * M + x];
+        out[(line0 + l) * M + x] = {(R)A.re, (R)A.im, (R)B.re, (R)B.im};
     }
 }
 
@@ -843,21 +993,23 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(const C1<R>* __restrict__ in,
 template <typename R, int M, int W>
 __global__ __launch_bounds__(256) void k_fft_y(C1<R>* __restrict__ data, const double* __restrict__ twg,
                                                int sgn) {
-    __shared__ C1<R> buf[2][4 * W * M];
-    __shared__ C1<R> tw[M];
-    load_twiddles<R, M>(tw, twg, sgn);
+    using T = typename FftT<R>::type;
+    __shared__ C1<T> buf[2][4 * W * M];
+    __shared__ C1<T> tw[M];
+    load_twiddles<T, M>(tw, twg, sgn);
     constexpr int HX = M / 2;
     const int x0 = (blockIdx.x % (HX / W)) * W;
     const int z = blockIdx.x / (HX / W);
     for (int e = threadIdx.x; e < W * M * 4; e += blockDim.x) {
         const int c = e & 3, w = (e >> 2) % W, y = (e >> 2) / W;
-        buf[0][(w * 4 + c) * M + y] = data[(((size_t)z * M + y) * HX + x0 + w) * 4 + c];
+        buf[0][(w * 4 + c) * M + y] = up<T>(data[(((size_t)z * M + y) * HX + x0 + w) * 4 + c]);
     }
     __syncthreads();
-    C1<R>* r = lds_fft<R, M>(buf[0], buf[1], 4 * W, tw, sgn);
+    C1<T>* r = lds_fft<T, M>(buf[0], buf[1], 4 * W, tw, sgn);
     for (int e = threadIdx.x; e < W * M * 4; e += blockDim.x) {
         const int c = e & 3, w = (e >> 2) % W, y = (e >> 2) / W;
-        data[(((size_t)z * M + y) * HX + x0 + w) * 4 + c] = r[(w * 4 + c) * M + y];
+        const C1<T> v = r[(w * 4 + c) * M + y];
+        data[(((size_t)z * M + y) * HX + x0 + w) * 4 + c] = C1<R>{(R)v.re, (R)v.im};
     }
 }
 
@@ -875,46 +1027,47 @@ struct KScale {
 template <typename R, int M, int W>
 __global__ __launch_bounds__(256) void k_fft_z_scale(C1<R>* __restrict__ data,
                                                      const double* __restrict__ twg, KScale ks) {
-    __shared__ C1<R> buf[2][4 * W * M];
-    __shared__ C1<R> twf[M], twi[M];
-    load_twiddles<R, M>(twf, twg, +1);
-    load_twiddles<R, M>(twi, twg, -1);
+    using T = typename FftT<R>::type;
+    __shared__ C1<T> buf[2][4 * W * M];
+    __shared__ C1<T> twf[M], twi[M];
+    load_twiddles<T, M>(twf, twg, +1);
+    load_twiddles<T, M>(twi, twg, -1);
     constexpr int HX = M / 2;
     const int x0 = (blockIdx.x % (HX / W)) * W;
     const int y = blockIdx.x / (HX / W);
     const size_t zstride = (size_t)M * HX * 4;
     for (int e = threadIdx.x; e < W * M * 4; e += blockDim.x) {
         const int c = e & 3, w = (e >> 2) % W, z = (e >> 2) / W;
-        buf[0][(w * 4 + c) * M + z] = data[z * zstride + ((size_t)y * HX + x0 + w) * 4 + c];
+        buf[0][(w * 4 + c) * M + z] = up<T>(data[z * zstride + ((size_t)y * HX + x0 + w) * 4 + c]);
     }
     __syncthreads();
-    C1<R>* a = lds_fft<R, M>(buf[0], buf[1], 4 * W, twf, +1);
-    C1<R>* b = (a == buf[0]) ? buf[1] : buf[0];
+    C1<T>* a = lds_fft<T, M>(buf[0], buf[1], 4 * W, twf, +1);
+    C1<T>* b = (a == buf[0]) ? buf[1] : buf[0];
     const int qy = (y < M / 2) ? y : y - M;
     for (int e = threadIdx.x; e < W * M; e += blockDim.x) {
         const int w = e % W, z = e / W;
         const int qx = x0 + w;
         const int qz = (z < M / 2) ? z : z - M;
-        C1<R>* f0 = a + (w * 4 + 0) * M + z;
-        C1<R>* f1 = a + (w * 4 + 1) * M + z;
-        C1<R>* f2 = a + (w * 4 + 2) * M + z;
-        C1<R>* f3 = a + (w * 4 + 3) * M + z;
+        C1<T>* f0 = a + (w * 4 + 0) * M + z;
+        C1<T>* f1 = a + (w * 4 + 1) * M + z;
+        C1<T>* f2 = a + (w * 4 + 2) * M + z;
+        C1<T>* f3 = a + (w * 4 + 3) * M + z;
         const bool zero = (qx == 0 && qy == 0 && qz == 0) || (y == M / 2) || (z == M / 2);
         if (zero) {
-            *f0 = *f1 = *f2 = *f3 = {R(0), R(0)};
+            *f0 = *f1 = *f2 = *f3 = {T(0), T(0)};
             continue;
         }
         const double kx = ks.twopi_over_L * qx, ky = ks.twopi_over_L * qy, kz = ks.twopi_over_L * qz;
         const double k2 = kx * kx + ky * ky + kz * kz;
         const double ex = exp(k2 * (ks.two_tau - ks.inv4xi2)) * ks.norm / k2;
-        const R st = (R)(ks.inv_eta * (1.0 + k2 * ks.inv4xi2) * ex);   // Stokes, incl. 1/k^2
-        const R lp = (R)ex;                                              // Laplace 1/k^2
-        const R rkx = (R)kx, rky = (R)ky, rkz = (R)kz, ik2 = (R)(1.0 / k2);
-        const C1<R> h0 = *f0, h1 = *f1, h2 = *f2, h3 = *f3;
+        const T st = (T)(ks.inv_eta * (1.0 + k2 * ks.inv4xi2) * ex);   // Stokes, incl. 1/k^2
+        const T lp = (T)ex;                                              // Laplace 1/k^2
+        const T rkx = (T)kx, rky = (T)ky, rkz = (T)kz, ik2 = (T)(1.0 / k2);
+        const C1<T> h0 = *f0, h1 = *f1, h2 = *f2, h3 = *f3;
         // k.f and the transverse projection
-        const C1<R> kf = {rkx * h0.re + rky * h1.re + rkz * h2.re, rkx * h0.im + rky * h1.im + rkz * h2.im};
-        const C1<R> pk = {kf.re * ik2, kf.im * ik2};
-        const R sq = R(0.25) * (R)ks.inv_eta * lp;   // source flow (i k)/(4 eta k^2)
+        const C1<T> kf = {rkx * h0.re + rky * h1.re + rkz * h2.re, rkx * h0.im + rky * h1.im + rkz * h2.im};
+        const C1<T> pk = {kf.re * ik2, kf.im * ik2};
+        const T sq = T(0.25) * (T)ks.inv_eta * lp;   // source flow (i k)/(4 eta k^2)
         // v = st (f - k (k.f)/k^2) + sq i k h3 ; i k h3 = k (-h3.im, h3.re)
         *f0 = {st * (h0.re - rkx * pk.re) - sq * rkx * h3.im, st * (h0.im - rkx * pk.im) + sq * rkx * h3.re};
         *f1 = {st * (h1.re - rky * pk.re) - sq * rky * h3.im, st * (h1.im - rky * pk.im) + sq * rky * h3.re};
@@ -923,10 +1076,11 @@ __global__ __launch_bounds__(256) void k_fft_z_scale(C1<R>* __restrict__ data,
         *f3 = {-lp * kf.im, lp * kf.re};
     }
     __syncthreads();
-    C1<R>* r = lds_fft<R, M>(a, b, 4 * W, twi, -1);
+    C1<T>* r = lds_fft<T, M>(a, b, 4 * W, twi, -1);
     for (int e = threadIdx.x; e < W * M * 4; e += blockDim.x) {
         const int c = e & 3, w = (e >> 2) % W, z = (e >> 2) / W;
-        data[z * zstride + ((size_t)y * HX + x0 + w) * 4 + c] = r[(w * 4 + c) * M + z];
+        const C1<T> v = r[(w * 4 + c) * M + z];
+        data[z * zstride + ((size_t)y * HX + x0 + w) * 4 + c] = C1<R>{(R)v.re, (R)v.im};
     }
 }
 
@@ -1094,8 +1248,14 @@ int launch_pairlist(const ApplyArgs& A, hipStream_t st) {
     const int n = (int)A.n;
     if (!(A.parts & kPartsReal)) return 0;
     hipMemsetAsync(A.maxcount, 0, sizeof(int), st);
-    hipLaunchKernelGGL(k_pair_fill, dim3((n + 255) / 256), dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb, A.L,
-                       A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount, A.maxcount, A.list, A.err);
+    if (n < kWaveSpheres)
+        hipLaunchKernelGGL(k_pair_fill_wave, dim3((n + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb,
+                           A.L, A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount, A.maxcount, A.list,
+                           A.err);
+    else
+        hipLaunchKernelGGL(k_pair_fill, dim3((n + 255) / 256), dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb,
+                           A.L, A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount, A.maxcount, A.list,
+                           A.err);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -1129,8 +1289,12 @@ int launch_moments(const ApplyArgs& A, hipStream_t st) {
 int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     const int n = (int)A.n;
     tm->begin(kPhasePair, st);
-    hipLaunchKernelGGL(k_pair_eval, dim3((n + 127) / 128), dim3(128), 0, st, n, A.sp, A.sa, A.sx, A.ncount,
-                       A.cap, A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
+    if (n < kWaveSpheres)
+        hipLaunchKernelGGL(k_pair_eval_wave, dim3((n + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.ncount,
+                           A.cap, A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
+    else
+        hipLaunchKernelGGL(k_pair_eval, dim3((n + 127) / 128), dim3(128), 0, st, n, A.sp, A.sa, A.sx, A.ncount,
+                           A.cap, A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
     const bool wave = (A.parts & kPartsWave) != 0;
     const int tiles = A.M / A.tile;
     KScale ks{2.0 * kPi / A.L, 1.0 / (4.0 * A.xi * A.xi), 2.0 * A.tau,
