@@ -614,7 +614,8 @@ constexpr int kMaxP = 32;
 // w (e0 + d1 r2): c0 = 1 - a^2 alpha, c1 = (2/3) a^2 alpha^2,
 // e0 = 2 alpha - 2 a^2 alpha^2, d1 = 0.8 a^2 alpha^3.
 constexpr int kRecHead = 24;
-__host__ __device__ inline int rec_stride(int P) { return kRecHead + 3 * P; }
+// record length rounded up to 4 reals, so staged records keep 16-byte alignment
+__host__ __device__ inline int rec_stride(int P) { return (kRecHead + 3 * P + 3) & ~3; }
 
 __device__ inline void fgg_factors(double d0, double h, double alpha, int P, double* out) {
     const int kc = P / 2 - 1;               // d0 + kc h lies in (-h, 0]
@@ -713,12 +714,13 @@ __global__ __launch_bounds__(spread_threads<TILE>()) void k_spread(
     constexpr int NT = spread_threads<TILE>();  // threads per workgroup
     constexpr int NW = NT / 64;                 // wavefronts
     constexpr int NPT = 8 / (TILE == 8 ? NW : 8);   // points per lane
+    static_assert(TILE == 4 || NW == 4, "a lane's points must share x and y");
     constexpr int MAXB = 729;                  // (2 reach + 1)^3 for reach <= 4
     // a 64-lane workgroup stages fewer records, keeping LDS per workgroup
     // small enough for several workgroups per CU
     constexpr int STAGE = TILE == 8 ? kStage : kStage / 2;
     constexpr int MAXC = TILE == 8 ? kMaxCand : kMaxCand / 2;
-    __shared__ R st[STAGE * (kRecHead + 3 * kMaxP)];
+    __shared__ __attribute__((aligned(16))) R st[STAGE * (kRecHead + 3 * kMaxP)];
     __shared__ int cand[MAXC];
     __shared__ int bins[MAXB], pre[MAXB + 1];
     __shared__ int nbins_used;
@@ -743,23 +745,26 @@ __global__ __launch_bounds__(spread_threads<TILE>()) void k_spread(
 
     const int reach = (P / 2 + TILE - 1) / TILE;
     const int span = min(2 * reach + 1, nb);
+    // neighbour bins and their sizes in parallel, then one running sum in LDS
+    const int nused = span * span * span;
+    for (int k = t; k < nused; k += NT) {
+        const int kx = k % span, ky = (k / span) % span, kz = k / (span * span);
+        const int bx = (span == nb) ? kx : ((tx - reach + kx) % nb + nb) % nb;
+        const int by = (span == nb) ? ky : ((ty - reach + ky) % nb + nb) % nb;
+        const int bz = (span == nb) ? kz : ((tz - reach + kz) % nb + nb) % nb;
+        const int b = bin_id(bx, by, bz);
+        bins[k] = b;
+        pre[k + 1] = start[b + 1] - start[b];
+    }
+    __syncthreads();
     if (t == 0) {
-        int c = 0;
-        for (int kz = 0; kz < span; ++kz)
-            for (int ky = 0; ky < span; ++ky)
-                for (int kx = 0; kx < span; ++kx) {
-                    const int bx = (span == nb) ? kx : ((tx - reach + kx) % nb + nb) % nb;
-                    const int by = (span == nb) ? ky : ((ty - reach + ky) % nb + nb) % nb;
-                    const int bz = (span == nb) ? kz : ((tz - reach + kz) % nb + nb) % nb;
-                    bins[c++] = bin_id(bx, by, bz);
-                }
-        nbins_used = c;
+        nbins_used = nused;
         int run = 0;
-        for (int k = 0; k < c; ++k) {
+        pre[0] = 0;
+        for (int k = 1; k <= nused; ++k) {
+            run += pre[k];
             pre[k] = run;
-            run += start[bins[k] + 1] - start[bins[k]];
         }
-        pre[c] = run;
     }
     __syncthreads();
     const int ncand = pre[nbins_used];
@@ -788,38 +793,45 @@ __global__ __launch_bounds__(spread_threads<TILE>()) void k_spread(
             for (int a = 0; a < NPT; ++a)
                 for (int c = 0; c < 4; ++c) part[a][c] = R(0);
             for (int q = 0; q < cnt; ++q) {
-                const R* rc = st + q * RS;
+                const R* rc = static_cast<const R*>(__builtin_assume_aligned(st + q * RS, 16));
                 const int i0x = rec_i0(rc, 0), i0y = rec_i0(rc, 1), i0z = rec_i0(rc, 2);
+                // a lane's points share x and y (they differ by 4 in z)
+                const int kx = (gx[0] - i0x) & mask, ky = (gy[0] - i0y) & mask;
+                const bool inxy = (kx < P) && (ky < P);
                 bool in[NPT];
-                int kx[NPT], ky[NPT], kz[NPT];
+                int kz[NPT];
                 bool any = false;
                 for (int p = 0; p < NPT; ++p) {
-                    kx[p] = (gx[p] - i0x) & mask;
-                    ky[p] = (gy[p] - i0y) & mask;
                     kz[p] = (gz[p] - i0z) & mask;
-                    in[p] = (kx[p] < P) && (ky[p] < P) && (kz[p] < P);
+                    in[p] = inxy && (kz[p] < P);
                     any = any || in[p];
                 }
                 if (!__any(any)) continue;
+                if (!inxy) continue;
                 const R F0 = rc[8], F1 = rc[9], F2 = rc[10], T0 = rc[11], T1 = rc[12], T2 = rc[13];
                 const R S0 = rc[14], S1 = rc[15], S2 = rc[16], S3 = rc[17], S4 = rc[18], S5 = rc[19];
                 const R sq = rc[20], c0 = rc[21], c1 = rc[22], e0 = rc[23], d1 = rc[3];
                 const R* fa = rc + kRecHead;
+                const R rx = rc[4] + kx * hh, ry = rc[5] + ky * hh;
+                const R wxy = cwr * fa[kx] * fa[P + ky];
+                const R rxy2 = rx * rx + ry * ry;
+                const R Sx = S0 * rx + S3 * ry, Sy = S3 * rx + S1 * ry, Sz = S4 * rx + S5 * ry;
+                const R tz = rx * T1 - ry * T0;
 #pragma unroll
                 for (int p = 0; p < NPT; ++p) {
                     if (!in[p]) continue;
-                    const R rx = rc[4] + kx[p] * hh, ry = rc[5] + ky[p] * hh, rz = rc[6] + kz[p] * hh;
-                    const R r2 = rx * rx + ry * ry + rz * rz;
-                    const R w = cwr * fa[kx[p]] * fa[P + ky[p]] * fa[2 * P + kz[p]];
+                    const R rz = rc[6] + kz[p] * hh;
+                    const R r2 = rxy2 + rz * rz;
+                    const R w = wxy * fa[2 * P + kz[p]];
                     const R cF = w * (c0 + c1 * r2);
                     const R cS = w * (e0 + d1 * r2);
                     const R cT = -al * w;
-                    const R Srx = S0 * rx + S3 * ry + S4 * rz;
-                    const R Sry = S3 * rx + S1 * ry + S5 * rz;
-                    const R Srz = S4 * rx + S5 * ry + S2 * rz;
+                    const R Srx = Sx + S4 * rz;
+                    const R Sry = Sy + S5 * rz;
+                    const R Srz = Sz + S2 * rz;
                     part[p][0] += cF * F0 + cT * (ry * T2 - rz * T1) + cS * Srx;
                     part[p][1] += cF * F1 + cT * (rz * T0 - rx * T2) + cS * Sry;
-                    part[p][2] += cF * F2 + cT * (rx * T1 - ry * T0) + cS * Srz;
+                    part[p][2] += cF * F2 + cT * tz + cS * Srz;
                     part[p][3] += w * sq;
                 }
             }
