@@ -1025,6 +1025,77 @@ __global__ __launch_bounds__(256) void k_fft_y(C1<R>* __restrict__ data, const d
     }
 }
 
+// ---------------------------------------------------------------------------
+// 256-point lines as 16 x 16 (four-step): each line is owned by 16 threads;
+// thread t holds x[16 n1 + t], n1 = 0..15, transforms over n1 in registers,
+// applies the twiddle w^(t k1), exchanges through LDS once and transforms
+// over the other index. One LDS buffer (padded rows of 17, lines of 273) and
+// 16 lines per workgroup, so a workgroup reads whole 128-byte rows.
+
+// 4-point DFT in place, exponent sign sgn: Y_k = sum_n a_n (sgn i)^(n k)
+template <typename T>
+__device__ inline void dft4(C1<T>& a0, C1<T>& a1, C1<T>& a2, C1<T>& a3, int sgn) {
+    const C1<T> s02 = cadd(a0, a2), d02 = csub(a0, a2);
+    const C1<T> s13 = cadd(a1, a3), d13 = cmuli(csub(a1, a3), sgn);
+    a0 = cadd(s02, s13);
+    a1 = cadd(d02, d13);
+    a2 = csub(s02, s13);
+    a3 = csub(d02, d13);
+}
+
+// 16-point DFT in registers (4 x 4); tw256 is the table of w256^j (same
+// sign), so w16^j = tw256[16 j]. On return X_k sits in v[4 (k % 4) + k / 4].
+template <typename T>
+__device__ inline void dft16(C1<T>* v, const C1<T>* tw256, int sgn) {
+#pragma unroll
+    for (int m2 = 0; m2 < 4; ++m2) dft4(v[m2], v[4 + m2], v[8 + m2], v[12 + m2], sgn);
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1)
+#pragma unroll
+        for (int m2 = 1; m2 < 4; ++m2) v[4 * k1 + m2] = cmul(tw256[(16 * m2 * k1) & 255], v[4 * k1 + m2]);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3], sgn);
+}
+
+constexpr int kL16Row = 17;               // padded row of the 16 x 16 exchange
+constexpr int kL16Line = 16 * 17 + 1;     // padded line (273 complex)
+
+// v[n1] = x[16 n1 + t] of one line in, X[16 k2 + t] = v[4 (k2 % 4) + k2 / 4] out
+template <typename T>
+__device__ inline void fft256_line(C1<T>* v, C1<T>* ln, const C1<T>* tw, int t, int sgn) {
+    dft16(v, tw, sgn);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1)
+        ln[k1 * kL16Row + t] = cmul(tw[(t * k1) & 255], v[4 * (k1 & 3) + (k1 >> 2)]);
+    __syncthreads();
+#pragma unroll
+    for (int n2 = 0; n2 < 16; ++n2) v[n2] = ln[t * kL16Row + n2];
+    dft16(v, tw, sgn);
+}
+
+// y pass for M = 256 (FP32 storage): a workgroup owns 4 qx columns at one z,
+// 16 lines (4 columns x 4 fields).
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_y256(C1<R>* __restrict__ data, const double* __restrict__ twg,
+                                                  int sgn) {
+    constexpr int M = 256, HX = 128, W = 4;
+    __shared__ C1<R> buf[16 * kL16Line];
+    __shared__ C1<R> tw[M];
+    load_twiddles<R, M>(tw, twg, sgn);
+    const int lane = threadIdx.x & 63;
+    const int l = lane & 15, t = (lane >> 4) + 4 * (threadIdx.x >> 6);
+    const int x0 = (blockIdx.x % (HX / W)) * W;
+    const int z = blockIdx.x / (HX / W);
+    C1<R>* base = data + ((size_t)z * M * HX + x0) * 4 + l;   // + (y HX) * 4
+    C1<R> v[16];
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) v[n1] = base[(size_t)(16 * n1 + t) * HX * 4];
+    __syncthreads();   // twiddles
+    fft256_line(v, buf + l * kL16Line, tw, t, sgn);
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) base[(size_t)(16 * k2 + t) * HX * 4] = v[4 * (k2 & 3) + (k2 >> 2)];
+}
+
 struct KScale {
     double twopi_over_L;   // k = (2 pi / L) q
     double inv4xi2;        // 1 / (4 xi^2)
@@ -1094,6 +1165,72 @@ __global__ __launch_bounds__(256) void k_fft_z_scale(C1<R>* __restrict__ data,
         const C1<T> v = r[(w * 4 + c) * M + z];
         data[z * zstride + ((size_t)y * HX + x0 + w) * 4 + c] = C1<R>{(R)v.re, (R)v.im};
     }
+}
+
+// z pass for M = 256 (FP32 storage): forward z transform, k-space multiply
+// (as in k_fft_z_scale), inverse z transform; a workgroup owns 4 qx columns
+// at one qy.
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_z256(C1<R>* __restrict__ data, const double* __restrict__ twg,
+                                                  KScale ks) {
+    constexpr int M = 256, HX = 128, W = 4;
+    __shared__ C1<R> buf[16 * kL16Line];
+    __shared__ C1<R> twf[M], twi[M];
+    load_twiddles<R, M>(twf, twg, +1);
+    load_twiddles<R, M>(twi, twg, -1);
+    const int lane = threadIdx.x & 63;
+    const int l = lane & 15, t = (lane >> 4) + 4 * (threadIdx.x >> 6);
+    const int x0 = (blockIdx.x % (HX / W)) * W;
+    const int y = blockIdx.x / (HX / W);
+    const size_t zstride = (size_t)M * HX * 4;
+    C1<R>* base = data + ((size_t)y * HX + x0) * 4 + l;   // + z zstride
+    C1<R>* ln = buf + l * kL16Line;
+    C1<R> v[16];
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) v[n1] = base[(size_t)(16 * n1 + t) * zstride];
+    __syncthreads();   // twiddles
+    fft256_line(v, ln, twf, t, +1);
+    __syncthreads();   // every thread has read its exchange row
+    // spectrum of this line in natural order: element qz at ln[qz]
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) ln[16 * k2 + t] = v[4 * (k2 & 3) + (k2 >> 2)];
+    __syncthreads();
+    const int qy = (y < M / 2) ? y : y - M;
+    for (int e = threadIdx.x; e < W * M; e += 256) {
+        const int w = e & 3, z = e >> 2;
+        const int qx = x0 + w;
+        const int qz = (z < M / 2) ? z : z - M;
+        C1<R>* f0 = buf + (w * 4 + 0) * kL16Line + z;
+        C1<R>* f1 = buf + (w * 4 + 1) * kL16Line + z;
+        C1<R>* f2 = buf + (w * 4 + 2) * kL16Line + z;
+        C1<R>* f3 = buf + (w * 4 + 3) * kL16Line + z;
+        const bool zero = (qx == 0 && qy == 0 && qz == 0) || (y == M / 2) || (z == M / 2);
+        if (zero) {
+            *f0 = *f1 = *f2 = *f3 = {R(0), R(0)};
+            continue;
+        }
+        const double kx = ks.twopi_over_L * qx, ky = ks.twopi_over_L * qy, kz = ks.twopi_over_L * qz;
+        const double k2 = kx * kx + ky * ky + kz * kz;
+        const double ex = exp(k2 * (ks.two_tau - ks.inv4xi2)) * ks.norm / k2;
+        const R st = (R)(ks.inv_eta * (1.0 + k2 * ks.inv4xi2) * ex);
+        const R lp = (R)ex;
+        const R rkx = (R)kx, rky = (R)ky, rkz = (R)kz, ik2 = (R)(1.0 / k2);
+        const C1<R> h0 = *f0, h1 = *f1, h2 = *f2, h3 = *f3;
+        const C1<R> kf = {rkx * h0.re + rky * h1.re + rkz * h2.re, rkx * h0.im + rky * h1.im + rkz * h2.im};
+        const C1<R> pk = {kf.re * ik2, kf.im * ik2};
+        const R sq = R(0.25) * (R)ks.inv_eta * lp;
+        *f0 = {st * (h0.re - rkx * pk.re) - sq * rkx * h3.im, st * (h0.im - rkx * pk.im) + sq * rkx * h3.re};
+        *f1 = {st * (h1.re - rky * pk.re) - sq * rky * h3.im, st * (h1.im - rky * pk.im) + sq * rky * h3.re};
+        *f2 = {st * (h2.re - rkz * pk.re) - sq * rkz * h3.im, st * (h2.im - rkz * pk.im) + sq * rkz * h3.re};
+        *f3 = {-lp * kf.im, lp * kf.re};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) v[n1] = ln[16 * n1 + t];
+    __syncthreads();   // the exchange below reuses the line
+    fft256_line(v, ln, twi, t, -1);
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) base[(size_t)(16 * k2 + t) * zstride] = v[4 * (k2 & 3) + (k2 >> 2)];
 }
 
 // ---------------------------------------------------------------------------
@@ -1195,25 +1332,34 @@ template <typename R>
 static int launch_fft_chain_M(int M, void* rgrid, void* spec, const double* tw, const KScale& ks,
                               hipStream_t st, PhaseTimer* tm);
 
-#define FFT_CASE(MM, LPB, W)                                                                            \
-    case MM: {                                                                                          \
-        const int lines = MM * MM;                                                                      \
-        tm->begin(kPhaseFftXFwd, st);                                                                   \
-        hipLaunchKernelGGL((k_fft_x_fwd<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,              \
-                           (const R4<R>*)rgrid, (C1<R>*)spec, tw);                                      \
-        tm->begin(kPhaseFftYFwd, st);                                                                   \
-        hipLaunchKernelGGL((k_fft_y<R, MM, W>), dim3((MM / 2 / W) * MM), dim3(256), 0, st,              \
-                           (C1<R>*)spec, tw, +1);                                                       \
-        tm->begin(kPhaseFftZ, st);                                                                      \
-        hipLaunchKernelGGL((k_fft_z_scale<R, MM, W>), dim3((MM / 2 / W) * MM), dim3(256), 0, st,        \
-                           (C1<R>*)spec, tw, ks);                                                       \
-        tm->begin(kPhaseFftYInv, st);                                                                   \
-        hipLaunchKernelGGL((k_fft_y<R, MM, W>), dim3((MM / 2 / W) * MM), dim3(256), 0, st,              \
-                           (C1<R>*)spec, tw, -1);                                                       \
-        tm->begin(kPhaseFftXInv, st);                                                                   \
-        hipLaunchKernelGGL((k_fft_x_inv<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,              \
-                           (const C1<R>*)spec, (R4<R>*)rgrid, tw);                                      \
-        break;                                                                                          \
+#define FFT_CASE(MM, LPB, W)                                                                              \
+    case MM: {                                                                                            \
+        const int lines = MM * MM;                                                                        \
+        tm->begin(kPhaseFftXFwd, st);                                                                     \
+        hipLaunchKernelGGL((k_fft_x_fwd<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,                \
+                           (const R4<R>*)rgrid, (C1<R>*)spec, tw);                                        \
+        if (MM == 256 && !dbl && !kFftCompute64) {                                                        \
+            tm->begin(kPhaseFftYFwd, st);                                                                 \
+            hipLaunchKernelGGL((k_fft_y256<R>), dim3(32 * 256), dim3(256), 0, st, (C1<R>*)spec, tw, +1);  \
+            tm->begin(kPhaseFftZ, st);                                                                    \
+            hipLaunchKernelGGL((k_fft_z256<R>), dim3(32 * 256), dim3(256), 0, st, (C1<R>*)spec, tw, ks);  \
+            tm->begin(kPhaseFftYInv, st);                                                                 \
+            hipLaunchKernelGGL((k_fft_y256<R>), dim3(32 * 256), dim3(256), 0, st, (C1<R>*)spec, tw, -1);  \
+        } else {                                                                                          \
+            tm->begin(kPhaseFftYFwd, st);                                                                 \
+            hipLaunchKernelGGL((k_fft_y<R, MM, W>), dim3((MM / 2 / W) * MM), dim3(256), 0, st,            \
+                               (C1<R>*)spec, tw, +1);                                                     \
+            tm->begin(kPhaseFftZ, st);                                                                    \
+            hipLaunchKernelGGL((k_fft_z_scale<R, MM, W>), dim3((MM / 2 / W) * MM), dim3(256), 0, st,      \
+                               (C1<R>*)spec, tw, ks);                                                     \
+            tm->begin(kPhaseFftYInv, st);                                                                 \
+            hipLaunchKernelGGL((k_fft_y<R, MM, W>), dim3((MM / 2 / W) * MM), dim3(256), 0, st,            \
+                               (C1<R>*)spec, tw, -1);                                                     \
+        }                                                                                                 \
+        tm->begin(kPhaseFftXInv, st);                                                                     \
+        hipLaunchKernelGGL((k_fft_x_inv<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,                \
+                           (const C1<R>*)spec, (R4<R>*)rgrid, tw);                                        \
+        break;                                                                                            \
     }
 
 template <typename R>
