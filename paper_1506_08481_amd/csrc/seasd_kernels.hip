@@ -1096,6 +1096,100 @@ __global__ __launch_bounds__(256) void k_fft_y256(C1<R>* __restrict__ data, cons
     for (int k2 = 0; k2 < 16; ++k2) base[(size_t)(16 * k2 + t) * HX * 4] = v[4 * (k2 & 3) + (k2 >> 2)];
 }
 
+// x pass, forward, M = 256 (FP32): 8 real lines per workgroup, each a pair
+// of complex transforms (x + i y fields, z + i w fields), then the same
+// half-spectrum unpacking as k_fft_x_fwd.
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_x_fwd256(const R4<R>* __restrict__ in, C1<R>* __restrict__ out,
+                                                      const double* __restrict__ twg) {
+    constexpr int M = 256;
+    __shared__ C1<R> buf[16 * kL16Line];
+    __shared__ C1<R> tw[M];
+    load_twiddles<R, M>(tw, twg, +1);
+    const int lane = threadIdx.x & 63;
+    const int l16 = (lane >> 4) + 4 * (threadIdx.x >> 6), t = lane & 15;
+    const int line = l16 >> 1, g = l16 & 1;
+    const size_t line0 = (size_t)blockIdx.x * 8;
+    const R4<R>* src = in + (line0 + line) * M + t;
+    C1<R> v[16];
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) {
+        const R4<R> e = src[16 * n1];
+        v[n1] = g ? C1<R>{e.z, e.w} : C1<R>{e.x, e.y};
+    }
+    __syncthreads();   // twiddles
+    C1<R>* ln = buf + l16 * kL16Line;
+    fft256_line(v, ln, tw, t, +1);
+    __syncthreads();
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) ln[16 * k2 + t] = v[4 * (k2 & 3) + (k2 >> 2)];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 8 * (M / 2); e += 256) {
+        const int l = e >> 7, q = e & 127;
+        const int qn = (M - q) & (M - 1);
+        C1<R> o[4];
+#pragma unroll
+        for (int gg = 0; gg < 2; ++gg) {
+            const C1<R> A = buf[(2 * l + gg) * kL16Line + q];
+            const C1<R> B = buf[(2 * l + gg) * kL16Line + qn];
+            o[2 * gg] = {R(0.5) * (A.re + B.re), R(0.5) * (A.im - B.im)};
+            o[2 * gg + 1] = {R(0.5) * (A.im + B.im), R(-0.5) * (A.re - B.re)};
+        }
+        C1<R>* dst = out + ((line0 + l) * (M / 2) + q) * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) dst[c] = o[c];
+    }
+}
+
+// x pass, inverse, M = 256 (FP32): half spectrum -> 8 real lines per workgroup
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_x_inv256(const C1<R>* __restrict__ in, R4<R>* __restrict__ out,
+                                                      const double* __restrict__ twg) {
+    constexpr int M = 256;
+    __shared__ C1<R> buf[16 * kL16Line];
+    __shared__ C1<R> tw[M];
+    load_twiddles<R, M>(tw, twg, -1);
+    const size_t line0 = (size_t)blockIdx.x * 8;
+    for (int e = threadIdx.x; e < 8 * M; e += 256) {
+        const int l = e >> 8, x = e & 255;
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            C1<R> A;
+            if (x == 0) {
+                const C1<R>* sp = in + ((line0 + l) * (M / 2)) * 4 + 2 * g;
+                A = {sp[0].re, sp[1].re};
+            } else if (x < M / 2) {
+                const C1<R>* sp = in + ((line0 + l) * (M / 2) + x) * 4 + 2 * g;
+                A = {sp[0].re - sp[1].im, sp[0].im + sp[1].re};
+            } else if (x == M / 2) {
+                A = {R(0), R(0)};
+            } else {
+                const C1<R>* sp = in + ((line0 + l) * (M / 2) + (M - x)) * 4 + 2 * g;
+                A = {sp[0].re + sp[1].im, sp[1].re - sp[0].im};
+            }
+            buf[(2 * l + g) * kL16Line + x] = A;
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int l16 = (lane >> 4) + 4 * (threadIdx.x >> 6), t = lane & 15;
+    C1<R>* ln = buf + l16 * kL16Line;
+    C1<R> v[16];
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) v[n1] = ln[16 * n1 + t];
+    __syncthreads();   // the exchange below reuses the line
+    fft256_line(v, ln, tw, t, -1);
+    __syncthreads();
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) ln[16 * k2 + t] = v[4 * (k2 & 3) + (k2 >> 2)];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 8 * M; e += 256) {
+        const int l = e >> 8, x = e & 255;
+        const C1<R> A = buf[(2 * l) * kL16Line + x], B = buf[(2 * l + 1) * kL16Line + x];
+        out[(line0 + l) * M + x] = {A.re, A.im, B.re, B.im};
+    }
+}
+
 struct KScale {
     double twopi_over_L;   // k = (2 pi / L) q
     double inv4xi2;        // 1 / (4 xi^2)
@@ -1336,8 +1430,12 @@ static int launch_fft_chain_M(int M, void* rgrid, void* spec, const double* tw, 
     case MM: {                                                                                            \
         const int lines = MM * MM;                                                                        \
         tm->begin(kPhaseFftXFwd, st);                                                                     \
-        hipLaunchKernelGGL((k_fft_x_fwd<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,                \
-                           (const R4<R>*)rgrid, (C1<R>*)spec, tw);                                        \
+        if (MM == 256 && !dbl && !kFftCompute64)                                                          \
+            hipLaunchKernelGGL((k_fft_x_fwd256<R>), dim3(lines / 8), dim3(256), 0, st,                    \
+                               (const R4<R>*)rgrid, (C1<R>*)spec, tw);                                    \
+        else                                                                                              \
+            hipLaunchKernelGGL((k_fft_x_fwd<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,            \
+                               (const R4<R>*)rgrid, (C1<R>*)spec, tw);                                    \
         if (MM == 256 && !dbl && !kFftCompute64) {                                                        \
             tm->begin(kPhaseFftYFwd, st);                                                                 \
             hipLaunchKernelGGL((k_fft_y256<R>), dim3(32 * 256), dim3(256), 0, st, (C1<R>*)spec, tw, +1);  \
@@ -1357,8 +1455,12 @@ static int launch_fft_chain_M(int M, void* rgrid, void* spec, const double* tw, 
                                (C1<R>*)spec, tw, -1);                                                     \
         }                                                                                                 \
         tm->begin(kPhaseFftXInv, st);                                                                     \
-        hipLaunchKernelGGL((k_fft_x_inv<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,                \
-                           (const C1<R>*)spec, (R4<R>*)rgrid, tw);                                        \
+        if (MM == 256 && !dbl && !kFftCompute64)                                                          \
+            hipLaunchKernelGGL((k_fft_x_inv256<R>), dim3(lines / 8), dim3(256), 0, st,                    \
+                               (const C1<R>*)spec, (R4<R>*)rgrid, tw);                                    \
+        else                                                                                              \
+            hipLaunchKernelGGL((k_fft_x_inv<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,            \
+                               (const C1<R>*)spec, (R4<R>*)rgrid, tw);                                    \
         break;                                                                                            \
     }
 
