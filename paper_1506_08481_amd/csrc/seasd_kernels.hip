@@ -270,6 +270,8 @@ __global__ void k_bin_gather(int n, const int* __restrict__ perm, const double* 
 // below this many spheres the neighbour list and the pair sum use one
 // wavefront per sphere (one thread per sphere would leave most CUs idle)
 constexpr int kWaveSpheres = 32768;
+// lanes per sphere of the neighbour-list search for larger suspensions (1: one thread)
+constexpr int kGroupLarge = 1;
 
 __device__ inline int floordiv(int c, int nb) { return (c >= 0) ? c / nb : -((-c + nb - 1) / nb); }
 
@@ -342,21 +344,24 @@ __global__ __launch_bounds__(256) void k_pair_fill(int n, const double* __restri
     atomicMax(maxcount, k);
 }
 
-// The same list with one wavefront per sphere, for suspensions too small to
-// fill the chip with one thread per sphere: lane l takes bins l, l + 64, ... of the
+// The same list with a group of G lanes per sphere (G = 64: a wavefront, for
+// suspensions too small to fill the chip with one thread per sphere; smaller G
+// for large ones, where neighbouring spheres of one wavefront share bins):
+// lane l of the group takes bins l, l + G, ... of the
 // (2 reach + 1)^3 neighbour bins in the visiting order of for_each_neighbour,
 // counts its hits, a wavefront prefix sum gives every lane its first slot and
 // a second sweep over the lane's bin writes the entries, so the list comes out
 // in the same order as the serial search.
-__global__ __launch_bounds__(256) void k_pair_fill_wave(int n, const double* __restrict__ sp,
+template <int G>
+__global__ __launch_bounds__(256) void k_pair_fill_group(int n, const double* __restrict__ sp,
                                                         const double* __restrict__ sa, const int* __restrict__ start,
                                                         int nb, double L, double binw, double rc_factor,
                                                         const unsigned long long* __restrict__ amax_bits, int checks,
                                                         int cap, int* __restrict__ ncount, int* __restrict__ maxcount,
                                                         int2* __restrict__ list, int* __restrict__ err) {
-    const int lane = threadIdx.x & 63;
-    const int s = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
-    if (s >= n) return;   // whole wavefronts only; the kernel has no barrier
+    const int lane = threadIdx.x & (G - 1);
+    const int s = xcd_block(blockIdx.x, gridDim.x) * (256 / G) + threadIdx.x / G;
+    if (s >= n) return;   // whole groups only; the kernel has no barrier
     const double amax = __longlong_as_double((long long)*amax_bits);
     const double px = sp[3 * s], py = sp[3 * s + 1], pz = sp[3 * s + 2];
     const double ai = sa[s];
@@ -370,7 +375,7 @@ __global__ __launch_bounds__(256) void k_pair_fill_wave(int n, const double* __r
               bz = min(nb - 1, (int)(pz / binw));
     int2* dst = list + (size_t)cap * s;
     int total = 0;
-    for (int base = 0; base < nbins; base += 64) {
+    for (int base = 0; base < nbins; base += G) {
         const int q = base + lane;
         int j0 = 0, j1 = 0, code = 0;
         double ox = 0.0, oy = 0.0, oz = 0.0;
@@ -402,8 +407,8 @@ __global__ __launch_bounds__(256) void k_pair_fill_wave(int n, const double* __r
             ++cnt;
         }
         int incl = cnt;
-        for (int off = 1; off < 64; off <<= 1) {
-            const int v = __shfl_up(incl, off, 64);
+        for (int off = 1; off < G; off <<= 1) {
+            const int v = __shfl_up(incl, off, G);
             if (lane >= off) incl += v;
         }
         int k = total + incl - cnt;
@@ -419,7 +424,7 @@ __global__ __launch_bounds__(256) void k_pair_fill_wave(int n, const double* __r
                 ++k;
             }
         }
-        total += __shfl(incl, 63, 64);
+        total += __shfl(incl, G - 1, G);
     }
     if (lane == 0) {
         ncount[s] = total;
@@ -1509,9 +1514,13 @@ int launch_pairlist(const ApplyArgs& A, hipStream_t st) {
     if (!(A.parts & kPartsReal)) return 0;
     hipMemsetAsync(A.maxcount, 0, sizeof(int), st);
     if (n < kWaveSpheres)
-        hipLaunchKernelGGL(k_pair_fill_wave, dim3((n + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb,
-                           A.L, A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount, A.maxcount, A.list,
-                           A.err);
+        hipLaunchKernelGGL((k_pair_fill_group<64>), dim3((n + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa, A.start,
+                           A.nb, A.L, A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount, A.maxcount,
+                           A.list, A.err);
+    else if (kGroupLarge > 1)
+        hipLaunchKernelGGL((k_pair_fill_group<kGroupLarge>), dim3((n + 256 / kGroupLarge - 1) / (256 / kGroupLarge)),
+                           dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb, A.L, A.binw, A.rc_factor, A.amax_bits,
+                           A.checks, A.cap, A.ncount, A.maxcount, A.list, A.err);
     else
         hipLaunchKernelGGL(k_pair_fill, dim3((n + 255) / 256), dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb,
                            A.L, A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount, A.maxcount, A.list,
