@@ -97,8 +97,7 @@ extern "C" {
 typedef struct seasd_config {
     int32_t grid;           /* M, grid points per dimension: power of two, 8..512            */
     int32_t P;              /* window support in grid points per dimension: even, 4..min(M,32) */
-    int32_t tile;           /* spreading tile = bin edge in grid points: 4, 8, or 0 (auto:    */
-                            /* 4 below M = 128, else 8)                                      */
+    int32_t tile;           /* spreading tile = bin edge in grid points: 4, 8, or 0 (auto: 8) */
     double  m;              /* window shape parameter (eq. theta-param); <= 0: sqrt(pi P)   */
     double  xi;             /* Ewald splitting parameter, Beenakker convention (Sec. 2.2)   */
     double  rc_factor;      /* real-space cut-off r_c = rc_factor (a_i + a_j), > 1           */
@@ -206,8 +205,8 @@ int seasd_profile_read(seasd_handle handle, double* ms, int32_t count);
  * (1e-6 or looser) in the given precision. It picks the grid M (a power of
  * two, 32..256: for targets of 1e-6 or looser the finest with spacing
  * L/M >= 0.21 a_max, below which the window's Faxen terms lose accuracy;
- * for tighter targets the spacing nearest 0.4 a_max; the bins are tiles of
- * 4^3 grid points below M = 128 and of 8^3 from 128 up), xi from the grid spacing so that the k-space tail
+ * for tighter targets the spacing nearest 0.4 a_max; the bins are 8^3
+ * tiles of that grid), xi from the grid spacing so that the k-space tail
  * exp(-k_max^2/(4 xi^2)) stays fixed, the real-space cut-off factor so that
  * xi r_c is fixed for a pair of spheres of radius a_min (the batch planner
  * passes the 10th-percentile radius), and the window (P, m) from accuracy

