@@ -1344,20 +1344,27 @@ __global__ __launch_bounds__(256) void k_gather(
     double alpha, double cwh3, double inv_eta, int parts, int compressible,
     const double* __restrict__ ybuf, double* __restrict__ yout) {
     constexpr int WPB = 4;
-    __shared__ R fac[WPB][3 * kMaxP];
+    __shared__ R fac[WPB][2 * kMaxP];
+    __shared__ R zt[WPB][4][kMaxP];   // f_z(kz) r_z(kz)^k, k = 0..3
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int nblk = (n + WPB - 1) / WPB;
     const int s0 = xcd_block(blockIdx.x, nblk) * WPB + wv;
     const bool active = s0 < n;       // every wavefront reaches the barrier
     const int s = active ? s0 : n - 1;
     const int mask = M - 1;
-    const int fl = 3 * P;
     const R* rc = recs + (size_t)rec_stride(P) * s;
-    for (int k = lane; k < fl; k += 64) fac[wv][k] = rc[kRecHead + k];
+    for (int k = lane; k < 2 * P; k += 64) fac[wv][k] = rc[kRecHead + k];
+    if (lane < P) {
+        const R rz = rc[6] + lane * (R)h, fz = rc[kRecHead + 2 * P + lane];
+        zt[wv][0][lane] = fz;
+        zt[wv][1][lane] = fz * rz;
+        zt[wv][2][lane] = fz * rz * rz;
+        zt[wv][3][lane] = fz * rz * rz * rz;
+    }
     __syncthreads();
     if (!active) return;
     const int4 i0 = make_int4(rec_i0(rc, 0), rec_i0(rc, 1), rec_i0(rc, 2), 0);
-    const R d0x = rc[4], d0y = rc[5], d0z = rc[6];
+    const R d0x = rc[4], d0y = rc[5];
     const R c0 = rc[21], c1 = rc[22], e0 = rc[23], d1 = rc[3];
     double acc[13];
     for (int c = 0; c < 13; ++c) acc[c] = 0.0;
@@ -1366,13 +1373,18 @@ __global__ __launch_bounds__(256) void k_gather(
         R ac[13], cp[13];
         for (int c = 0; c < 13; ++c) ac[c] = cp[c] = R(0);
         const int P2 = P * P;
+        // The window factorises into f_x f_y f_z and the Faxen polynomials
+        // are cubic in r_z, so each (x, y) column is reduced over z to the
+        // moments M_k[c] = sum_z f_z r_z^k g_c (k <= 3) first; the 13 outputs
+        // follow from them per column.
         for (int e = lane; e < P2; e += 64) {
             const int kx = e % P, ky = e / P;
             const R rx = d0x + kx * hh, ry = d0y + ky * hh;
             const R wxy = (R)cwh3 * fac[wv][kx] * fac[wv][P + ky];
+            const R rxy2 = rx * rx + ry * ry;
             const int gx = (i0.x + kx) & mask, gy = (i0.y + ky) & mask;
-            R col[13];
-            for (int c = 0; c < 13; ++c) col[c] = R(0);
+            R m0x = 0, m0y = 0, m0z = 0, m0w = 0, m1x = 0, m1y = 0, m1z = 0;
+            R m2x = 0, m2y = 0, m2z = 0, m3x = 0, m3y = 0, m3z = 0;
             const R4<R>* colp = grid + (size_t)gy * M + gx;
             const size_t zs = (size_t)M * M;
             // P is even: two grid loads in flight per step, several steps unrolled
@@ -1383,27 +1395,49 @@ __global__ __launch_bounds__(256) void k_gather(
               for (int hz = 0; hz < 2; ++hz) {
                 const int kz = kz2 + hz;
                 const R4<R> g = gpair[hz];
-                const R rz = d0z + kz * hh;
-                const R r2 = rx * rx + ry * ry + rz * rz;
-                const R w = wxy * fac[wv][2 * P + kz];
-                const R cU = w * (c0 + c1 * r2);
-                const R cE = w * (e0 + d1 * r2);
-                const R cW = al * w;
-                col[0] += cU * g.x;
-                col[1] += cU * g.y;
-                col[2] += cU * g.z;
-                col[3] += cW * (ry * g.z - rz * g.y);
-                col[4] += cW * (rz * g.x - rx * g.z);
-                col[5] += cW * (rx * g.y - ry * g.x);
-                col[6] += cE * g.x * rx;
-                col[7] += cE * g.y * ry;
-                col[8] += cE * g.z * rz;
-                col[9] += cE * R(0.5) * (g.x * ry + g.y * rx);
-                col[10] += cE * R(0.5) * (g.x * rz + g.z * rx);
-                col[11] += cE * R(0.5) * (g.y * rz + g.z * ry);
-                col[12] += w * g.w;
+                const R t0 = zt[wv][0][kz], t1 = zt[wv][1][kz], t2 = zt[wv][2][kz], t3 = zt[wv][3][kz];
+                m0x += t0 * g.x;
+                m0y += t0 * g.y;
+                m0z += t0 * g.z;
+                m0w += t0 * g.w;
+                m1x += t1 * g.x;
+                m1y += t1 * g.y;
+                m1z += t1 * g.z;
+                m2x += t2 * g.x;
+                m2y += t2 * g.y;
+                m2z += t2 * g.z;
+                m3x += t3 * g.x;
+                m3y += t3 * g.y;
+                m3z += t3 * g.z;
               }
             }
+            // with w = wxy f_z and r^2 = rxy2 + r_z^2:
+            //   sum w (c0 + c1 r^2) g = wxy (c0 M0 + c1 (rxy2 M0 + M2)),
+            //   Q = sum (w/wxy)(e0 + d1 r^2) g, R = the same with one more r_z
+            const R ux = c0 * m0x + c1 * (rxy2 * m0x + m2x);
+            const R uy = c0 * m0y + c1 * (rxy2 * m0y + m2y);
+            const R uz = c0 * m0z + c1 * (rxy2 * m0z + m2z);
+            const R qx = e0 * m0x + d1 * (rxy2 * m0x + m2x);
+            const R qy = e0 * m0y + d1 * (rxy2 * m0y + m2y);
+            const R qz = e0 * m0z + d1 * (rxy2 * m0z + m2z);
+            const R sx = e0 * m1x + d1 * (rxy2 * m1x + m3x);
+            const R sy = e0 * m1y + d1 * (rxy2 * m1y + m3y);
+            const R sz = e0 * m1z + d1 * (rxy2 * m1z + m3z);
+            const R aw = al * wxy, hw = R(0.5) * wxy;
+            R col[13];
+            col[0] = wxy * ux;
+            col[1] = wxy * uy;
+            col[2] = wxy * uz;
+            col[3] = aw * (ry * m0z - m1y);
+            col[4] = aw * (m1x - rx * m0z);
+            col[5] = aw * (rx * m0y - ry * m0x);
+            col[6] = wxy * rx * qx;
+            col[7] = wxy * ry * qy;
+            col[8] = wxy * sz;
+            col[9] = hw * (ry * qx + rx * qy);
+            col[10] = hw * (sx + rx * qz);
+            col[11] = hw * (sy + ry * qz);
+            col[12] = wxy * m0w;
             for (int c = 0; c < 13; ++c) neumaier(ac[c], cp[c], col[c]);
         }
         for (int c = 0; c < 13; ++c) acc[c] = (double)ac[c] + (double)cp[c];
