@@ -789,9 +789,16 @@ __global__ __launch_bounds__(spread_threads<TILE>()) void k_spread(
         __syncthreads();
         for (int c0 = 0; c0 < clen; c0 += STAGE) {
             const int cnt = min(STAGE, clen - c0);
-            for (int e = t; e < cnt * RS; e += NT) {
-                const int q = e / RS, k = e - q * RS;
-                st[q * RS + k] = recs[(size_t)RS * cand[c0 + q] + k];
+            {   // records are multiples of 16 bytes: copy them in 16-byte pieces
+                constexpr int V = 16 / sizeof(R);
+                const int RV = RS / V;
+                using V4 = typename std::conditional<sizeof(R) == 4, float4, double2>::type;
+                V4* stv = reinterpret_cast<V4*>(st);
+                const V4* rv = reinterpret_cast<const V4*>(recs);
+                for (int e = t; e < cnt * RV; e += NT) {
+                    const int q = e / RV, k = e - q * RV;
+                    stv[q * RV + k] = rv[(size_t)RV * cand[c0 + q] + k];
+                }
             }
             __syncthreads();
             R part[NPT][4];  // this round's contributions, plain sums
