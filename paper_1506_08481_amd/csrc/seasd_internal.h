@@ -116,7 +116,7 @@ struct ApplyArgs {
     int* perm;
     int* scan_tmp;   // block sums of the device scans
     int* ncount;     // [n] neighbours per binned sphere
-    int* maxcount;   // largest entry of ncount
+    int* maxcount;   // largest entry of ncount above cap (0 when every list fit)
     int cap;         // list slots per sphere
     int2* list;      // [n][cap] neighbour entries (j, packed image shift)
     unsigned long long* amax_bits;

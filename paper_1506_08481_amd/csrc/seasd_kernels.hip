@@ -90,26 +90,30 @@ __global__ void k_bin_count(int n, const double* __restrict__ pos, const double*
                             double L, int nb, double binw, int* __restrict__ bin_of,
                             int* __restrict__ counts, unsigned long long* __restrict__ amax_bits,
                             int* __restrict__ err) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double p[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
-    double a = rad[i];
-    bool bad = !(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]) && isfinite(a)) || !(a > 0.0);
-    if (bad) {
-        atomicOr(err, kErrNonfinite);
-        p[0] = p[1] = p[2] = 0.0;
-        a = 1.0;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double a = 0.0;   // radii are positive: 0 is neutral for the maximum
+    if (i < n) {
+        double p[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+        a = rad[i];
+        bool bad = !(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]) && isfinite(a)) || !(a > 0.0);
+        if (bad) {
+            atomicOr(err, kErrNonfinite);
+            p[0] = p[1] = p[2] = 0.0;
+            a = 1.0;
+        }
+        int b[3];
+        for (int d = 0; d < 3; ++d) {
+            double w = wrap_coord(p[d], L);
+            int k = (int)floor(w / binw);
+            b[d] = k < 0 ? 0 : (k >= nb ? nb - 1 : k);
+        }
+        int bin = bin_id(b[0], b[1], b[2]);
+        bin_of[i] = bin;
+        atomicAdd(&counts[bin], 1);
     }
-    int b[3];
-    for (int d = 0; d < 3; ++d) {
-        double w = wrap_coord(p[d], L);
-        int k = (int)floor(w / binw);
-        b[d] = k < 0 ? 0 : (k >= nb ? nb - 1 : k);
-    }
-    int bin = bin_id(b[0], b[1], b[2]);
-    bin_of[i] = bin;
-    atomicAdd(&counts[bin], 1);
-    atomicMax(amax_bits, (unsigned long long)__double_as_longlong(a));
+    // largest radius: one atomic per wavefront
+    for (int off = 32; off > 0; off >>= 1) a = fmax(a, __shfl_xor(a, off, 64));
+    if ((threadIdx.x & 63) == 0 && a > 0.0) atomicMax(amax_bits, (unsigned long long)__double_as_longlong(a));
 }
 
 // Device-wide exclusive scan of int counts: each workgroup of 256 threads
@@ -270,7 +274,12 @@ __global__ void k_bin_gather(int n, const int* __restrict__ perm, const double* 
 // below this many spheres the neighbour list and the pair sum use one
 // wavefront per sphere (one thread per sphere would leave most CUs idle)
 constexpr int kWaveSpheres = 32768;
-// lanes per sphere of the neighbour-list search for larger suspensions (1: one thread)
+// neighbour-list search for larger suspensions: one wavefront per bin, else
+// kGroupLarge lanes per sphere (1: one thread)
+#ifndef SEASD_FILL_BY_BIN
+#define SEASD_FILL_BY_BIN 1
+#endif
+constexpr bool kFillByBin = SEASD_FILL_BY_BIN != 0;
 constexpr int kGroupLarge = 1;
 
 __device__ inline int floordiv(int c, int nb) { return (c >= 0) ? c / nb : -((-c + nb - 1) / nb); }
@@ -323,8 +332,9 @@ __device__ inline void for_each_neighbour(int s, const double* __restrict__ sp, 
 }
 
 // One pass: every sphere lists its neighbours into its own slot of `cap`
-// entries (in visiting order), stores the full count and raises the running
-// maximum; the host grows cap and repeats the pass if the maximum exceeded it.
+// entries (in visiting order) and stores the full count; a count beyond cap
+// raises the overflow maximum, and the host then grows cap and repeats the
+// pass. Only overflowing spheres touch that one shared word.
 __global__ __launch_bounds__(256) void k_pair_fill(int n, const double* __restrict__ sp,
                                                    const double* __restrict__ sa, const int* __restrict__ start,
                                                    int nb, double L, double binw, double rc_factor,
@@ -341,7 +351,7 @@ __global__ __launch_bounds__(256) void k_pair_fill(int n, const double* __restri
         ++k;
     });
     ncount[s] = k;
-    atomicMax(maxcount, k);
+    if (k > cap) atomicMax(maxcount, k);
 }
 
 // The same list with a group of G lanes per sphere (G = 64: a wavefront, for
@@ -428,7 +438,159 @@ __global__ __launch_bounds__(256) void k_pair_fill_group(int n, const double* __
     }
     if (lane == 0) {
         ncount[s] = total;
-        atomicMax(maxcount, total);
+        if (total > cap) atomicMax(maxcount, total);
+    }
+}
+
+// The same lists with one wavefront per bin (large suspensions). The
+// wavefront holds the spheres of its bin, 64 at a time, one per lane ("home"
+// spheres), and walks the (2 reach + 1)^3 neighbour bins in the visiting order
+// of for_each_neighbour, reach taken from the largest home radius: 64 bins at a
+// time give their sphere ranges (one bin per lane) and a wavefront prefix sum;
+// the candidates of those bins are listed in LDS in visiting order and taken
+// into registers up to 512 at a time (slot r of lane l: candidate 64 r + l),
+// then every home sphere is tested against them in order, a ballot giving
+// each hit its slot. A bin beyond a sphere's own reach holds no sphere within
+// its cut-off, so each list is exactly the one the serial search writes; the
+// candidate loads are coalesced and shared by all spheres of the bin.
+constexpr int kFillSlots = 8;   // candidate slots per lane and pass
+
+__device__ inline int lanes_below(unsigned long long m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+// value of lane l (l uniform across the wavefront)
+__device__ inline int lane_value(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ inline double lane_value(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+// orders the LDS accesses of one wavefront before and after it
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(256) void k_pair_fill_bin(int n, const double* __restrict__ sp,
+                                                      const double* __restrict__ sa, const int* __restrict__ start,
+                                                      int nb, double L, double binw, double rc_factor,
+                                                      const unsigned long long* __restrict__ amax_bits, int checks,
+                                                      int cap, int* __restrict__ ncount, int* __restrict__ maxcount,
+                                                      int2* __restrict__ list, int* __restrict__ err) {
+    constexpr int W = kFillSlots * 64;
+    constexpr int kOwn = (512 << 20) | (512 << 10) | 512;   // image code of the unshifted sphere
+    __shared__ int2 cand_lds[4][W];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int2* cl = cand_lds[wv];
+    const int nbins = nb * nb * nb;
+    const int b = xcd_block(blockIdx.x, gridDim.x) * 4 + wv;
+    if (b >= nbins) return;   // whole wavefronts only; the kernel has no workgroup barrier
+    const int h0 = start[b], h1 = start[b + 1];
+    const double amax = __longlong_as_double((long long)*amax_bits);
+    const int bx = (int)compact_bits3((unsigned)b), by = (int)compact_bits3((unsigned)b >> 1),
+              bz = (int)compact_bits3((unsigned)b >> 2);
+    for (int hb = h0; hb < h1; hb += 64) {
+        const int nh = min(64, h1 - hb);
+        double hx = 0.0, hy = 0.0, hz = 0.0, ha = 0.0;
+        if (lane < nh) {
+            hx = sp[3 * (hb + lane)];
+            hy = sp[3 * (hb + lane) + 1];
+            hz = sp[3 * (hb + lane) + 2];
+            ha = sa[hb + lane];
+        }
+        double amx = 0.0;
+        for (int h = 0; h < nh; ++h) amx = fmax(amx, lane_value(ha, h));
+        int reach = (int)ceil(rc_factor * (amx + amax) / binw);
+        if (reach > 3 * nb + 2) {
+            if (lane == 0) atomicOr(err, kErrCutoff);
+            reach = 3 * nb + 2;
+        }
+        const int span = 2 * reach + 1, nnb = span * span * span;
+        int cnt = 0;   // lane h: entries of home sphere hb + h so far
+        for (int q0 = 0; q0 < nnb; q0 += 64) {
+            int j0 = 0, len = 0, code = 0;
+            {   // lane u: neighbour bin q0 + u
+                const int q = q0 + lane;
+                if (q < nnb) {
+                    int cx = bx + q % span - reach, cy = by + (q / span) % span - reach,
+                        cz = bz + q / (span * span) - reach;
+                    const int wx = floordiv(cx, nb), wy = floordiv(cy, nb), wz = floordiv(cz, nb);
+                    cx -= wx * nb;
+                    cy -= wy * nb;
+                    cz -= wz * nb;
+                    const int bin = bin_id(cx, cy, cz);
+                    j0 = start[bin];
+                    len = start[bin + 1] - j0;
+                    code = ((wz + 512) << 20) | ((wy + 512) << 10) | (wx + 512);
+                }
+            }
+            int incl = len;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int v = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += v;
+            }
+            const int excl = incl - len;
+            const int tot = lane_value(incl, 63);
+            for (int w0 = 0; w0 < tot; w0 += W) {
+                const int wlen = min(W, tot - w0);
+                {   // list this window's candidates in LDS, in visiting order
+                    const int lo = max(excl, w0), hi = min(excl + len, w0 + wlen);
+                    for (int c = lo; c < hi; ++c) cl[c - w0] = make_int2(j0 + (c - excl), code);
+                }
+                wave_sync();
+                double cx[kFillSlots], cy[kFillSlots], cz[kFillSlots], ca[kFillSlots];
+                int cj[kFillSlots], cc[kFillSlots];
+#pragma unroll
+                for (int r = 0; r < kFillSlots; ++r) {
+                    const int c = 64 * r + lane;
+                    cj[r] = -1;
+                    cc[r] = 0;
+                    cx[r] = cy[r] = cz[r] = ca[r] = 0.0;
+                    if (c < wlen) {
+                        const int2 e = cl[c];
+                        const int wx = (e.y & 1023) - 512, wy = ((e.y >> 10) & 1023) - 512,
+                                  wz = ((e.y >> 20) & 1023) - 512;
+                        cj[r] = e.x;
+                        cc[r] = e.y;
+                        cx[r] = sp[3 * e.x] + wx * L;
+                        cy[r] = sp[3 * e.x + 1] + wy * L;
+                        cz[r] = sp[3 * e.x + 2] + wz * L;
+                        ca[r] = sa[e.x];
+                    }
+                }
+                wave_sync();   // the LDS list is read before the next window overwrites it
+                const int nslots = (wlen + 63) / 64;
+                for (int h = 0; h < nh; ++h) {
+                    const double px = lane_value(hx, h), py = lane_value(hy, h), pz = lane_value(hz, h);
+                    const double ai = lane_value(ha, h);
+                    const int sh = hb + h;
+                    int base = lane_value(cnt, h);
+#pragma unroll
+                    for (int r = 0; r < kFillSlots; ++r) {
+                        if (r >= nslots) break;
+                        bool hit = false;
+                        if (cj[r] >= 0 && !(cj[r] == sh && cc[r] == kOwn)) {
+                            const double dx = px - cx[r], dy = py - cy[r], dz = pz - cz[r];
+                            const double r2 = dx * dx + dy * dy + dz * dz;
+                            const double rc = rc_factor * (ai + ca[r]);
+                            hit = r2 < rc * rc;
+                            if (hit && checks && r2 < (ai + ca[r]) * (ai + ca[r]) * (1.0 - 1e-12))
+                                atomicOr(err, kErrOverlap);
+                        }
+                        const unsigned long long m = __ballot(hit);
+                        const int k = base + lanes_below(m);
+                        if (hit && k < cap) list[(size_t)cap * sh + k] = make_int2(cj[r], cc[r]);
+                        base += __popcll(m);
+                    }
+                    if (lane == h) cnt = base;
+                }
+            }
+        }
+        if (lane < nh) {
+            ncount[hb + lane] = cnt;
+            if (cnt > cap) atomicMax(maxcount, cnt);
+        }
     }
 }
 
@@ -1549,7 +1711,7 @@ int launch_geometry(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
 }
 
 // neighbour list into slots of A.cap entries; *A.maxcount receives the
-// largest count (the list is complete when it does not exceed A.cap)
+// largest count above A.cap (it stays 0 when every list fit its slots)
 int launch_pairlist(const ApplyArgs& A, hipStream_t st) {
     const int n = (int)A.n;
     if (!(A.parts & kPartsReal)) return 0;
@@ -1558,6 +1720,10 @@ int launch_pairlist(const ApplyArgs& A, hipStream_t st) {
         hipLaunchKernelGGL((k_pair_fill_group<64>), dim3((n + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa, A.start,
                            A.nb, A.L, A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount, A.maxcount,
                            A.list, A.err);
+    else if (kFillByBin)
+        hipLaunchKernelGGL(k_pair_fill_bin, dim3((A.nb * A.nb * A.nb + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa,
+                           A.start, A.nb, A.L, A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount,
+                           A.maxcount, A.list, A.err);
     else if (kGroupLarge > 1)
         hipLaunchKernelGGL((k_pair_fill_group<kGroupLarge>), dim3((n + 256 / kGroupLarge - 1) / (256 / kGroupLarge)),
                            dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb, A.L, A.binw, A.rc_factor, A.amax_bits,
