@@ -174,7 +174,7 @@ static int ensure_product_ws(seasd_handle h, int64_t n) {
     rc |= h->ncount.ensure(sizeof(int) * n);
     rc |= h->maxcount.ensure(sizeof(int));
     rc |= h->scan_tmp.ensure(sizeof(int) * (((size_t)std::max<int64_t>(n, (int64_t)nbins) + 2047) / 2048 + 2));
-    rc |= h->wrec.ensure(R * ((24 + 3 * h->cfg.P + 3) & ~3) * n);   // padded window records
+    rc |= h->wrec.ensure(R * rec_stride(h->cfg.P) * n);   // padded window records
     if (h->cfg.parts & SEASD_PARTS_WAVE) {
         rc |= h->rgrid.ensure(R * 4 * (size_t)M * M * M);
         rc |= h->spec.ensure(R * 4 * (size_t)M * M * M);

@@ -9,6 +9,12 @@
 namespace seasd {
 
 constexpr int kPartsReal = 1, kPartsWave = 2, kPartsSelf = 4;
+
+// window records: a header of kRecHead reals, then the 1-D window factors
+// x[P], y[P], z[P]; the length is rounded up to 4 reals so that staged records
+// keep 16-byte alignment
+constexpr int kRecHead = 24;
+__host__ __device__ inline int rec_stride(int P) { return (kRecHead + 3 * P + 3) & ~3; }
 constexpr int kErrNonfinite = 1, kErrOverlap = 2, kErrCutoff = 4;
 
 enum Phase {
@@ -125,7 +131,7 @@ struct ApplyArgs {
     double* sa;
     double* sx;
     double* ybuf;
-    void* wrec;      // [n][24 + 3P] R window records
+    void* wrec;      // [n][rec_stride(P)] R window records
     void* rgrid;
     void* spec;
     const double* twiddle;

@@ -780,9 +780,7 @@ constexpr int kMaxP = 32;
 // (1 + a^2 lap/6) h is w (c0 + c1 r2) and -(d/dr)(1 + a^2 lap/10) h / r is
 // w (e0 + d1 r2): c0 = 1 - a^2 alpha, c1 = (2/3) a^2 alpha^2,
 // e0 = 2 alpha - 2 a^2 alpha^2, d1 = 0.8 a^2 alpha^3.
-constexpr int kRecHead = 24;
-// record length rounded up to 4 reals, so staged records keep 16-byte alignment
-__host__ __device__ inline int rec_stride(int P) { return (kRecHead + 3 * P + 3) & ~3; }
+static_assert(kRecHead == 24, "record header layout above");
 
 __device__ inline void fgg_factors(double d0, double h, double alpha, int P, double* out) {
     const int kc = P / 2 - 1;               // d0 + kc h lies in (-h, 0]
