@@ -281,6 +281,11 @@ constexpr int kWaveSpheres = 32768;
 #endif
 constexpr bool kFillByBin = SEASD_FILL_BY_BIN != 0;
 constexpr int kGroupLarge = 1;
+// lanes per sphere of the pair sum for larger suspensions (1: one thread)
+#ifndef SEASD_EVAL_GROUP
+#define SEASD_EVAL_GROUP 1
+#endif
+constexpr int kEvalGroupLarge = SEASD_EVAL_GROUP;
 
 __device__ inline int floordiv(int c, int nb) { return (c >= 0) ? c / nb : -((-c + nb - 1) / nb); }
 
@@ -631,24 +636,29 @@ __global__ __launch_bounds__(128) void k_pair_eval(int n, const double* __restri
     for (int c = 0; c < 12; ++c) ybuf[12 * (size_t)s + c] = y[c];
 }
 
-// Pair sum with one wavefront per sphere (small suspensions): lane l
-// evaluates list entries l, l + 64, ...; the 12 partial sums are reduced
-// across the wavefront in a fixed butterfly order.
-__global__ __launch_bounds__(256) void k_pair_eval_wave(int n, const double* __restrict__ sp,
-                                                        const double* __restrict__ sa, const double* __restrict__ sx,
-                                                        const int* __restrict__ ncount, int cap,
-                                                        const int2* __restrict__ list, double L, double xi,
-                                                        double inv_eta, int parts, double* __restrict__ ybuf) {
-    const int lane = threadIdx.x & 63;
-    const int s = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
-    if (s >= n) return;   // whole wavefronts only; the kernel has no barrier
+// Pair sum with a group of G lanes per sphere: lane l of the group evaluates
+// list entries l, l + G, ..., and the 12 partial sums are reduced across the
+// group in a fixed butterfly order. G = 64 (a wavefront) serves suspensions
+// too small to fill the chip with one thread per sphere; for large ones a few
+// lanes per sphere read runs of consecutive neighbours together, which cuts
+// the cache lines each load instruction touches.
+template <int G>
+__global__ __launch_bounds__(256) void k_pair_eval_group(int n, const double* __restrict__ sp,
+                                                         const double* __restrict__ sa,
+                                                         const double* __restrict__ sx,
+                                                         const int* __restrict__ ncount, int cap,
+                                                         const int2* __restrict__ list, double L, double xi,
+                                                         double inv_eta, int parts, double* __restrict__ ybuf) {
+    const int lane = threadIdx.x & (G - 1);
+    const int s = xcd_block(blockIdx.x, gridDim.x) * (256 / G) + threadIdx.x / G;
+    if (s >= n) return;   // whole groups only; the kernel has no barrier
     const double px = sp[3 * s], py = sp[3 * s + 1], pz = sp[3 * s + 2];
     const double ai = sa[s];
     double y[12];
     for (int c = 0; c < 12; ++c) y[c] = 0.0;
     if (parts & kPartsReal) {
         const int k0 = cap * s, k1 = k0 + min(ncount[s], cap);
-        for (int k = k0 + lane; k < k1; k += 64) {
+        for (int k = k0 + lane; k < k1; k += G) {
             const int2 e = list[k];
             const int j = e.x;
             const int wx = (e.y & 1023) - 512, wy = ((e.y >> 10) & 1023) - 512, wz = ((e.y >> 20) & 1023) - 512;
@@ -659,8 +669,8 @@ __global__ __launch_bounds__(256) void k_pair_eval_wave(int n, const double* __r
             for (int c = 0; c < 12; ++c) xj[c] = sx[12 * (size_t)j + c];
             pair_coupling<double>(dx, dy, dz, ai, sa[j], xi, inv_eta, xj, y);
         }
-        for (int off = 32; off > 0; off >>= 1)
-            for (int c = 0; c < 12; ++c) y[c] += __shfl_xor(y[c], off, 64);
+        for (int off = G / 2; off > 0; off >>= 1)
+            for (int c = 0; c < 12; ++c) y[c] += __shfl_xor(y[c], off, G);
     }
     if (lane != 0) return;
     if (parts & kPartsSelf) {
@@ -1764,8 +1774,12 @@ int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     const int n = (int)A.n;
     tm->begin(kPhasePair, st);
     if (n < kWaveSpheres)
-        hipLaunchKernelGGL(k_pair_eval_wave, dim3((n + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.ncount,
-                           A.cap, A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
+        hipLaunchKernelGGL((k_pair_eval_group<64>), dim3((n + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa, A.sx,
+                           A.ncount, A.cap, A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
+    else if (kEvalGroupLarge > 1)
+        hipLaunchKernelGGL((k_pair_eval_group<kEvalGroupLarge>),
+                           dim3((n + 256 / kEvalGroupLarge - 1) / (256 / kEvalGroupLarge)), dim3(256), 0, st, n,
+                           A.sp, A.sa, A.sx, A.ncount, A.cap, A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
     else
         hipLaunchKernelGGL(k_pair_eval, dim3((n + 127) / 128), dim3(128), 0, st, n, A.sp, A.sa, A.sx, A.ncount,
                            A.cap, A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
