@@ -453,12 +453,15 @@ __global__ __launch_bounds__(256) void k_pair_fill_group(int n, const double* __
 // of for_each_neighbour, reach taken from the largest home radius: 64 bins at a
 // time give their sphere ranges (one bin per lane) and a wavefront prefix sum;
 // the candidates of those bins are listed in LDS in visiting order and taken
-// into registers up to 512 at a time (slot r of lane l: candidate 64 r + l),
+// into registers 64 kFillSlots at a time (slot r of lane l: candidate 64 r + l),
 // then every home sphere is tested against them in order, a ballot giving
 // each hit its slot. A bin beyond a sphere's own reach holds no sphere within
 // its cut-off, so each list is exactly the one the serial search writes; the
 // candidate loads are coalesced and shared by all spheres of the bin.
-constexpr int kFillSlots = 8;   // candidate slots per lane and pass
+#ifndef SEASD_FILL_SLOTS
+#define SEASD_FILL_SLOTS 4
+#endif
+constexpr int kFillSlots = SEASD_FILL_SLOTS;   // candidate slots per lane and pass
 
 __device__ inline int lanes_below(unsigned long long m) {
     return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
@@ -821,40 +824,63 @@ __device__ inline int rec_i0(const R* rec, int d) {
     else return (int)__double_as_longlong(rec[d]);
 }
 
+// One workgroup builds the records of 64 consecutive spheres in LDS (four
+// threads per sphere: the header, and the anchor, offset and factors of one
+// dimension each) and writes them out as one contiguous block, so every
+// record line is written whole.
+constexpr int kWinSpheres = 64;
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_window(int n, const double* __restrict__ sp, const double* __restrict__ sa,
                                                 const double* __restrict__ sx, int P, double h, double alpha,
                                                 R* __restrict__ rec_out) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    R* rec = rec_out + (size_t)rec_stride(P) * s;
-    double f[kMaxP];
-    for (int d = 0; d < 3; ++d) {
-        const double p = sp[3 * s + d];
-        const int i0 = (int)floor(p / h) - P / 2 + 1;
-        const double d0 = i0 * h - p;
-        if constexpr (sizeof(R) == 4) rec[d] = __int_as_float(i0);
-        else rec[d] = __longlong_as_double((long long)i0);
-        rec[4 + d] = (R)d0;
-        fgg_factors(d0, h, alpha, P, f);
-        for (int k = 0; k < P; ++k) rec[kRecHead + d * P + k] = (R)f[k];
+    __shared__ __attribute__((aligned(16))) R buf[kWinSpheres * ((kRecHead + 3 * kMaxP + 3) & ~3)];
+    const int RS = rec_stride(P);
+    const int s0 = blockIdx.x * kWinSpheres;
+    const int ns = min(kWinSpheres, n - s0);
+    const int t = threadIdx.x;
+    const int q = t >> 2, piece = t & 3;
+    if (q < ns) {
+        const int s = s0 + q;
+        R* rec = buf + q * RS;
+        if (piece > 0) {
+            const int d = piece - 1;
+            const double p = sp[3 * s + d];
+            const int i0 = (int)floor(p / h) - P / 2 + 1;
+            const double d0 = i0 * h - p;
+            if constexpr (sizeof(R) == 4) rec[d] = __int_as_float(i0);
+            else rec[d] = __longlong_as_double((long long)i0);
+            rec[4 + d] = (R)d0;
+            double f[kMaxP];
+            fgg_factors(d0, h, alpha, P, f);
+            for (int k = 0; k < P; ++k) rec[kRecHead + d * P + k] = (R)f[k];
+        } else {
+            const double a = sa[s];
+            const double a2 = a * a;
+            const double* xs = sx + 12 * (size_t)s;
+            rec[3] = (R)(0.8 * a2 * alpha * alpha * alpha);
+            rec[7] = (R)a2;
+            rec[21] = (R)(1.0 - a2 * alpha);
+            rec[22] = (R)(2.0 / 3.0 * a2 * alpha * alpha);
+            rec[23] = (R)(2.0 * alpha - 2.0 * a2 * alpha * alpha);
+            for (int d = 0; d < 3; ++d) {
+                rec[8 + d] = (R)xs[d];
+                rec[11 + d] = (R)xs[3 + d];
+            }
+            double S[6];
+            s5_to_sym<double>(xs + 6, S);
+            for (int d = 0; d < 6; ++d) rec[14 + d] = (R)S[d];
+            rec[20] = (R)(kSqrt3 * xs[11]);
+            for (int k = kRecHead + 3 * P; k < RS; ++k) rec[k] = R(0);   // padding
+        }
     }
-    const double a = sa[s];
-    const double a2 = a * a;
-    const double* xs = sx + 12 * (size_t)s;
-    rec[3] = (R)(0.8 * a2 * alpha * alpha * alpha);
-    rec[7] = (R)a2;
-    rec[21] = (R)(1.0 - a2 * alpha);
-    rec[22] = (R)(2.0 / 3.0 * a2 * alpha * alpha);
-    rec[23] = (R)(2.0 * alpha - 2.0 * a2 * alpha * alpha);
-    for (int d = 0; d < 3; ++d) {
-        rec[8 + d] = (R)xs[d];
-        rec[11 + d] = (R)xs[3 + d];
-    }
-    double S[6];
-    s5_to_sym<double>(xs + 6, S);
-    for (int d = 0; d < 6; ++d) rec[14 + d] = (R)S[d];
-    rec[20] = (R)(kSqrt3 * xs[11]);
+    __syncthreads();
+    // records are multiples of 16 bytes and the block starts on a record
+    using V = typename std::conditional<sizeof(R) == 4, float4, double2>::type;
+    constexpr int PV = 16 / sizeof(R);
+    const V* src = reinterpret_cast<const V*>(buf);
+    V* dst = reinterpret_cast<V*>(rec_out + (size_t)s0 * RS);
+    for (int e = t; e < ns * RS / PV; e += 256) dst[e] = src[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -1787,12 +1813,12 @@ int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     const int tiles = A.M / A.tile;
     KScale ks{2.0 * kPi / A.L, 1.0 / (4.0 * A.xi * A.xi), 2.0 * A.tau,
               1.0 / ((double)A.M * A.M * A.M), A.inv_eta};
-    const int gw = (n + 255) / 256;
+    const int gwin = (n + kWinSpheres - 1) / kWinSpheres;
     const int gg = (n + 3) / 4;
     const double cwh3 = A.cw * A.h * A.h * A.h;
     if (A.fp32) {
         tm->begin(kPhaseSpread, st);
-        hipLaunchKernelGGL((k_window<float>), dim3(gw), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.P, A.h, A.alpha,
+        hipLaunchKernelGGL((k_window<float>), dim3(gwin), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.P, A.h, A.alpha,
                            (float*)A.wrec);
         if (wave) {
             if (A.tile == 8)
@@ -1810,7 +1836,7 @@ int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
                            A.h, A.alpha, cwh3, A.inv_eta, A.parts, A.compressible, A.ybuf, A.y);
     } else {
         tm->begin(kPhaseSpread, st);
-        hipLaunchKernelGGL((k_window<double>), dim3(gw), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.P, A.h, A.alpha,
+        hipLaunchKernelGGL((k_window<double>), dim3(gwin), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.P, A.h, A.alpha,
                            (double*)A.wrec);
         if (wave) {
             if (A.tile == 8)
