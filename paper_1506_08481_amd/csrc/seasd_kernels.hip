@@ -1318,13 +1318,12 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd256(const R4<R>* __restrict__ 
     const int l16 = (lane >> 4) + 4 * (threadIdx.x >> 6), t = lane & 15;
     const int line = l16 >> 1, g = l16 & 1;
     const size_t line0 = (size_t)blockIdx.x * 8;
-    const R4<R>* src = in + (line0 + line) * M + t;
+    // the lanes of fields (x, y) and (z, w) of one line sit side by side in a
+    // wavefront, so each load instruction covers whole 256-byte rows once
+    const C1<R>* src = reinterpret_cast<const C1<R>*>(in) + ((line0 + line) * M + t) * 2 + g;
     C1<R> v[16];
 #pragma unroll
-    for (int n1 = 0; n1 < 16; ++n1) {
-        const R4<R> e = src[16 * n1];
-        v[n1] = g ? C1<R>{e.z, e.w} : C1<R>{e.x, e.y};
-    }
+    for (int n1 = 0; n1 < 16; ++n1) v[n1] = src[32 * n1];
     __syncthreads();   // twiddles
     C1<R>* ln = buf + l16 * kL16Line;
     fft256_line(v, ln, tw, t, +1);
@@ -1358,24 +1357,24 @@ __global__ __launch_bounds__(256) void k_fft_x_inv256(const C1<R>* __restrict__ 
     __shared__ C1<R> tw[M];
     load_twiddles<R, M>(tw, twg, -1);
     const size_t line0 = (size_t)blockIdx.x * 8;
-    for (int e = threadIdx.x; e < 8 * M; e += 256) {
-        const int l = e >> 8, x = e & 255;
+    // thread (l, q) reads the four spectra at q once and fills x = q and M - q
+    for (int e = threadIdx.x; e < 8 * (M / 2); e += 256) {
+        const int l = e >> 7, q = e & 127;
+        const C1<R>* sp = in + ((line0 + l) * (M / 2) + q) * 4;
+        C1<R> S[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) S[c] = sp[c];
 #pragma unroll
         for (int g = 0; g < 2; ++g) {
-            C1<R> A;
-            if (x == 0) {
-                const C1<R>* sp = in + ((line0 + l) * (M / 2)) * 4 + 2 * g;
-                A = {sp[0].re, sp[1].re};
-            } else if (x < M / 2) {
-                const C1<R>* sp = in + ((line0 + l) * (M / 2) + x) * 4 + 2 * g;
-                A = {sp[0].re - sp[1].im, sp[0].im + sp[1].re};
-            } else if (x == M / 2) {
-                A = {R(0), R(0)};
+            const C1<R> a = S[2 * g], b = S[2 * g + 1];
+            C1<R>* ln = buf + (2 * l + g) * kL16Line;
+            if (q == 0) {
+                ln[0] = {a.re, b.re};
+                ln[M / 2] = {R(0), R(0)};
             } else {
-                const C1<R>* sp = in + ((line0 + l) * (M / 2) + (M - x)) * 4 + 2 * g;
-                A = {sp[0].re + sp[1].im, sp[1].re - sp[0].im};
+                ln[q] = {a.re - b.im, a.im + b.re};
+                ln[M - q] = {a.re + b.im, b.re - a.im};
             }
-            buf[(2 * l + g) * kL16Line + x] = A;
         }
     }
     __syncthreads();
