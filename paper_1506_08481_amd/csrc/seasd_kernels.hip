@@ -286,6 +286,11 @@ constexpr int kGroupLarge = 1;
 #define SEASD_EVAL_GROUP 1
 #endif
 constexpr int kEvalGroupLarge = SEASD_EVAL_GROUP;
+// lanes per sphere of the pair sum below kWaveSpheres
+#ifndef SEASD_EVAL_GROUP_SMALL
+#define SEASD_EVAL_GROUP_SMALL 64
+#endif
+constexpr int kEvalGroupSmall = SEASD_EVAL_GROUP_SMALL;
 
 __device__ inline int floordiv(int c, int nb) { return (c >= 0) ? c / nb : -((-c + nb - 1) / nb); }
 
@@ -1180,23 +1185,23 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(const C1<R>* __restrict__ in,
     __shared__ C1<T> tw[M];
     load_twiddles<T, M>(tw, twg, -1);
     const size_t line0 = (size_t)blockIdx.x * LPB;
-    for (int e = threadIdx.x; e < LPB * M; e += blockDim.x) {
-        const int l = e / M, x = e - l * M;
+    // thread (l, q) reads the four spectra at q once and fills x = q and M - q:
+    // G0 + i G1 at q, conj G0 + i conj G1 at M - q, zero at the Nyquist plane
+    for (int e = threadIdx.x; e < LPB * (M / 2); e += blockDim.x) {
+        const int l = e / (M / 2), q = e - l * (M / 2);
+        const C1<R>* sp = in + ((line0 + l) * (M / 2) + q) * 4;
+        C1<R> S[4];
+        for (int c = 0; c < 4; ++c) S[c] = sp[c];
         for (int g = 0; g < 2; ++g) {
-            C1<T> A;
-            if (x == 0) {
-                const C1<R>* s = in + ((line0 + l) * (M / 2)) * 4 + 2 * g;
-                A = {(T)s[0].re, (T)s[1].re};
-            } else if (x < M / 2) {
-                const C1<R>* s = in + ((line0 + l) * (M / 2) + x) * 4 + 2 * g;
-                A = {(T)s[0].re - (T)s[1].im, (T)s[0].im + (T)s[1].re};       // G0 + i G1
-            } else if (x == M / 2) {
-                A = {T(0), T(0)};
+            const C1<R> a = S[2 * g], b = S[2 * g + 1];
+            C1<T>* ln = buf[0] + (2 * l + g) * M;
+            if (q == 0) {
+                ln[0] = {(T)a.re, (T)b.re};
+                ln[M / 2] = {T(0), T(0)};
             } else {
-                const C1<R>* s = in + ((line0 + l) * (M / 2) + (M - x)) * 4 + 2 * g;
-                A = {(T)s[0].re + (T)s[1].im, (T)s[1].re - (T)s[0].im};       // conj G0 + i conj G1
+                ln[q] = {(T)a.re - (T)b.im, (T)a.im + (T)b.re};
+                ln[M - q] = {(T)a.re + (T)b.im, (T)b.re - (T)a.im};
             }
-            buf[0][(2 * l + g) * M + x] = A;
         }
     }
     __syncthreads();
@@ -1799,8 +1804,9 @@ int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     const int n = (int)A.n;
     tm->begin(kPhasePair, st);
     if (n < kWaveSpheres)
-        hipLaunchKernelGGL((k_pair_eval_group<64>), dim3((n + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa, A.sx,
-                           A.ncount, A.cap, A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
+        hipLaunchKernelGGL((k_pair_eval_group<kEvalGroupSmall>),
+                           dim3((n + 256 / kEvalGroupSmall - 1) / (256 / kEvalGroupSmall)), dim3(256), 0, st, n,
+                           A.sp, A.sa, A.sx, A.ncount, A.cap, A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
     else if (kEvalGroupLarge > 1)
         hipLaunchKernelGGL((k_pair_eval_group<kEvalGroupLarge>),
                            dim3((n + 256 / kEvalGroupLarge - 1) / (256 / kEvalGroupLarge)), dim3(256), 0, st, n,
