@@ -22,8 +22,9 @@ struct seasd_handle_s {
     bool have_cfg = false;
     // product workspace
     DevBuf bin_of, counts, start, fill, perm, amax, err, sp, sa, sx, ybuf, rgrid, spec, twiddle;
-    DevBuf ncount, maxcount, list, total, wrec, scan_tmp;
+    DevBuf ncount, nstats, list, total, wrec, scan_tmp;
     int cap = 64;             // neighbour-list slots per sphere, grown on demand
+    int pair_group = 1;       // lanes per sphere of the pair sum chosen for the held geometry
     int64_t geom_n = -1;      // spheres in the geometry currently held in the workspace
     int twiddle_M = 0;
     // solver workspace
@@ -101,7 +102,7 @@ extern "C" int seasd_destroy(seasd_handle h) {
     hipSetDevice(h->device);
     DevBuf* bufs[] = {&h->bin_of, &h->counts, &h->start, &h->fill, &h->perm, &h->amax, &h->err,
                       &h->sp, &h->sa, &h->sx, &h->ybuf, &h->rgrid, &h->spec, &h->twiddle,
-                      &h->ncount, &h->maxcount, &h->list, &h->total, &h->wrec, &h->scan_tmp,
+                      &h->ncount, &h->nstats, &h->list, &h->total, &h->wrec, &h->scan_tmp,
                       &h->V, &h->w, &h->z, &h->u, &h->r, &h->bred, &h->hdev, &h->partial, &h->blocks,
                       &h->inv, &h->coef, &h->singular, &h->one_pos, &h->one_rad, &h->one_x, &h->one_y,
                       &h->inv2, &h->bad, &h->lx0, &h->lg, &h->lb, &h->lax, &h->lres};
@@ -172,7 +173,7 @@ static int ensure_product_ws(seasd_handle h, int64_t n) {
     rc |= h->sx.ensure(sizeof(double) * 12 * n);
     rc |= h->ybuf.ensure(sizeof(double) * 12 * n);
     rc |= h->ncount.ensure(sizeof(int) * n);
-    rc |= h->maxcount.ensure(sizeof(int));
+    rc |= h->nstats.ensure(2 * sizeof(unsigned long long));
     rc |= h->scan_tmp.ensure(sizeof(int) * (((size_t)std::max<int64_t>(n, (int64_t)nbins) + 2047) / 2048 + 2));
     rc |= h->wrec.ensure(R * rec_stride(h->cfg.P) * n);   // padded window records
     if (h->cfg.parts & SEASD_PARTS_WAVE) {
@@ -231,7 +232,8 @@ static void fill_args(seasd_handle h, ApplyArgs& A, int64_t n, const double* pos
     A.perm = h->perm.as<int>();
     A.scan_tmp = h->scan_tmp.as<int>();
     A.ncount = h->ncount.as<int>();
-    A.maxcount = h->maxcount.as<int>();
+    A.nstats = h->nstats.as<unsigned long long>();
+    A.pair_group = h->pair_group;
     A.cap = h->cap;
     A.list = h->list.as<int2>();
     A.amax_bits = h->amax.as<unsigned long long>();
@@ -272,10 +274,16 @@ static int queue_apply(seasd_handle h, int64_t n, const double* pos, const doubl
             A.cap = h->cap;
             if (launch_pairlist(A, st)) return SEASD_E_HIP;
             if (!(A.parts & kPartsReal)) break;
-            int mx = 0;
-            if (hipMemcpyAsync(&mx, A.maxcount, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+            unsigned long long ns[2] = {0, 0};
+            if (hipMemcpyAsync(ns, A.nstats, sizeof(ns), hipMemcpyDeviceToHost, st) != hipSuccess)
                 return SEASD_E_HIP;
             if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
+            // lists much longer than the average (spheres of very different
+            // sizes): one thread per sphere would leave most lanes waiting for
+            // the longest list of their wavefront
+            h->pair_group = ((double)ns[0] > kPairImbalance * (double)ns[1] / (double)n) ? 64 : 1;
+            A.pair_group = h->pair_group;
+            const int mx = (int)ns[0];
             if (mx <= h->cap) break;
             h->cap = mx + mx / 4 + 8;     // rare: grow and list again
         }

@@ -9,6 +9,12 @@
 namespace seasd {
 
 constexpr int kPartsReal = 1, kPartsWave = 2, kPartsSelf = 4;
+// a wavefront per sphere in the pair sum once the longest neighbour list
+// exceeds this multiple of the mean (measured: N = 5e4 spheres of radii 1 and
+// 2 at r_c = 6 (a_i + a_j), ratio about 5: 3.8 -> 0.76 ms; N = 1e5 equal
+// spheres at r_c = 3 (a_i + a_j), ratio about 1.3: one thread per sphere is
+// 1.35x faster)
+constexpr double kPairImbalance = 2.0;
 
 // window records: a header of kRecHead reals, then the 1-D window factors
 // x[P], y[P], z[P]; the length is rounded up to 4 reals so that staged records
@@ -122,7 +128,8 @@ struct ApplyArgs {
     int* perm;
     int* scan_tmp;   // block sums of the device scans
     int* ncount;     // [n] neighbours per binned sphere
-    int* maxcount;   // largest entry of ncount above cap (0 when every list fit)
+    unsigned long long* nstats;   // [0] largest entry of ncount, [1] their sum
+    int pair_group;  // lanes per sphere of the pair sum from kWaveSpheres spheres on (1 or 64)
     int cap;         // list slots per sphere
     int2* list;      // [n][cap] neighbour entries (j, packed image shift)
     unsigned long long* amax_bits;

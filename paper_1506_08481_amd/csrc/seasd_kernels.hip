@@ -21,6 +21,7 @@
 //              qx = M/2 plane is the Nyquist plane, which the method zeroes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 #include <stdint.h>
 
@@ -342,14 +343,13 @@ __device__ inline void for_each_neighbour(int s, const double* __restrict__ sp, 
 }
 
 // One pass: every sphere lists its neighbours into its own slot of `cap`
-// entries (in visiting order) and stores the full count; a count beyond cap
-// raises the overflow maximum, and the host then grows cap and repeats the
-// pass. Only overflowing spheres touch that one shared word.
+// entries (in visiting order) and stores the full count; when the largest
+// count exceeds cap the host grows cap and repeats the pass.
 __global__ __launch_bounds__(256) void k_pair_fill(int n, const double* __restrict__ sp,
                                                    const double* __restrict__ sa, const int* __restrict__ start,
                                                    int nb, double L, double binw, double rc_factor,
                                                    const unsigned long long* __restrict__ amax_bits, int checks,
-                                                   int cap, int* __restrict__ ncount, int* __restrict__ maxcount,
+                                                   int cap, int* __restrict__ ncount,
                                                    int2* __restrict__ list, int* __restrict__ err) {
     const int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -361,7 +361,6 @@ __global__ __launch_bounds__(256) void k_pair_fill(int n, const double* __restri
         ++k;
     });
     ncount[s] = k;
-    if (k > cap) atomicMax(maxcount, k);
 }
 
 // The same list with a group of G lanes per sphere (G = 64: a wavefront, for
@@ -377,7 +376,7 @@ __global__ __launch_bounds__(256) void k_pair_fill_group(int n, const double* __
                                                         const double* __restrict__ sa, const int* __restrict__ start,
                                                         int nb, double L, double binw, double rc_factor,
                                                         const unsigned long long* __restrict__ amax_bits, int checks,
-                                                        int cap, int* __restrict__ ncount, int* __restrict__ maxcount,
+                                                        int cap, int* __restrict__ ncount,
                                                         int2* __restrict__ list, int* __restrict__ err) {
     const int lane = threadIdx.x & (G - 1);
     const int s = xcd_block(blockIdx.x, gridDim.x) * (256 / G) + threadIdx.x / G;
@@ -448,7 +447,6 @@ __global__ __launch_bounds__(256) void k_pair_fill_group(int n, const double* __
     }
     if (lane == 0) {
         ncount[s] = total;
-        if (total > cap) atomicMax(maxcount, total);
     }
 }
 
@@ -489,7 +487,7 @@ __global__ __launch_bounds__(256) void k_pair_fill_bin(int n, const double* __re
                                                       const double* __restrict__ sa, const int* __restrict__ start,
                                                       int nb, double L, double binw, double rc_factor,
                                                       const unsigned long long* __restrict__ amax_bits, int checks,
-                                                      int cap, int* __restrict__ ncount, int* __restrict__ maxcount,
+                                                      int cap, int* __restrict__ ncount,
                                                       int2* __restrict__ list, int* __restrict__ err) {
     constexpr int W = kFillSlots * 64;
     constexpr int kOwn = (512 << 20) | (512 << 10) | 512;   // image code of the unshifted sphere
@@ -600,10 +598,37 @@ __global__ __launch_bounds__(256) void k_pair_fill_bin(int n, const double* __re
                 }
             }
         }
-        if (lane < nh) {
-            ncount[hb + lane] = cnt;
-            if (cnt > cap) atomicMax(maxcount, cnt);
+        if (lane < nh) ncount[hb + lane] = cnt;
+    }
+}
+
+// Largest and total list length (one atomic pair per workgroup): the host
+// reads them with the overflow check to choose how the pair sum spreads the
+// lists over lanes.
+__global__ __launch_bounds__(256) void k_count_stats(int n, const int* __restrict__ ncount,
+                                                    unsigned long long* __restrict__ stats) {
+    __shared__ unsigned long long ssum[256];
+    __shared__ int smax[256];
+    unsigned long long sum = 0;
+    int mx = 0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const int c = ncount[i];
+        sum += (unsigned long long)c;
+        mx = max(mx, c);
+    }
+    ssum[threadIdx.x] = sum;
+    smax[threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            ssum[threadIdx.x] += ssum[threadIdx.x + o];
+            smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + o]);
         }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMax(&stats[0], (unsigned long long)smax[0]);
+        atomicAdd(&stats[1], ssum[0]);
     }
 }
 
@@ -1748,28 +1773,29 @@ int launch_geometry(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-// neighbour list into slots of A.cap entries; *A.maxcount receives the
-// largest count above A.cap (it stays 0 when every list fit its slots)
+// neighbour list into slots of A.cap entries; A.nstats receives the largest
+// and the total count (the list is complete when the largest fits A.cap)
 int launch_pairlist(const ApplyArgs& A, hipStream_t st) {
     const int n = (int)A.n;
     if (!(A.parts & kPartsReal)) return 0;
-    hipMemsetAsync(A.maxcount, 0, sizeof(int), st);
+    hipMemsetAsync(A.nstats, 0, 2 * sizeof(unsigned long long), st);
     if (n < kWaveSpheres)
         hipLaunchKernelGGL((k_pair_fill_group<64>), dim3((n + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa, A.start,
-                           A.nb, A.L, A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount, A.maxcount,
+                           A.nb, A.L, A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount,
                            A.list, A.err);
     else if (kFillByBin)
         hipLaunchKernelGGL(k_pair_fill_bin, dim3((A.nb * A.nb * A.nb + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa,
                            A.start, A.nb, A.L, A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount,
-                           A.maxcount, A.list, A.err);
+                           A.list, A.err);
     else if (kGroupLarge > 1)
         hipLaunchKernelGGL((k_pair_fill_group<kGroupLarge>), dim3((n + 256 / kGroupLarge - 1) / (256 / kGroupLarge)),
                            dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb, A.L, A.binw, A.rc_factor, A.amax_bits,
-                           A.checks, A.cap, A.ncount, A.maxcount, A.list, A.err);
+                           A.checks, A.cap, A.ncount, A.list, A.err);
     else
         hipLaunchKernelGGL(k_pair_fill, dim3((n + 255) / 256), dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb,
-                           A.L, A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount, A.maxcount, A.list,
+                           A.L, A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount, A.list,
                            A.err);
+    hipLaunchKernelGGL(k_count_stats, dim3(std::min(256, (n + 255) / 256)), dim3(256), 0, st, n, A.ncount, A.nstats);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -1807,6 +1833,9 @@ int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
         hipLaunchKernelGGL((k_pair_eval_group<kEvalGroupSmall>),
                            dim3((n + 256 / kEvalGroupSmall - 1) / (256 / kEvalGroupSmall)), dim3(256), 0, st, n,
                            A.sp, A.sa, A.sx, A.ncount, A.cap, A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
+    else if (A.pair_group == 64)   // uneven lists (a wide radius distribution): a wavefront per sphere
+        hipLaunchKernelGGL((k_pair_eval_group<64>), dim3((n + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa, A.sx,
+                           A.ncount, A.cap, A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
     else if (kEvalGroupLarge > 1)
         hipLaunchKernelGGL((k_pair_eval_group<kEvalGroupLarge>),
                            dim3((n + 256 / kEvalGroupLarge - 1) / (256 / kEvalGroupLarge)), dim3(256), 0, st, n,
