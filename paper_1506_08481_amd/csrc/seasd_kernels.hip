@@ -825,7 +825,8 @@ constexpr int kMaxP = 32;
 // e0 = 2 alpha - 2 a^2 alpha^2, d1 = 0.8 a^2 alpha^3.
 static_assert(kRecHead == 24, "record header layout above");
 
-__device__ inline void fgg_factors(double d0, double h, double alpha, int P, double* out) {
+template <typename O>
+__device__ inline void fgg_factors(double d0, double h, double alpha, int P, O* out) {
     const int kc = P / 2 - 1;               // d0 + kc h lies in (-h, 0]
     const double dc = d0 + kc * h;
     const double e0 = exp(-alpha * dc * dc);
@@ -833,18 +834,18 @@ __device__ inline void fgg_factors(double d0, double h, double alpha, int P, dou
     const double q = exp(-alpha * h * h);          // exp(-alpha h^2)^(j^2)
     const double q2 = q * q;
     double v = e0, stp = up * q;
-    out[kc] = e0;
+    out[kc] = (O)e0;
     for (int k = kc + 1; k < P; ++k) {
         v *= stp;
         stp *= q2;
-        out[k] = v;
+        out[k] = (O)v;
     }
     v = e0;
     stp = q / up;
     for (int k = kc - 1; k >= 0; --k) {
         v *= stp;
         stp *= q2;
-        out[k] = v;
+        out[k] = (O)v;
     }
 }
 
@@ -881,9 +882,7 @@ __global__ __launch_bounds__(256) void k_window(int n, const double* __restrict_
             if constexpr (sizeof(R) == 4) rec[d] = __int_as_float(i0);
             else rec[d] = __longlong_as_double((long long)i0);
             rec[4 + d] = (R)d0;
-            double f[kMaxP];
-            fgg_factors(d0, h, alpha, P, f);
-            for (int k = 0; k < P; ++k) rec[kRecHead + d * P + k] = (R)f[k];
+            fgg_factors(d0, h, alpha, P, rec + kRecHead + d * P);   // straight into the LDS record
         } else {
             const double a = sa[s];
             const double a2 = a * a;
