@@ -87,7 +87,19 @@ __device__ inline double wrap_coord(double p, double L) {
     return (w < L && w >= 0.0) ? w : 0.0;
 }
 
-__global__ void k_bin_count(int n, const double* __restrict__ pos, const double* __restrict__ rad,
+// clears the per-bin counters and the radius maximum of a new geometry in
+// one launch
+__global__ void k_zero_geometry(int nbins, int* __restrict__ counts, int* __restrict__ fill,
+                                unsigned long long* __restrict__ amax_bits) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nbins) {
+        counts[i] = 0;
+        fill[i] = 0;
+    }
+    if (i == 0) *amax_bits = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_bin_count(int n, const double* __restrict__ pos, const double* __restrict__ rad,
                             double L, int nb, double binw, int* __restrict__ bin_of,
                             int* __restrict__ counts, unsigned long long* __restrict__ amax_bits,
                             int* __restrict__ err) {
@@ -112,9 +124,15 @@ __global__ void k_bin_count(int n, const double* __restrict__ pos, const double*
         bin_of[i] = bin;
         atomicAdd(&counts[bin], 1);
     }
-    // largest radius: one atomic per wavefront
+    // largest radius: one atomic per workgroup
+    __shared__ double wmax[4];
     for (int off = 32; off > 0; off >>= 1) a = fmax(a, __shfl_xor(a, off, 64));
-    if ((threadIdx.x & 63) == 0 && a > 0.0) atomicMax(amax_bits, (unsigned long long)__double_as_longlong(a));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+        if (m > 0.0) atomicMax(amax_bits, (unsigned long long)__double_as_longlong(m));
+    }
 }
 
 // Device-wide exclusive scan of int counts: each workgroup of 256 threads
@@ -602,16 +620,16 @@ __global__ __launch_bounds__(256) void k_pair_fill_bin(int n, const double* __re
     }
 }
 
-// Largest and total list length (one atomic pair per workgroup): the host
-// reads them with the overflow check to choose how the pair sum spreads the
-// lists over lanes.
-__global__ __launch_bounds__(256) void k_count_stats(int n, const int* __restrict__ ncount,
-                                                    unsigned long long* __restrict__ stats) {
-    __shared__ unsigned long long ssum[256];
-    __shared__ int smax[256];
+// Largest and total list length, by one workgroup of 1024 threads (no
+// atomics, nothing to clear): the host reads them with the overflow check to
+// choose how the pair sum spreads the lists over lanes.
+__global__ __launch_bounds__(1024) void k_count_stats(int n, const int* __restrict__ ncount,
+                                                     unsigned long long* __restrict__ stats) {
+    __shared__ unsigned long long ssum[1024];
+    __shared__ int smax[1024];
     unsigned long long sum = 0;
     int mx = 0;
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    for (int i = threadIdx.x; i < n; i += 1024) {
         const int c = ncount[i];
         sum += (unsigned long long)c;
         mx = max(mx, c);
@@ -619,7 +637,7 @@ __global__ __launch_bounds__(256) void k_count_stats(int n, const int* __restric
     ssum[threadIdx.x] = sum;
     smax[threadIdx.x] = mx;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (int o = 512; o > 0; o >>= 1) {
         if (threadIdx.x < o) {
             ssum[threadIdx.x] += ssum[threadIdx.x + o];
             smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + o]);
@@ -627,11 +645,13 @@ __global__ __launch_bounds__(256) void k_count_stats(int n, const int* __restric
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        atomicMax(&stats[0], (unsigned long long)smax[0]);
-        atomicAdd(&stats[1], ssum[0]);
+        stats[0] = (unsigned long long)smax[0];
+        stats[1] = ssum[0];
     }
 }
 
+// 246 VGPRs, two wavefronts per SIMD: asking for three (168 VGPRs, 200 bytes
+// of spills per thread) made it 2.2x slower
 __global__ __launch_bounds__(128) void k_pair_eval(int n, const double* __restrict__ sp,
                                                    const double* __restrict__ sa, const double* __restrict__ sx,
                                                    const int* __restrict__ ncount, int cap, const int2* __restrict__ list,
@@ -1758,12 +1778,11 @@ int launch_geometry(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     const int gb = (n + T - 1) / T;
     const int nbins = A.nb * A.nb * A.nb;
     tm->begin(kPhaseBin, st);
-    hipMemsetAsync(A.counts, 0, sizeof(int) * nbins, st);
-    hipMemsetAsync(A.amax_bits, 0, sizeof(unsigned long long), st);
+    hipLaunchKernelGGL(k_zero_geometry, dim3((nbins + T - 1) / T), dim3(T), 0, st, nbins, A.counts, A.fill,
+                       A.amax_bits);
     hipLaunchKernelGGL(k_bin_count, dim3(gb), dim3(T), 0, st, n, A.pos, A.radius, A.L, A.nb, A.binw,
                        A.bin_of, A.counts, A.amax_bits, A.err);
     launch_scan(nbins, A.counts, A.start, A.scan_tmp, st);
-    hipMemsetAsync(A.fill, 0, sizeof(int) * nbins, st);
     hipLaunchKernelGGL(k_bin_scatter, dim3(gb), dim3(T), 0, st, n, A.bin_of, A.start, A.fill, A.perm);
     hipLaunchKernelGGL(k_bin_order, dim3((nbins + T - 1) / T), dim3(T), 0, st, nbins, A.start, A.perm);
     hipLaunchKernelGGL(k_bin_gather, dim3(gb), dim3(T), 0, st, n, A.perm, A.pos, A.radius, A.x, A.L,
@@ -1777,7 +1796,6 @@ int launch_geometry(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
 int launch_pairlist(const ApplyArgs& A, hipStream_t st) {
     const int n = (int)A.n;
     if (!(A.parts & kPartsReal)) return 0;
-    hipMemsetAsync(A.nstats, 0, 2 * sizeof(unsigned long long), st);
     if (n < kWaveSpheres)
         hipLaunchKernelGGL((k_pair_fill_group<64>), dim3((n + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa, A.start,
                            A.nb, A.L, A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount,
@@ -1794,7 +1812,7 @@ int launch_pairlist(const ApplyArgs& A, hipStream_t st) {
         hipLaunchKernelGGL(k_pair_fill, dim3((n + 255) / 256), dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb,
                            A.L, A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount, A.list,
                            A.err);
-    hipLaunchKernelGGL(k_count_stats, dim3(std::min(256, (n + 255) / 256)), dim3(256), 0, st, n, A.ncount, A.nstats);
+    hipLaunchKernelGGL(k_count_stats, dim3(1), dim3(1024), 0, st, n, A.ncount, A.nstats);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
