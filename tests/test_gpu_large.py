@@ -1,7 +1,9 @@
 """Parity at the full benchmark size: N = 100,000 spheres at phi = 0.4,
 grid 256^3, in the launch configurations the benchmark times, checked at 64
 sampled spheres against the FP64 oracle (tests/golden/large_oracle_sample.npz,
-written by tests/golden/make_large_sample.py from the oracle alone)."""
+written by tests/golden/make_large_sample.py from the oracle alone). A second
+sample (bidisperse_oracle_sample.npz) covers a large suspension of two sphere
+sizes, whose uneven neighbour lists take the wavefront-per-sphere pair sum."""
 import math
 import os
 
@@ -12,6 +14,7 @@ from paper_1506_08481_amd import workloads as wl
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 GOLD = os.path.join(HERE, "golden", "large_oracle_sample.npz")
+GOLD_BI = os.path.join(HERE, "golden", "bidisperse_oracle_sample.npz")
 
 pytestmark = pytest.mark.gpu
 
@@ -59,4 +62,40 @@ def test_large_fp32_candidates(large, k):
     from paper_1506_08481_amd import seasd
     err, _ = _sample_error(bench.CANDIDATES[k], seasd.SEASD_FP32, large)
     print(f"fp32 candidate {bench.CANDIDATES[k]} sample error {err:.3e}")
+    assert err < 2e-6
+
+
+@pytest.fixture(scope="module")
+def bidisperse():
+    import sys
+    import torch
+    sys.path.insert(0, os.path.join(HERE, "golden"))
+    import make_large_sample as mk
+    d = np.load(GOLD_BI)
+    s = mk.bidisperse_workload()
+    x = wl.force_moments(s.n, mk.BI_SEED_X)
+    np.testing.assert_allclose([s.pos.sum(), (s.pos ** 2).sum()], d["pos_checksum"], rtol=1e-12)
+    np.testing.assert_allclose([x.sum(), (x ** 2).sum()], d["x_checksum"], rtol=1e-12)
+    dev = torch.device("cuda:0")
+    return s, [torch.as_tensor(a, device=dev) for a in (s.pos, s.radius, x)], d["targets"], d["y"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_large_bidisperse_autotuned(bidisperse, prec):
+    """N = 40,000 spheres of radii 1 and 2 at phi = 0.35 in the configuration
+    the autotuner picks for a 1e-6 target (128^3, r_c about 6 (a_i + a_j)): a
+    large sphere then has about five times the mean number of neighbours, so
+    the pair sum runs with a wavefront per sphere. Sample error within twice
+    the target."""
+    from paper_1506_08481_amd import seasd
+    s, (P_, R_, X_), tg, yo = bidisperse
+    precision = seasd.SEASD_FP64 if prec == "fp64" else seasd.SEASD_FP32
+    c = seasd.seasd_autotune(s.n, s.L, float(np.quantile(s.radius, 0.1)), float(s.radius.max()), 1e-6, precision)
+    cfg = {f: getattr(c, f) for f in ("grid", "P", "tile", "m", "xi", "rc_factor")}
+    eng = seasd.Seasd(0, **cfg, precision=precision, checks=1)
+    y = eng.apply(P_, R_, s.box, X_).cpu().numpy()
+    eng.close()
+    assert np.all(np.isfinite(y))
+    err = float(np.linalg.norm(y[tg] - yo) / np.linalg.norm(yo))
+    print(f"bidisperse {prec} {cfg} sample error {err:.3e}")
     assert err < 2e-6
