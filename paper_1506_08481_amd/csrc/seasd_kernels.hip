@@ -1020,9 +1020,11 @@ __global__ __launch_bounds__(spread_threads<TILE>()) void k_spread(
     const int ncand = pre[nbins_used];
     const R al = (R)alpha;
     const R hh = (R)h, cwr = (R)cw;
-    R acc[NPT][4], cmp[NPT][4];
+    // FP32: plain sums per stage (part) added to acc with Neumaier
+    // compensation (cmp); FP64 accumulates straight into part
+    R acc[NPT][4], cmp[NPT][4], part[NPT][4];
     for (int a = 0; a < NPT; ++a)
-        for (int c = 0; c < 4; ++c) acc[a][c] = cmp[a][c] = R(0);
+        for (int c = 0; c < 4; ++c) acc[a][c] = cmp[a][c] = part[a][c] = R(0);
 
     for (int cbase = 0; cbase < ncand; cbase += MAXC) {
         const int clen = min(MAXC, ncand - cbase);
@@ -1046,9 +1048,9 @@ __global__ __launch_bounds__(spread_threads<TILE>()) void k_spread(
                 }
             }
             __syncthreads();
-            R part[NPT][4];  // this round's contributions, plain sums
-            for (int a = 0; a < NPT; ++a)
-                for (int c = 0; c < 4; ++c) part[a][c] = R(0);
+            if constexpr (sizeof(R) == 4)
+                for (int a = 0; a < NPT; ++a)
+                    for (int c = 0; c < 4; ++c) part[a][c] = R(0);
             for (int q = 0; q < cnt; ++q) {
                 const R* rc = static_cast<const R*>(__builtin_assume_aligned(st + q * RS, 16));
                 const int i0x = rec_i0(rc, 0), i0y = rec_i0(rc, 1), i0z = rec_i0(rc, 2);
@@ -1092,18 +1094,26 @@ __global__ __launch_bounds__(spread_threads<TILE>()) void k_spread(
                     part[p][3] += w * sq;
                 }
             }
-            for (int a = 0; a < NPT; ++a)
-                for (int c = 0; c < 4; ++c) neumaier(acc[a][c], cmp[a][c], part[a][c]);
+            if constexpr (sizeof(R) == 4)
+                for (int a = 0; a < NPT; ++a)
+                    for (int c = 0; c < 4; ++c) neumaier(acc[a][c], cmp[a][c], part[a][c]);
             __syncthreads();
         }
     }
 #pragma unroll
     for (int p = 0; p < NPT; ++p) {
         R4<R> out;
-        out.x = acc[p][0] + cmp[p][0];
-        out.y = acc[p][1] + cmp[p][1];
-        out.z = acc[p][2] + cmp[p][2];
-        out.w = acc[p][3] + cmp[p][3];
+        if constexpr (sizeof(R) == 4) {
+            out.x = acc[p][0] + cmp[p][0];
+            out.y = acc[p][1] + cmp[p][1];
+            out.z = acc[p][2] + cmp[p][2];
+            out.w = acc[p][3] + cmp[p][3];
+        } else {   // FP64 sums need no compensation
+            out.x = part[p][0];
+            out.y = part[p][1];
+            out.z = part[p][2];
+            out.w = part[p][3];
+        }
         grid[((size_t)gz[p] * M + gy[p]) * M + gx[p]] = out;
     }
 }
@@ -1689,7 +1699,10 @@ __global__ __launch_bounds__(256) void k_gather(
             col[10] = hw * (sx + rx * qz);
             col[11] = hw * (sy + ry * qz);
             col[12] = wxy * m0w;
-            for (int c = 0; c < 13; ++c) neumaier(ac[c], cp[c], col[c]);
+            for (int c = 0; c < 13; ++c) {
+                if constexpr (sizeof(R) == 4) neumaier(ac[c], cp[c], col[c]);
+                else ac[c] += col[c];   // FP64 sums need no compensation
+            }
         }
         for (int c = 0; c < 13; ++c) acc[c] = (double)ac[c] + (double)cp[c];
         for (int off = 32; off > 0; off >>= 1)
