@@ -272,6 +272,8 @@ static int queue_apply(seasd_handle h, int64_t n, const double* pos, const doubl
             if (h->list.ensure(sizeof(int2) * (size_t)h->cap * n)) return SEASD_E_NOMEM;
             A.list = h->list.as<int2>();
             A.cap = h->cap;
+            if (attempt > 0 && hipMemsetAsync(A.nstats, 0, 2 * sizeof(unsigned long long), st) != hipSuccess)
+                return SEASD_E_HIP;
             if (launch_pairlist(A, st)) return SEASD_E_HIP;
             if (!(A.parts & kPartsReal)) break;
             unsigned long long ns[2] = {0, 0};

@@ -87,16 +87,21 @@ __device__ inline double wrap_coord(double p, double L) {
     return (w < L && w >= 0.0) ? w : 0.0;
 }
 
-// clears the per-bin counters and the radius maximum of a new geometry in
-// one launch
+// clears the per-bin counters, the radius maximum and the list statistics
+// of a new geometry in one launch
 __global__ void k_zero_geometry(int nbins, int* __restrict__ counts, int* __restrict__ fill,
-                                unsigned long long* __restrict__ amax_bits) {
+                                unsigned long long* __restrict__ amax_bits,
+                                unsigned long long* __restrict__ nstats) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nbins) {
         counts[i] = 0;
         fill[i] = 0;
     }
-    if (i == 0) *amax_bits = 0ull;
+    if (i == 0) {
+        *amax_bits = 0ull;
+        nstats[0] = 0ull;
+        nstats[1] = 0ull;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_bin_count(int n, const double* __restrict__ pos, const double* __restrict__ rad,
@@ -620,16 +625,19 @@ __global__ __launch_bounds__(256) void k_pair_fill_bin(int n, const double* __re
     }
 }
 
-// Largest and total list length, by one workgroup of 1024 threads (no
-// atomics, nothing to clear): the host reads them with the overflow check to
-// choose how the pair sum spreads the lists over lanes.
-__global__ __launch_bounds__(1024) void k_count_stats(int n, const int* __restrict__ ncount,
-                                                     unsigned long long* __restrict__ stats) {
-    __shared__ unsigned long long ssum[1024];
-    __shared__ int smax[1024];
+// Largest and total list length (one atomic pair per workgroup, at most 64
+// workgroups; the statistics are cleared with the geometry): the host reads
+// them with the overflow check to choose how the pair sum spreads the lists
+// over lanes.
+constexpr int kStatsBlocks = 64;
+
+__global__ __launch_bounds__(256) void k_count_stats(int n, const int* __restrict__ ncount,
+                                                    unsigned long long* __restrict__ stats) {
+    __shared__ unsigned long long ssum[256];
+    __shared__ int smax[256];
     unsigned long long sum = 0;
     int mx = 0;
-    for (int i = threadIdx.x; i < n; i += 1024) {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
         const int c = ncount[i];
         sum += (unsigned long long)c;
         mx = max(mx, c);
@@ -637,7 +645,7 @@ __global__ __launch_bounds__(1024) void k_count_stats(int n, const int* __restri
     ssum[threadIdx.x] = sum;
     smax[threadIdx.x] = mx;
     __syncthreads();
-    for (int o = 512; o > 0; o >>= 1) {
+    for (int o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o) {
             ssum[threadIdx.x] += ssum[threadIdx.x + o];
             smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + o]);
@@ -645,13 +653,11 @@ __global__ __launch_bounds__(1024) void k_count_stats(int n, const int* __restri
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        stats[0] = (unsigned long long)smax[0];
-        stats[1] = ssum[0];
+        atomicMax(&stats[0], (unsigned long long)smax[0]);
+        atomicAdd(&stats[1], ssum[0]);
     }
 }
 
-// 246 VGPRs, two wavefronts per SIMD: asking for three (168 VGPRs, 200 bytes
-// of spills per thread) made it 2.2x slower
 __global__ __launch_bounds__(128) void k_pair_eval(int n, const double* __restrict__ sp,
                                                    const double* __restrict__ sa, const double* __restrict__ sx,
                                                    const int* __restrict__ ncount, int cap, const int2* __restrict__ list,
@@ -1792,7 +1798,7 @@ int launch_geometry(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     const int nbins = A.nb * A.nb * A.nb;
     tm->begin(kPhaseBin, st);
     hipLaunchKernelGGL(k_zero_geometry, dim3((nbins + T - 1) / T), dim3(T), 0, st, nbins, A.counts, A.fill,
-                       A.amax_bits);
+                       A.amax_bits, A.nstats);
     hipLaunchKernelGGL(k_bin_count, dim3(gb), dim3(T), 0, st, n, A.pos, A.radius, A.L, A.nb, A.binw,
                        A.bin_of, A.counts, A.amax_bits, A.err);
     launch_scan(nbins, A.counts, A.start, A.scan_tmp, st);
@@ -1804,8 +1810,9 @@ int launch_geometry(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-// neighbour list into slots of A.cap entries; A.nstats receives the largest
-// and the total count (the list is complete when the largest fits A.cap)
+// neighbour list into slots of A.cap entries; A.nstats (cleared by
+// launch_geometry, or by the caller before a repeated pass) receives the
+// largest and the total count (the list is complete when the largest fits A.cap)
 int launch_pairlist(const ApplyArgs& A, hipStream_t st) {
     const int n = (int)A.n;
     if (!(A.parts & kPartsReal)) return 0;
@@ -1825,7 +1832,8 @@ int launch_pairlist(const ApplyArgs& A, hipStream_t st) {
         hipLaunchKernelGGL(k_pair_fill, dim3((n + 255) / 256), dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb,
                            A.L, A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount, A.list,
                            A.err);
-    hipLaunchKernelGGL(k_count_stats, dim3(1), dim3(1024), 0, st, n, A.ncount, A.nstats);
+    hipLaunchKernelGGL(k_count_stats, dim3(std::min(kStatsBlocks, (n + 255) / 256)), dim3(256), 0, st, n, A.ncount,
+                       A.nstats);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
