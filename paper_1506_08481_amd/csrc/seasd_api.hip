@@ -39,6 +39,10 @@ struct seasd_handle_s {
     DevBuf inv2, bad, lx0, lg, lb, lax, lres;
     PhaseTimer timer;
     hipStream_t last_stream = nullptr;
+    // list statistics read back after each neighbour-list build: pinned host
+    // words and the event that marks their copy
+    unsigned long long* ns_host = nullptr;
+    hipEvent_t ev_stats = nullptr;
 };
 
 static int hip_ok(hipError_t e) { return e == hipSuccess ? 0 : SEASD_E_HIP; }
@@ -107,6 +111,8 @@ extern "C" int seasd_destroy(seasd_handle h) {
                       &h->inv, &h->coef, &h->singular, &h->one_pos, &h->one_rad, &h->one_x, &h->one_y,
                       &h->inv2, &h->bad, &h->lx0, &h->lg, &h->lb, &h->lax, &h->lres};
     for (DevBuf* b : bufs) b->release();
+    if (h->ns_host) hipHostFree(h->ns_host);
+    if (h->ev_stats) hipEventDestroy(h->ev_stats);
     if (h->own_net) seasd_net_destroy(h->own_net);
     h->timer.destroy();
     delete h;
@@ -250,9 +256,10 @@ static void fill_args(seasd_handle h, ApplyArgs& A, int64_t n, const double* pos
 
 // Queue one product. With reuse_geometry the binning and neighbour list of the
 // previous call (same spheres) are kept and only the moments are re-binned.
-// Building a geometry waits once for the largest neighbour count (one 4-byte
-// copy) to confirm the list fit its slots; everything else is queued without
-// synchronisation.
+// Building a geometry waits once for the list statistics (one 16-byte copy
+// into pinned memory) to confirm the list fit its slots and to choose the pair
+// sum's lanes per sphere; the wave part, which does not read the list, is
+// queued before that wait. Everything else is queued without synchronisation.
 static int queue_apply(seasd_handle h, int64_t n, const double* pos, const double* radius, double L,
                        const double* x, double* y, hipStream_t st, bool checks, bool reuse_geometry = false,
                        int compressible = -1) {
@@ -265,9 +272,18 @@ static int queue_apply(seasd_handle h, int64_t n, const double* pos, const doubl
     h->timer.start_product();
     if (reuse_geometry && h->geom_n == n) {
         if (launch_moments(A, st)) return SEASD_E_HIP;
+        if (launch_compute(A, st, &h->timer)) return SEASD_E_HIP;
     } else {
         h->geom_n = -1;
         if (launch_geometry(A, st, &h->timer)) return SEASD_E_HIP;
+        if (!h->ns_host) {
+            if (hipHostMalloc((void**)&h->ns_host, 2 * sizeof(unsigned long long)) != hipSuccess) {
+                h->ns_host = nullptr;
+                return SEASD_E_NOMEM;
+            }
+            if (hipEventCreateWithFlags(&h->ev_stats, hipEventDisableTiming) != hipSuccess) return SEASD_E_HIP;
+        }
+        bool wave_queued = false;
         for (int attempt = 0; attempt < 3; ++attempt) {
             if (h->list.ensure(sizeof(int2) * (size_t)h->cap * n)) return SEASD_E_NOMEM;
             A.list = h->list.as<int2>();
@@ -276,22 +292,31 @@ static int queue_apply(seasd_handle h, int64_t n, const double* pos, const doubl
                 return SEASD_E_HIP;
             if (launch_pairlist(A, st)) return SEASD_E_HIP;
             if (!(A.parts & kPartsReal)) break;
-            unsigned long long ns[2] = {0, 0};
-            if (hipMemcpyAsync(ns, A.nstats, sizeof(ns), hipMemcpyDeviceToHost, st) != hipSuccess)
+            if (hipMemcpyAsync(h->ns_host, A.nstats, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                               st) != hipSuccess ||
+                hipEventRecord(h->ev_stats, st) != hipSuccess)
                 return SEASD_E_HIP;
-            if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
+            // the wave part does not read the list: queue it before waiting
+            // for the statistics, so the GPU keeps working meanwhile
+            if (!wave_queued) {
+                if (launch_wave(A, st, &h->timer)) return SEASD_E_HIP;
+                wave_queued = true;
+            }
+            if (hipEventSynchronize(h->ev_stats) != hipSuccess) return SEASD_E_HIP;
+            const unsigned long long mxl = h->ns_host[0], sum = h->ns_host[1];
             // lists much longer than the average (spheres of very different
             // sizes): one thread per sphere would leave most lanes waiting for
             // the longest list of their wavefront
-            h->pair_group = ((double)ns[0] > kPairImbalance * (double)ns[1] / (double)n) ? 64 : 1;
+            h->pair_group = ((double)mxl > kPairImbalance * (double)sum / (double)n) ? 64 : 1;
             A.pair_group = h->pair_group;
-            const int mx = (int)ns[0];
+            const int mx = (int)mxl;
             if (mx <= h->cap) break;
             h->cap = mx + mx / 4 + 8;     // rare: grow and list again
         }
         h->geom_n = n;
+        if (!wave_queued && launch_wave(A, st, &h->timer)) return SEASD_E_HIP;
+        if (launch_pair_gather(A, st, &h->timer)) return SEASD_E_HIP;
     }
-    if (launch_compute(A, st, &h->timer)) return SEASD_E_HIP;
     h->last_stream = st;
     return SEASD_OK;
 }

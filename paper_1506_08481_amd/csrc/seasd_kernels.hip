@@ -1863,8 +1863,52 @@ int launch_moments(const ApplyArgs& A, hipStream_t st) {
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-// pair sum, wave-space part and gather on an existing geometry
-int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
+// Wave-space part up to the inverse FFT (window records, spreading, the FFT
+// chain with the k-space multiply); it reads the binned geometry but not the
+// neighbour list.
+int launch_wave(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
+    const int n = (int)A.n;
+    const bool wave = (A.parts & kPartsWave) != 0;
+    const int tiles = A.M / A.tile;
+    KScale ks{2.0 * kPi / A.L, 1.0 / (4.0 * A.xi * A.xi), 2.0 * A.tau,
+              1.0 / ((double)A.M * A.M * A.M), A.inv_eta};
+    const int gwin = (n + kWinSpheres - 1) / kWinSpheres;
+    tm->begin(kPhaseSpread, st);
+    if (A.fp32) {
+        hipLaunchKernelGGL((k_window<float>), dim3(gwin), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.P, A.h, A.alpha,
+                           (float*)A.wrec);
+        if (wave) {
+            if (A.tile == 8)
+                hipLaunchKernelGGL((k_spread<float, 8>), dim3(tiles * tiles * tiles), dim3(spread_threads<8>()), 0, st, n,
+                                   (const float*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
+                                   (R4<float>*)A.rgrid);
+            else
+                hipLaunchKernelGGL((k_spread<float, 4>), dim3(tiles * tiles * tiles), dim3(64), 0, st, n,
+                                   (const float*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
+                                   (R4<float>*)A.rgrid);
+            if (launch_fft_chain_M<float>(A.M, A.rgrid, A.spec, A.twiddle, ks, st, tm)) return -1;
+        }
+    } else {
+        hipLaunchKernelGGL((k_window<double>), dim3(gwin), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.P, A.h, A.alpha,
+                           (double*)A.wrec);
+        if (wave) {
+            if (A.tile == 8)
+                hipLaunchKernelGGL((k_spread<double, 8>), dim3(tiles * tiles * tiles), dim3(spread_threads<8>()), 0, st, n,
+                                   (const double*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
+                                   (R4<double>*)A.rgrid);
+            else
+                hipLaunchKernelGGL((k_spread<double, 4>), dim3(tiles * tiles * tiles), dim3(64), 0, st, n,
+                                   (const double*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
+                                   (R4<double>*)A.rgrid);
+            if (launch_fft_chain_M<double>(A.M, A.rgrid, A.spec, A.twiddle, ks, st, tm)) return -1;
+        }
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// Pair sum (real-space part and self terms, on the neighbour list) and the
+// gather, which adds the wave-space velocities to it.
+int launch_pair_gather(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     const int n = (int)A.n;
     tm->begin(kPhasePair, st);
     if (n < kWaveSpheres)
@@ -1881,52 +1925,25 @@ int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     else
         hipLaunchKernelGGL(k_pair_eval, dim3((n + 127) / 128), dim3(128), 0, st, n, A.sp, A.sa, A.sx, A.ncount,
                            A.cap, A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
-    const bool wave = (A.parts & kPartsWave) != 0;
-    const int tiles = A.M / A.tile;
-    KScale ks{2.0 * kPi / A.L, 1.0 / (4.0 * A.xi * A.xi), 2.0 * A.tau,
-              1.0 / ((double)A.M * A.M * A.M), A.inv_eta};
-    const int gwin = (n + kWinSpheres - 1) / kWinSpheres;
     const int gg = (n + 3) / 4;
     const double cwh3 = A.cw * A.h * A.h * A.h;
-    if (A.fp32) {
-        tm->begin(kPhaseSpread, st);
-        hipLaunchKernelGGL((k_window<float>), dim3(gwin), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.P, A.h, A.alpha,
-                           (float*)A.wrec);
-        if (wave) {
-            if (A.tile == 8)
-                hipLaunchKernelGGL((k_spread<float, 8>), dim3(tiles * tiles * tiles), dim3(spread_threads<8>()), 0, st, n,
-                                   (const float*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
-                                   (R4<float>*)A.rgrid);
-            else
-                hipLaunchKernelGGL((k_spread<float, 4>), dim3(tiles * tiles * tiles), dim3(64), 0, st, n,
-                                   (const float*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
-                                   (R4<float>*)A.rgrid);
-            if (launch_fft_chain_M<float>(A.M, A.rgrid, A.spec, A.twiddle, ks, st, tm)) return -1;
-        }
-        tm->begin(kPhaseGather, st);
-        hipLaunchKernelGGL((k_gather<float>), dim3(gg), dim3(256), 0, st, n, (const float*)A.wrec, A.perm, (const R4<float>*)A.rgrid, A.M, A.P,
-                           A.h, A.alpha, cwh3, A.inv_eta, A.parts, A.compressible, A.ybuf, A.y);
-    } else {
-        tm->begin(kPhaseSpread, st);
-        hipLaunchKernelGGL((k_window<double>), dim3(gwin), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.P, A.h, A.alpha,
-                           (double*)A.wrec);
-        if (wave) {
-            if (A.tile == 8)
-                hipLaunchKernelGGL((k_spread<double, 8>), dim3(tiles * tiles * tiles), dim3(spread_threads<8>()), 0, st, n,
-                                   (const double*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
-                                   (R4<double>*)A.rgrid);
-            else
-                hipLaunchKernelGGL((k_spread<double, 4>), dim3(tiles * tiles * tiles), dim3(64), 0, st, n,
-                                   (const double*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
-                                   (R4<double>*)A.rgrid);
-            if (launch_fft_chain_M<double>(A.M, A.rgrid, A.spec, A.twiddle, ks, st, tm)) return -1;
-        }
-        tm->begin(kPhaseGather, st);
-        hipLaunchKernelGGL((k_gather<double>), dim3(gg), dim3(256), 0, st, n, (const double*)A.wrec, A.perm, (const R4<double>*)A.rgrid, A.M,
-                           A.P, A.h, A.alpha, cwh3, A.inv_eta, A.parts, A.compressible, A.ybuf, A.y);
-    }
+    tm->begin(kPhaseGather, st);
+    if (A.fp32)
+        hipLaunchKernelGGL((k_gather<float>), dim3(gg), dim3(256), 0, st, n, (const float*)A.wrec, A.perm,
+                           (const R4<float>*)A.rgrid, A.M, A.P, A.h, A.alpha, cwh3, A.inv_eta, A.parts,
+                           A.compressible, A.ybuf, A.y);
+    else
+        hipLaunchKernelGGL((k_gather<double>), dim3(gg), dim3(256), 0, st, n, (const double*)A.wrec, A.perm,
+                           (const R4<double>*)A.rgrid, A.M, A.P, A.h, A.alpha, cwh3, A.inv_eta, A.parts,
+                           A.compressible, A.ybuf, A.y);
     tm->end(st);
     return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// pair sum, wave-space part and gather on an existing geometry
+int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
+    if (launch_wave(A, st, tm)) return -1;
+    return launch_pair_gather(A, st, tm);
 }
 
 }  // namespace seasd
