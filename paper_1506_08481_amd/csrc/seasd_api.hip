@@ -258,8 +258,9 @@ static void fill_args(seasd_handle h, ApplyArgs& A, int64_t n, const double* pos
 // previous call (same spheres) are kept and only the moments are re-binned.
 // Building a geometry waits once for the list statistics (one 16-byte copy
 // into pinned memory) to confirm the list fit its slots and to choose the pair
-// sum's lanes per sphere; the wave part, which does not read the list, is
-// queued before that wait. Everything else is queued without synchronisation.
+// sum's lanes per sphere for the next products; the pair sum and the wave part
+// are queued before that wait. Everything else is queued without
+// synchronisation.
 static int queue_apply(seasd_handle h, int64_t n, const double* pos, const double* radius, double L,
                        const double* x, double* y, hipStream_t st, bool checks, bool reuse_geometry = false,
                        int compressible = -1) {
@@ -283,7 +284,7 @@ static int queue_apply(seasd_handle h, int64_t n, const double* pos, const doubl
             }
             if (hipEventCreateWithFlags(&h->ev_stats, hipEventDisableTiming) != hipSuccess) return SEASD_E_HIP;
         }
-        bool wave_queued = false;
+        bool queued = false;
         for (int attempt = 0; attempt < 3; ++attempt) {
             if (h->list.ensure(sizeof(int2) * (size_t)h->cap * n)) return SEASD_E_NOMEM;
             A.list = h->list.as<int2>();
@@ -296,11 +297,15 @@ static int queue_apply(seasd_handle h, int64_t n, const double* pos, const doubl
                                st) != hipSuccess ||
                 hipEventRecord(h->ev_stats, st) != hipSuccess)
                 return SEASD_E_HIP;
-            // the wave part does not read the list: queue it before waiting
-            // for the statistics, so the GPU keeps working meanwhile
-            if (!wave_queued) {
+            // The pair sum (lanes per sphere as chosen for the previous
+            // geometry: the choice changes the speed, not the result) and the
+            // wave part are queued before waiting for the statistics, so the
+            // GPU keeps working meanwhile; a list that overflowed its slots is
+            // built again and the pair sum repeated before the gather.
+            if (launch_pair(A, st, &h->timer)) return SEASD_E_HIP;
+            if (!queued) {
                 if (launch_wave(A, st, &h->timer)) return SEASD_E_HIP;
-                wave_queued = true;
+                queued = true;
             }
             if (hipEventSynchronize(h->ev_stats) != hipSuccess) return SEASD_E_HIP;
             const unsigned long long mxl = h->ns_host[0], sum = h->ns_host[1];
@@ -314,8 +319,10 @@ static int queue_apply(seasd_handle h, int64_t n, const double* pos, const doubl
             h->cap = mx + mx / 4 + 8;     // rare: grow and list again
         }
         h->geom_n = n;
-        if (!wave_queued && launch_wave(A, st, &h->timer)) return SEASD_E_HIP;
-        if (launch_pair_gather(A, st, &h->timer)) return SEASD_E_HIP;
+        if (!queued) {
+            if (launch_pair(A, st, &h->timer) || launch_wave(A, st, &h->timer)) return SEASD_E_HIP;
+        }
+        if (launch_gather(A, st, &h->timer)) return SEASD_E_HIP;
     }
     h->last_stream = st;
     return SEASD_OK;

@@ -149,7 +149,8 @@ int launch_pairlist(const ApplyArgs& a, hipStream_t st);
 int launch_moments(const ApplyArgs& a, hipStream_t st);
 int launch_compute(const ApplyArgs& a, hipStream_t st, PhaseTimer* tm);
 int launch_wave(const ApplyArgs& a, hipStream_t st, PhaseTimer* tm);
-int launch_pair_gather(const ApplyArgs& a, hipStream_t st, PhaseTimer* tm);
+int launch_pair(const ApplyArgs& a, hipStream_t st, PhaseTimer* tm);
+int launch_gather(const ApplyArgs& a, hipStream_t st, PhaseTimer* tm);
 
 // GMRES / preconditioner helpers (seasd_solver.hip)
 int launch_block_apply(int64_t n, const double* blocks, const double* v, double* z, hipStream_t st);

@@ -1906,9 +1906,8 @@ int launch_wave(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-// Pair sum (real-space part and self terms, on the neighbour list) and the
-// gather, which adds the wave-space velocities to it.
-int launch_pair_gather(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
+// Pair sum (real-space part and self terms, on the neighbour list) into ybuf.
+int launch_pair(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     const int n = (int)A.n;
     tm->begin(kPhasePair, st);
     if (n < kWaveSpheres)
@@ -1925,6 +1924,13 @@ int launch_pair_gather(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     else
         hipLaunchKernelGGL(k_pair_eval, dim3((n + 127) / 128), dim3(128), 0, st, n, A.sp, A.sa, A.sx, A.ncount,
                            A.cap, A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// Gather: the wave-space velocities added to the pair sum, scattered back to
+// the caller's order.
+int launch_gather(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
+    const int n = (int)A.n;
     const int gg = (n + 3) / 4;
     const double cwh3 = A.cw * A.h * A.h * A.h;
     tm->begin(kPhaseGather, st);
@@ -1942,8 +1948,9 @@ int launch_pair_gather(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
 
 // pair sum, wave-space part and gather on an existing geometry
 int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
+    if (launch_pair(A, st, tm)) return -2;
     if (launch_wave(A, st, tm)) return -1;
-    return launch_pair_gather(A, st, tm);
+    return launch_gather(A, st, tm);
 }
 
 }  // namespace seasd

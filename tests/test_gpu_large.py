@@ -85,17 +85,20 @@ def test_large_bidisperse_autotuned(bidisperse, prec):
     """N = 40,000 spheres of radii 1 and 2 at phi = 0.35 in the configuration
     the autotuner picks for a 1e-6 target (128^3, r_c about 6 (a_i + a_j)): a
     large sphere then has about five times the mean number of neighbours, so
-    the pair sum runs with a wavefront per sphere. Sample error within twice
-    the target."""
+    once the first product has measured the lists, the pair sum runs with a
+    wavefront per sphere. Both products agree to rounding; the second one's
+    sample error is within twice the target."""
     from paper_1506_08481_amd import seasd
     s, (P_, R_, X_), tg, yo = bidisperse
     precision = seasd.SEASD_FP64 if prec == "fp64" else seasd.SEASD_FP32
     c = seasd.seasd_autotune(s.n, s.L, float(np.quantile(s.radius, 0.1)), float(s.radius.max()), 1e-6, precision)
     cfg = {f: getattr(c, f) for f in ("grid", "P", "tile", "m", "xi", "rc_factor")}
     eng = seasd.Seasd(0, **cfg, precision=precision, checks=1)
-    y = eng.apply(P_, R_, s.box, X_).cpu().numpy()
+    y1 = eng.apply(P_, R_, s.box, X_).cpu().numpy()   # one thread per sphere, lists measured
+    y = eng.apply(P_, R_, s.box, X_).cpu().numpy()    # a wavefront per sphere
     eng.close()
     assert np.all(np.isfinite(y))
+    assert np.linalg.norm(y - y1) <= 1e-12 * np.linalg.norm(y)
     err = float(np.linalg.norm(y[tg] - yo) / np.linalg.norm(yo))
     print(f"bidisperse {prec} {cfg} sample error {err:.3e}")
     assert err < 2e-6
