@@ -1605,28 +1605,39 @@ __global__ __launch_bounds__(256) void k_fft_z256(C1<R>* __restrict__ data, cons
 // column sums are added with Neumaier compensation and the wavefront reduces
 // in FP64. Adds the pair/self part and writes y in input order.
 
-template <typename R>
+// G lanes per sphere (64, 32 or 16): a wavefront gathers 64 / G spheres at
+// once, each group of G lanes reading its sphere's columns 16 x-points at a
+// time, and the 13 sums are reduced over log2(G) butterfly levels. Measured at
+// N = 1e5, 256^3: 504 / 579 / 740 us for G = 64 / 32 / 16 (the shorter
+// butterfly does not pay for the longer load chain of each lane).
+#ifndef SEASD_GATHER_LANES
+#define SEASD_GATHER_LANES 64
+#endif
+constexpr int kGatherLanes = SEASD_GATHER_LANES;
+
+template <typename R, int G>
 __global__ __launch_bounds__(256) void k_gather(
     int n, const R* __restrict__ recs, const int* __restrict__ perm, const R4<R>* __restrict__ grid, int M, int P, double h,
     double alpha, double cwh3, double inv_eta, int parts, int compressible,
     const double* __restrict__ ybuf, double* __restrict__ yout) {
-    constexpr int WPB = 4;
-    __shared__ R fac[WPB][2 * kMaxP];
-    __shared__ R zt[WPB][4][kMaxP];   // f_z(kz) r_z(kz)^k, k = 0..3
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int nblk = (n + WPB - 1) / WPB;
-    const int s0 = xcd_block(blockIdx.x, nblk) * WPB + wv;
-    const bool active = s0 < n;       // every wavefront reaches the barrier
+    static_assert(G == 16 || G == 32 || G == 64, "lanes per sphere");
+    constexpr int SPB = 4 * (64 / G);   // spheres per workgroup
+    __shared__ R fac[SPB][2 * kMaxP];
+    __shared__ R zt[SPB][4][kMaxP];   // f_z(kz) r_z(kz)^k, k = 0..3
+    const int lane = threadIdx.x & (G - 1), sb = threadIdx.x / G;
+    const int nblk = (n + SPB - 1) / SPB;
+    const int s0 = xcd_block(blockIdx.x, nblk) * SPB + sb;
+    const bool active = s0 < n;       // every thread reaches the barrier
     const int s = active ? s0 : n - 1;
     const int mask = M - 1;
     const R* rc = recs + (size_t)rec_stride(P) * s;
-    for (int k = lane; k < 2 * P; k += 64) fac[wv][k] = rc[kRecHead + k];
-    if (lane < P) {
-        const R rz = rc[6] + lane * (R)h, fz = rc[kRecHead + 2 * P + lane];
-        zt[wv][0][lane] = fz;
-        zt[wv][1][lane] = fz * rz;
-        zt[wv][2][lane] = fz * rz * rz;
-        zt[wv][3][lane] = fz * rz * rz * rz;
+    for (int k = lane; k < 2 * P; k += G) fac[sb][k] = rc[kRecHead + k];
+    for (int kz = lane; kz < P; kz += G) {
+        const R rz = rc[6] + kz * (R)h, fz = rc[kRecHead + 2 * P + kz];
+        zt[sb][0][kz] = fz;
+        zt[sb][1][kz] = fz * rz;
+        zt[sb][2][kz] = fz * rz * rz;
+        zt[sb][3][kz] = fz * rz * rz * rz;
     }
     __syncthreads();
     if (!active) return;
@@ -1644,10 +1655,10 @@ __global__ __launch_bounds__(256) void k_gather(
         // are cubic in r_z, so each (x, y) column is reduced over z to the
         // moments M_k[c] = sum_z f_z r_z^k g_c (k <= 3) first; the 13 outputs
         // follow from them per column.
-        for (int e = lane; e < P2; e += 64) {
+        for (int e = lane; e < P2; e += G) {
             const int kx = e % P, ky = e / P;
             const R rx = d0x + kx * hh, ry = d0y + ky * hh;
-            const R wxy = (R)cwh3 * fac[wv][kx] * fac[wv][P + ky];
+            const R wxy = (R)cwh3 * fac[sb][kx] * fac[sb][P + ky];
             const R rxy2 = rx * rx + ry * ry;
             const int gx = (i0.x + kx) & mask, gy = (i0.y + ky) & mask;
             R m0x = 0, m0y = 0, m0z = 0, m0w = 0, m1x = 0, m1y = 0, m1z = 0;
@@ -1662,7 +1673,7 @@ __global__ __launch_bounds__(256) void k_gather(
               for (int hz = 0; hz < 2; ++hz) {
                 const int kz = kz2 + hz;
                 const R4<R> g = gpair[hz];
-                const R t0 = zt[wv][0][kz], t1 = zt[wv][1][kz], t2 = zt[wv][2][kz], t3 = zt[wv][3][kz];
+                const R t0 = zt[sb][0][kz], t1 = zt[sb][1][kz], t2 = zt[sb][2][kz], t3 = zt[sb][3][kz];
                 m0x += t0 * g.x;
                 m0y += t0 * g.y;
                 m0z += t0 * g.z;
@@ -1711,8 +1722,8 @@ __global__ __launch_bounds__(256) void k_gather(
             }
         }
         for (int c = 0; c < 13; ++c) acc[c] = (double)ac[c] + (double)cp[c];
-        for (int off = 32; off > 0; off >>= 1)
-            for (int c = 0; c < 13; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
+        for (int off = G / 2; off > 0; off >>= 1)
+            for (int c = 0; c < 13; ++c) acc[c] += __shfl_xor(acc[c], off, G);
     }
     if (lane == 0) {
         const int i = perm[s];
@@ -1931,15 +1942,16 @@ int launch_pair(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
 // the caller's order.
 int launch_gather(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     const int n = (int)A.n;
-    const int gg = (n + 3) / 4;
+    constexpr int spb = 4 * (64 / kGatherLanes);
+    const int gg = (n + spb - 1) / spb;
     const double cwh3 = A.cw * A.h * A.h * A.h;
     tm->begin(kPhaseGather, st);
     if (A.fp32)
-        hipLaunchKernelGGL((k_gather<float>), dim3(gg), dim3(256), 0, st, n, (const float*)A.wrec, A.perm,
+        hipLaunchKernelGGL((k_gather<float, kGatherLanes>), dim3(gg), dim3(256), 0, st, n, (const float*)A.wrec, A.perm,
                            (const R4<float>*)A.rgrid, A.M, A.P, A.h, A.alpha, cwh3, A.inv_eta, A.parts,
                            A.compressible, A.ybuf, A.y);
     else
-        hipLaunchKernelGGL((k_gather<double>), dim3(gg), dim3(256), 0, st, n, (const double*)A.wrec, A.perm,
+        hipLaunchKernelGGL((k_gather<double, kGatherLanes>), dim3(gg), dim3(256), 0, st, n, (const double*)A.wrec, A.perm,
                            (const R4<double>*)A.rgrid, A.M, A.P, A.h, A.alpha, cwh3, A.inv_eta, A.parts,
                            A.compressible, A.ybuf, A.y);
     tm->end(st);
