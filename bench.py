@@ -44,8 +44,8 @@ REF = (0.7, 3.5, 18, 0.95, 8)   # FP64 reference product (SE error ~1e-8)
 # profiles/product_n100000_phi0.4_grid256_traffic.md. Any other configuration
 # reports null.
 MEASURED_TRAFFIC = {
-    ("spread", 256, 16, 8): 321.9e6,
-    ("gather", 256, 16, 8): 1437.6e6,
+    ("spread", 256, 16, 8): 321.8e6,
+    ("gather", 256, 16, 8): 1445.1e6,
 }
 
 
