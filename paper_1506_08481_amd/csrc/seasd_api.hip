@@ -904,6 +904,14 @@ extern "C" int seasd_autotune(int64_t n, double L, double a_min, double a_max, d
     return SEASD_OK;
 }
 
+// streams the batch graph forks its suspensions over (256 suspensions,
+// 658,127 spheres: 24.8 / 24.6 / 24.3 ms per launch with 4 / 8 / 16 streams,
+// within run-to-run spread; HIP maps them onto 4 hardware queues)
+#ifndef SEASD_BATCH_STREAMS
+#define SEASD_BATCH_STREAMS 8
+#endif
+constexpr int kBatchStreams = SEASD_BATCH_STREAMS;
+
 struct seasd_batch_s {
     int device = 0;
     int nsys = 0;
@@ -912,8 +920,8 @@ struct seasd_batch_s {
     std::vector<seasd_handle> sub;
     std::vector<seasd_config> cfg;
     DevBuf pos, rad, xin, yout;
-    hipStream_t streams[8] = {};
-    hipEvent_t fork = nullptr, join[8] = {};
+    hipStream_t streams[kBatchStreams] = {};
+    hipEvent_t fork = nullptr, join[kBatchStreams] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -1001,7 +1009,7 @@ extern "C" int seasd_batch_create(seasd_handle h, int32_t nsys, const int64_t* o
         if (rc) return fail(rc);
     }
     if (hipStreamSynchronize(st) != hipSuccess) return fail(SEASD_E_HIP);
-    // capture: fork to 8 streams, one product per suspension, join
+    // capture: fork to kBatchStreams streams, one product per suspension, join
     for (auto& s8 : b->streams)
         if (hipStreamCreateWithFlags(&s8, hipStreamNonBlocking) != hipSuccess) return fail(SEASD_E_HIP);
     if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) return fail(SEASD_E_HIP);
@@ -1010,7 +1018,7 @@ extern "C" int seasd_batch_create(seasd_handle h, int32_t nsys, const int64_t* o
     hipStream_t cap = b->streams[0];
     if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return fail(SEASD_E_HIP);
     bool ok = hipEventRecord(b->fork, cap) == hipSuccess;
-    for (int k = 1; k < 8 && ok; ++k) ok = hipStreamWaitEvent(b->streams[k], b->fork, 0) == hipSuccess;
+    for (int k = 1; k < kBatchStreams && ok; ++k) ok = hipStreamWaitEvent(b->streams[k], b->fork, 0) == hipSuccess;
     // heaviest suspensions first, round-robin over the streams
     std::vector<int> order(nsys);
     for (int k = 0; k < nsys; ++k) order[k] = k;
@@ -1023,11 +1031,11 @@ extern "C" int seasd_batch_create(seasd_handle h, int32_t nsys, const int64_t* o
         const int k = order[r];
         const int64_t n = offsets[k + 1] - offsets[k], o = offsets[k];
         rc = queue_apply(b->sub[k], n, b->pos.as<double>() + 3 * o, b->rad.as<double>() + o, b->L[k],
-                         b->xin.as<double>() + 12 * o, b->yout.as<double>() + 12 * o, b->streams[r % 8], false,
+                         b->xin.as<double>() + 12 * o, b->yout.as<double>() + 12 * o, b->streams[r % kBatchStreams], false,
                          true);
         ok = rc == SEASD_OK;
     }
-    for (int k = 1; k < 8 && ok; ++k) {
+    for (int k = 1; k < kBatchStreams && ok; ++k) {
         ok = hipEventRecord(b->join[k], b->streams[k]) == hipSuccess &&
              hipStreamWaitEvent(cap, b->join[k], 0) == hipSuccess;
     }
