@@ -947,7 +947,9 @@ __global__ __launch_bounds__(256) void k_window(int n, const double* __restrict_
 // in registers with Neumaier compensation: each grid point is written by
 // exactly one lane, with no atomics.
 
-constexpr int kStage = 16;     // spheres staged per round
+// spheres staged per round (N = 1e5, 256^3: 0.82 ms with 16, 0.92 with 8,
+// 0.89 with 32, whose larger LDS buffer costs workgroups per CU)
+constexpr int kStage = 16;
 constexpr int kMaxCand = 2048; // candidate list held in LDS
 
 template <typename R>
