@@ -188,14 +188,15 @@ int seasd_solve_farfield(seasd_handle handle, int64_t n,
 
 /* Per-phase timing of mobility products, recorded with HIP events on each
  * call's stream while enabled (off by default; one event per phase, no
- * synchronisation). Phases, in order: bin, pair, spread, fft_x_fwd,
- * fft_y_fwd, fft_z_scale, fft_y_inv, fft_x_inv, gather.
+ * synchronisation). Phases, in order: bin, pair, window, spread, fft_x_fwd,
+ * fft_y_fwd, fft_z_scale, fft_y_inv, fft_x_inv, gather (window: the
+ * per-sphere window records; spread: the spreading kernel alone).
  * seasd_profile_enable(h, 1) starts a new recording (also discarding any
  * unread one); seasd_profile_read synchronises the stream of the last
  * product, writes the average duration in ms of each phase over the products
- * recorded since then into ms[0..8], the number of those products into ms[9]
- * (when count > 9), starts a new recording and returns the number of phases
- * (9), or a negative error. */
+ * recorded since then into ms[0..9], the number of those products into ms[10]
+ * (when count > 10), starts a new recording and returns the number of phases
+ * (10), or a negative error. */
 int seasd_profile_enable(seasd_handle handle, int32_t enable);
 int seasd_profile_read(seasd_handle handle, double* ms, int32_t count);
 

@@ -26,6 +26,7 @@ constexpr int kErrNonfinite = 1, kErrOverlap = 2, kErrCutoff = 4;
 enum Phase {
     kPhaseBin = 0,
     kPhasePair,
+    kPhaseWindow,
     kPhaseSpread,
     kPhaseFftXFwd,
     kPhaseFftYFwd,

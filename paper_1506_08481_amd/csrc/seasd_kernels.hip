@@ -1886,10 +1886,11 @@ int launch_wave(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     KScale ks{2.0 * kPi / A.L, 1.0 / (4.0 * A.xi * A.xi), 2.0 * A.tau,
               1.0 / ((double)A.M * A.M * A.M), A.inv_eta};
     const int gwin = (n + kWinSpheres - 1) / kWinSpheres;
-    tm->begin(kPhaseSpread, st);
+    tm->begin(kPhaseWindow, st);
     if (A.fp32) {
         hipLaunchKernelGGL((k_window<float>), dim3(gwin), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.P, A.h, A.alpha,
                            (float*)A.wrec);
+        tm->begin(kPhaseSpread, st);
         if (wave) {
             if (A.tile == 8)
                 hipLaunchKernelGGL((k_spread<float, 8>), dim3(tiles * tiles * tiles), dim3(spread_threads<8>()), 0, st, n,
@@ -1904,6 +1905,7 @@ int launch_wave(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     } else {
         hipLaunchKernelGGL((k_window<double>), dim3(gwin), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.P, A.h, A.alpha,
                            (double*)A.wrec);
+        tm->begin(kPhaseSpread, st);
         if (wave) {
             if (A.tile == 8)
                 hipLaunchKernelGGL((k_spread<double, 8>), dim3(tiles * tiles * tiles), dim3(spread_threads<8>()), 0, st, n,

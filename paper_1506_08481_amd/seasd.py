@@ -34,7 +34,8 @@ SEASD_FP64, SEASD_FP32 = 0, 1
 SEASD_PARTS_REAL, SEASD_PARTS_WAVE, SEASD_PARTS_SELF, SEASD_PARTS_ALL = 1, 2, 4, 7
 SEASD_PRECOND_NONE, SEASD_PRECOND_BLOCKDIAG, SEASD_PRECOND_LEARNED, SEASD_PRECOND_LEARNED_GUESS = 0, 1, 2, 3
 
-PHASES = ("bin", "pair", "spread", "fft_x_fwd", "fft_y_fwd", "fft_z_scale", "fft_y_inv", "fft_x_inv", "gather")
+PHASES = ("bin", "pair", "window", "spread", "fft_x_fwd", "fft_y_fwd", "fft_z_scale", "fft_y_inv", "fft_x_inv",
+          "gather")
 
 # exported symbols of include/seasd.h
 SYMBOLS = ("seasd_create", "seasd_destroy", "seasd_default_config", "seasd_set_config",
