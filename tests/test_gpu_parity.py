@@ -220,3 +220,23 @@ def test_gmres_preconditioner_helps_bidisperse(lib):
     print(stats)
     assert stats[lib.SEASD_PRECOND_BLOCKDIAG]["converged"] == 1
     assert stats[lib.SEASD_PRECOND_BLOCKDIAG]["iterations"] < stats[lib.SEASD_PRECOND_NONE]["iterations"]
+
+
+def test_phase_timing_reports_every_phase(lib, small_case):
+    """Per-phase timing: every documented phase of a product is recorded, in
+    the documented order, and the profiled products give the same result as
+    an unprofiled one."""
+    s, x, _ = small_case
+    y0 = _gpu_apply(lib, s, x, **SMALL)
+    eng = lib.Seasd(0, **SMALL)
+    eng.profile(True)
+    for _ in range(3):
+        y = eng.apply(_t(s.pos), _t(s.radius), s.box, _t(x))
+    ph = eng.profile_read()
+    eng.close()
+    assert list(ph)[:-1] == list(lib.PHASES)
+    assert lib.PHASES[:4] == ("bin", "pair", "window", "spread")
+    assert ph["products"] == 3
+    for k in lib.PHASES:
+        assert ph[k] > 0.0, k
+    np.testing.assert_array_equal(y.cpu().numpy(), y0)

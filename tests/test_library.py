@@ -59,3 +59,15 @@ def test_default_config_and_validation_on_host():
     c = seasd.default_config()
     assert c.grid == 64 and c.P == 16 and c.rc_factor == 4.0 and c.precision == seasd.SEASD_FP64
     assert seasd.lib().seasd_error_string(seasd.SEASD_E_OVERLAP).decode().startswith("overlapping")
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU; asking for more exits with a message
+    before anything touches a device."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
