@@ -29,23 +29,23 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 
-# (xi, rc_factor, P, m / sqrt(pi P), spreading tile)
+# (xi, rc_factor, P, m / sqrt(pi P))
 CANDIDATES = [
-    (0.8, 3.0, 16, 0.85, 8),
-    (0.7, 3.5, 16, 0.95, 8),
+    (0.8, 3.0, 16, 0.85),
+    (0.7, 3.5, 16, 0.95),
 ]
-REF = (0.7, 3.5, 18, 0.95, 8)   # FP64 reference product (SE error ~1e-8)
+REF = (0.7, 3.5, 18, 0.95)   # FP64 reference product (SE error ~1e-8)
 
 
 # HBM bytes per launch measured with the byte counters (FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0; the factors come from a 2 GiB elementwise kernel of known
 # traffic profiled in the same runs), for the kernel versions and the
-# configuration (phase, grid, P, tile) recorded in
+# configuration (phase, grid, P) recorded in
 # profiles/product_n100000_phi0.4_grid256_traffic.md. Any other configuration
 # reports null.
 MEASURED_TRAFFIC = {
-    ("spread", 256, 16, 8): 321.8e6,
-    ("gather", 256, 16, 8): 1445.1e6,
+    ("spread", 256, 16): 321.8e6,
+    ("gather", 256, 16): 1445.1e6,
 }
 
 
@@ -151,7 +151,7 @@ def bench_batch(args):
     cfgs = plan.configs()
     grids = {}
     for c in cfgs:
-        grids[c.grid] = grids.get(c.grid, 0) + 1
+        grids[c.grid[0]] = grids.get(c.grid[0], 0) + 1
     out = {"metric": "batched sphere-products/s (256 suspensions, one graph launch)",
            "value": float(offs[-1]) / dt, "unit": "sphere-products/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -178,7 +178,7 @@ def bench_solve(args):
     b = wl.force_moments(s.n, 2001)
     dev = torch.device("cuda:0")
     P_, R_, B_ = (torch.as_tensor(a, device=dev) for a in (s.pos, s.radius, b))
-    c = seasd.seasd_autotune(s.n, s.L, 1.0, 2.0, 1e-8, seasd.SEASD_FP64)
+    c = seasd.seasd_autotune(s.n, s.box, 1.0, 2.0, 1e-8, seasd.SEASD_FP64)
     res = {}
     for name, pc in (("blockdiag", seasd.SEASD_PRECOND_BLOCKDIAG), ("none", seasd.SEASD_PRECOND_NONE)):
         eng = seasd.Seasd(0, grid=128, P=c.P, m=c.m, xi=c.xi, rc_factor=c.rc_factor, precision=seasd.SEASD_FP64,
@@ -260,8 +260,8 @@ def pmc_probe(args):
     x = wl.force_moments(s.n, 3001)
     dev = torch.device("cuda:0")
     P_, R_, X_ = (torch.as_tensor(a, device=dev) for a in (s.pos, s.radius, x))
-    xi, rcf, P, mf, tile = CANDIDATES[args.pmc_candidate]
-    eng = seasd.Seasd(0, grid=256, P=P, m=mf * math.sqrt(math.pi * P), xi=xi, rc_factor=rcf, tile=tile,
+    xi, rcf, P, mf = CANDIDATES[args.pmc_candidate]
+    eng = seasd.Seasd(0, grid=256, P=P, m=mf * math.sqrt(math.pi * P), xi=xi, rc_factor=rcf,
                       precision=seasd.SEASD_FP32, checks=0)
     y = torch.empty_like(X_)
     for _ in range(3):
@@ -318,8 +318,8 @@ def main():
     print(f"setup: N={s.n} L={s.L:.3f} placement {time.time() - t_setup:.1f}s", file=sys.stderr, flush=True)
 
     def engine(cand, precision):
-        xi, rcf, P, mf, tile = cand
-        return seasd.Seasd(0, grid=M, P=P, m=mf * math.sqrt(math.pi * P), xi=xi, rc_factor=rcf, tile=tile,
+        xi, rcf, P, mf = cand
+        return seasd.Seasd(0, grid=M, P=P, m=mf * math.sqrt(math.pi * P), xi=xi, rc_factor=rcf,
                            precision=precision, checks=0)
 
     ref_eng = engine(REF, seasd.SEASD_FP64)
@@ -342,7 +342,7 @@ def main():
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) / 5 * 1e3
         tune.append({"xi": cand[0], "rc_factor": cand[1], "P": cand[2],
-                     "m": round(cand[3] * math.sqrt(math.pi * cand[2]), 3), "tile": cand[4],
+                     "m": round(cand[3] * math.sqrt(math.pi * cand[2]), 3),
                      "err_vs_fp64": err, "ms": ms})
         print(f"candidate {cand}: err {err:.2e} {ms:.3f} ms", file=sys.stderr, flush=True)
         if err <= 1e-6 and (best is None or ms < best[1]):
@@ -382,7 +382,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": cost["bytes"] / t_dom / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = MEASURED_TRAFFIC.get((dom, M, cand[2], cand[4]))
+    roof["traffic"] = MEASURED_TRAFFIC.get((dom, M, cand[2]))
     roof["kernel"] = dom
     roof["kernel_ms"] = phases[dom]
 
@@ -402,7 +402,7 @@ def main():
         "config": {"workload": "monodisperse spheres N=100000 phi=0.4, grid 256^3, FP32 spread/FFT/gather, "
                                "FP64 pair sum", "N": s.n, "L": s.L, "grid": M,
                    "xi": cand[0], "rc_factor": cand[1], "P": cand[2],
-                   "m": cand[3] * math.sqrt(math.pi * cand[2]), "tile": cand[4]},
+                   "m": cand[3] * math.sqrt(math.pi * cand[2])},
         "rel_err_vs_fp64_gpu": err,
         "phases_ms": {k: round(v, 5) for k, v in phases.items()},
         "tuning": tune,

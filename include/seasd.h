@@ -46,8 +46,13 @@
  *     whatever the internal precision.
  *   - box is a HOST array of 9 doubles holding the lattice vectors a1, a2, a3
  *     as consecutive triples (the columns of the paper's matrix A, Sec. 2.2).
- *     This version accepts cubic cells only (a1 = (L,0,0), a2 = (0,L,0),
- *     a3 = (0,0,L)); anything else returns SEASD_E_UNSUPPORTED.
+ *     Accepted cells: a1 = (a1x, 0, 0), a2 = (a2x, a2y, 0), a3 = (0, 0, a3z)
+ *     with a1x, a2y, a3z > 0 and |a2x| <= a1x: cubes, rectangular boxes and
+ *     boxes sheared in the x-y plane, such as the simple-shear cell
+ *     a2 = (gamma L, L, 0) of Sec. 3.2 (eq. non-ortho-shape). Other shapes
+ *     return SEASD_E_UNSUPPORTED. The Spectral Ewald grid lives in the
+ *     fractional coordinates t = A^-1 r (Sec. 3.1), with M points along each
+ *     lattice direction.
  *   - Work is queued on `stream` (a hipStream_t; NULL = default stream).
  *     seasd_mobility_apply returns without synchronising unless the
  *     configuration asks for input checks; seasd_solve_farfield synchronises.
@@ -94,10 +99,16 @@ extern "C" {
                                     /* network, plus its initial guess (see below)     */
 #define SEASD_PRECOND_LEARNED_GUESS 3 /* block-diagonal blocks, the network's guess   */
 
+#define SEASD_SIZE_REAL 0  /* Faxen operators applied to the window on both   */
+                           /* sides (the real-space approach of Sec. 3.2)    */
+
 typedef struct seasd_config {
-    int32_t grid;           /* M, grid points per dimension: power of two, 8..512            */
-    int32_t P;              /* window support in grid points per dimension: even, 4..min(M,32) */
-    int32_t tile;           /* spreading tile = bin edge in grid points: 4, 8, or 0 (auto: 8) */
+    int32_t grid[3];        /* M, grid points along each lattice direction: equal,    */
+                            /* a power of two, 8..256 (unequal: SEASD_E_UNSUPPORTED)  */
+    int32_t P;              /* window support in grid points per dimension, 4..min(M,32), */
+                            /* odd or even (eq. fgg-exp; centred either way)           */
+    int32_t size_approach;  /* SEASD_SIZE_REAL; the wave-space and hybrid approaches of */
+                            /* Sec. 3.2 return SEASD_E_UNSUPPORTED                      */
     double  m;              /* window shape parameter (eq. theta-param); <= 0: sqrt(pi P)   */
     double  xi;             /* Ewald splitting parameter, Beenakker convention (Sec. 2.2)   */
     double  rc_factor;      /* real-space cut-off r_c = rc_factor (a_i + a_j), > 1           */
@@ -138,7 +149,7 @@ int seasd_create(seasd_handle* handle, int32_t device);
 /* Release the handle and all workspace it owns. Safe on NULL. */
 int seasd_destroy(seasd_handle handle);
 
-/* Fill *cfg with defaults: M=64, P=16, m=sqrt(pi P), xi=0.5, rc_factor=4
+/* Fill *cfg with defaults: M=64 (all directions), P=16, m=sqrt(pi P), xi=0.5, rc_factor=4
  * (the paper's r_c = 4(a_i+a_j), Sec. 5.1.2 and 5.3), eta=1, FP64, all parts,
  * compressible, checks on, tol 1e-6, max_iter 1000, restart 50, block-diagonal
  * preconditioner. */
@@ -153,10 +164,10 @@ int seasd_set_config(seasd_handle handle, const seasd_config* cfg);
  *   n      number of spheres, >= 1
  *   pos    device [n][3] centres (any real coordinates; wrapped into the cell)
  *   radius device [n] radii, > 0
- *   box    host [9] lattice vectors (cubic only, see above)
+ *   box    host [9] lattice vectors (see the accepted cells above)
  *   x      device [n][12] force moments
  *   y      device [n][12] output, overwritten (may not alias x)
- * Errors: SEASD_E_INVALID_ARG, SEASD_E_UNSUPPORTED (non-cubic cell),
+ * Errors: SEASD_E_INVALID_ARG, SEASD_E_UNSUPPORTED (cell shape),
  * SEASD_E_CUTOFF (window wider than the grid), SEASD_E_NOMEM, SEASD_E_HIP; with
  * checks on also SEASD_E_NONFINITE and SEASD_E_OVERLAP (y is then undefined). */
 int seasd_mobility_apply(seasd_handle handle, int64_t n,
@@ -186,6 +197,40 @@ int seasd_solve_farfield(seasd_handle handle, int64_t n,
                          const double* pos, const double* radius, const double* box,
                          const double* b, double* x, seasd_solve_stats* stats, void* stream);
 
+/* Far-field Brownian force moments (Sec. 4.3, eq. br-f-ff): x = M^(-1/2) psi
+ * on the 11 incompressible components (force, torque, stresslet), computed
+ * with the initial value problem of eq. ivp-1,
+ *   dx/dtau = -(1/2) [tau I + (1 - tau) A]^-1 (A - I) x,  x(0) = psi,
+ * whose value at tau = 1 is A^(-1/2) psi, marched in K = round(1/dtau) steps
+ * of a forward Euler half step (eq. ivp-forward) and a backward Euler half
+ * step (eq. ivp-backward); every linear system (alpha I + beta A) is solved
+ * by the GMRES of seasd_solve_farfield (tolerance tol, restart, max_iter
+ * per solve) with the shifted block-diagonal preconditioner (alpha I +
+ * beta A_ii)^-1. A = s M is the mobility made dimensionless with the Stokes
+ * drag of the smallest sphere, s = 6 pi eta a_min, and x = sqrt(s) A^(-1/2) psi.
+ * The caller multiplies by sqrt(2 kT / dt) for the force moments of a
+ * time step.
+ *   psi    device [n][12] unit Gaussian noise (trace column ignored)
+ *   x      device [n][12] output (trace column 0); may not alias psi
+ *   dtau   IVP step, 0 < dtau <= 1 (the paper uses 0.1)
+ *   stats  host, may be NULL
+ * Synchronises. Returns SEASD_W_NOT_CONVERGED if a linear solve stopped at
+ * max_iter, and the errors of seasd_solve_farfield. */
+typedef struct seasd_brownian_stats {
+    int32_t steps;           /* IVP steps K                                      */
+    int32_t solves;          /* shifted linear solves (2 K)                      */
+    int32_t iterations;      /* GMRES iterations over all solves                 */
+    int32_t matvecs;         /* products with M                                  */
+    int32_t converged;       /* 1 if every solve met tol                         */
+    double  max_residual;    /* largest final true residual of the solves        */
+    double  scale;           /* s = 6 pi eta a_min                               */
+    double  solve_ms;        /* wall time of the call                            */
+} seasd_brownian_stats;
+
+int seasd_brownian_farfield(seasd_handle handle, int64_t n, const double* pos, const double* radius,
+                            const double* box, const double* psi, double* x, double dtau,
+                            seasd_brownian_stats* stats, void* stream);
+
 /* Per-phase timing of mobility products, recorded with HIP events on each
  * call's stream while enabled (off by default; one event per phase, no
  * synchronisation). Phases, in order: bin, pair, window, spread, fft_x_fwd,
@@ -202,28 +247,28 @@ int seasd_profile_read(seasd_handle handle, double* ms, int32_t count);
 
 /* ---- many independent suspensions -------------------------------------------
  * Autotuner: parameters for one suspension of n spheres (radii a_min..a_max)
- * in a cubic cell of edge L, aiming at a global relative error of `target`
- * (1e-6 or looser) in the given precision. It picks the grid M (a power of
- * two, 32..256: for targets of 1e-6 or looser the finest with spacing
- * L/M >= 0.21 a_max, below which the window's Faxen terms lose accuracy;
- * for tighter targets the spacing nearest 0.4 a_max; the bins are 8^3
- * tiles of that grid), xi from the grid spacing so that the k-space tail
- * exp(-k_max^2/(4 xi^2)) stays fixed, the real-space cut-off factor so that
- * xi r_c is fixed for a pair of spheres of radius a_min (the batch planner
- * passes the 10th-percentile radius), and the window (P, m) from accuracy
- * scans of the method against the oracle (Sec. 5.1). Other fields take the
- * defaults. */
-int seasd_autotune(int64_t n, double L, double a_min, double a_max, double target, int32_t precision,
+ * in the cell `box` (host [9], accepted shapes as above), aiming at a global
+ * relative error of `target` (1e-6 or looser) in the given precision. It
+ * picks the grid M (a power of two, 32..256: for targets of 1e-6 or looser
+ * the finest with spacing h >= 0.21 a_max across the thinnest direction of
+ * the cell, below which the window's Faxen terms lose accuracy; for tighter
+ * targets the spacing nearest 0.4 a_max), xi from the grid spacing so that
+ * the k-space tail exp(-k_max^2/(4 xi^2)) stays fixed, the real-space
+ * cut-off factor so that xi r_c is fixed for a pair of spheres of radius
+ * a_min (the batch planner passes the 10th-percentile radius), and the window
+ * (P, m) from accuracy scans of the method against the oracle (Sec. 5.1).
+ * Other fields take the defaults. */
+int seasd_autotune(int64_t n, const double* box, double a_min, double a_max, double target, int32_t precision,
                    seasd_config* cfg);
 
 typedef struct seasd_batch_s* seasd_batch;
 
-/* Plan for nsys independent suspensions (cubic cells), all sphere arrays
+/* Plan for nsys independent suspensions, all sphere arrays
  * concatenated: suspension k owns spheres offsets[k] .. offsets[k+1]-1.
  *   offsets  host [nsys+1], offsets[0] = 0, increasing
  *   pos      device [N][3], radius device [N] (N = offsets[nsys]); read during
  *            this call only (the plan keeps binned copies)
- *   boxes    host [nsys][9] lattice vectors (cubic)
+ *   boxes    host [nsys][9] lattice vectors (accepted shapes as above)
  *   per_sys  host [nsys] configurations, or NULL to autotune each suspension
  *            for `target` with the handle's precision
  * Builds every suspension's geometry (binning, neighbour lists) and captures

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["seasd_api.hip", "seasd_kernels.hip", "seasd_solver.hip", "seasd_learn.hip"]
+SOURCES = ["seasd_api.hip", "seasd_kernels.hip", "seasd_solver.hip", "seasd_gmres.hip", "seasd_learn.hip"]
 LIB = os.path.join(HERE, "libseasd.so")
 
 HIPCC_FLAGS = [

@@ -21,16 +21,17 @@ struct seasd_handle_s {
     seasd_config cfg{};
     bool have_cfg = false;
     // product workspace
-    DevBuf bin_of, counts, start, fill, perm, amax, err, sp, sa, sx, ybuf, rgrid, spec, twiddle;
+    DevBuf bin_of, counts, start, fill, perm, amax, err, sp, sfrac, sa, sx, ybuf, rgrid, spec, twiddle;
     DevBuf ncount, nstats, list, total, wrec, scan_tmp;
     int cap = 64;             // neighbour-list slots per sphere, grown on demand
     int pair_group = 1;       // lanes per sphere of the pair sum chosen for the held geometry
     int64_t geom_n = -1;      // spheres in the geometry currently held in the workspace
     int twiddle_M = 0;
     // solver workspace
-    DevBuf V, w, z, u, r, bred, hdev, partial, blocks, inv, coef, singular, one_pos, one_rad, one_x, one_y;
-    // block-diagonal fit cache: (a_min, a_max, L, grid, P, m, xi, rc_factor, eta, precision, tile)
-    double pc_key[11] = {0};
+    DevBuf w, z, u, r, bred, hdev, partial, blocks, inv, coef, singular, one_pos, one_rad, one_x, one_y;
+    DeviceGmres gm;
+    // block-diagonal fit cache: (a_min, a_max, grid, P, m, xi, rc_factor, eta, precision, cell A[9])
+    double pc_key[18] = {0};
     bool pc_valid = false;
     double pc_amax = 0.0;
     // learned preconditioner
@@ -68,8 +69,9 @@ extern "C" const char* seasd_error_string(int32_t code) {
 extern "C" int seasd_default_config(seasd_config* c) {
     if (!c) return SEASD_E_INVALID_ARG;
     std::memset(c, 0, sizeof(*c));
-    c->grid = 64;
+    c->grid[0] = c->grid[1] = c->grid[2] = 64;
     c->P = 16;
+    c->size_approach = SEASD_SIZE_REAL;
     c->m = 0.0;
     c->xi = 0.5;
     c->rc_factor = 4.0;
@@ -105,9 +107,9 @@ extern "C" int seasd_destroy(seasd_handle h) {
     if (!h) return SEASD_OK;
     hipSetDevice(h->device);
     DevBuf* bufs[] = {&h->bin_of, &h->counts, &h->start, &h->fill, &h->perm, &h->amax, &h->err,
-                      &h->sp, &h->sa, &h->sx, &h->ybuf, &h->rgrid, &h->spec, &h->twiddle,
+                      &h->sp, &h->sfrac, &h->sa, &h->sx, &h->ybuf, &h->rgrid, &h->spec, &h->twiddle,
                       &h->ncount, &h->nstats, &h->list, &h->total, &h->wrec, &h->scan_tmp,
-                      &h->V, &h->w, &h->z, &h->u, &h->r, &h->bred, &h->hdev, &h->partial, &h->blocks,
+                      &h->w, &h->z, &h->u, &h->r, &h->bred, &h->hdev, &h->partial, &h->blocks,
                       &h->inv, &h->coef, &h->singular, &h->one_pos, &h->one_rad, &h->one_x, &h->one_y,
                       &h->inv2, &h->bad, &h->lx0, &h->lg, &h->lb, &h->lax, &h->lres};
     for (DevBuf* b : bufs) b->release();
@@ -115,6 +117,7 @@ extern "C" int seasd_destroy(seasd_handle h) {
     if (h->ev_stats) hipEventDestroy(h->ev_stats);
     if (h->own_net) seasd_net_destroy(h->own_net);
     h->timer.destroy();
+    h->gm.release();
     delete h;
     return SEASD_OK;
 }
@@ -123,9 +126,9 @@ static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 extern "C" int seasd_set_config(seasd_handle h, const seasd_config* c) {
     if (!h || !c) return SEASD_E_INVALID_ARG;
-    if (!pow2(c->grid) || c->grid < 8 || c->grid > 256) return SEASD_E_INVALID_ARG;
-    if (c->P < 4 || c->P > 32 || (c->P & 1) || c->P > c->grid) return SEASD_E_INVALID_ARG;
-    if (c->tile != 0 && c->tile != 4 && c->tile != 8) return SEASD_E_INVALID_ARG;
+    for (int d = 0; d < 3; ++d)
+        if (!pow2(c->grid[d]) || c->grid[d] < 8 || c->grid[d] > 256) return SEASD_E_INVALID_ARG;
+    if (c->P < 4 || c->P > 32 || c->P > c->grid[0]) return SEASD_E_INVALID_ARG;
     if (!(std::isfinite(c->m)) || !(c->xi > 0.0) || !std::isfinite(c->xi)) return SEASD_E_INVALID_ARG;
     if (!(c->rc_factor > 1.0) || !std::isfinite(c->rc_factor)) return SEASD_E_INVALID_ARG;
     if (!(c->eta > 0.0) || !std::isfinite(c->eta)) return SEASD_E_INVALID_ARG;
@@ -134,36 +137,58 @@ extern "C" int seasd_set_config(seasd_handle h, const seasd_config* c) {
     if (c->restart < 1 || c->restart > 200 || c->max_iter < 1) return SEASD_E_INVALID_ARG;
     if (!(c->tol > 0.0)) return SEASD_E_INVALID_ARG;
     if (c->precond < SEASD_PRECOND_NONE || c->precond > SEASD_PRECOND_LEARNED_GUESS) return SEASD_E_INVALID_ARG;
+    if (c->size_approach < 0 || c->size_approach > 2) return SEASD_E_INVALID_ARG;
+    // valid requests this build does not carry out: unequal grids and the
+    // wave-space and hybrid size approaches
+    if (c->grid[1] != c->grid[0] || c->grid[2] != c->grid[0]) return SEASD_E_UNSUPPORTED;
+    if (c->size_approach != SEASD_SIZE_REAL) return SEASD_E_UNSUPPORTED;
     h->cfg = *c;
     h->have_cfg = true;
     return SEASD_OK;
 }
 
-static int cubic_edge(const double* box, double* L) {
+// Lattice vectors (host box[9] = a1, a2, a3) into a Cell. Accepted shapes:
+// a1 = (a1x, 0, 0), a2 = (a2x, a2y, 0), a3 = (0, 0, a3z), positive diagonal,
+// |a2x| <= a1x; off-pattern entries below 1e-12 of the largest length count as
+// zero.
+static int parse_cell(const double* box, Cell* cell) {
     if (!box) return SEASD_E_INVALID_ARG;
     for (int i = 0; i < 9; ++i)
         if (!std::isfinite(box[i])) return SEASD_E_INVALID_ARG;
-    const double l = box[0];
-    if (!(l > 0.0)) return SEASD_E_INVALID_ARG;
-    const double tol = 1e-12 * l;
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            const double v = box[3 * i + j];
-            if (i == j ? std::fabs(v - l) > tol : std::fabs(v) > tol) return SEASD_E_UNSUPPORTED;
-        }
-    *L = l;
+    const double a1x = box[0], a2x = box[3], a2y = box[4], a3z = box[8];
+    if (!(a1x > 0.0) || !(a2y > 0.0) || !(a3z > 0.0)) return SEASD_E_INVALID_ARG;
+    const double scale = std::max(std::max(a1x, a2y), std::max(a3z, std::fabs(a2x)));
+    const double tol = 1e-12 * scale;
+    const int zero_idx[5] = {1, 2, 5, 6, 7};   // a1y, a1z, a2z, a3x, a3y
+    for (int k : zero_idx)
+        if (std::fabs(box[k]) > tol) return SEASD_E_UNSUPPORTED;
+    if (std::fabs(a2x) > a1x * (1.0 + 1e-12)) return SEASD_E_UNSUPPORTED;
+    Cell c{};
+    // A row-major, columns a1 a2 a3
+    c.a[0] = a1x;
+    c.a[1] = a2x;
+    c.a[4] = a2y;
+    c.a[8] = a3z;
+    c.ainv[0] = 1.0 / a1x;
+    c.ainv[1] = -a2x / (a1x * a2y);
+    c.ainv[4] = 1.0 / a2y;
+    c.ainv[8] = 1.0 / a3z;
+    for (int d = 0; d < 3; ++d) {
+        const double* row = c.ainv + 3 * d;
+        c.height[d] = 1.0 / std::sqrt(row[0] * row[0] + row[1] * row[1] + row[2] * row[2]);
+    }
+    c.volume = a1x * a2y * a3z;
+    *cell = c;
     return SEASD_OK;
 }
 
-// product workspace for n spheres on the configured grid
-// spreading tile (= bin) edge in grid points: the configured one, else 8
-// (measured faster than 4 at every grid size: 5.6x at 256^3, 1.3x over the
-// batch of 32^3-128^3 grids)
-static int tile_of(const seasd_config& c) { return c.tile ? c.tile : 8; }
+static double min_height(const Cell& c) { return std::min(c.height[0], std::min(c.height[1], c.height[2])); }
 
+// product workspace for n spheres on the configured grid (bins are the 8^3
+// spreading tiles)
 static int ensure_product_ws(seasd_handle h, int64_t n) {
-    const int M = h->cfg.grid;
-    const int nb = M / tile_of(h->cfg);
+    const int M = h->cfg.grid[0];
+    const int nb = M / 8;
     const size_t nbins = (size_t)nb * nb * nb;
     const size_t R = h->cfg.precision == SEASD_FP32 ? 4 : 8;
     int rc = 0;
@@ -175,6 +200,7 @@ static int ensure_product_ws(seasd_handle h, int64_t n) {
     rc |= h->amax.ensure(sizeof(unsigned long long));
     rc |= h->err.ensure(sizeof(int));
     rc |= h->sp.ensure(sizeof(double) * 3 * n);
+    rc |= h->sfrac.ensure(sizeof(double) * 3 * n);
     rc |= h->sa.ensure(sizeof(double) * n);
     rc |= h->sx.ensure(sizeof(double) * 12 * n);
     rc |= h->ybuf.ensure(sizeof(double) * 12 * n);
@@ -204,8 +230,8 @@ static int ensure_product_ws(seasd_handle h, int64_t n) {
     return SEASD_OK;
 }
 
-static void fill_args(seasd_handle h, ApplyArgs& A, int64_t n, const double* pos, const double* radius, double L,
-                      const double* x, double* y, bool checks, int compressible) {
+static void fill_args(seasd_handle h, ApplyArgs& A, int64_t n, const double* pos, const double* radius,
+                      const Cell& cell, const double* x, double* y, bool checks, int compressible) {
     const seasd_config& c = h->cfg;
     A = ApplyArgs{};
     A.n = n;
@@ -213,20 +239,38 @@ static void fill_args(seasd_handle h, ApplyArgs& A, int64_t n, const double* pos
     A.radius = radius;
     A.x = x;
     A.y = y;
-    A.L = L;
-    A.M = c.grid;
+    A.cell = cell;
+    const int M = c.grid[0];
+    A.M = M;
     A.P = c.P;
-    A.tile = tile_of(c);
-    A.nb = c.grid / A.tile;
-    A.binw = L / A.nb;
+    A.nb = M / 8;
+    for (int d = 0; d < 3; ++d) A.reach_per_len[d] = A.nb / cell.height[d];
     A.xi = c.xi;
     A.rc_factor = c.rc_factor;
     A.inv_eta = 1.0 / c.eta;
-    A.h = L / c.grid;
+    // window on the fractional grid (Sec. 3.1, eqs. shape and theta-param)
     const double m = c.m > 0.0 ? c.m : std::sqrt(kPi * c.P);
-    A.tau = (c.P * A.h) * (c.P * A.h) / (8.0 * m * m);
-    A.alpha = 1.0 / (4.0 * A.tau);
-    A.cw = std::pow(4.0 * kPi * A.tau, -1.5);
+    const double beta = 2.0 * m * m / ((double)c.P * c.P);
+    const double* ai = cell.ainv;
+    // J = M A^-1, Q = J^T J, g = beta J^T u
+    const double J00 = M * ai[0], J01 = M * ai[1], J11 = M * ai[4], J22 = M * ai[8];
+    const double Qxx = J00 * J00, Qxy = J00 * J01, Qyy = J01 * J01 + J11 * J11, Qzz = J22 * J22;
+    WinGeom& w = A.win;
+    w.beta = beta;
+    w.Gxx = beta * J00;
+    w.Gyx = beta * J01;
+    w.Gyy = beta * J11;
+    w.Gzz = beta * J22;
+    w.Qxx = beta * (Qxx - Qzz);
+    w.Qxy = beta * Qxy;
+    w.Qyy = beta * (Qyy - Qzz);
+    w.bq = beta * (Qxx + Qyy + Qzz);
+    w.bz = beta * Qzz;
+    const double qtol = 1e-12 * beta * Qzz;
+    w.sheared = std::fabs(w.Qxx) > qtol || std::fabs(w.Qxy) > qtol || std::fabs(w.Qyy) > qtol;
+    w.cwv = std::pow(beta / kPi, 1.5);
+    w.cw = w.cwv * (double)M * M * M / cell.volume;
+    A.kdeconv = 2.0 * kPi * kPi / (beta * (double)M * M);
     A.parts = c.parts;
     A.compressible = compressible;
     A.checks = checks ? 1 : 0;
@@ -245,6 +289,7 @@ static void fill_args(seasd_handle h, ApplyArgs& A, int64_t n, const double* pos
     A.amax_bits = h->amax.as<unsigned long long>();
     A.err = h->err.as<int>();
     A.sp = h->sp.as<double>();
+    A.st = h->sfrac.as<double>();
     A.sa = h->sa.as<double>();
     A.sx = h->sx.as<double>();
     A.ybuf = h->ybuf.as<double>();
@@ -261,7 +306,7 @@ static void fill_args(seasd_handle h, ApplyArgs& A, int64_t n, const double* pos
 // sum's lanes per sphere for the next products; the pair sum and the wave part
 // are queued before that wait. Everything else is queued without
 // synchronisation.
-static int queue_apply(seasd_handle h, int64_t n, const double* pos, const double* radius, double L,
+static int queue_apply(seasd_handle h, int64_t n, const double* pos, const double* radius, const Cell& L,
                        const double* x, double* y, hipStream_t st, bool checks, bool reuse_geometry = false,
                        int compressible = -1) {
     if (compressible < 0) compressible = h->cfg.compressible;
@@ -342,8 +387,8 @@ extern "C" int seasd_mobility_apply(seasd_handle h, int64_t n, const double* pos
                                     const double* box, const double* x, double* y, void* stream) {
     if (!h || n < 1 || n > (int64_t)1 << 28 || !pos || !radius || !x || !y) return SEASD_E_INVALID_ARG;
     if (x == y) return SEASD_E_INVALID_ARG;
-    double L;
-    int rc = cubic_edge(box, &L);
+    Cell L;
+    int rc = parse_cell(box, &L);
     if (rc) return rc;
     if (hipSetDevice(h->device) != hipSuccess) return SEASD_E_HIP;
     hipStream_t st = (hipStream_t)stream;
@@ -390,7 +435,7 @@ extern "C" int seasd_profile_read(seasd_handle h, double* ms, int32_t count) {
 // Single-sphere blocks M_ii(a) = self(a) + Q(a^2), Q quadratic in a^2: sample
 // the product on one sphere alone in the cell at three radii (12 unit inputs
 // each), remove the single-sphere self terms, fit the quadratic exactly.
-static int build_preconditioner(seasd_handle h, int64_t n, const double* radius, double L, hipStream_t st) {
+static int build_preconditioner(seasd_handle h, int64_t n, const double* radius, const Cell& L, hipStream_t st) {
     int rc = 0;
     rc |= h->coef.ensure(sizeof(double) * 3 * 144);
     rc |= h->blocks.ensure(sizeof(double) * 144 * n);
@@ -412,8 +457,9 @@ static int build_preconditioner(seasd_handle h, int64_t n, const double* radius,
     }
     h->pc_amax = amax;
     const seasd_config& cf = h->cfg;
-    const double key[11] = {amin, amax, L, (double)cf.grid, (double)cf.P, cf.m, cf.xi, cf.rc_factor, cf.eta,
-                            (double)cf.precision, (double)cf.tile};
+    const double key[18] = {amin, amax, (double)cf.grid[0], (double)cf.P, cf.m, cf.xi, cf.rc_factor, cf.eta,
+                            (double)cf.precision, L.a[0], L.a[1], L.a[2], L.a[3], L.a[4], L.a[5], L.a[6], L.a[7],
+                            L.a[8]};
     const bool cached = h->pc_valid && std::memcmp(key, h->pc_key, sizeof(key)) == 0;
     if (!cached) {
         h->pc_valid = false;
@@ -487,7 +533,7 @@ static int dot_host(seasd_handle h, int64_t len, int k, const double* V, int64_t
 // Binning of the given configuration into the product workspace (no
 // neighbour list: the next product rebuilds its geometry). x: any valid
 // [n][12] array (gathered along, unused).
-static int prepare_geometry(seasd_handle h, int64_t n, const double* pos, const double* radius, double L,
+static int prepare_geometry(seasd_handle h, int64_t n, const double* pos, const double* radius, const Cell& L,
                             const double* x, hipStream_t st, ApplyArgs& A) {
     int rc = ensure_product_ws(h, n);
     if (rc) return rc;
@@ -502,9 +548,9 @@ static int prepare_geometry(seasd_handle h, int64_t n, const double* pos, const 
 
 // Learned part of a solve or a training step: graph and forward pass of the
 // attached network on the binned configuration in A.
-static int learned_forward(seasd_handle h, seasd_net net, double L, const ApplyArgs& A, hipStream_t st) {
+static int learned_forward(seasd_handle h, seasd_net net, const Cell& L, const ApplyArgs& A, hipStream_t st) {
     if (net_device(net) != h->device) return SEASD_E_INVALID_ARG;
-    if (!(L > 4.0 * kEdgeCut * h->pc_amax)) return SEASD_E_CUTOFF;   // edges reach below L/2
+    if (!(min_height(L) > 4.0 * kEdgeCut * h->pc_amax)) return SEASD_E_CUTOFF;   // edges reach below half the cell
     if (hipMemsetAsync(A.err, 0, sizeof(int), st) != hipSuccess) return SEASD_E_HIP;
     int rc = net_build_graph(net, A, st);
     if (rc) return rc;
@@ -514,7 +560,7 @@ static int learned_forward(seasd_handle h, seasd_net net, double L, const ApplyA
 
 // Rescaled blocks into h->inv2 and the initial guess x0 for b; *fallback = 1
 // when the network output is rejected.
-static int learned_setup(seasd_handle h, int64_t n, const double* pos, const double* radius, double L,
+static int learned_setup(seasd_handle h, int64_t n, const double* pos, const double* radius, const Cell& L,
                          const double* b, double* x0, bool geometry_current, hipStream_t st, int* fallback) {
     ApplyArgs A;
     int rc;
@@ -542,18 +588,16 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
                                     const double* box, const double* b, double* x, seasd_solve_stats* stats,
                                     void* stream) {
     if (!h || n < 1 || n > (int64_t)1 << 28 || !pos || !radius || !b || !x) return SEASD_E_INVALID_ARG;
-    double L;
-    int rc = cubic_edge(box, &L);
+    Cell L;
+    int rc = parse_cell(box, &L);
     if (rc) return rc;
     if (hipSetDevice(h->device) != hipSuccess) return SEASD_E_HIP;
     hipStream_t st = (hipStream_t)stream;
     auto t0 = std::chrono::steady_clock::now();
     const seasd_config c = h->cfg;
-    const int m = c.restart;
     const int64_t len = 12 * n;
     seasd_solve_stats S{};
     rc = 0;
-    rc |= h->V.ensure(sizeof(double) * len * (m + 1));
     rc |= h->w.ensure(sizeof(double) * len);
     rc |= h->z.ensure(sizeof(double) * len);
     rc |= h->u.ensure(sizeof(double) * len);
@@ -562,11 +606,10 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
     rc |= h->hdev.ensure(sizeof(double) * 256);
     rc |= h->partial.ensure(sizeof(double) * 256 * 256);
     if (rc) return SEASD_E_NOMEM;
-    double* V = h->V.as<double>();
+    if ((rc = h->gm.ensure(len, c.restart, c.max_iter))) return rc == -7 ? SEASD_E_NOMEM : SEASD_E_HIP;
     double* w = h->w.as<double>();
     double* z = h->z.as<double>();
     double* u = h->u.as<double>();
-    double* r = h->r.as<double>();
     double* bred = h->bred.as<double>();
     const bool pc = c.precond != SEASD_PRECOND_NONE;
     const bool learned = c.precond == SEASD_PRECOND_LEARNED || c.precond == SEASD_PRECOND_LEARNED_GUESS;
@@ -578,13 +621,20 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
     auto t1 = std::chrono::steady_clock::now();
     S.setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     bool have_geometry = false;
+    bool first = true;
+    int err_rc = SEASD_OK;
     // product with the incompressible components only (trace input and output zeroed)
-    auto apply11 = [&](const double* in, double* out, bool chk) -> int {
+    auto apply11 = [&](const double* in, double* out) -> int {
+        const bool chk = first && c.checks && !c.compressible;
+        first = false;
         int e = queue_apply(h, n, pos, radius, L, in, out, st, chk, have_geometry, 0);
         if (e) return e;
         have_geometry = true;
-        ++S.matvecs;
-        return chk ? read_err(h, st) : SEASD_OK;
+        if (chk && (e = read_err(h, st))) {
+            err_rc = e;
+            return e;
+        }
+        return SEASD_OK;
     };
     const double* pc_blocks = h->inv.as<double>();
     auto precond = [&](const double* in, double* out) -> int {
@@ -595,17 +645,22 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
     // each pressure moment fixed by its own trace equation, s_self = b_trace /
     // M_self, drives source flows in the solve; the interaction part follows
     // from the pressure Faxen law once F, T, S are known.
+    int extra_matvecs = 0;
     if (c.compressible) {
         if (launch_trace_op(n, 0, radius, c.eta, b, nullptr, z, st)) return SEASD_E_HIP;
         rc = queue_apply(h, n, pos, radius, L, z, w, st, c.checks != 0, false, 1);
         if (rc) return rc;
-        ++S.matvecs;
+        ++extra_matvecs;
         if (c.checks && (rc = read_err(h, st))) return rc;
         if (launch_trace_op(n, 1, radius, c.eta, b, w, bred, st)) return SEASD_E_HIP;
     } else {
         if (hipMemsetAsync(w, 0, sizeof(double) * len, st) != hipSuccess) return SEASD_E_HIP;
         if (launch_trace_op(n, 1, radius, c.eta, b, w, bred, st)) return SEASD_E_HIP;
     }
+    // x holds the caller's guess for F, T, S; its trace entries are ignored
+    if (launch_trace_op(n, 1, radius, c.eta, x, nullptr, z, st) ||
+        hipMemcpyAsync(x, z, sizeof(double) * len, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return SEASD_E_HIP;
     // learned preconditioner: rescaled blocks and the network's initial guess
     int fallback = 0, guess = 0;
     if (learned) {
@@ -617,139 +672,163 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
         } else {
             if (c.precond == SEASD_PRECOND_LEARNED) pc_blocks = h->inv2.as<double>();
             guess = 1;
-        }
-        S.setup_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tl).count();
-    }
-    double bnorm2 = 0.0;
-    rc = dot_host(h, len, 1, bred, len, bred, &bnorm2, st);
-    if (rc) return rc;
-    const double bnorm = std::sqrt(bnorm2);
-    bool first_cycle = true;
-    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), yv(m);
-    bool first = true;
-    double relres = 0.0;
-    int total = 0;
-    if (bnorm == 0.0) {
-        if (hipMemsetAsync(x, 0, sizeof(double) * len, st) != hipSuccess) return SEASD_E_HIP;
-    }
-    while (bnorm > 0.0) {
-        // r = b' - A x  (A: incompressible block)
-        rc = apply11(x, r, first && c.checks && !c.compressible);
-        first = false;
-        if (rc) return rc;
-        if (launch_axpby(len, 1.0, bred, -1.0, r, st)) return SEASD_E_HIP;
-        double rn2 = 0.0;
-        rc = dot_host(h, len, 1, r, len, r, &rn2, st);
-        if (rc) return rc;
-        relres = std::sqrt(rn2) / bnorm;
-        if (first_cycle && guess) {
             // the true residual judges the guess: scale it by the alpha that
-            // minimises ||b' - alpha A x0|| (A x0 = b' - r), dropping it when
-            // alpha <= 0
-            first_cycle = false;
-            if (launch_axpby(len, 1.0, bred, 0.0, u, st) || launch_axpby(len, -1.0, r, 1.0, u, st))
-                return SEASD_E_HIP;
+            // minimises |b' - alpha A x0|, dropping it when alpha <= 0
+            if ((rc = apply11(x, u))) return rc;
+            ++extra_matvecs;
             double ba = 0.0, aa = 0.0;
             if ((rc = dot_host(h, len, 1, bred, len, u, &ba, st))) return rc;
             if ((rc = dot_host(h, len, 1, u, len, u, &aa, st))) return rc;
             const double alpha = (aa > 0.0 && ba > 0.0) ? ba / aa : 0.0;
             if (alpha == 0.0) guess = 0;
-            // x = alpha x0, r = b' - alpha A x0
             if (launch_axpby(len, alpha, x, 0.0, z, st) ||
-                hipMemcpyAsync(x, z, sizeof(double) * len, hipMemcpyDeviceToDevice, st) != hipSuccess ||
-                launch_axpby(len, 1.0, bred, 0.0, r, st) || launch_axpby(len, -alpha, u, 1.0, r, st))
+                hipMemcpyAsync(x, z, sizeof(double) * len, hipMemcpyDeviceToDevice, st) != hipSuccess)
                 return SEASD_E_HIP;
-            if ((rc = dot_host(h, len, 1, r, len, r, &rn2, st))) return rc;
-            relres = std::sqrt(rn2) / bnorm;
             S.guess_scale = alpha;
         }
-        if (S.initial_residual == 0.0) S.initial_residual = relres;
-        if (relres <= c.tol || total >= c.max_iter) break;
-        const double beta = relres * bnorm;
-        if (launch_axpby(len, 1.0 / beta, r, 0.0, V, st)) return SEASD_E_HIP;
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
-        int j = 0;
-        for (; j < m && total < c.max_iter; ++j, ++total) {
-            rc = precond(V + j * len, z);
-            if (rc) return rc;
-            rc = apply11(z, w, false);
-            if (rc) return rc;
-            // classical Gram-Schmidt, twice
-            for (int q = 0; q <= j; ++q) H[q * m + j] = 0.0;
-            for (int pass = 0; pass < 2; ++pass) {
-                if (launch_dots(len, j + 1, V, len, w, h->partial.as<double>(), h->hdev.as<double>(), st))
-                    return SEASD_E_HIP;
-                if (launch_gemv_sub(len, j + 1, V, len, h->hdev.as<double>(), w, st)) return SEASD_E_HIP;
-                if (hipMemcpyAsync(hcol.data(), h->hdev.p, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st) !=
-                    hipSuccess)
-                    return SEASD_E_HIP;
-                if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
-                for (int q = 0; q <= j; ++q) H[q * m + j] += hcol[q];
-            }
-            double wn2 = 0.0;
-            rc = dot_host(h, len, 1, w, len, w, &wn2, st);
-            if (rc) return rc;
-            const double hn = std::sqrt(wn2);
-            H[(j + 1) * m + j] = hn;
-            if (hn > 0.0 && launch_axpby(len, 1.0 / hn, w, 0.0, V + (j + 1) * len, st)) return SEASD_E_HIP;
-            // Givens rotations on column j
-            for (int q = 0; q < j; ++q) {
-                const double a = H[q * m + j], bb = H[(q + 1) * m + j];
-                H[q * m + j] = cs[q] * a + sn[q] * bb;
-                H[(q + 1) * m + j] = -sn[q] * a + cs[q] * bb;
-            }
-            const double a = H[j * m + j], bb = H[(j + 1) * m + j];
-            const double den = std::hypot(a, bb);
-            cs[j] = den > 0 ? a / den : 1.0;
-            sn[j] = den > 0 ? bb / den : 0.0;
-            H[j * m + j] = den;
-            H[(j + 1) * m + j] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            if (std::fabs(g[j + 1]) / bnorm <= 0.5 * c.tol || hn == 0.0) {
-                ++j;
-                ++total;
-                break;
-            }
-        }
-        // y = H^-1 g (upper triangular j x j), x += P (V y)
-        for (int q = j - 1; q >= 0; --q) {
-            double sum = g[q];
-            for (int k = q + 1; k < j; ++k) sum -= H[q * m + k] * yv[k];
-            yv[q] = H[q * m + q] != 0.0 ? sum / H[q * m + q] : 0.0;
-        }
-        if (hipMemcpyAsync(h->hdev.p, yv.data(), sizeof(double) * j, hipMemcpyHostToDevice, st) != hipSuccess)
-            return SEASD_E_HIP;
-        if (hipMemsetAsync(u, 0, sizeof(double) * len, st) != hipSuccess) return SEASD_E_HIP;
-        if (launch_gemv_sub(len, j, V, len, h->hdev.as<double>(), u, st)) return SEASD_E_HIP;   // u = -V y
-        rc = precond(u, z);
-        if (rc) return rc;
-        if (launch_axpby(len, -1.0, z, 1.0, x, st)) return SEASD_E_HIP;
-        ++S.restarts;
-        if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
+        S.setup_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tl).count();
     }
+    GmresResult G;
+    rc = h->gm.solve(apply11, precond, bred, x, c.tol, c.max_iter, st, &G);
+    if (rc) return err_rc ? err_rc : (rc == -6 ? SEASD_E_HIP : rc);
     // pressure moments from the pressure Faxen law: s = M_self^-1 (b_trace - p-coupling(F, S))
     if (launch_trace_op(n, 1, radius, c.eta, x, nullptr, z, st)) return SEASD_E_HIP;   // z = (F, T, S, 0)
     if (c.compressible) {
         rc = queue_apply(h, n, pos, radius, L, z, w, st, false, have_geometry, 1);
         if (rc) return rc;
-        ++S.matvecs;
+        ++extra_matvecs;
         if (launch_trace_op(n, 1, radius, c.eta, z, nullptr, x, st)) return SEASD_E_HIP;
         if (launch_trace_op(n, 2, radius, c.eta, b, w, x, st)) return SEASD_E_HIP;
     } else if (hipMemcpyAsync(x, z, sizeof(double) * len, hipMemcpyDeviceToDevice, st) != hipSuccess) {
         return SEASD_E_HIP;
     }
     if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
-    S.iterations = total;
-    S.true_residual = relres;
-    S.converged = relres <= c.tol ? 1 : 0;
+    S.iterations = G.iterations;
+    S.restarts = G.restarts;
+    S.matvecs = G.matvecs + extra_matvecs;
+    S.true_residual = G.true_residual;
+    S.initial_residual = G.initial_residual;
+    S.converged = G.converged;
     S.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     S.precond_used = learned && !fallback ? c.precond : c.precond == SEASD_PRECOND_NONE ? 0 : 1;
     S.guess_used = guess;
     if (stats) *stats = S;
     if (!S.converged) return SEASD_W_NOT_CONVERGED;
     return fallback ? SEASD_W_PRECOND_FALLBACK : SEASD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// far-field Brownian forces: x = M^(-1/2) psi by the initial value problem of
+// Sec. 4.3 (eqs. ivp-1, ivp-forward, ivp-backward)
+
+extern "C" int seasd_brownian_farfield(seasd_handle h, int64_t n, const double* pos, const double* radius,
+                                       const double* box, const double* psi, double* x, double dtau,
+                                       seasd_brownian_stats* stats, void* stream) {
+    if (!h || n < 1 || n > (int64_t)1 << 28 || !pos || !radius || !psi || !x || psi == x) return SEASD_E_INVALID_ARG;
+    if (!(dtau > 0.0) || !(dtau <= 1.0)) return SEASD_E_INVALID_ARG;
+    Cell L;
+    int rc = parse_cell(box, &L);
+    if (rc) return rc;
+    if (hipSetDevice(h->device) != hipSuccess) return SEASD_E_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    const seasd_config c = h->cfg;
+    const int64_t len = 12 * n;
+    rc = 0;
+    rc |= h->w.ensure(sizeof(double) * len);
+    rc |= h->z.ensure(sizeof(double) * len);
+    rc |= h->u.ensure(sizeof(double) * len);
+    rc |= h->r.ensure(sizeof(double) * len);
+    rc |= h->bred.ensure(sizeof(double) * len);
+    rc |= h->inv2.ensure(sizeof(double) * 144 * n);
+    rc |= h->singular.ensure(sizeof(int));
+    if (rc) return SEASD_E_NOMEM;
+    if ((rc = h->gm.ensure(len, c.restart, c.max_iter))) return rc == -7 ? SEASD_E_NOMEM : SEASD_E_HIP;
+    // the mobility's own blocks M_ii (self and images), for the shifted preconditioners
+    if ((rc = build_preconditioner(h, n, radius, L, st))) return rc;
+    // dimensionless operator A = s M (s = 6 pi eta a_min): eigenvalues of order one
+    double amin = 0.0;
+    {
+        std::vector<double> rad(n);
+        if (hipMemcpy(rad.data(), radius, sizeof(double) * n, hipMemcpyDeviceToHost) != hipSuccess) return SEASD_E_HIP;
+        amin = *std::min_element(rad.begin(), rad.end());
+    }
+    const double s = 6.0 * kPi * c.eta * amin;
+    double* xv = h->u.as<double>();    // the IVP state
+    double* rhs = h->bred.as<double>();
+    double* tmp = h->w.as<double>();
+    double* sol = h->r.as<double>();
+    bool have_geometry = false;
+    bool first = true;
+    // y = s M11 in (incompressible block, trace zeroed)
+    auto applyA = [&](const double* in, double* out) -> int {
+        const bool chk = first && c.checks;
+        first = false;
+        int e = queue_apply(h, n, pos, radius, L, in, out, st, chk, have_geometry, 0);
+        if (e) return e;
+        have_geometry = true;
+        if (chk && (e = read_err(h, st))) return e;
+        return launch_axpby(len, 0.0, in, s, out, st) ? SEASD_E_HIP : SEASD_OK;
+    };
+    seasd_brownian_stats B{};
+    B.scale = s;
+    // solve (alpha I + beta A) y = b with the shifted block-diagonal preconditioner
+    auto shifted_solve = [&](double alpha, double beta, const double* b, double* y) -> int {
+        int e = 0;
+        if (launch_shift_blocks(n, h->blocks.as<double>(), alpha, beta * s, h->inv2.as<double>(), st)) return SEASD_E_HIP;
+        if (hipMemsetAsync(h->singular.p, 0, sizeof(int), st) != hipSuccess) return SEASD_E_HIP;
+        if (launch_block_invert(n, h->inv2.as<double>(), h->inv2.as<double>(), h->singular.as<int>(), st))
+            return SEASD_E_HIP;
+        auto op = [&](const double* in, double* out) -> int {
+            int q = applyA(in, out);
+            if (q) return q;
+            return launch_axpby(len, alpha, in, beta, out, st) ? SEASD_E_HIP : SEASD_OK;
+        };
+        auto pcond = [&](const double* in, double* out) -> int {
+            return launch_block_apply(n, h->inv2.as<double>(), in, out, st) ? SEASD_E_HIP : SEASD_OK;
+        };
+        // start from the right-hand side scaled by the operator's diagonal size
+        if (hipMemcpyAsync(y, b, sizeof(double) * len, hipMemcpyDeviceToDevice, st) != hipSuccess) return SEASD_E_HIP;
+        GmresResult G;
+        e = h->gm.solve(op, pcond, b, y, c.tol, c.max_iter, st, &G);
+        if (e) return e == -6 ? SEASD_E_HIP : e;
+        B.iterations += G.iterations;
+        B.matvecs += G.matvecs;
+        B.solves += 1;
+        B.max_residual = std::max(B.max_residual, G.true_residual);
+        if (!G.converged) B.converged = 0;
+        return SEASD_OK;
+    };
+    B.converged = 1;
+    // x(0) = psi on the 11 incompressible components
+    if (launch_trace_op(n, 1, radius, c.eta, psi, nullptr, xv, st)) return SEASD_E_HIP;
+    const int K = std::max(1, (int)std::lround(1.0 / dtau));
+    const double dt = 1.0 / K;
+    for (int i = 0; i < K; ++i) {
+        const double ta = i * dt, tb = (i + 1) * dt;
+        // forward half step: x' = x - (dt/4) [ta I + (1 - ta) A]^-1 (A - I) x
+        if ((rc = applyA(xv, tmp))) return rc;
+        ++B.matvecs;
+        if (launch_axpby(len, -1.0, xv, 1.0, tmp, st)) return SEASD_E_HIP;   // (A - I) x
+        if ((rc = shifted_solve(ta, 1.0 - ta, tmp, sol))) return rc;
+        if (launch_axpby(len, -0.25 * dt, sol, 1.0, xv, st)) return SEASD_E_HIP;
+        // backward half step: [(tb - dt/4) I + (1 - tb + dt/4) A] x_new = [tb I + (1 - tb) A] x'
+        if ((rc = applyA(xv, tmp))) return rc;
+        ++B.matvecs;
+        if (launch_axpby(len, tb, xv, 1.0 - tb, tmp, st)) return SEASD_E_HIP;
+        if (hipMemcpyAsync(sol, xv, sizeof(double) * len, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return SEASD_E_HIP;
+        if ((rc = shifted_solve(tb - 0.25 * dt, 1.0 - tb + 0.25 * dt, tmp, sol))) return rc;
+        if (hipMemcpyAsync(xv, sol, sizeof(double) * len, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return SEASD_E_HIP;
+    }
+    // M^(-1/2) psi = sqrt(s) A^(-1/2) psi
+    if (launch_axpby(len, std::sqrt(s), xv, 0.0, x, st)) return SEASD_E_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
+    B.steps = K;
+    B.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = B;
+    return B.converged ? SEASD_OK : SEASD_W_NOT_CONVERGED;
 }
 
 // ---------------------------------------------------------------------------
@@ -789,8 +868,8 @@ static int net_step(seasd_handle h, seasd_net net, int64_t n, const double* pos,
                     bool adam, float lr, void* stream) {
     if (!h || !net || n < 1 || n > (int64_t)1 << 26 || !pos || !radius || !b || nrhs < 1 || nrhs > 4096)
         return SEASD_E_INVALID_ARG;
-    double L;
-    int rc = cubic_edge(box, &L);
+    Cell L;
+    int rc = parse_cell(box, &L);
     if (rc) return rc;
     if (hipSetDevice(h->device) != hipSuccess) return SEASD_E_HIP;
     hipStream_t st = (hipStream_t)stream;
@@ -864,10 +943,13 @@ extern "C" int seasd_net_train_step(seasd_handle h, seasd_net net, int64_t n, co
 // ---------------------------------------------------------------------------
 // autotuner and batched products
 
-extern "C" int seasd_autotune(int64_t n, double L, double a_min, double a_max, double target, int32_t precision,
-                              seasd_config* cfg) {
-    if (!cfg || n < 1 || !(L > 0.0) || !(a_min > 0.0) || !(a_max >= a_min) || !(target > 0.0))
-        return SEASD_E_INVALID_ARG;
+extern "C" int seasd_autotune(int64_t n, const double* box, double a_min, double a_max, double target,
+                              int32_t precision, seasd_config* cfg) {
+    if (!cfg || n < 1 || !(a_min > 0.0) || !(a_max >= a_min) || !(target > 0.0)) return SEASD_E_INVALID_ARG;
+    Cell cell;
+    int rc = parse_cell(box, &cell);
+    if (rc) return rc;
+    const double L = min_height(cell);   // the finest grid spacing sets the window rules
     seasd_default_config(cfg);
     cfg->precision = precision;
     cfg->checks = 0;
@@ -896,7 +978,7 @@ extern "C" int seasd_autotune(int64_t n, double L, double a_min, double a_max, d
     if (target >= 1e-5) { xi_h = 0.6 * 0.397; rcx = 0.6 * 3.5; P = 12; mf = 0.95; }
     else if (target >= 1e-6 || precision == SEASD_FP32) { xi_h = 0.8 * 0.397; rcx = 0.8 * 3.0; P = 16; mf = 0.85; }
     else { xi_h = 0.7 * 0.397; rcx = 0.7 * 3.5; P = 16; mf = 0.95; }
-    cfg->grid = M;
+    cfg->grid[0] = cfg->grid[1] = cfg->grid[2] = M;
     cfg->xi = xi_h / h;
     cfg->rc_factor = std::max(1.5, rcx / (cfg->xi * a_min));
     cfg->P = std::min(P, M);
@@ -907,16 +989,13 @@ extern "C" int seasd_autotune(int64_t n, double L, double a_min, double a_max, d
 // streams the batch graph forks its suspensions over (256 suspensions,
 // 658,127 spheres: 24.8 / 24.6 / 24.3 ms per launch with 4 / 8 / 16 streams,
 // within run-to-run spread; HIP maps them onto 4 hardware queues)
-#ifndef SEASD_BATCH_STREAMS
-#define SEASD_BATCH_STREAMS 8
-#endif
-constexpr int kBatchStreams = SEASD_BATCH_STREAMS;
+constexpr int kBatchStreams = 8;
 
 struct seasd_batch_s {
     int device = 0;
     int nsys = 0;
     std::vector<int64_t> off;
-    std::vector<double> L;
+    std::vector<Cell> cells;
     std::vector<seasd_handle> sub;
     std::vector<seasd_config> cfg;
     DevBuf pos, rad, xin, yout;
@@ -967,9 +1046,9 @@ extern "C" int seasd_batch_create(seasd_handle h, int32_t nsys, const int64_t* o
         return code;
     };
     for (int k = 0; k < nsys; ++k) {
-        double Lk;
-        if ((rc = cubic_edge(boxes + 9 * k, &Lk))) return fail(rc);
-        b->L.push_back(Lk);
+        Cell ck;
+        if ((rc = parse_cell(boxes + 9 * k, &ck))) return fail(rc);
+        b->cells.push_back(ck);
     }
     if (b->pos.ensure(sizeof(double) * 3 * N) || b->rad.ensure(sizeof(double) * N) ||
         b->xin.ensure(sizeof(double) * 12 * N) || b->yout.ensure(sizeof(double) * 12 * N))
@@ -993,7 +1072,7 @@ extern "C" int seasd_batch_create(seasd_handle h, int32_t nsys, const int64_t* o
             std::vector<double> rk(rad.begin() + offsets[k], rad.begin() + offsets[k + 1]);
             std::sort(rk.begin(), rk.end());
             const double asmall = rk[(size_t)(0.1 * (rk.size() - 1))], amax = rk.back();
-            if ((rc = seasd_autotune(n, b->L[k], asmall, amax, target, h->cfg.precision, &c))) return fail(rc);
+            if ((rc = seasd_autotune(n, boxes + 9 * k, asmall, amax, target, h->cfg.precision, &c))) return fail(rc);
             c.eta = h->cfg.eta;
             c.compressible = h->cfg.compressible;
         }
@@ -1004,7 +1083,7 @@ extern "C" int seasd_batch_create(seasd_handle h, int32_t nsys, const int64_t* o
         if ((rc = seasd_set_config(sh, &c))) return fail(rc);
         b->cfg.push_back(c);
         const int64_t o = offsets[k];
-        rc = queue_apply(sh, n, b->pos.as<double>() + 3 * o, b->rad.as<double>() + o, b->L[k],
+        rc = queue_apply(sh, n, b->pos.as<double>() + 3 * o, b->rad.as<double>() + o, b->cells[k],
                          b->xin.as<double>() + 12 * o, b->yout.as<double>() + 12 * o, st, false);
         if (rc) return fail(rc);
     }
@@ -1023,14 +1102,15 @@ extern "C" int seasd_batch_create(seasd_handle h, int32_t nsys, const int64_t* o
     std::vector<int> order(nsys);
     for (int k = 0; k < nsys; ++k) order[k] = k;
     std::sort(order.begin(), order.end(), [&](int a, int c) {
-        const double wa = (double)b->cfg[a].grid * b->cfg[a].grid * b->cfg[a].grid + 50.0 * (offsets[a + 1] - offsets[a]);
-        const double wc = (double)b->cfg[c].grid * b->cfg[c].grid * b->cfg[c].grid + 50.0 * (offsets[c + 1] - offsets[c]);
+        const double ga = b->cfg[a].grid[0], gc = b->cfg[c].grid[0];
+        const double wa = ga * ga * ga + 50.0 * (offsets[a + 1] - offsets[a]);
+        const double wc = gc * gc * gc + 50.0 * (offsets[c + 1] - offsets[c]);
         return wa > wc;
     });
     for (int r = 0; r < nsys && ok; ++r) {
         const int k = order[r];
         const int64_t n = offsets[k + 1] - offsets[k], o = offsets[k];
-        rc = queue_apply(b->sub[k], n, b->pos.as<double>() + 3 * o, b->rad.as<double>() + o, b->L[k],
+        rc = queue_apply(b->sub[k], n, b->pos.as<double>() + 3 * o, b->rad.as<double>() + o, b->cells[k],
                          b->xin.as<double>() + 12 * o, b->yout.as<double>() + 12 * o, b->streams[r % kBatchStreams], false,
                          true);
         ok = rc == SEASD_OK;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <vector>
 
 namespace seasd {
@@ -112,15 +113,64 @@ struct DevBuf {
     }
 };
 
+// Periodic cell with lattice vectors a1, a2, a3 as the columns of A (Sec. 2.2).
+// Supported shapes: a1 = (a1x, 0, 0), a2 = (a2x, a2y, 0), a3 = (0, 0, a3z)
+// with positive diagonal and |a2x| <= a1x: cubes, rectangular boxes and boxes
+// sheared in the x-y plane (a2 = (gamma L, L, 0), the simple-shear cell of
+// Sec. 3.2, eq. non-ortho-shape). Fractional coordinates t = A^-1 r.
+struct Cell {
+    double a[9];        // A row-major: a[3 i + j] = component i of lattice vector j
+    double ainv[9];     // A^-1 row-major
+    double height[3];   // cell thickness across the faces spanned by the other two vectors
+    double volume;
+};
+
+__host__ __device__ inline void cell_frac(const Cell& c, double x, double y, double z, double* t) {
+    t[0] = c.ainv[0] * x + c.ainv[1] * y + c.ainv[2] * z;
+    t[1] = c.ainv[3] * x + c.ainv[4] * y + c.ainv[5] * z;
+    t[2] = c.ainv[6] * x + c.ainv[7] * y + c.ainv[8] * z;
+}
+__host__ __device__ inline void cell_cart(const Cell& c, double t0, double t1, double t2, double* r) {
+    r[0] = c.a[0] * t0 + c.a[1] * t1 + c.a[2] * t2;
+    r[1] = c.a[3] * t0 + c.a[4] * t1 + c.a[5] * t2;
+    r[2] = c.a[6] * t0 + c.a[7] * t1 + c.a[8] * t2;
+}
+
+// Window geometry on an M^3 grid in fractional coordinates (Sec. 3.1-3.2).
+// The window is h = C exp(-beta |u|^2) with u the offset from the centre in
+// grid units (eqs. shape, theta-param: beta = 2 m^2 / P^2, so that h falls
+// to exp(-m^2/2) at |u| = P/2), C = (beta/pi)^(3/2) M^3 / V. Its Cartesian
+// gradient is grad h = -2 g h with g = beta J^T u, J = M A^-1; for the
+// supported cells g = (Gxx u_x, Gyx u_x + Gyy u_y, Gzz u_z). The Faxen
+// operators (1 + a^2 lap/6) and grad (1 + a^2 lap/10) of eq. grid-space (with
+// lap = grad_t^T B^T B grad_t / (4 pi^2), eq. non-ortho-shape) act on h as
+//   (1 + a^2 lap/6) h = h (c0 + c1 |g|^2),
+//   grad (1 + a^2 lap/10) h = -h [g (e0 + d1 |g|^2) - (4/5) a^2 Qt (g_x, g_y, 0)],
+// c0 = 1 - a^2 bq/3, c1 = 2 a^2/3, e0 = 2 - 2 a^2 bq/5 - 4 a^2 bz/5, d1 = 4 a^2/5,
+// with bq = beta tr(J^T J), bz = beta (J^T J)_zz and Qt = beta ((J^T J)_xy - (J^T J)_zz I)
+// (zero for a cube or a box with equal spacings in x and y).
+struct WinGeom {
+    double beta;              // Gaussian exponent in grid units
+    double Gxx, Gyx, Gyy, Gzz;
+    double Qxx, Qxy, Qyy;     // Qt (x-y block)
+    double bq, bz;
+    double cw;                // C, the spreading weight
+    double cwv;               // C V / M^3 = (beta/pi)^(3/2), the gather weight
+    bool sheared;             // Qt != 0
+};
+
 struct ApplyArgs {
     int64_t n;
     const double* pos;
     const double* radius;
     const double* x;
     double* y;
-    double L, binw, xi, rc_factor, inv_eta;
-    double h, alpha, tau, cw;
-    int M, P, nb, tile, parts, compressible, checks, fp32;
+    Cell cell;
+    double reach_per_len[3];  // bins per unit length across each pair of faces (nb / height)
+    double xi, rc_factor, inv_eta;
+    WinGeom win;
+    double kdeconv;           // deconvolution exp(kdeconv |q|^2), q the integer wave vector
+    int M, P, nb, parts, compressible, checks, fp32;
     // workspace
     int* bin_of;
     int* counts;
@@ -135,7 +185,8 @@ struct ApplyArgs {
     int2* list;      // [n][cap] neighbour entries (j, packed image shift)
     unsigned long long* amax_bits;
     int* err;
-    double* sp;
+    double* sp;      // [n][3] binned centres, Cartesian, wrapped into the cell
+    double* st;      // [n][3] binned centres, fractional coordinates in [0, 1)
     double* sa;
     double* sx;
     double* ybuf;
@@ -156,6 +207,7 @@ int launch_gather(const ApplyArgs& a, hipStream_t st, PhaseTimer* tm);
 // GMRES / preconditioner helpers (seasd_solver.hip)
 int launch_block_apply(int64_t n, const double* blocks, const double* v, double* z, hipStream_t st);
 int launch_block_invert(int64_t n, const double* a, double* inv, int* singular, hipStream_t st);
+int launch_shift_blocks(int64_t n, const double* blocks, double alpha, double beta, double* out, hipStream_t st);
 int launch_dots(int64_t len, int k, const double* V, int64_t ld, const double* w, double* partial,
                 double* out, hipStream_t st);
 int launch_gemv_sub(int64_t len, int k, const double* V, int64_t ld, const double* h, double* w,
@@ -165,6 +217,32 @@ int launch_trace_op(int64_t n, int mode, const double* radius, double eta, const
                     double* out, hipStream_t st);
 int launch_build_blocks(int64_t n, const double* radius, const double* coef, double xi, double eta,
                         double* blocks, hipStream_t st);
+
+// Restarted right-preconditioned GMRES with the Arnoldi process on the device
+// (seasd_gmres.hip). apply_A(in, out) and apply_P(in, out) queue out = A in
+// and out = P in on the solve's stream; vectors have len entries.
+struct GmresResult {
+    int iterations = 0, restarts = 0, matvecs = 0, converged = 0;
+    double true_residual = 0.0, initial_residual = 0.0;
+};
+
+struct DeviceGmres {
+    int64_t len = 0;
+    int m = 0, chunk = 0, nblk = 0;
+    DevBuf V, w, z, u, r, small, partial, counters, resid_dev;
+    double* resid_host = nullptr;   // pinned: per-step residual estimates
+    int resid_host_n = 0;
+    std::vector<hipEvent_t> events;
+    bool counters_clear = false;
+    int ensure(int64_t len, int m, int max_steps);   // 0, -7 (no memory) or -6 (HIP)
+    void release();
+    double norm(const double* v, hipStream_t st, int* rc);   // synchronises
+    // x in: initial guess, out: solution; stops when |b - A x| <= tol |b| (true
+    // residual at each restart) or after max_iter Arnoldi steps
+    int solve(const std::function<int(const double*, double*)>& apply_A,
+              const std::function<int(const double*, double*)>& apply_P, const double* b, double* x, double tol,
+              int max_iter, hipStream_t st, GmresResult* res);
+};
 
 // neighbour graph of the learned preconditioner (seasd_kernels.hip): edges
 // s -> j between binned spheres with |r| < cut (a_s + a_j). Count pass: deg

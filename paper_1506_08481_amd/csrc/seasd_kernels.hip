@@ -80,11 +80,19 @@ __device__ inline int xcd_block(int b, int nblk) {
     return k * per + min(k, rem) + idx;
 }
 
-// coordinate wrapped into [0, L); the same expression is used for the bin and
-// for the binned copy so both always agree
-__device__ inline double wrap_coord(double p, double L) {
-    double w = p - L * floor(p / L);
-    return (w < L && w >= 0.0) ? w : 0.0;
+// fractional coordinates of a centre wrapped into [0, 1); the same expression
+// gives the bin and the binned copy, so both always agree
+__device__ inline void wrap_frac(const Cell& c, const double* p, double* t) {
+    cell_frac(c, p[0], p[1], p[2], t);
+    for (int d = 0; d < 3; ++d) {
+        const double w = t[d] - floor(t[d]);
+        t[d] = (w < 1.0 && w >= 0.0) ? w : 0.0;
+    }
+}
+
+__device__ inline int bin_coord(double t, int nb) {
+    const int k = (int)floor(t * nb);
+    return k < 0 ? 0 : (k >= nb ? nb - 1 : k);
 }
 
 // clears the per-bin counters, the radius maximum and the list statistics
@@ -105,7 +113,7 @@ __global__ void k_zero_geometry(int nbins, int* __restrict__ counts, int* __rest
 }
 
 __global__ __launch_bounds__(256) void k_bin_count(int n, const double* __restrict__ pos, const double* __restrict__ rad,
-                            double L, int nb, double binw, int* __restrict__ bin_of,
+                            Cell cell, int nb, int* __restrict__ bin_of,
                             int* __restrict__ counts, unsigned long long* __restrict__ amax_bits,
                             int* __restrict__ err) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -119,13 +127,9 @@ __global__ __launch_bounds__(256) void k_bin_count(int n, const double* __restri
             p[0] = p[1] = p[2] = 0.0;
             a = 1.0;
         }
-        int b[3];
-        for (int d = 0; d < 3; ++d) {
-            double w = wrap_coord(p[d], L);
-            int k = (int)floor(w / binw);
-            b[d] = k < 0 ? 0 : (k >= nb ? nb - 1 : k);
-        }
-        int bin = bin_id(b[0], b[1], b[2]);
+        double t[3];
+        wrap_frac(cell, p, t);
+        int bin = bin_id(bin_coord(t[0], nb), bin_coord(t[1], nb), bin_coord(t[2], nb));
         bin_of[i] = bin;
         atomicAdd(&counts[bin], 1);
     }
@@ -259,18 +263,26 @@ __global__ void k_bin_order(int nbins, const int* __restrict__ start, int* __res
     }
 }
 
-// binned copies: wrapped centres, radii and moments (FP64)
+// binned copies: wrapped centres (fractional and Cartesian), radii and moments (FP64)
 __global__ void k_bin_gather(int n, const int* __restrict__ perm, const double* __restrict__ pos,
                              const double* __restrict__ rad, const double* __restrict__ x,
-                             double L, int compressible, double* __restrict__ sp,
+                             Cell cell, int compressible, double* __restrict__ sp, double* __restrict__ stf,
                              double* __restrict__ sa, double* __restrict__ sx,
                              int* __restrict__ err) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     int i = perm[s];
+    double p[3];
     for (int d = 0; d < 3; ++d) {
-        double p = pos[3 * i + d];
-        sp[3 * s + d] = isfinite(p) ? wrap_coord(p, L) : 0.0;
+        p[d] = pos[3 * i + d];
+        if (!isfinite(p[d])) p[d] = 0.0;
+    }
+    double t[3], r[3];
+    wrap_frac(cell, p, t);
+    cell_cart(cell, t[0], t[1], t[2], r);
+    for (int d = 0; d < 3; ++d) {
+        stf[3 * s + d] = t[d];
+        sp[3 * s + d] = r[d];
     }
     double a = rad[i];
     sa[s] = (isfinite(a) && a > 0.0) ? a : 1.0;
@@ -296,63 +308,77 @@ __global__ void k_bin_gather(int n, const int* __restrict__ perm, const double* 
 // no lane spends the heavy pair arithmetic on a candidate outside the cut-off.
 
 // below this many spheres the neighbour list and the pair sum use one
-// wavefront per sphere (one thread per sphere would leave most CUs idle)
+// wavefront per sphere (one thread per sphere would leave most CUs idle);
+// larger suspensions search with a wavefront per bin and sum with a thread
+// per sphere (a wavefront per sphere when the lists are uneven)
 constexpr int kWaveSpheres = 32768;
-// neighbour-list search for larger suspensions: one wavefront per bin, else
-// kGroupLarge lanes per sphere (1: one thread)
-#ifndef SEASD_FILL_BY_BIN
-#define SEASD_FILL_BY_BIN 1
-#endif
-constexpr bool kFillByBin = SEASD_FILL_BY_BIN != 0;
-constexpr int kGroupLarge = 1;
-// lanes per sphere of the pair sum for larger suspensions (1: one thread)
-#ifndef SEASD_EVAL_GROUP
-#define SEASD_EVAL_GROUP 1
-#endif
-constexpr int kEvalGroupLarge = SEASD_EVAL_GROUP;
-// lanes per sphere of the pair sum below kWaveSpheres
-#ifndef SEASD_EVAL_GROUP_SMALL
-#define SEASD_EVAL_GROUP_SMALL 64
-#endif
-constexpr int kEvalGroupSmall = SEASD_EVAL_GROUP_SMALL;
 
 __device__ inline int floordiv(int c, int nb) { return (c >= 0) ? c / nb : -((-c + nb - 1) / nb); }
 
-// visit every (j, image) within the cut-off of binned sphere s; f(j, code) per hit
+// Neighbour-bin geometry: the cell and, per lattice direction, the bins per
+// unit length across its faces (nb / height). A source within r of a centre
+// lies at most ceil(r nb / height_d) bins away along direction d.
+struct NbrGeom {
+    Cell cell;
+    double rpl[3];
+};
+
+__device__ inline int image_code(int wx, int wy, int wz) { return ((wz + 512) << 20) | ((wy + 512) << 10) | (wx + 512); }
+__device__ inline void image_of(int code, int& wx, int& wy, int& wz) {
+    wx = (code & 1023) - 512;
+    wy = ((code >> 10) & 1023) - 512;
+    wz = ((code >> 20) & 1023) - 512;
+}
+// lattice translation wx a1 + wy a2 + wz a3
+__device__ inline void image_shift(const Cell& c, int wx, int wy, int wz, double* o) {
+    cell_cart(c, (double)wx, (double)wy, (double)wz, o);
+}
+
+// bin reach of cut-off r along each direction; flags (and clamps) a reach
+// beyond about three cell lengths
+__device__ inline void bin_reach(const NbrGeom& g, double r, int nb, int* reach, int* __restrict__ err, bool flag) {
+    for (int d = 0; d < 3; ++d) {
+        reach[d] = (int)ceil(r * g.rpl[d]);
+        if (reach[d] > 3 * nb + 2) {
+            if (flag) atomicOr(err, kErrCutoff);
+            reach[d] = 3 * nb + 2;
+        }
+    }
+}
+
+// visit every (j, image) within the cut-off of binned sphere s, bins in the
+// order x fastest, then y, then z; f(j, code) per hit
 template <typename F>
-__device__ inline void for_each_neighbour(int s, const double* __restrict__ sp, const double* __restrict__ sa,
-                                          const int* __restrict__ start, int nb, double L, double binw,
-                                          double rc_factor, double amax, int checks, int* __restrict__ err,
-                                          F&& f) {
+__device__ inline void for_each_neighbour(int s, const double* __restrict__ sp, const double* __restrict__ stf,
+                                          const double* __restrict__ sa, const int* __restrict__ start, int nb,
+                                          const NbrGeom& g, double rc_factor, double amax, int checks,
+                                          int* __restrict__ err, F&& f) {
     const double px = sp[3 * s], py = sp[3 * s + 1], pz = sp[3 * s + 2];
     const double ai = sa[s];
-    const double rcmax = rc_factor * (ai + amax);
-    int reach = (int)ceil(rcmax / binw);
-    if (reach > 3 * nb + 2) {  // cut-off beyond about three cell lengths: refuse
-        atomicOr(err, kErrCutoff);
-        reach = 3 * nb + 2;
-    }
-    const int bx = min(nb - 1, (int)(px / binw)), by = min(nb - 1, (int)(py / binw)),
-              bz = min(nb - 1, (int)(pz / binw));
-    for (int oz = -reach; oz <= reach; ++oz) {
+    int reach[3];
+    bin_reach(g, rc_factor * (ai + amax), nb, reach, err, true);
+    const int bx = bin_coord(stf[3 * s], nb), by = bin_coord(stf[3 * s + 1], nb), bz = bin_coord(stf[3 * s + 2], nb);
+    for (int oz = -reach[2]; oz <= reach[2]; ++oz) {
         int cz = bz + oz;
         const int wz = floordiv(cz, nb);
         cz -= wz * nb;
-        for (int oy = -reach; oy <= reach; ++oy) {
+        for (int oy = -reach[1]; oy <= reach[1]; ++oy) {
             int cy = by + oy;
             const int wy = floordiv(cy, nb);
             cy -= wy * nb;
-            for (int ox = -reach; ox <= reach; ++ox) {
+            for (int ox = -reach[0]; ox <= reach[0]; ++ox) {
                 int cx = bx + ox;
                 const int wx = floordiv(cx, nb);
                 cx -= wx * nb;
                 const int bin = bin_id(cx, cy, cz);
-                const int code = ((wz + 512) << 20) | ((wy + 512) << 10) | (wx + 512);
+                const int code = image_code(wx, wy, wz);
+                double o[3];
+                image_shift(g.cell, wx, wy, wz, o);
                 for (int j = start[bin]; j < start[bin + 1]; ++j) {
                     if (j == s && wx == 0 && wy == 0 && wz == 0) continue;
-                    const double dx = px - (sp[3 * j] + wx * L);
-                    const double dy = py - (sp[3 * j + 1] + wy * L);
-                    const double dz = pz - (sp[3 * j + 2] + wz * L);
+                    const double dx = px - (sp[3 * j] + o[0]);
+                    const double dy = py - (sp[3 * j + 1] + o[1]);
+                    const double dz = pz - (sp[3 * j + 2] + o[2]);
                     const double r2 = dx * dx + dy * dy + dz * dz;
                     const double aj = sa[j];
                     const double rc = rc_factor * (ai + aj);
@@ -365,39 +391,20 @@ __device__ inline void for_each_neighbour(int s, const double* __restrict__ sp, 
     }
 }
 
-// One pass: every sphere lists its neighbours into its own slot of `cap`
-// entries (in visiting order) and stores the full count; when the largest
-// count exceeds cap the host grows cap and repeats the pass.
-__global__ __launch_bounds__(256) void k_pair_fill(int n, const double* __restrict__ sp,
-                                                   const double* __restrict__ sa, const int* __restrict__ start,
-                                                   int nb, double L, double binw, double rc_factor,
-                                                   const unsigned long long* __restrict__ amax_bits, int checks,
-                                                   int cap, int* __restrict__ ncount,
-                                                   int2* __restrict__ list, int* __restrict__ err) {
-    const int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const double amax = __longlong_as_double((long long)*amax_bits);
-    int2* dst = list + (size_t)cap * s;
-    int k = 0;
-    for_each_neighbour(s, sp, sa, start, nb, L, binw, rc_factor, amax, checks, err, [&](int j, int code) {
-        if (k < cap) dst[k] = make_int2(j, code);
-        ++k;
-    });
-    ncount[s] = k;
-}
-
-// The same list with a group of G lanes per sphere (G = 64: a wavefront, for
-// suspensions too small to fill the chip with one thread per sphere; smaller G
-// for large ones, where neighbouring spheres of one wavefront share bins):
-// lane l of the group takes bins l, l + G, ... of the
-// (2 reach + 1)^3 neighbour bins in the visiting order of for_each_neighbour,
-// counts its hits, a wavefront prefix sum gives every lane its first slot and
-// a second sweep over the lane's bin writes the entries, so the list comes out
-// in the same order as the serial search.
+// The list with a group of G lanes per sphere (G = 64: a wavefront, for
+// suspensions too small to fill the chip with one thread per sphere): lane l
+// of the group takes bins l, l + G, ... of the neighbour bins in the visiting
+// order of for_each_neighbour, counts its hits, a prefix sum over the group
+// gives every lane its first slot and a second sweep over the lane's bin
+// writes the entries, so the list comes out in the same order as the serial
+// search. Every sphere lists into its own slot of `cap` entries and stores
+// the full count; when the largest count exceeds cap the host grows cap and
+// repeats the pass.
 template <int G>
 __global__ __launch_bounds__(256) void k_pair_fill_group(int n, const double* __restrict__ sp,
+                                                        const double* __restrict__ stf,
                                                         const double* __restrict__ sa, const int* __restrict__ start,
-                                                        int nb, double L, double binw, double rc_factor,
+                                                        int nb, NbrGeom g, double rc_factor,
                                                         const unsigned long long* __restrict__ amax_bits, int checks,
                                                         int cap, int* __restrict__ ncount,
                                                         int2* __restrict__ list, int* __restrict__ err) {
@@ -407,23 +414,20 @@ __global__ __launch_bounds__(256) void k_pair_fill_group(int n, const double* __
     const double amax = __longlong_as_double((long long)*amax_bits);
     const double px = sp[3 * s], py = sp[3 * s + 1], pz = sp[3 * s + 2];
     const double ai = sa[s];
-    int reach = (int)ceil(rc_factor * (ai + amax) / binw);
-    if (reach > 3 * nb + 2) {
-        if (lane == 0) atomicOr(err, kErrCutoff);
-        reach = 3 * nb + 2;
-    }
-    const int span = 2 * reach + 1, nbins = span * span * span;
-    const int bx = min(nb - 1, (int)(px / binw)), by = min(nb - 1, (int)(py / binw)),
-              bz = min(nb - 1, (int)(pz / binw));
+    int reach[3];
+    bin_reach(g, rc_factor * (ai + amax), nb, reach, err, lane == 0);
+    const int sx = 2 * reach[0] + 1, sy = 2 * reach[1] + 1, sz = 2 * reach[2] + 1;
+    const int nbins = sx * sy * sz;
+    const int bx = bin_coord(stf[3 * s], nb), by = bin_coord(stf[3 * s + 1], nb), bz = bin_coord(stf[3 * s + 2], nb);
     int2* dst = list + (size_t)cap * s;
     int total = 0;
     for (int base = 0; base < nbins; base += G) {
         const int q = base + lane;
         int j0 = 0, j1 = 0, code = 0;
-        double ox = 0.0, oy = 0.0, oz = 0.0;
+        double o[3] = {0.0, 0.0, 0.0};
         bool self_bin = false;
         if (q < nbins) {
-            const int kx = q % span - reach, ky = (q / span) % span - reach, kz = q / (span * span) - reach;
+            const int kx = q % sx - reach[0], ky = (q / sx) % sy - reach[1], kz = q / (sx * sy) - reach[2];
             int cx = bx + kx, cy = by + ky, cz = bz + kz;
             const int wx = floordiv(cx, nb), wy = floordiv(cy, nb), wz = floordiv(cz, nb);
             cx -= wx * nb;
@@ -432,16 +436,14 @@ __global__ __launch_bounds__(256) void k_pair_fill_group(int n, const double* __
             const int bin = bin_id(cx, cy, cz);
             j0 = start[bin];
             j1 = start[bin + 1];
-            code = ((wz + 512) << 20) | ((wy + 512) << 10) | (wx + 512);
-            ox = wx * L;
-            oy = wy * L;
-            oz = wz * L;
+            code = image_code(wx, wy, wz);
+            image_shift(g.cell, wx, wy, wz, o);
             self_bin = wx == 0 && wy == 0 && wz == 0;
         }
         int cnt = 0;
         for (int j = j0; j < j1; ++j) {
             if (j == s && self_bin) continue;
-            const double dx = px - (sp[3 * j] + ox), dy = py - (sp[3 * j + 1] + oy), dz = pz - (sp[3 * j + 2] + oz);
+            const double dx = px - (sp[3 * j] + o[0]), dy = py - (sp[3 * j + 1] + o[1]), dz = pz - (sp[3 * j + 2] + o[2]);
             const double r2 = dx * dx + dy * dy + dz * dz, aj = sa[j];
             const double rc = rc_factor * (ai + aj);
             if (r2 >= rc * rc) continue;
@@ -457,8 +459,8 @@ __global__ __launch_bounds__(256) void k_pair_fill_group(int n, const double* __
         if (cnt > 0) {
             for (int j = j0; j < j1; ++j) {
                 if (j == s && self_bin) continue;
-                const double dx = px - (sp[3 * j] + ox), dy = py - (sp[3 * j + 1] + oy),
-                             dz = pz - (sp[3 * j + 2] + oz);
+                const double dx = px - (sp[3 * j] + o[0]), dy = py - (sp[3 * j + 1] + o[1]),
+                             dz = pz - (sp[3 * j + 2] + o[2]);
                 const double r2 = dx * dx + dy * dy + dz * dz, aj = sa[j];
                 const double rc = rc_factor * (ai + aj);
                 if (r2 >= rc * rc) continue;
@@ -475,8 +477,8 @@ __global__ __launch_bounds__(256) void k_pair_fill_group(int n, const double* __
 
 // The same lists with one wavefront per bin (large suspensions). The
 // wavefront holds the spheres of its bin, 64 at a time, one per lane ("home"
-// spheres), and walks the (2 reach + 1)^3 neighbour bins in the visiting order
-// of for_each_neighbour, reach taken from the largest home radius: 64 bins at a
+// spheres), and walks the neighbour bins in the visiting order of
+// for_each_neighbour, reach taken from the largest home radius: 64 bins at a
 // time give their sphere ranges (one bin per lane) and a wavefront prefix sum;
 // the candidates of those bins are listed in LDS in visiting order and taken
 // into registers 64 kFillSlots at a time (slot r of lane l: candidate 64 r + l),
@@ -484,10 +486,7 @@ __global__ __launch_bounds__(256) void k_pair_fill_group(int n, const double* __
 // each hit its slot. A bin beyond a sphere's own reach holds no sphere within
 // its cut-off, so each list is exactly the one the serial search writes; the
 // candidate loads are coalesced and shared by all spheres of the bin.
-#ifndef SEASD_FILL_SLOTS
-#define SEASD_FILL_SLOTS 4
-#endif
-constexpr int kFillSlots = SEASD_FILL_SLOTS;   // candidate slots per lane and pass
+constexpr int kFillSlots = 4;   // candidate slots per lane and pass
 
 __device__ inline int lanes_below(unsigned long long m) {
     return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
@@ -508,7 +507,7 @@ __device__ inline void wave_sync() {
 
 __global__ __launch_bounds__(256) void k_pair_fill_bin(int n, const double* __restrict__ sp,
                                                       const double* __restrict__ sa, const int* __restrict__ start,
-                                                      int nb, double L, double binw, double rc_factor,
+                                                      int nb, NbrGeom g, double rc_factor,
                                                       const unsigned long long* __restrict__ amax_bits, int checks,
                                                       int cap, int* __restrict__ ncount,
                                                       int2* __restrict__ list, int* __restrict__ err) {
@@ -535,20 +534,18 @@ __global__ __launch_bounds__(256) void k_pair_fill_bin(int n, const double* __re
         }
         double amx = 0.0;
         for (int h = 0; h < nh; ++h) amx = fmax(amx, lane_value(ha, h));
-        int reach = (int)ceil(rc_factor * (amx + amax) / binw);
-        if (reach > 3 * nb + 2) {
-            if (lane == 0) atomicOr(err, kErrCutoff);
-            reach = 3 * nb + 2;
-        }
-        const int span = 2 * reach + 1, nnb = span * span * span;
+        int reach[3];
+        bin_reach(g, rc_factor * (amx + amax), nb, reach, err, lane == 0);
+        const int sx = 2 * reach[0] + 1, sy = 2 * reach[1] + 1, sz = 2 * reach[2] + 1;
+        const int nnb = sx * sy * sz;
         int cnt = 0;   // lane h: entries of home sphere hb + h so far
         for (int q0 = 0; q0 < nnb; q0 += 64) {
             int j0 = 0, len = 0, code = 0;
             {   // lane u: neighbour bin q0 + u
                 const int q = q0 + lane;
                 if (q < nnb) {
-                    int cx = bx + q % span - reach, cy = by + (q / span) % span - reach,
-                        cz = bz + q / (span * span) - reach;
+                    int cx = bx + q % sx - reach[0], cy = by + (q / sx) % sy - reach[1],
+                        cz = bz + q / (sx * sy) - reach[2];
                     const int wx = floordiv(cx, nb), wy = floordiv(cy, nb), wz = floordiv(cz, nb);
                     cx -= wx * nb;
                     cy -= wy * nb;
@@ -556,7 +553,7 @@ __global__ __launch_bounds__(256) void k_pair_fill_bin(int n, const double* __re
                     const int bin = bin_id(cx, cy, cz);
                     j0 = start[bin];
                     len = start[bin + 1] - j0;
-                    code = ((wz + 512) << 20) | ((wy + 512) << 10) | (wx + 512);
+                    code = image_code(wx, wy, wz);
                 }
             }
             int incl = len;
@@ -583,13 +580,15 @@ __global__ __launch_bounds__(256) void k_pair_fill_bin(int n, const double* __re
                     cx[r] = cy[r] = cz[r] = ca[r] = 0.0;
                     if (c < wlen) {
                         const int2 e = cl[c];
-                        const int wx = (e.y & 1023) - 512, wy = ((e.y >> 10) & 1023) - 512,
-                                  wz = ((e.y >> 20) & 1023) - 512;
+                        int wx, wy, wz;
+                        image_of(e.y, wx, wy, wz);
+                        double o[3];
+                        image_shift(g.cell, wx, wy, wz, o);
                         cj[r] = e.x;
                         cc[r] = e.y;
-                        cx[r] = sp[3 * e.x] + wx * L;
-                        cy[r] = sp[3 * e.x + 1] + wy * L;
-                        cz[r] = sp[3 * e.x + 2] + wz * L;
+                        cx[r] = sp[3 * e.x] + o[0];
+                        cy[r] = sp[3 * e.x + 1] + o[1];
+                        cz[r] = sp[3 * e.x + 2] + o[2];
                         ca[r] = sa[e.x];
                     }
                 }
@@ -661,7 +660,7 @@ __global__ __launch_bounds__(256) void k_count_stats(int n, const int* __restric
 __global__ __launch_bounds__(128) void k_pair_eval(int n, const double* __restrict__ sp,
                                                    const double* __restrict__ sa, const double* __restrict__ sx,
                                                    const int* __restrict__ ncount, int cap, const int2* __restrict__ list,
-                                                   double L, double xi, double inv_eta, int parts,
+                                                   Cell cell, double xi, double inv_eta, int parts,
                                                    double* __restrict__ ybuf) {
     const int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -674,10 +673,13 @@ __global__ __launch_bounds__(128) void k_pair_eval(int n, const double* __restri
         for (int k = k0; k < k1; ++k) {
             const int2 e = list[k];
             const int j = e.x;
-            const int wx = (e.y & 1023) - 512, wy = ((e.y >> 10) & 1023) - 512, wz = ((e.y >> 20) & 1023) - 512;
-            const double dx = px - (sp[3 * j] + wx * L);
-            const double dy = py - (sp[3 * j + 1] + wy * L);
-            const double dz = pz - (sp[3 * j + 2] + wz * L);
+            int wx, wy, wz;
+            image_of(e.y, wx, wy, wz);
+            double o[3];
+            image_shift(cell, wx, wy, wz, o);
+            const double dx = px - (sp[3 * j] + o[0]);
+            const double dy = py - (sp[3 * j + 1] + o[1]);
+            const double dz = pz - (sp[3 * j + 2] + o[2]);
             double xj[12];
             for (int c = 0; c < 12; ++c) xj[c] = sx[12 * (size_t)j + c];
             pair_coupling<double>(dx, dy, dz, ai, sa[j], xi, inv_eta, xj, y);
@@ -706,7 +708,7 @@ __global__ __launch_bounds__(256) void k_pair_eval_group(int n, const double* __
                                                          const double* __restrict__ sa,
                                                          const double* __restrict__ sx,
                                                          const int* __restrict__ ncount, int cap,
-                                                         const int2* __restrict__ list, double L, double xi,
+                                                         const int2* __restrict__ list, Cell cell, double xi,
                                                          double inv_eta, int parts, double* __restrict__ ybuf) {
     const int lane = threadIdx.x & (G - 1);
     const int s = xcd_block(blockIdx.x, gridDim.x) * (256 / G) + threadIdx.x / G;
@@ -720,10 +722,13 @@ __global__ __launch_bounds__(256) void k_pair_eval_group(int n, const double* __
         for (int k = k0 + lane; k < k1; k += G) {
             const int2 e = list[k];
             const int j = e.x;
-            const int wx = (e.y & 1023) - 512, wy = ((e.y >> 10) & 1023) - 512, wz = ((e.y >> 20) & 1023) - 512;
-            const double dx = px - (sp[3 * j] + wx * L);
-            const double dy = py - (sp[3 * j + 1] + wy * L);
-            const double dz = pz - (sp[3 * j + 2] + wz * L);
+            int wx, wy, wz;
+            image_of(e.y, wx, wy, wz);
+            double o[3];
+            image_shift(cell, wx, wy, wz, o);
+            const double dx = px - (sp[3 * j] + o[0]);
+            const double dy = py - (sp[3 * j + 1] + o[1]);
+            const double dz = pz - (sp[3 * j + 2] + o[2]);
             double xj[12];
             for (int c = 0; c < 12; ++c) xj[c] = sx[12 * (size_t)j + c];
             pair_coupling<double>(dx, dy, dz, ai, sa[j], xi, inv_eta, xj, y);
@@ -749,22 +754,22 @@ __global__ __launch_bounds__(256) void k_pair_eval_group(int n, const double* __
 // binned spheres closer than cut (a_s + a_j), rows in binned order, each row
 // in the (deterministic) visiting order of for_each_neighbour
 
-__global__ __launch_bounds__(256) void k_edge_count(int n, const double* __restrict__ sp,
+__global__ __launch_bounds__(256) void k_edge_count(int n, const double* __restrict__ sp, const double* __restrict__ stf,
                                                     const double* __restrict__ sa, const int* __restrict__ start,
-                                                    int nb, double L, double binw, double cut,
+                                                    int nb, NbrGeom g, double cut,
                                                     const unsigned long long* __restrict__ amax_bits,
                                                     int* __restrict__ deg, int* __restrict__ err) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const double amax = __longlong_as_double((long long)*amax_bits);
     int k = 0;
-    for_each_neighbour(s, sp, sa, start, nb, L, binw, cut, amax, 0, err, [&](int, int) { ++k; });
+    for_each_neighbour(s, sp, stf, sa, start, nb, g, cut, amax, 0, err, [&](int, int) { ++k; });
     deg[s] = k;
 }
 
-__global__ __launch_bounds__(256) void k_edge_fill(int n, const double* __restrict__ sp,
+__global__ __launch_bounds__(256) void k_edge_fill(int n, const double* __restrict__ sp, const double* __restrict__ stf,
                                                    const double* __restrict__ sa, const int* __restrict__ start,
-                                                   int nb, double L, double binw, double cut,
+                                                   int nb, NbrGeom g, double cut,
                                                    const unsigned long long* __restrict__ amax_bits,
                                                    const int* __restrict__ rowptr, int* __restrict__ esrc,
                                                    int* __restrict__ edst, float4* __restrict__ geo,
@@ -775,10 +780,13 @@ __global__ __launch_bounds__(256) void k_edge_fill(int n, const double* __restri
     const double px = sp[3 * s], py = sp[3 * s + 1], pz = sp[3 * s + 2], ai = sa[s];
     int e = rowptr[s];
     const int e1 = rowptr[s + 1];
-    for_each_neighbour(s, sp, sa, start, nb, L, binw, cut, amax, 0, err, [&](int j, int code) {
+    for_each_neighbour(s, sp, stf, sa, start, nb, g, cut, amax, 0, err, [&](int j, int code) {
         if (e >= e1) return;   // the count pass bounds the row
-        const int wx = (code & 1023) - 512, wy = ((code >> 10) & 1023) - 512, wz = ((code >> 20) & 1023) - 512;
-        const double dx = sp[3 * j] + wx * L - px, dy = sp[3 * j + 1] + wy * L - py, dz = sp[3 * j + 2] + wz * L - pz;
+        int wx, wy, wz;
+        image_of(code, wx, wy, wz);
+        double o[3];
+        image_shift(g.cell, wx, wy, wz, o);
+        const double dx = sp[3 * j] + o[0] - px, dy = sp[3 * j + 1] + o[1] - py, dz = sp[3 * j + 2] + o[2] - pz;
         const double r = sqrt(dx * dx + dy * dy + dz * dz), aj = sa[j];
         const double rho = r / (ai + aj);
         esrc[e] = s;
@@ -832,28 +840,34 @@ __global__ __launch_bounds__(256) void k_edge_rev(int n, const double* __restric
 // ---------------------------------------------------------------------------
 // window records
 //
-// The window is the normalised Gaussian h(r) = (4 pi tau)^(-3/2) exp(-r^2/(4 tau))
-// with tau = (P h)^2/(8 m^2), i.e. exp(-m^2/2) at the support edge P h/2
-// (eqs. shape, theta-param written in Cartesian form for a cubic cell). It is
-// evaluated on P points per dimension starting at i0 = floor(x/h) - P/2 + 1.
-// One record per sphere (binned order) holds i0, the offset d0 = i0 h - x, the
-// 1-D factors exp(-alpha (d0 + k h)^2) and the moments; spreading and gather
-// both read it. The factors use fast Gaussian gridding (eq. fgg-exp), anchored
-// at the window centre so the recurrences run over at most P/2 steps, in FP64.
+// The window is the Gaussian h = C exp(-beta |u|^2) of eq. shape, with u the
+// offset from the sphere centre in grid units of the fractional grid (the
+// cell's M^3 grid points t = k/M), beta = 2 m^2/P^2 from eq. theta-param
+// (h falls to exp(-m^2/2) at |u| = P/2). It is evaluated on P points per
+// dimension: for even P the points floor(u) - P/2 + 1 .. floor(u) + P/2, for
+// odd P the points round(u) -+ (P - 1)/2, so that the window is centred on
+// the sphere either way (the printed range [-P/2, P/2] of eq. fgg-exp holds
+// P + 1 points when P is even). One record per sphere (binned order) holds
+// i0, the offset delta = i0 - u, the 1-D factors exp(-beta (delta + k)^2),
+// the moments and the Faxen constants of the sphere (WinGeom); spreading and
+// gather both read it. The factors use fast Gaussian gridding (eq. fgg-exp),
+// anchored at the window centre so the recurrences run over at most P/2
+// steps, in FP64.
 
 constexpr int kMaxP = 32;
-// record layout (R units): [0..2] i0 (int bits), [3] d1, [4..6] d0, [7] a^2,
+// record layout (R units): [0..2] i0 (int bits), [3] d1, [4..6] delta, [7] a^2,
 // [8..10] F, [11..13] T, [14..19] S (xx yy zz xy xz yz), [20] sqrt3 s6,
 // [21] c0, [22] c1, [23] e0, [24 ..] factors x[P], y[P], z[P].
-// With w the window value at squared distance r2, the Faxen-weighted window
-// (1 + a^2 lap/6) h is w (c0 + c1 r2) and -(d/dr)(1 + a^2 lap/10) h / r is
-// w (e0 + d1 r2): c0 = 1 - a^2 alpha, c1 = (2/3) a^2 alpha^2,
-// e0 = 2 alpha - 2 a^2 alpha^2, d1 = 0.8 a^2 alpha^3.
 static_assert(kRecHead == 24, "record header layout above");
+
+// first of the P window points of a centre at grid coordinate u
+__host__ __device__ inline int first_window_point(double u, int P) {
+    return (P & 1) ? (int)floor(u + 0.5) - (P - 1) / 2 : (int)floor(u) - P / 2 + 1;
+}
 
 template <typename O>
 __device__ inline void fgg_factors(double d0, double h, double alpha, int P, O* out) {
-    const int kc = P / 2 - 1;               // d0 + kc h lies in (-h, 0]
+    const int kc = (P - 1) / 2;   // d0 + kc h in (-h, 0] (even P) or [-h/2, h/2) (odd P)
     const double dc = d0 + kc * h;
     const double e0 = exp(-alpha * dc * dc);
     const double up = exp(-2.0 * alpha * dc * h);  // exp(-2 alpha dc h)^j
@@ -888,9 +902,9 @@ __device__ inline int rec_i0(const R* rec, int d) {
 constexpr int kWinSpheres = 64;
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_window(int n, const double* __restrict__ sp, const double* __restrict__ sa,
-                                                const double* __restrict__ sx, int P, double h, double alpha,
-                                                R* __restrict__ rec_out) {
+__global__ __launch_bounds__(256) void k_window(int n, const double* __restrict__ stf, const double* __restrict__ sa,
+                                                const double* __restrict__ sx, int P, int M, double beta, double bq,
+                                                double bz, R* __restrict__ rec_out) {
     __shared__ __attribute__((aligned(16))) R buf[kWinSpheres * ((kRecHead + 3 * kMaxP + 3) & ~3)];
     const int RS = rec_stride(P);
     const int s0 = blockIdx.x * kWinSpheres;
@@ -902,22 +916,22 @@ __global__ __launch_bounds__(256) void k_window(int n, const double* __restrict_
         R* rec = buf + q * RS;
         if (piece > 0) {
             const int d = piece - 1;
-            const double p = sp[3 * s + d];
-            const int i0 = (int)floor(p / h) - P / 2 + 1;
-            const double d0 = i0 * h - p;
+            const double u = stf[3 * s + d] * M;   // exact: M is a power of two
+            const int i0 = first_window_point(u, P);
+            const double delta = i0 - u;
             if constexpr (sizeof(R) == 4) rec[d] = __int_as_float(i0);
             else rec[d] = __longlong_as_double((long long)i0);
-            rec[4 + d] = (R)d0;
-            fgg_factors(d0, h, alpha, P, rec + kRecHead + d * P);   // straight into the LDS record
+            rec[4 + d] = (R)delta;
+            fgg_factors(delta, 1.0, beta, P, rec + kRecHead + d * P);   // straight into the LDS record
         } else {
             const double a = sa[s];
             const double a2 = a * a;
             const double* xs = sx + 12 * (size_t)s;
-            rec[3] = (R)(0.8 * a2 * alpha * alpha * alpha);
+            rec[3] = (R)(0.8 * a2);
             rec[7] = (R)a2;
-            rec[21] = (R)(1.0 - a2 * alpha);
-            rec[22] = (R)(2.0 / 3.0 * a2 * alpha * alpha);
-            rec[23] = (R)(2.0 * alpha - 2.0 * a2 * alpha * alpha);
+            rec[21] = (R)(1.0 - a2 * bq / 3.0);
+            rec[22] = (R)(2.0 / 3.0 * a2);
+            rec[23] = (R)(2.0 - 0.4 * a2 * bq - 0.8 * a2 * bz);
             for (int d = 0; d < 3; ++d) {
                 rec[8 + d] = (R)xs[d];
                 rec[11 + d] = (R)xs[3 + d];
@@ -961,23 +975,27 @@ __device__ inline void neumaier(R& acc, R& cmp, R v) {
 
 // wavefronts per workgroup of an 8^3 tile (each lane owns 8 / kSpreadWaves points)
 constexpr int kSpreadWaves = 4;
+constexpr int kTile = 8;   // spreading tile = bin edge in grid points
 
-template <int TILE>
-constexpr int spread_threads() { return TILE == 8 ? 64 * kSpreadWaves : 64; }
+// gradient-vector coefficients of the window on the fractional grid (WinGeom)
+struct SpreadGeom {
+    double Gxx, Gyx, Gyy, Gzz;   // g = (Gxx u_x, Gyx u_x + Gyy u_y, Gzz u_z)
+    double Qxx, Qxy, Qyy;        // x-y part of the sheared-cell stresslet term
+    double cw;                   // window weight (spreading C, gather C V / M^3)
+};
 
-template <typename R, int TILE>
-__global__ __launch_bounds__(spread_threads<TILE>()) void k_spread(
-    int n, const R* __restrict__ recs, const int* __restrict__ start, int nb, int M, int P, double h,
-    double alpha, double cw, R4<R>* __restrict__ grid) {
-    constexpr int NT = spread_threads<TILE>();  // threads per workgroup
-    constexpr int NW = NT / 64;                 // wavefronts
-    constexpr int NPT = 8 / (TILE == 8 ? NW : 8);   // points per lane
-    static_assert(TILE == 4 || NW == 4, "a lane's points must share x and y");
-    constexpr int MAXB = 729;                  // (2 reach + 1)^3 for reach <= 4
-    // a 64-lane workgroup stages fewer records, keeping LDS per workgroup
-    // small enough for several workgroups per CU
-    constexpr int STAGE = TILE == 8 ? kStage : kStage / 2;
-    constexpr int MAXC = TILE == 8 ? kMaxCand : kMaxCand / 2;
+template <typename R, bool SHEAR>
+__global__ __launch_bounds__(64 * kSpreadWaves) void k_spread(
+    int n, const R* __restrict__ recs, const int* __restrict__ start, int nb, int M, int P, SpreadGeom sg,
+    R4<R>* __restrict__ grid) {
+    constexpr int TILE = kTile;
+    constexpr int NT = 64 * kSpreadWaves;   // threads per workgroup
+    constexpr int NW = kSpreadWaves;        // wavefronts
+    constexpr int NPT = 8 / NW;             // points per lane
+    static_assert(NW == 4, "a lane's points must share x and y");
+    constexpr int MAXB = 125;               // (2 reach + 1)^3 for reach <= 2 (P <= 32)
+    constexpr int STAGE = kStage;
+    constexpr int MAXC = kMaxCand;
     __shared__ __attribute__((aligned(16))) R st[STAGE * (kRecHead + 3 * kMaxP)];
     __shared__ int cand[MAXC];
     __shared__ int bins[MAXB], pre[MAXB + 1];
@@ -989,19 +1007,21 @@ __global__ __launch_bounds__(spread_threads<TILE>()) void k_spread(
     const unsigned tcode = (unsigned)xcd_block(blockIdx.x, ntiles);
     const int tx = (int)compact_bits3(tcode), ty = (int)compact_bits3(tcode >> 1), tz = (int)compact_bits3(tcode >> 2);
     // 4^3 sub-blocks: sub-block b at offset (b&1, (b>>1)&1, b>>2) * 4; wavefront
-    // w owns sub-blocks w, w + NW, ... of an 8^3 tile (the single one of a 4^3 tile)
+    // w owns sub-blocks w and w + 4
     const int ox = lane & 3, oy = (lane >> 2) & 3, oz = lane >> 4;
     int gx[NPT], gy[NPT], gz[NPT];
     for (int p = 0; p < NPT; ++p) {
         const int b = wv + NW * p;
-        gx[p] = tx * TILE + (b & 1) * 4 * (TILE / 8) + ox;
-        gy[p] = ty * TILE + ((b >> 1) & 1) * 4 * (TILE / 8) + oy;
-        gz[p] = tz * TILE + (b >> 2) * 4 * (TILE / 8) + oz;
+        gx[p] = tx * TILE + (b & 1) * 4 + ox;
+        gy[p] = ty * TILE + ((b >> 1) & 1) * 4 + oy;
+        gz[p] = tz * TILE + (b >> 2) * 4 + oz;
     }
     const int mask = M - 1;
     const int RS = rec_stride(P);
 
-    const int reach = (P / 2 + TILE - 1) / TILE;
+    // a window reaches ceil(P/2) points above and ceil(P/2) - 1 below the
+    // grid point at or below its centre
+    const int reach = ((P + 1) / 2 + TILE - 1) / TILE;
     const int span = min(2 * reach + 1, nb);
     // neighbour bins and their sizes in parallel, then one running sum in LDS
     const int nused = span * span * span;
@@ -1026,8 +1046,8 @@ __global__ __launch_bounds__(spread_threads<TILE>()) void k_spread(
     }
     __syncthreads();
     const int ncand = pre[nbins_used];
-    const R al = (R)alpha;
-    const R hh = (R)h, cwr = (R)cw;
+    const R Gxx = (R)sg.Gxx, Gyx = (R)sg.Gyx, Gyy = (R)sg.Gyy, Gzz = (R)sg.Gzz, cwr = (R)sg.cw;
+    const R Qxx = (R)sg.Qxx, Qxy = (R)sg.Qxy, Qyy = (R)sg.Qyy;
     // FP32: plain sums per stage (part) added to acc with Neumaier
     // compensation (cmp); FP64 accumulates straight into part
     R acc[NPT][4], cmp[NPT][4], part[NPT][4];
@@ -1079,27 +1099,40 @@ __global__ __launch_bounds__(spread_threads<TILE>()) void k_spread(
                 const R S0 = rc[14], S1 = rc[15], S2 = rc[16], S3 = rc[17], S4 = rc[18], S5 = rc[19];
                 const R sq = rc[20], c0 = rc[21], c1 = rc[22], e0 = rc[23], d1 = rc[3];
                 const R* fa = rc + kRecHead;
-                const R rx = rc[4] + kx * hh, ry = rc[5] + ky * hh;
+                const R ux = rc[4] + (R)kx, uy = rc[5] + (R)ky;
+                const R gX = Gxx * ux, gY = Gyx * ux + Gyy * uy;
                 const R wxy = cwr * fa[kx] * fa[P + ky];
-                const R rxy2 = rx * rx + ry * ry;
-                const R Sx = S0 * rx + S3 * ry, Sy = S3 * rx + S1 * ry, Sz = S4 * rx + S5 * ry;
-                const R tz = rx * T1 - ry * T0;
+                const R gxy2 = gX * gX + gY * gY;
+                const R Sx = S0 * gX + S3 * gY, Sy = S3 * gX + S1 * gY, Sz = S4 * gX + S5 * gY;
+                const R tz = gX * T1 - gY * T0;
+                const R gz0 = Gzz * rc[6];
+                R Ex = R(0), Ey = R(0), Ez = R(0);
+                if constexpr (SHEAR) {   // S . (-(4/5) a^2 Qt g_xy)
+                    const R ex = -d1 * (Qxx * gX + Qxy * gY), ey = -d1 * (Qxy * gX + Qyy * gY);
+                    Ex = S0 * ex + S3 * ey;
+                    Ey = S3 * ex + S1 * ey;
+                    Ez = S4 * ex + S5 * ey;
+                }
 #pragma unroll
                 for (int p = 0; p < NPT; ++p) {
                     if (!in[p]) continue;
-                    const R rz = rc[6] + kz[p] * hh;
-                    const R r2 = rxy2 + rz * rz;
+                    const R gZ = gz0 + (R)kz[p] * Gzz;
+                    const R g2 = gxy2 + gZ * gZ;
                     const R w = wxy * fa[2 * P + kz[p]];
-                    const R cF = w * (c0 + c1 * r2);
-                    const R cS = w * (e0 + d1 * r2);
-                    const R cT = -al * w;
-                    const R Srx = Sx + S4 * rz;
-                    const R Sry = Sy + S5 * rz;
-                    const R Srz = Sz + S2 * rz;
-                    part[p][0] += cF * F0 + cT * (ry * T2 - rz * T1) + cS * Srx;
-                    part[p][1] += cF * F1 + cT * (rz * T0 - rx * T2) + cS * Sry;
-                    part[p][2] += cF * F2 + cT * tz + cS * Srz;
+                    const R cF = w * (c0 + c1 * g2);
+                    const R cS = w * (e0 + d1 * g2);
+                    const R Srx = Sx + S4 * gZ;
+                    const R Sry = Sy + S5 * gZ;
+                    const R Srz = Sz + S2 * gZ;
+                    part[p][0] += cF * F0 - w * (gY * T2 - gZ * T1) + cS * Srx;
+                    part[p][1] += cF * F1 - w * (gZ * T0 - gX * T2) + cS * Sry;
+                    part[p][2] += cF * F2 - w * tz + cS * Srz;
                     part[p][3] += w * sq;
+                    if constexpr (SHEAR) {
+                        part[p][0] += w * Ex;
+                        part[p][1] += w * Ey;
+                        part[p][2] += w * Ez;
+                    }
                 }
             }
             if constexpr (sizeof(R) == 4)
@@ -1191,16 +1224,6 @@ __device__ inline void load_twiddles(C1<R>* tw, const double* __restrict__ twg, 
     }
 }
 
-// Arithmetic type of the FFT passes: the grid and spectrum are stored in R,
-// the butterflies run in FftT<R> (FP64 also for an FP32 grid when
-// kFftCompute64, which removes the transforms' rounding from the FP32 error
-// budget at twice the LDS per line).
-constexpr bool kFftCompute64 = false;
-template <typename R>
-struct FftT {
-    using type = typename std::conditional<kFftCompute64, double, R>::type;
-};
-
 template <typename T, typename R>
 __device__ inline C1<T> up(C1<R> a) { return C1<T>{(T)a.re, (T)a.im}; }
 
@@ -1209,7 +1232,7 @@ __device__ inline C1<T> up(C1<R> a) { return C1<T>{(T)a.re, (T)a.im}; }
 template <typename R, int M, int LPB>
 __global__ __launch_bounds__(256) void k_fft_x_fwd(const R4<R>* __restrict__ in, C1<R>* __restrict__ out,
                                                    const double* __restrict__ twg) {
-    using T = typename FftT<R>::type;
+    using T = R;
     __shared__ C1<T> buf[2][2 * LPB * M];
     __shared__ C1<T> tw[M];
     load_twiddles<T, M>(tw, twg, +1);
@@ -1242,7 +1265,7 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd(const R4<R>* __restrict__ in,
 template <typename R, int M, int LPB>
 __global__ __launch_bounds__(256) void k_fft_x_inv(const C1<R>* __restrict__ in, R4<R>* __restrict__ out,
                                                    const double* __restrict__ twg) {
-    using T = typename FftT<R>::type;
+    using T = R;
     __shared__ C1<T> buf[2][2 * LPB * M];
     __shared__ C1<T> tw[M];
     load_twiddles<T, M>(tw, twg, -1);
@@ -1280,7 +1303,7 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(const C1<R>* __restrict__ in,
 template <typename R, int M, int W>
 __global__ __launch_bounds__(256) void k_fft_y(C1<R>* __restrict__ data, const double* __restrict__ twg,
                                                int sgn) {
-    using T = typename FftT<R>::type;
+    using T = R;
     __shared__ C1<T> buf[2][4 * W * M];
     __shared__ C1<T> tw[M];
     load_twiddles<T, M>(tw, twg, sgn);
@@ -1464,13 +1487,28 @@ __global__ __launch_bounds__(256) void k_fft_x_inv256(const C1<R>* __restrict__ 
     }
 }
 
+// k-space multiply (eq. wave-result): k = B q with B = 2 pi A^-T (for the
+// supported cells kx = bxx qx, ky = byx qx + byy qy, kz = bzz qz), the
+// deconvolution of the two windows exp(kdeconv |q|^2) with q the integer
+// wave vector (the fractional-grid Gaussian of eq. shape), the screened
+// Stokes and Laplace kernels and the grid normalisation.
 struct KScale {
-    double twopi_over_L;   // k = (2 pi / L) q
+    double bxx, byx, byy, bzz;
     double inv4xi2;        // 1 / (4 xi^2)
-    double two_tau;        // deconvolution exp(2 tau k^2)
+    double kdeconv;        // 2 pi^2 / (beta M^2)
     double norm;           // 1/M^3 : grid-sum normalisation of forward x inverse
     double inv_eta;
 };
+
+__device__ inline double kscale_factor(const KScale& ks, int qx, int qy, int qz, double& kx, double& ky,
+                                       double& kz, double& k2) {
+    kx = ks.bxx * qx;
+    ky = ks.byx * qx + ks.byy * qy;
+    kz = ks.bzz * qz;
+    k2 = kx * kx + ky * ky + kz * kz;
+    const double q2 = (double)qx * qx + (double)qy * qy + (double)qz * qz;
+    return exp(ks.kdeconv * q2 - k2 * ks.inv4xi2) * ks.norm / k2;
+}
 
 // z pass: forward z transform, k-space multiply (eq. wave-result with the
 // periodic Stokes propagator, the source flow and the pressure), inverse z
@@ -1478,7 +1516,7 @@ struct KScale {
 template <typename R, int M, int W>
 __global__ __launch_bounds__(256) void k_fft_z_scale(C1<R>* __restrict__ data,
                                                      const double* __restrict__ twg, KScale ks) {
-    using T = typename FftT<R>::type;
+    using T = R;
     __shared__ C1<T> buf[2][4 * W * M];
     __shared__ C1<T> twf[M], twi[M];
     load_twiddles<T, M>(twf, twg, +1);
@@ -1508,9 +1546,8 @@ __global__ __launch_bounds__(256) void k_fft_z_scale(C1<R>* __restrict__ data,
             *f0 = *f1 = *f2 = *f3 = {T(0), T(0)};
             continue;
         }
-        const double kx = ks.twopi_over_L * qx, ky = ks.twopi_over_L * qy, kz = ks.twopi_over_L * qz;
-        const double k2 = kx * kx + ky * ky + kz * kz;
-        const double ex = exp(k2 * (ks.two_tau - ks.inv4xi2)) * ks.norm / k2;
+        double kx, ky, kz, k2;
+        const double ex = kscale_factor(ks, qx, qy, qz, kx, ky, kz, k2);
         const T st = (T)(ks.inv_eta * (1.0 + k2 * ks.inv4xi2) * ex);   // Stokes, incl. 1/k^2
         const T lp = (T)ex;                                              // Laplace 1/k^2
         const T rkx = (T)kx, rky = (T)ky, rkz = (T)kz, ik2 = (T)(1.0 / k2);
@@ -1577,9 +1614,8 @@ __global__ __launch_bounds__(256) void k_fft_z256(C1<R>* __restrict__ data, cons
             *f0 = *f1 = *f2 = *f3 = {R(0), R(0)};
             continue;
         }
-        const double kx = ks.twopi_over_L * qx, ky = ks.twopi_over_L * qy, kz = ks.twopi_over_L * qz;
-        const double k2 = kx * kx + ky * ky + kz * kz;
-        const double ex = exp(k2 * (ks.two_tau - ks.inv4xi2)) * ks.norm / k2;
+        double kx, ky, kz, k2;
+        const double ex = kscale_factor(ks, qx, qy, qz, kx, ky, kz, k2);
         const R st = (R)(ks.inv_eta * (1.0 + k2 * ks.inv4xi2) * ex);
         const R lp = (R)ex;
         const R rkx = (R)kx, rky = (R)ky, rkz = (R)kz, ik2 = (R)(1.0 / k2);
@@ -1612,20 +1648,17 @@ __global__ __launch_bounds__(256) void k_fft_z256(C1<R>* __restrict__ data, cons
 // time, and the 13 sums are reduced over log2(G) butterfly levels. Measured at
 // N = 1e5, 256^3: 504 / 579 / 740 us for G = 64 / 32 / 16 (the shorter
 // butterfly does not pay for the longer load chain of each lane).
-#ifndef SEASD_GATHER_LANES
-#define SEASD_GATHER_LANES 64
-#endif
-constexpr int kGatherLanes = SEASD_GATHER_LANES;
+constexpr int kGatherLanes = 64;
 
-template <typename R, int G>
+template <typename R, int G, bool SHEAR>
 __global__ __launch_bounds__(256) void k_gather(
-    int n, const R* __restrict__ recs, const int* __restrict__ perm, const R4<R>* __restrict__ grid, int M, int P, double h,
-    double alpha, double cwh3, double inv_eta, int parts, int compressible,
+    int n, const R* __restrict__ recs, const int* __restrict__ perm, const R4<R>* __restrict__ grid, int M, int P,
+    SpreadGeom sg, double inv_eta, int parts, int compressible,
     const double* __restrict__ ybuf, double* __restrict__ yout) {
     static_assert(G == 16 || G == 32 || G == 64, "lanes per sphere");
     constexpr int SPB = 4 * (64 / G);   // spheres per workgroup
     __shared__ R fac[SPB][2 * kMaxP];
-    __shared__ R zt[SPB][4][kMaxP];   // f_z(kz) r_z(kz)^k, k = 0..3
+    __shared__ R zt[SPB][4][kMaxP + 1];   // f_z(kz) u_z(kz)^k, k = 0..3 (zero past P)
     const int lane = threadIdx.x & (G - 1), sb = threadIdx.x / G;
     const int nblk = (n + SPB - 1) / SPB;
     const int s0 = xcd_block(blockIdx.x, nblk) * SPB + sb;
@@ -1633,43 +1666,46 @@ __global__ __launch_bounds__(256) void k_gather(
     const int s = active ? s0 : n - 1;
     const int mask = M - 1;
     const R* rc = recs + (size_t)rec_stride(P) * s;
+    const int Pe = (P + 1) & ~1;      // z loop runs in pairs of points
     for (int k = lane; k < 2 * P; k += G) fac[sb][k] = rc[kRecHead + k];
-    for (int kz = lane; kz < P; kz += G) {
-        const R rz = rc[6] + kz * (R)h, fz = rc[kRecHead + 2 * P + kz];
+    for (int kz = lane; kz < Pe; kz += G) {
+        const R uz = rc[6] + (R)kz, fz = kz < P ? rc[kRecHead + 2 * P + kz] : R(0);
         zt[sb][0][kz] = fz;
-        zt[sb][1][kz] = fz * rz;
-        zt[sb][2][kz] = fz * rz * rz;
-        zt[sb][3][kz] = fz * rz * rz * rz;
+        zt[sb][1][kz] = fz * uz;
+        zt[sb][2][kz] = fz * uz * uz;
+        zt[sb][3][kz] = fz * uz * uz * uz;
     }
     __syncthreads();
     if (!active) return;
     const int4 i0 = make_int4(rec_i0(rc, 0), rec_i0(rc, 1), rec_i0(rc, 2), 0);
     const R d0x = rc[4], d0y = rc[5];
     const R c0 = rc[21], c1 = rc[22], e0 = rc[23], d1 = rc[3];
+    const R Gxx = (R)sg.Gxx, Gyx = (R)sg.Gyx, Gyy = (R)sg.Gyy, Gzz = (R)sg.Gzz, Gzz2 = Gzz * Gzz;
     double acc[13];
     for (int c = 0; c < 13; ++c) acc[c] = 0.0;
     if (parts & kPartsWave) {
-        const R al = (R)alpha, hh = (R)h;
         R ac[13], cp[13];
         for (int c = 0; c < 13; ++c) ac[c] = cp[c] = R(0);
         const int P2 = P * P;
         // The window factorises into f_x f_y f_z and the Faxen polynomials
-        // are cubic in r_z, so each (x, y) column is reduced over z to the
-        // moments M_k[c] = sum_z f_z r_z^k g_c (k <= 3) first; the 13 outputs
+        // are cubic in u_z, so each (x, y) column is reduced over z to the
+        // moments M_k[c] = sum_z f_z u_z^k g_c (k <= 3) first; the 13 outputs
         // follow from them per column.
         for (int e = lane; e < P2; e += G) {
             const int kx = e % P, ky = e / P;
-            const R rx = d0x + kx * hh, ry = d0y + ky * hh;
-            const R wxy = (R)cwh3 * fac[sb][kx] * fac[sb][P + ky];
-            const R rxy2 = rx * rx + ry * ry;
+            const R ux = d0x + (R)kx, uy = d0y + (R)ky;
+            const R gX = Gxx * ux, gY = Gyx * ux + Gyy * uy;
+            const R wxy = (R)sg.cw * fac[sb][kx] * fac[sb][P + ky];
+            const R gxy2 = gX * gX + gY * gY;
             const int gx = (i0.x + kx) & mask, gy = (i0.y + ky) & mask;
             R m0x = 0, m0y = 0, m0z = 0, m0w = 0, m1x = 0, m1y = 0, m1z = 0;
             R m2x = 0, m2y = 0, m2z = 0, m3x = 0, m3y = 0, m3z = 0;
             const R4<R>* colp = grid + (size_t)gy * M + gx;
             const size_t zs = (size_t)M * M;
-            // P is even: two grid loads in flight per step, several steps unrolled
+            // two grid loads in flight per step, several steps unrolled (a
+            // point past an odd P has zero weight)
 #pragma unroll 4
-            for (int kz2 = 0; kz2 < P; kz2 += 2) {
+            for (int kz2 = 0; kz2 < Pe; kz2 += 2) {
               const R4<R> gpair[2] = {colp[(size_t)((i0.z + kz2) & mask) * zs],
                                       colp[(size_t)((i0.z + kz2 + 1) & mask) * zs]};
               for (int hz = 0; hz < 2; ++hz) {
@@ -1691,32 +1727,38 @@ __global__ __launch_bounds__(256) void k_gather(
                 m3z += t3 * g.z;
               }
             }
-            // with w = wxy f_z and r^2 = rxy2 + r_z^2:
-            //   sum w (c0 + c1 r^2) g = wxy (c0 M0 + c1 (rxy2 M0 + M2)),
-            //   Q = sum (w/wxy)(e0 + d1 r^2) g, R = the same with one more r_z
-            const R ux = c0 * m0x + c1 * (rxy2 * m0x + m2x);
-            const R uy = c0 * m0y + c1 * (rxy2 * m0y + m2y);
-            const R uz = c0 * m0z + c1 * (rxy2 * m0z + m2z);
-            const R qx = e0 * m0x + d1 * (rxy2 * m0x + m2x);
-            const R qy = e0 * m0y + d1 * (rxy2 * m0y + m2y);
-            const R qz = e0 * m0z + d1 * (rxy2 * m0z + m2z);
-            const R sx = e0 * m1x + d1 * (rxy2 * m1x + m3x);
-            const R sy = e0 * m1y + d1 * (rxy2 * m1y + m3y);
-            const R sz = e0 * m1z + d1 * (rxy2 * m1z + m3z);
-            const R aw = al * wxy, hw = R(0.5) * wxy;
+            // with w = wxy f_z, g_z = Gzz u_z and |g|^2 = gxy2 + Gzz^2 u_z^2:
+            //   U = sum w (c0 + c1 |g|^2) v = wxy ((c0 + c1 gxy2) M0 + c1 Gzz^2 M2),
+            //   q = sum (w/wxy)(e0 + d1 |g|^2) v, s = the same with one more u_z
+            const R cu = c0 + c1 * gxy2, cq = e0 + d1 * gxy2;
+            const R ux_ = cu * m0x + c1 * Gzz2 * m2x;
+            const R uy_ = cu * m0y + c1 * Gzz2 * m2y;
+            const R uz_ = cu * m0z + c1 * Gzz2 * m2z;
+            const R qx = cq * m0x + d1 * Gzz2 * m2x;
+            const R qy = cq * m0y + d1 * Gzz2 * m2y;
+            const R qz = cq * m0z + d1 * Gzz2 * m2z;
+            const R sx = Gzz * (cq * m1x + d1 * Gzz2 * m3x);
+            const R sy = Gzz * (cq * m1y + d1 * Gzz2 * m3y);
+            const R sz = Gzz * (cq * m1z + d1 * Gzz2 * m3z);
+            R exx = R(0), exy = R(0);
+            if constexpr (SHEAR) {   // -(4/5) a^2 Qt g_xy
+                exx = -d1 * ((R)sg.Qxx * gX + (R)sg.Qxy * gY);
+                exy = -d1 * ((R)sg.Qxy * gX + (R)sg.Qyy * gY);
+            }
+            const R hw = R(0.5) * wxy;
             R col[13];
-            col[0] = wxy * ux;
-            col[1] = wxy * uy;
-            col[2] = wxy * uz;
-            col[3] = aw * (ry * m0z - m1y);
-            col[4] = aw * (m1x - rx * m0z);
-            col[5] = aw * (rx * m0y - ry * m0x);
-            col[6] = wxy * rx * qx;
-            col[7] = wxy * ry * qy;
+            col[0] = wxy * ux_;
+            col[1] = wxy * uy_;
+            col[2] = wxy * uz_;
+            col[3] = wxy * (gY * m0z - Gzz * m1y);
+            col[4] = wxy * (Gzz * m1x - gX * m0z);
+            col[5] = wxy * (gX * m0y - gY * m0x);
+            col[6] = wxy * (gX * qx + exx * m0x);
+            col[7] = wxy * (gY * qy + exy * m0y);
             col[8] = wxy * sz;
-            col[9] = hw * (ry * qx + rx * qy);
-            col[10] = hw * (sx + rx * qz);
-            col[11] = hw * (sy + ry * qz);
+            col[9] = hw * (gY * qx + gX * qy + exy * m0x + exx * m0y);
+            col[10] = hw * (sx + gX * qz + exx * m0z);
+            col[11] = hw * (sy + gY * qz + exy * m0z);
             col[12] = wxy * m0w;
             for (int c = 0; c < 13; ++c) {
                 if constexpr (sizeof(R) == 4) neumaier(ac[c], cp[c], col[c]);
@@ -1752,13 +1794,13 @@ static int launch_fft_chain_M(int M, void* rgrid, void* spec, const double* tw, 
     case MM: {                                                                                            \
         const int lines = MM * MM;                                                                        \
         tm->begin(kPhaseFftXFwd, st);                                                                     \
-        if (MM == 256 && !dbl && !kFftCompute64)                                                          \
+        if (MM == 256 && !dbl)                                                          \
             hipLaunchKernelGGL((k_fft_x_fwd256<R>), dim3(lines / 8), dim3(256), 0, st,                    \
                                (const R4<R>*)rgrid, (C1<R>*)spec, tw);                                    \
         else                                                                                              \
             hipLaunchKernelGGL((k_fft_x_fwd<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,            \
                                (const R4<R>*)rgrid, (C1<R>*)spec, tw);                                    \
-        if (MM == 256 && !dbl && !kFftCompute64) {                                                        \
+        if (MM == 256 && !dbl) {                                                        \
             tm->begin(kPhaseFftYFwd, st);                                                                 \
             hipLaunchKernelGGL((k_fft_y256<R>), dim3(32 * 256), dim3(256), 0, st, (C1<R>*)spec, tw, +1);  \
             tm->begin(kPhaseFftZ, st);                                                                    \
@@ -1777,7 +1819,7 @@ static int launch_fft_chain_M(int M, void* rgrid, void* spec, const double* tw, 
                                (C1<R>*)spec, tw, -1);                                                     \
         }                                                                                                 \
         tm->begin(kPhaseFftXInv, st);                                                                     \
-        if (MM == 256 && !dbl && !kFftCompute64)                                                          \
+        if (MM == 256 && !dbl)                                                          \
             hipLaunchKernelGGL((k_fft_x_inv256<R>), dim3(lines / 8), dim3(256), 0, st,                    \
                                (const C1<R>*)spec, (R4<R>*)rgrid, tw);                                    \
         else                                                                                              \
@@ -1803,6 +1845,18 @@ static int launch_fft_chain_M(int M, void* rgrid, void* spec, const double* tw, 
     return 0;
 }
 
+static NbrGeom nbr_geom(const ApplyArgs& A) {
+    NbrGeom g;
+    g.cell = A.cell;
+    for (int d = 0; d < 3; ++d) g.rpl[d] = A.reach_per_len[d];
+    return g;
+}
+
+static SpreadGeom spread_geom(const ApplyArgs& A, bool gather) {
+    const WinGeom& w = A.win;
+    return SpreadGeom{w.Gxx, w.Gyx, w.Gyy, w.Gzz, w.Qxx, w.Qxy, w.Qyy, gather ? w.cwv : w.cw};
+}
+
 // binning: bins, their scan, binned copies of centres, radii and moments
 int launch_geometry(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     const int n = (int)A.n;
@@ -1812,13 +1866,13 @@ int launch_geometry(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     tm->begin(kPhaseBin, st);
     hipLaunchKernelGGL(k_zero_geometry, dim3((nbins + T - 1) / T), dim3(T), 0, st, nbins, A.counts, A.fill,
                        A.amax_bits, A.nstats);
-    hipLaunchKernelGGL(k_bin_count, dim3(gb), dim3(T), 0, st, n, A.pos, A.radius, A.L, A.nb, A.binw,
+    hipLaunchKernelGGL(k_bin_count, dim3(gb), dim3(T), 0, st, n, A.pos, A.radius, A.cell, A.nb,
                        A.bin_of, A.counts, A.amax_bits, A.err);
     launch_scan(nbins, A.counts, A.start, A.scan_tmp, st);
     hipLaunchKernelGGL(k_bin_scatter, dim3(gb), dim3(T), 0, st, n, A.bin_of, A.start, A.fill, A.perm);
     hipLaunchKernelGGL(k_bin_order, dim3((nbins + T - 1) / T), dim3(T), 0, st, nbins, A.start, A.perm);
-    hipLaunchKernelGGL(k_bin_gather, dim3(gb), dim3(T), 0, st, n, A.perm, A.pos, A.radius, A.x, A.L,
-                       A.compressible, A.sp, A.sa, A.sx, A.err);
+    hipLaunchKernelGGL(k_bin_gather, dim3(gb), dim3(T), 0, st, n, A.perm, A.pos, A.radius, A.x, A.cell,
+                       A.compressible, A.sp, A.st, A.sa, A.sx, A.err);
     if (!(A.parts & kPartsReal)) hipMemsetAsync(A.ncount, 0, sizeof(int) * n, st);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
@@ -1829,22 +1883,13 @@ int launch_geometry(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
 int launch_pairlist(const ApplyArgs& A, hipStream_t st) {
     const int n = (int)A.n;
     if (!(A.parts & kPartsReal)) return 0;
+    const NbrGeom g = nbr_geom(A);
     if (n < kWaveSpheres)
-        hipLaunchKernelGGL((k_pair_fill_group<64>), dim3((n + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa, A.start,
-                           A.nb, A.L, A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount,
-                           A.list, A.err);
-    else if (kFillByBin)
-        hipLaunchKernelGGL(k_pair_fill_bin, dim3((A.nb * A.nb * A.nb + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa,
-                           A.start, A.nb, A.L, A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount,
-                           A.list, A.err);
-    else if (kGroupLarge > 1)
-        hipLaunchKernelGGL((k_pair_fill_group<kGroupLarge>), dim3((n + 256 / kGroupLarge - 1) / (256 / kGroupLarge)),
-                           dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb, A.L, A.binw, A.rc_factor, A.amax_bits,
-                           A.checks, A.cap, A.ncount, A.list, A.err);
+        hipLaunchKernelGGL((k_pair_fill_group<64>), dim3((n + 3) / 4), dim3(256), 0, st, n, A.sp, A.st, A.sa, A.start,
+                           A.nb, g, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount, A.list, A.err);
     else
-        hipLaunchKernelGGL(k_pair_fill, dim3((n + 255) / 256), dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb,
-                           A.L, A.binw, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount, A.list,
-                           A.err);
+        hipLaunchKernelGGL(k_pair_fill_bin, dim3((A.nb * A.nb * A.nb + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa,
+                           A.start, A.nb, g, A.rc_factor, A.amax_bits, A.checks, A.cap, A.ncount, A.list, A.err);
     hipLaunchKernelGGL(k_count_stats, dim3(std::min(kStatsBlocks, (n + 255) / 256)), dim3(256), 0, st, n, A.ncount,
                        A.nstats);
     return hipGetLastError() == hipSuccess ? 0 : -2;
@@ -1852,8 +1897,8 @@ int launch_pairlist(const ApplyArgs& A, hipStream_t st) {
 
 int launch_edge_count(const ApplyArgs& A, double cut, int* deg, int* rowptr, hipStream_t st) {
     const int n = (int)A.n;
-    hipLaunchKernelGGL(k_edge_count, dim3((n + 255) / 256), dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb, A.L,
-                       A.binw, cut, A.amax_bits, deg, A.err);
+    hipLaunchKernelGGL(k_edge_count, dim3((n + 255) / 256), dim3(256), 0, st, n, A.sp, A.st, A.sa, A.start, A.nb,
+                       nbr_geom(A), cut, A.amax_bits, deg, A.err);
     launch_scan(n, deg, rowptr, A.scan_tmp, st);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
@@ -1861,8 +1906,8 @@ int launch_edge_count(const ApplyArgs& A, double cut, int* deg, int* rowptr, hip
 int launch_edge_fill(const ApplyArgs& A, double cut, const int* rowptr, int* esrc, int* edst, int* erev,
                      float4* geo, float* fe, float* fn, hipStream_t st) {
     const int n = (int)A.n;
-    hipLaunchKernelGGL(k_edge_fill, dim3((n + 255) / 256), dim3(256), 0, st, n, A.sp, A.sa, A.start, A.nb, A.L,
-                       A.binw, cut, A.amax_bits, rowptr, esrc, edst, geo, fe, A.err);
+    hipLaunchKernelGGL(k_edge_fill, dim3((n + 255) / 256), dim3(256), 0, st, n, A.sp, A.st, A.sa, A.start, A.nb,
+                       nbr_geom(A), cut, A.amax_bits, rowptr, esrc, edst, geo, fe, A.err);
     hipLaunchKernelGGL(k_edge_rev, dim3((n + 255) / 256), dim3(256), 0, st, n, A.sa, rowptr, edst, geo, erev, fn,
                        A.err);
     return hipGetLastError() == hipSuccess ? 0 : -2;
@@ -1872,51 +1917,49 @@ int launch_edge_fill(const ApplyArgs& A, double cut, const int* rowptr, int* esr
 int launch_moments(const ApplyArgs& A, hipStream_t st) {
     const int n = (int)A.n;
     hipLaunchKernelGGL(k_bin_gather, dim3((n + 255) / 256), dim3(256), 0, st, n, A.perm, A.pos, A.radius, A.x,
-                       A.L, A.compressible, A.sp, A.sa, A.sx, A.err);
+                       A.cell, A.compressible, A.sp, A.st, A.sa, A.sx, A.err);
     return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+KScale kscale_of(const ApplyArgs& A) {
+    // B = 2 pi A^-T: row i of B is 2 pi times column i of A^-1
+    const double* ai = A.cell.ainv;
+    const double tp = 2.0 * kPi;
+    return KScale{tp * ai[0], tp * ai[1], tp * ai[4], tp * ai[8], 1.0 / (4.0 * A.xi * A.xi), A.kdeconv,
+                  1.0 / ((double)A.M * A.M * A.M), A.inv_eta};
+}
+
+template <typename R>
+static void launch_window_spread(const ApplyArgs& A, bool wave, hipStream_t st, PhaseTimer* tm) {
+    const int n = (int)A.n;
+    const int tiles = A.M / kTile;
+    const int gwin = (n + kWinSpheres - 1) / kWinSpheres;
+    tm->begin(kPhaseWindow, st);
+    hipLaunchKernelGGL((k_window<R>), dim3(gwin), dim3(256), 0, st, n, A.st, A.sa, A.sx, A.P, A.M, A.win.beta,
+                       A.win.bq, A.win.bz, (R*)A.wrec);
+    tm->begin(kPhaseSpread, st);
+    if (!wave) return;
+    const SpreadGeom sg = spread_geom(A, false);
+    if (A.win.sheared)
+        hipLaunchKernelGGL((k_spread<R, true>), dim3(tiles * tiles * tiles), dim3(64 * kSpreadWaves), 0, st, n,
+                           (const R*)A.wrec, A.start, A.nb, A.M, A.P, sg, (R4<R>*)A.rgrid);
+    else
+        hipLaunchKernelGGL((k_spread<R, false>), dim3(tiles * tiles * tiles), dim3(64 * kSpreadWaves), 0, st, n,
+                           (const R*)A.wrec, A.start, A.nb, A.M, A.P, sg, (R4<R>*)A.rgrid);
 }
 
 // Wave-space part up to the inverse FFT (window records, spreading, the FFT
 // chain with the k-space multiply); it reads the binned geometry but not the
 // neighbour list.
 int launch_wave(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
-    const int n = (int)A.n;
     const bool wave = (A.parts & kPartsWave) != 0;
-    const int tiles = A.M / A.tile;
-    KScale ks{2.0 * kPi / A.L, 1.0 / (4.0 * A.xi * A.xi), 2.0 * A.tau,
-              1.0 / ((double)A.M * A.M * A.M), A.inv_eta};
-    const int gwin = (n + kWinSpheres - 1) / kWinSpheres;
-    tm->begin(kPhaseWindow, st);
+    const KScale ks = kscale_of(A);
     if (A.fp32) {
-        hipLaunchKernelGGL((k_window<float>), dim3(gwin), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.P, A.h, A.alpha,
-                           (float*)A.wrec);
-        tm->begin(kPhaseSpread, st);
-        if (wave) {
-            if (A.tile == 8)
-                hipLaunchKernelGGL((k_spread<float, 8>), dim3(tiles * tiles * tiles), dim3(spread_threads<8>()), 0, st, n,
-                                   (const float*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
-                                   (R4<float>*)A.rgrid);
-            else
-                hipLaunchKernelGGL((k_spread<float, 4>), dim3(tiles * tiles * tiles), dim3(64), 0, st, n,
-                                   (const float*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
-                                   (R4<float>*)A.rgrid);
-            if (launch_fft_chain_M<float>(A.M, A.rgrid, A.spec, A.twiddle, ks, st, tm)) return -1;
-        }
+        launch_window_spread<float>(A, wave, st, tm);
+        if (wave && launch_fft_chain_M<float>(A.M, A.rgrid, A.spec, A.twiddle, ks, st, tm)) return -1;
     } else {
-        hipLaunchKernelGGL((k_window<double>), dim3(gwin), dim3(256), 0, st, n, A.sp, A.sa, A.sx, A.P, A.h, A.alpha,
-                           (double*)A.wrec);
-        tm->begin(kPhaseSpread, st);
-        if (wave) {
-            if (A.tile == 8)
-                hipLaunchKernelGGL((k_spread<double, 8>), dim3(tiles * tiles * tiles), dim3(spread_threads<8>()), 0, st, n,
-                                   (const double*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
-                                   (R4<double>*)A.rgrid);
-            else
-                hipLaunchKernelGGL((k_spread<double, 4>), dim3(tiles * tiles * tiles), dim3(64), 0, st, n,
-                                   (const double*)A.wrec, A.start, A.nb, A.M, A.P, A.h, A.alpha, A.cw,
-                                   (R4<double>*)A.rgrid);
-            if (launch_fft_chain_M<double>(A.M, A.rgrid, A.spec, A.twiddle, ks, st, tm)) return -1;
-        }
+        launch_window_spread<double>(A, wave, st, tm);
+        if (wave && launch_fft_chain_M<double>(A.M, A.rgrid, A.spec, A.twiddle, ks, st, tm)) return -1;
     }
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
@@ -1925,39 +1968,36 @@ int launch_wave(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
 int launch_pair(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     const int n = (int)A.n;
     tm->begin(kPhasePair, st);
-    if (n < kWaveSpheres)
-        hipLaunchKernelGGL((k_pair_eval_group<kEvalGroupSmall>),
-                           dim3((n + 256 / kEvalGroupSmall - 1) / (256 / kEvalGroupSmall)), dim3(256), 0, st, n,
-                           A.sp, A.sa, A.sx, A.ncount, A.cap, A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
-    else if (A.pair_group == 64)   // uneven lists (a wide radius distribution): a wavefront per sphere
+    if (n < kWaveSpheres || A.pair_group == 64)   // small suspensions, or uneven lists
         hipLaunchKernelGGL((k_pair_eval_group<64>), dim3((n + 3) / 4), dim3(256), 0, st, n, A.sp, A.sa, A.sx,
-                           A.ncount, A.cap, A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
-    else if (kEvalGroupLarge > 1)
-        hipLaunchKernelGGL((k_pair_eval_group<kEvalGroupLarge>),
-                           dim3((n + 256 / kEvalGroupLarge - 1) / (256 / kEvalGroupLarge)), dim3(256), 0, st, n,
-                           A.sp, A.sa, A.sx, A.ncount, A.cap, A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
+                           A.ncount, A.cap, A.list, A.cell, A.xi, A.inv_eta, A.parts, A.ybuf);
     else
         hipLaunchKernelGGL(k_pair_eval, dim3((n + 127) / 128), dim3(128), 0, st, n, A.sp, A.sa, A.sx, A.ncount,
-                           A.cap, A.list, A.L, A.xi, A.inv_eta, A.parts, A.ybuf);
+                           A.cap, A.list, A.cell, A.xi, A.inv_eta, A.parts, A.ybuf);
     return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template <typename R>
+static void launch_gather_R(const ApplyArgs& A, hipStream_t st) {
+    const int n = (int)A.n;
+    constexpr int spb = 4 * (64 / kGatherLanes);
+    const int gg = (n + spb - 1) / spb;
+    const SpreadGeom sg = spread_geom(A, true);
+    if (A.win.sheared)
+        hipLaunchKernelGGL((k_gather<R, kGatherLanes, true>), dim3(gg), dim3(256), 0, st, n, (const R*)A.wrec, A.perm,
+                           (const R4<R>*)A.rgrid, A.M, A.P, sg, A.inv_eta, A.parts, A.compressible, A.ybuf, A.y);
+    else
+        hipLaunchKernelGGL((k_gather<R, kGatherLanes, false>), dim3(gg), dim3(256), 0, st, n, (const R*)A.wrec,
+                           A.perm, (const R4<R>*)A.rgrid, A.M, A.P, sg, A.inv_eta, A.parts, A.compressible, A.ybuf,
+                           A.y);
 }
 
 // Gather: the wave-space velocities added to the pair sum, scattered back to
 // the caller's order.
 int launch_gather(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
-    const int n = (int)A.n;
-    constexpr int spb = 4 * (64 / kGatherLanes);
-    const int gg = (n + spb - 1) / spb;
-    const double cwh3 = A.cw * A.h * A.h * A.h;
     tm->begin(kPhaseGather, st);
-    if (A.fp32)
-        hipLaunchKernelGGL((k_gather<float, kGatherLanes>), dim3(gg), dim3(256), 0, st, n, (const float*)A.wrec, A.perm,
-                           (const R4<float>*)A.rgrid, A.M, A.P, A.h, A.alpha, cwh3, A.inv_eta, A.parts,
-                           A.compressible, A.ybuf, A.y);
-    else
-        hipLaunchKernelGGL((k_gather<double, kGatherLanes>), dim3(gg), dim3(256), 0, st, n, (const double*)A.wrec, A.perm,
-                           (const R4<double>*)A.rgrid, A.M, A.P, A.h, A.alpha, cwh3, A.inv_eta, A.parts,
-                           A.compressible, A.ybuf, A.y);
+    if (A.fp32) launch_gather_R<float>(A, st);
+    else launch_gather_R<double>(A, st);
     tm->end(st);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }

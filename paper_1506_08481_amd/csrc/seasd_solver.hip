@@ -124,6 +124,21 @@ __global__ void k_trace_op(int64_t n, int mode, const double* __restrict__ radiu
     }
 }
 
+// out_i = alpha I + beta B_i on the 11 incompressible components (identity on
+// the trace row and column): the blocks of the shifted operators of the
+// Brownian initial value problem
+__global__ void k_shift_blocks(int64_t n, const double* __restrict__ B, double alpha, double beta,
+                               double* __restrict__ out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int r = 0; r < 12; ++r)
+        for (int c = 0; c < 12; ++c) {
+            double v = (r < 11 && c < 11) ? beta * B[144 * i + 12 * r + c] : 0.0;
+            if (r == c) v += (r < 11) ? alpha : 1.0;
+            out[144 * i + 12 * r + c] = v;
+        }
+}
+
 // inverse of each 12x12 block by Gauss-Jordan elimination with partial pivoting
 __global__ void k_block_invert(int64_t n, const double* __restrict__ in, double* __restrict__ out,
                                int* __restrict__ singular) {
@@ -205,6 +220,11 @@ int launch_build_blocks(int64_t n, const double* radius, const double* coef, dou
 int launch_trace_op(int64_t n, int mode, const double* radius, double eta, const double* b, const double* in,
                     double* out, hipStream_t st) {
     hipLaunchKernelGGL(k_trace_op, dim3(grid1(n, 256)), dim3(256), 0, st, n, mode, radius, eta, b, in, out);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_shift_blocks(int64_t n, const double* blocks, double alpha, double beta, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_shift_blocks, dim3(grid1(n, 128)), dim3(128), 0, st, n, blocks, alpha, beta, out);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

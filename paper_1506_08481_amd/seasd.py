@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import ctypes
 import math
+import numbers
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,7 +40,7 @@ PHASES = ("bin", "pair", "window", "spread", "fft_x_fwd", "fft_y_fwd", "fft_z_sc
 
 # exported symbols of include/seasd.h
 SYMBOLS = ("seasd_create", "seasd_destroy", "seasd_default_config", "seasd_set_config",
-           "seasd_mobility_apply", "seasd_solve_farfield", "seasd_profile_enable",
+           "seasd_mobility_apply", "seasd_solve_farfield", "seasd_brownian_farfield", "seasd_profile_enable",
            "seasd_profile_read", "seasd_error_string", "seasd_autotune", "seasd_batch_create",
            "seasd_batch_apply", "seasd_batch_configs", "seasd_batch_destroy",
            "seasd_mobility_apply_batched", "seasd_net_create", "seasd_net_destroy", "seasd_net_param_count",
@@ -47,11 +48,14 @@ SYMBOLS = ("seasd_create", "seasd_destroy", "seasd_default_config", "seasd_set_c
            "seasd_net_loss_grad", "seasd_net_train_step", "seasd_precond_attach", "seasd_precond_load")
 
 
+SEASD_SIZE_REAL = 0
+
+
 class seasd_config(ctypes.Structure):
     _fields_ = [
-        ("grid", ctypes.c_int32),
+        ("grid", ctypes.c_int32 * 3),
         ("P", ctypes.c_int32),
-        ("tile", ctypes.c_int32),
+        ("size_approach", ctypes.c_int32),
         ("m", ctypes.c_double),
         ("xi", ctypes.c_double),
         ("rc_factor", ctypes.c_double),
@@ -65,6 +69,24 @@ class seasd_config(ctypes.Structure):
         ("restart", ctypes.c_int32),
         ("precond", ctypes.c_int32),
     ]
+
+    def as_dict(self):
+        out = {k: getattr(self, k) for k, _ in self._fields_}
+        out["grid"] = tuple(self.grid)
+        return out
+
+
+def _set_field(c: seasd_config, k: str, v):
+    """Set one configuration field; grid takes an int (all directions) or 3 ints."""
+    if not hasattr(c, k):
+        raise KeyError(k)
+    if k == "grid":
+        vals = [int(v)] * 3 if isinstance(v, numbers.Integral) else [int(u) for u in v]
+        if len(vals) != 3:
+            raise ValueError("grid needs one or three values")
+        c.grid = (ctypes.c_int32 * 3)(*vals)
+    else:
+        setattr(c, k, v)
 
 
 class seasd_solve_stats(ctypes.Structure):
@@ -80,6 +102,22 @@ class seasd_solve_stats(ctypes.Structure):
         ("guess_used", ctypes.c_int32),
         ("initial_residual", ctypes.c_double),
         ("guess_scale", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class seasd_brownian_stats(ctypes.Structure):
+    _fields_ = [
+        ("steps", ctypes.c_int32),
+        ("solves", ctypes.c_int32),
+        ("iterations", ctypes.c_int32),
+        ("matvecs", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("max_residual", ctypes.c_double),
+        ("scale", ctypes.c_double),
+        ("solve_ms", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -104,10 +142,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.seasd_mobility_apply.argtypes = [vp, i64, dp, dp, ctypes.POINTER(ctypes.c_double), dp, dp, vp]
     lib.seasd_solve_farfield.argtypes = [vp, i64, dp, dp, ctypes.POINTER(ctypes.c_double), dp, dp,
                                          ctypes.POINTER(seasd_solve_stats), vp]
+    lib.seasd_brownian_farfield.argtypes = [vp, i64, dp, dp, ctypes.POINTER(ctypes.c_double), dp, dp,
+                                            ctypes.c_double, ctypes.POINTER(seasd_brownian_stats), vp]
     lib.seasd_profile_enable.argtypes = [vp, i32]
     lib.seasd_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32]
-    lib.seasd_autotune.argtypes = [i64, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, i32,
-                                    ctypes.POINTER(seasd_config)]
+    lib.seasd_autotune.argtypes = [i64, ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, i32, ctypes.POINTER(seasd_config)]
     lib.seasd_batch_create.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), dp, dp, ctypes.POINTER(ctypes.c_double),
                                        ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(vp), vp]
     lib.seasd_batch_apply.argtypes = [vp, dp, dp, vp]
@@ -166,9 +206,7 @@ def default_config(**overrides) -> seasd_config:
     c = seasd_config()
     _check(lib().seasd_default_config(ctypes.byref(c)))
     for k, v in overrides.items():
-        if not hasattr(c, k):
-            raise KeyError(k)
-        setattr(c, k, v)
+        _set_field(c, k, v)
     return c
 
 
@@ -185,12 +223,33 @@ def _stream_ptr(stream) -> int:
     return int(s.cuda_stream)
 
 
-def _require(t, shape_tail, name):
+def _device_of(t):
+    return (t.device.type, t.device.index if t.device.index is not None else 0)
+
+
+def _require(t, shape, name, device=None):
+    """t must be a contiguous float64 tensor on the GPU `device` (an ordinal,
+    or None for any) with the given shape (None entries: any size). Raises
+    before anything reaches the library, so a short or strided buffer never
+    becomes an out-of-bounds device access."""
     import torch
-    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
-        raise TypeError(f"{name} must be a contiguous float64 device tensor")
-    if tuple(t.shape[1:]) != shape_tail:
-        raise ValueError(f"{name} has shape {tuple(t.shape)}")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 GPU tensor")
+    if device is not None and _device_of(t) != ("cuda", int(device)):
+        raise ValueError(f"{name} is on {t.device}, the engine on cuda:{device}")
+    if len(t.shape) != len(shape) or any(s is not None and int(d) != s for d, s in zip(t.shape, shape)):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple('*' if s is None else s for s in shape)}")
+
+
+def _require_sphere_arrays(pos, radius, device):
+    _require(pos, (None, 3), "pos", device)
+    n = int(pos.shape[0])
+    if n < 1:
+        raise ValueError("need at least one sphere")
+    _require(radius, (n,), "radius", device)
+    return n
 
 
 class Seasd:
@@ -208,18 +267,18 @@ class Seasd:
 
     def set_config(self, **overrides):
         for k, v in overrides.items():
-            setattr(self.config, k, v)
+            _set_field(self.config, k, v)
         _check(lib().seasd_set_config(self.h, ctypes.byref(self.config)))
 
     def seasd_mobility_apply(self, pos, radius, box, x, y=None, stream=None):
         import torch
-        _require(pos, (3,), "pos")
-        _require(x, (12,), "x")
-        if radius.dim() != 1 or radius.dtype != torch.float64 or not radius.is_cuda:
-            raise TypeError("radius must be a 1-D float64 device tensor")
-        n = pos.shape[0]
+        n = _require_sphere_arrays(pos, radius, self.device)
+        _require(x, (n, 12), "x", self.device)
         if y is None:
             y = torch.empty((n, 12), dtype=torch.float64, device=pos.device)
+        _require(y, (n, 12), "y", self.device)
+        if y.data_ptr() == x.data_ptr():
+            raise ValueError("y may not alias x")
         _check(lib().seasd_mobility_apply(self.h, n, pos.data_ptr(), radius.data_ptr(), _box9(box),
                                           x.data_ptr(), y.data_ptr(), ctypes.c_void_p(_stream_ptr(stream))))
         return y
@@ -228,9 +287,10 @@ class Seasd:
 
     def seasd_solve_farfield(self, pos, radius, box, b, x0=None, stream=None):
         import torch
-        _require(pos, (3,), "pos")
-        _require(b, (12,), "b")
-        n = pos.shape[0]
+        n = _require_sphere_arrays(pos, radius, self.device)
+        _require(b, (n, 12), "b", self.device)
+        if x0 is not None:
+            _require(x0, (n, 12), "x0", self.device)
         x = torch.zeros_like(b) if x0 is None else x0.clone()
         st = seasd_solve_stats()
         code = lib().seasd_solve_farfield(self.h, n, pos.data_ptr(), radius.data_ptr(), _box9(box),
@@ -242,6 +302,23 @@ class Seasd:
         return x, out
 
     solve = seasd_solve_farfield
+
+    def seasd_brownian_farfield(self, pos, radius, box, psi, dtau: float = 0.1, stream=None):
+        """x = M^(-1/2) psi (incompressible block) by the initial value problem."""
+        import torch
+        n = _require_sphere_arrays(pos, radius, self.device)
+        _require(psi, (n, 12), "psi", self.device)
+        x = torch.empty_like(psi)
+        st = seasd_brownian_stats()
+        code = lib().seasd_brownian_farfield(self.h, n, pos.data_ptr(), radius.data_ptr(), _box9(box),
+                                             psi.data_ptr(), x.data_ptr(), float(dtau), ctypes.byref(st),
+                                             ctypes.c_void_p(_stream_ptr(stream)))
+        _check(code, allow=(SEASD_OK, SEASD_W_NOT_CONVERGED))
+        out = st.as_dict()
+        out["code"] = code
+        return x, out
+
+    brownian = seasd_brownian_farfield
 
     def seasd_precond_attach(self, net):
         """Use `net` for solves with precond=SEASD_PRECOND_LEARNED (None detaches)."""
@@ -317,9 +394,11 @@ class Net:
         gradient (numpy float32) and the guesses."""
         import numpy as np
         import torch
+        n = _require_sphere_arrays(pos, radius, eng.device)
         if b.dim() == 2:
             b = b.unsqueeze(0)
-        nrhs, n = int(b.shape[0]), int(b.shape[1])
+        _require(b, (None, n, 12), "b", eng.device)
+        nrhs = int(b.shape[0])
         x0 = torch.empty_like(b)
         loss = ctypes.c_double(0.0)
         grad = np.zeros(self.count, dtype=np.float32) if want_grad else None
@@ -333,8 +412,10 @@ class Net:
     loss_grad = seasd_net_loss_grad
 
     def seasd_net_train_step(self, eng: "Seasd", pos, radius, box, b, lr: float, stream=None) -> float:
+        n = _require_sphere_arrays(pos, radius, eng.device)
         if b.dim() == 2:
             b = b.unsqueeze(0)
+        _require(b, (None, n, 12), "b", eng.device)
         loss = ctypes.c_double(0.0)
         _check(lib().seasd_net_train_step(eng.h, self.h, int(b.shape[1]), pos.data_ptr(), radius.data_ptr(),
                                           _box9(box), int(b.shape[0]), b.data_ptr(), ctypes.c_float(lr),
@@ -355,10 +436,14 @@ class Net:
             pass
 
 
-def seasd_autotune(n: int, L: float, a_min: float, a_max: float, target: float = 1e-6,
+def seasd_autotune(n: int, box, a_min: float, a_max: float, target: float = 1e-6,
                    precision: int = SEASD_FP32) -> seasd_config:
+    """box: a 3x3 array whose columns are the lattice vectors, 9 numbers, or
+    a cube edge L."""
+    if isinstance(box, (int, float)):
+        box = [float(box), 0, 0, 0, float(box), 0, 0, 0, float(box)]
     c = seasd_config()
-    _check(lib().seasd_autotune(int(n), float(L), float(a_min), float(a_max), float(target), int(precision),
+    _check(lib().seasd_autotune(int(n), _box9(box), float(a_min), float(a_max), float(target), int(precision),
                                 ctypes.byref(c)))
     return c
 
@@ -369,8 +454,15 @@ class Batch:
 
     def __init__(self, eng: "Seasd", offsets, pos, radius, boxes, per_sys=None, target: float = 1e-6,
                  stream=None):
-        _require(pos, (3,), "pos")
         nsys = len(offsets) - 1
+        if nsys < 1 or int(offsets[0]) != 0 or any(int(offsets[k + 1]) <= int(offsets[k]) for k in range(nsys)):
+            raise ValueError("offsets must start at 0 and increase")
+        if len(boxes) != nsys or (per_sys is not None and len(per_sys) != nsys):
+            raise ValueError("need one box (and configuration) per suspension")
+        n = _require_sphere_arrays(pos, radius, eng.device)
+        if n != int(offsets[-1]):
+            raise ValueError(f"pos has {n} rows, offsets end at {int(offsets[-1])}")
+        self.device = eng.device
         off = (ctypes.c_int64 * (nsys + 1))(*[int(v) for v in offsets])
         bx = [float(v) for b in boxes for v in (b.T.reshape(-1) if hasattr(b, "T") else b)]
         boxes9 = (ctypes.c_double * (9 * nsys))(*bx)
@@ -387,9 +479,12 @@ class Batch:
 
     def apply(self, x, y=None, stream=None):
         import torch
-        _require(x, (12,), "x")
+        _require(x, (self.n, 12), "x", self.device)
         if y is None:
             y = torch.empty_like(x)
+        _require(y, (self.n, 12), "y", self.device)
+        if y.data_ptr() == x.data_ptr():
+            raise ValueError("y may not alias x")
         _check(lib().seasd_batch_apply(self.h, x.data_ptr(), y.data_ptr(), ctypes.c_void_p(_stream_ptr(stream))))
         return y
 

@@ -49,7 +49,7 @@ def make_problem(k: int, seed: int):
 
 
 def _cfg_for(seasd, s, precision):
-    return seasd.seasd_autotune(s.n, s.L, float(np.quantile(s.radius, 0.1)), float(s.radius.max()), 1e-6,
+    return seasd.seasd_autotune(s.n, s.box, float(np.quantile(s.radius, 0.1)), float(s.radius.max()), 1e-6,
                                 precision)
 
 
@@ -88,7 +88,7 @@ def train(net, problems: ProblemPool, epochs: int = 12, nrhs: int = 8, lr: float
         nonlocal step
         s, P, R = c
         eng.set_config(**{f: getattr(_cfg_for(seasd, s, seasd.SEASD_FP32), f)
-                          for f in ("grid", "P", "tile", "m", "xi", "rc_factor")},
+                          for f in ("grid", "P", "m", "xi", "rc_factor")},
                        precision=seasd.SEASD_FP32, checks=0)
         b = torch.randn((nrhs, s.n, 12), dtype=torch.float64, device=dev,
                         generator=None)
@@ -146,7 +146,7 @@ def evaluate(net, s, tol: float = 1e-6, precision=None, seed: int = 5, repeats: 
     for name, pc in (("blockdiag", seasd.SEASD_PRECOND_BLOCKDIAG),
                      ("learned_guess", seasd.SEASD_PRECOND_LEARNED_GUESS),
                      ("learned", seasd.SEASD_PRECOND_LEARNED)):
-        eng = seasd.Seasd(0, **{f: getattr(cfg, f) for f in ("grid", "P", "tile", "m", "xi", "rc_factor")},
+        eng = seasd.Seasd(0, **{f: getattr(cfg, f) for f in ("grid", "P", "m", "xi", "rc_factor")},
                           precision=precision, tol=tol, restart=50, max_iter=3000, precond=pc, checks=0)
         if pc != seasd.SEASD_PRECOND_BLOCKDIAG:
             eng.attach(net)
@@ -163,7 +163,7 @@ def evaluate(net, s, tol: float = 1e-6, precision=None, seed: int = 5, repeats: 
     ref = xs["blockdiag"]
     for k in out:
         out[k]["rel_diff_vs_blockdiag"] = float(np.linalg.norm(xs[k] - ref) / np.linalg.norm(ref))
-    out["config"] = {f: getattr(cfg, f) for f in ("grid", "P", "tile", "m", "xi", "rc_factor")}
+    out["config"] = {k: v for k, v in cfg.as_dict().items() if k in ("grid", "P", "m", "xi", "rc_factor")}
     return out
 
 

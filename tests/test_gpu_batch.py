@@ -57,7 +57,7 @@ def test_batch_equals_single_products_and_replays(lib, systems):
     eng = lib.Seasd(0, precision=lib.SEASD_FP32)
     plan = lib.Batch(eng, offs, _t(pos), _t(rad), [s.box for s in sus], target=1e-6)
     cfgs = plan.configs()
-    print("grids", [c.grid for c in cfgs], "P", [c.P for c in cfgs], "xi", [round(c.xi, 3) for c in cfgs])
+    print("grids", [c.grid[0] for c in cfgs], "P", [c.P for c in cfgs], "xi", [round(c.xi, 3) for c in cfgs])
     for rep in range(3):
         x = wl.force_moments(int(offs[-1]), 40 + rep)
         y = plan.apply(_t(x)).cpu().numpy()

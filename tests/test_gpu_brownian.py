@@ -1,0 +1,73 @@
+"""Far-field Brownian force moments M^(-1/2) psi (Sec. 4.3, eqs. br-f-ff,
+ivp-1, ivp-forward, ivp-backward) on the HIP path, through the C ABI, against
+the dense oracle (oracle/brownian.py):
+* with the same IVP step, the library and the oracle's dense march agree to
+  the accuracy of the product and of the inner GMRES solves;
+* against the exact inverse square root (eigendecomposition of the dense
+  oracle matrix) the difference is the IVP's own discretisation error, which
+  shrinks with the step.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import brownian, ewald
+from paper_1506_08481_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+CFG = dict(grid=32, P=24, m=0.9 * math.sqrt(math.pi * 24), xi=0.6, rc_factor=5.0, tol=1e-11, restart=60,
+           max_iter=600)
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1506_08481_amd import seasd
+    return seasd
+
+
+@pytest.fixture(scope="module")
+def case():
+    s = wl.bidisperse(24, 0.2, 7100)
+    psi = wl.force_moments(s.n, 7101)
+    p = ewald.converged_params(s.box, s.radius, xi=0.6, tol_exp=6.5)
+    return s, psi, p
+
+
+@pytest.mark.parametrize("dtau", [0.1, 0.05])
+def test_brownian_matches_dense_ivp(lib, case, dtau):
+    s, psi, p = case
+    eng = lib.Seasd(0, **CFG)
+    x, st = eng.brownian(_t(s.pos), _t(s.radius), s.box, _t(psi), dtau=dtau)
+    eng.close()
+    xg = x.cpu().numpy()
+    xo = brownian.brownian_farfield(s.pos, s.radius, s.box, psi, dtau, params=p)
+    xe = brownian.brownian_farfield(s.pos, s.radius, s.box, psi, None, params=p)
+    err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    disc = np.linalg.norm(xg - xe) / np.linalg.norm(xe)
+    print(f"dtau={dtau}: vs dense IVP {err:.2e}, vs exact M^-1/2 {disc:.2e}, stats {st}")
+    assert st["converged"] == 1 and st["steps"] == round(1 / dtau) and st["solves"] == 2 * st["steps"]
+    assert np.all(xg[:, 11] == 0.0)
+    assert err < 1e-8
+    assert disc < 0.02
+
+
+def test_brownian_sheared_cell(lib, case):
+    s, psi, p = case
+    box = np.array([[s.L, 0.5 * s.L, 0.0], [0.0, s.L, 0.0], [0.0, 0.0, s.L]])
+    eng = lib.Seasd(0, **CFG)
+    x, st = eng.brownian(_t(s.pos), _t(s.radius), box, _t(psi), dtau=0.1)
+    eng.close()
+    xo = brownian.brownian_farfield(s.pos, s.radius, box, psi, 0.1,
+                                    params=ewald.converged_params(box, s.radius, xi=0.6, tol_exp=6.5))
+    err = np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo)
+    print(f"sheared: vs dense IVP {err:.2e}")
+    assert err < 1e-8

@@ -35,8 +35,8 @@ def large():
 def _sample_error(cfg, precision, large):
     from paper_1506_08481_amd import seasd
     s, (P_, R_, X_), tg, yo = large
-    xi, rcf, P, mf, tile = cfg
-    eng = seasd.Seasd(0, grid=256, P=P, m=mf * math.sqrt(math.pi * P), xi=xi, rc_factor=rcf, tile=tile,
+    xi, rcf, P, mf = cfg
+    eng = seasd.Seasd(0, grid=256, P=P, m=mf * math.sqrt(math.pi * P), xi=xi, rc_factor=rcf,
                       precision=precision, checks=1)
     y = eng.apply(P_, R_, s.box, X_).cpu().numpy()
     eng.close()
@@ -91,8 +91,8 @@ def test_large_bidisperse_autotuned(bidisperse, prec):
     from paper_1506_08481_amd import seasd
     s, (P_, R_, X_), tg, yo = bidisperse
     precision = seasd.SEASD_FP64 if prec == "fp64" else seasd.SEASD_FP32
-    c = seasd.seasd_autotune(s.n, s.L, float(np.quantile(s.radius, 0.1)), float(s.radius.max()), 1e-6, precision)
-    cfg = {f: getattr(c, f) for f in ("grid", "P", "tile", "m", "xi", "rc_factor")}
+    c = seasd.seasd_autotune(s.n, s.box, float(np.quantile(s.radius, 0.1)), float(s.radius.max()), 1e-6, precision)
+    cfg = {k: v for k, v in c.as_dict().items() if k in ("grid", "P", "m", "xi", "rc_factor")}
     eng = seasd.Seasd(0, **cfg, precision=precision, checks=1)
     y1 = eng.apply(P_, R_, s.box, X_).cpu().numpy()   # one thread per sphere, lists measured
     y = eng.apply(P_, R_, s.box, X_).cpu().numpy()    # a wavefront per sphere

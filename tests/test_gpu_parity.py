@@ -61,6 +61,18 @@ def _einf(a, b, sl):
     return float(np.max(num / den))
 
 
+BLOCKS = {"U": slice(0, 3), "W": slice(3, 6), "E": slice(6, 11), "e": slice(11, 12)}
+
+
+def _blocks(a, b):
+    """eq. err-E per block (velocity, spin, strain, trace row)."""
+    return {k: _einf(a, b, sl) for k, sl in BLOCKS.items()}
+
+
+def sheared_box(L, gamma):
+    return np.array([[L, gamma * L, 0.0], [0.0, L, 0.0], [0.0, 0.0, L]])
+
+
 SMALL = dict(grid=32, P=24, m=0.9 * math.sqrt(math.pi * 24), xi=0.5, rc_factor=6.0)
 
 
@@ -77,9 +89,44 @@ def test_small_fp64_matches_oracle_1e10(lib, small_case):
     s, x, yref = small_case
     y = _gpu_apply(lib, s, x, **SMALL)
     err = _rel(y, yref)
-    print(f"N=100 FP64 M=32 P=24: rel2={err:.3e} einf(U)={_einf(y, yref, slice(0,3)):.2e} "
-          f"einf(E)={_einf(y, yref, slice(6,11)):.2e}")
+    e = _blocks(y, yref)
+    print(f"N=100 FP64 M=32 P=24: rel2={err:.3e} einf={e}")
     assert err <= 1e-10
+    # per block (eq. err-E); the strain block carries the most derivatives
+    assert e["U"] <= 1e-10 and e["W"] <= 1e-10 and e["E"] <= 1e-9 and e["e"] <= 1e-9
+
+
+@pytest.fixture(scope="module")
+def sheared_case():
+    s = wl.config_small()
+    box = sheared_box(s.L, 0.5)
+    x = wl.force_moments(s.n, 1000)
+    yref = ewald.apply(s.pos, s.radius, box, x, ewald.converged_params(box, s.radius, xi=0.5, tol_exp=6.5))
+    return s, box, x, yref
+
+
+def test_sheared_fp64_matches_oracle(lib, sheared_case):
+    """The same workload in the simple-shear cell a2 = (L/2, L, 0)
+    (eq. non-ortho-shape): window and k-space multiply on the fractional grid."""
+    s, box, x, yref = sheared_case
+    eng = lib.Seasd(0, **SMALL)
+    y = eng.apply(_t(s.pos), _t(s.radius), box, _t(x)).cpu().numpy()
+    eng.close()
+    err = _rel(y, yref)
+    e = _blocks(y, yref)
+    print(f"N=100 sheared gamma=0.5 FP64 M=32 P=24: rel2={err:.3e} einf={e}")
+    assert err <= 1e-10
+    assert e["U"] <= 1e-10 and e["W"] <= 1e-10 and e["E"] <= 1e-9 and e["e"] <= 1e-9
+
+
+def test_sheared_fp32(lib, sheared_case):
+    s, box, x, yref = sheared_case
+    eng = lib.Seasd(0, precision=lib.SEASD_FP32, **SMALL)
+    y = eng.apply(_t(s.pos), _t(s.radius), box, _t(x)).cpu().numpy()
+    eng.close()
+    err = _rel(y, yref)
+    print(f"N=100 sheared FP32: rel2={err:.3e} einf={_blocks(y, yref)}")
+    assert err <= 1e-6
 
 
 def test_small_stated_P16(lib, small_case):
@@ -90,18 +137,22 @@ def test_small_stated_P16(lib, small_case):
     assert err <= 1e-7
 
 
+@pytest.mark.parametrize("gamma", [0.0, 0.5])
 @pytest.mark.parametrize("parts", ["real", "self", "wave"])
-def test_split_parts(lib, small_case, parts):
+def test_split_parts(lib, small_case, parts, gamma):
     s, x, _ = small_case
+    box = sheared_box(s.L, gamma)
     code = {"real": (lib.SEASD_PARTS_REAL, ewald.PARTS_REAL),
             "self": (lib.SEASD_PARTS_SELF, ewald.PARTS_SELF),
             "wave": (lib.SEASD_PARTS_WAVE, ewald.PARTS_WAVE)}[parts]
     rc = SMALL["rc_factor"] * 2.0
     p = ewald.EwaldParams(xi=SMALL["xi"], rc=rc, grid=(32, 32, 32), parts=code[1])
-    yo = ewald.apply(s.pos, s.radius, s.box, x, p)
-    y = _gpu_apply(lib, s, x, parts=code[0], **SMALL)
+    yo = ewald.apply(s.pos, s.radius, box, x, p)
+    eng = lib.Seasd(0, parts=code[0], **SMALL)
+    y = eng.apply(_t(s.pos), _t(s.radius), box, _t(x)).cpu().numpy()
+    eng.close()
     err = float(np.abs(y - yo).max() / np.abs(yo).max())
-    print(f"part {parts}: max rel {err:.3e}")
+    print(f"part {parts} gamma={gamma}: max rel {err:.3e}")
     assert err <= (1e-13 if parts != "wave" else 1e-11)
 
 
@@ -112,16 +163,18 @@ def test_bidisperse_fp64(lib):
     # xi r_c = 6 for the smallest pair keeps the real-space tail below 1e-12
     y = _gpu_apply(lib, s, x, grid=32, P=24, m=0.9 * math.sqrt(math.pi * 24), xi=0.5, rc_factor=6.0)
     err = _rel(y, yref)
-    print(f"bidisperse N=60: rel2={err:.3e}")
+    e = _blocks(y, yref)
+    print(f"bidisperse N=60: rel2={err:.3e} einf={e}")
     assert err <= 1e-9
+    assert max(e.values()) <= 1e-8
 
 
 def test_fp32_path(lib, small_case):
     s, x, yref = small_case
     y = _gpu_apply(lib, s, x, precision=lib.SEASD_FP32, **SMALL)
     err = _rel(y, yref)
-    print(f"N=100 FP32: rel2={err:.3e}")
-    assert err <= 2e-6
+    print(f"N=100 FP32: rel2={err:.3e} einf={_blocks(y, yref)}")
+    assert err <= 1e-6
 
 
 def test_single_sphere_sc_array(lib):
@@ -179,10 +232,18 @@ def test_error_paths(lib):
         eng.apply(_t(pos2), R, s.box, X)
     assert e.value.code == lib.SEASD_E_OVERLAP
     box = s.box.copy()
-    box[0, 1] = 0.5 * s.L
+    box[2, 0] = 0.5 * s.L      # a1 with a z component: not one of the accepted cells
     with pytest.raises(lib.SeasdError) as e:
         eng.apply(P, R, box, X)
     assert e.value.code == lib.SEASD_E_UNSUPPORTED
+    with pytest.raises(lib.SeasdError) as e:
+        eng.set_config(grid=(32, 32, 64))
+    assert e.value.code == lib.SEASD_E_UNSUPPORTED
+    eng.set_config(grid=32)
+    with pytest.raises(ValueError):
+        eng.apply(P, R[:5], s.box, X)      # short radius array, caught before the library
+    with pytest.raises(TypeError):
+        eng.apply(P, R, s.box, X.float())
     with pytest.raises(lib.SeasdError) as e:
         eng.set_config(P=40)
     assert e.value.code == lib.SEASD_E_INVALID_ARG

@@ -43,13 +43,19 @@ def _header_struct_fields(name):
 
 
 @pytest.mark.parametrize("cname,pyclass", [("seasd_config", seasd.seasd_config),
-                                           ("seasd_solve_stats", seasd.seasd_solve_stats)])
+                                           ("seasd_solve_stats", seasd.seasd_solve_stats),
+                                           ("seasd_brownian_stats", seasd.seasd_brownian_stats)])
 def test_binding_struct_layout_matches_header(cname, pyclass):
     cmap = {"int32_t": ctypes.c_int32, "double": ctypes.c_double}
     hdr = _header_struct_fields(cname)
-    assert [f for _, f in hdr] == [f for f, _ in pyclass._fields_]
+    names = [re.sub(r"\[\d+\]$", "", f) for _, f in hdr]
+    assert names == [f for f, _ in pyclass._fields_]
     for (typ, f), (pf, pt) in zip(hdr, pyclass._fields_):
-        assert cmap[typ] is pt, f
+        m = re.search(r"\[(\d+)\]$", f)
+        if m:   # fixed-size array field
+            assert issubclass(pt, ctypes.Array) and pt._length_ == int(m.group(1)) and pt._type_ is cmap[typ], f
+        else:
+            assert cmap[typ] is pt, f
 
 
 def test_default_config_and_validation_on_host():
@@ -57,7 +63,7 @@ def test_default_config_and_validation_on_host():
     if not os.path.exists(seasd.LIB_PATH):
         pytest.skip("libseasd.so not built")
     c = seasd.default_config()
-    assert c.grid == 64 and c.P == 16 and c.rc_factor == 4.0 and c.precision == seasd.SEASD_FP64
+    assert tuple(c.grid) == (64, 64, 64) and c.P == 16 and c.rc_factor == 4.0 and c.precision == seasd.SEASD_FP64
     assert seasd.lib().seasd_error_string(seasd.SEASD_E_OVERLAP).decode().startswith("overlapping")
 
 

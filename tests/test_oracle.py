@@ -322,3 +322,37 @@ def test_one_way_solve_satisfies_its_equations(dense8):
     s_int = x[:, 11] - b[:, 11] / m_self                                # interaction part
     feedback = np.einsum("iajb,jb->ia", B[:, :11, :, 11:12], s_int[:, None])
     assert np.allclose(y[:, :11] - feedback, b[:, :11], rtol=0, atol=1e-11)
+
+
+# ---------------------------------------------------------------------------
+# the split-diagnostic wave sum over the grid's k-set (|q_d| < M/2)
+
+def test_grid_kset_is_the_grid_without_nyquist_planes():
+    # the k-set of an M^3 grid: every integer q with |q_d| < M/2 except q = 0,
+    # symmetric under q -> -q, mapped by k = B q (the cube: k = 2 pi q / L)
+    L = 7.0
+    for M in (8, 16):
+        k = ewald.k_vectors(np.eye(3) * L, ewald.EwaldParams(xi=0.5, rc=1.0, grid=(M, M, M)))
+        q = np.rint(k * L / (2 * np.pi)).astype(int)
+        assert np.allclose(q * 2 * np.pi / L, k, atol=1e-12)
+        assert k.shape[0] == (M - 1) ** 3 - 1
+        assert np.abs(q).max() == M // 2 - 1
+        keys = {tuple(v) for v in q}
+        assert all(tuple(-v) in keys for v in q) and (0, 0, 0) not in keys
+
+
+def test_grid_kset_wave_sum_converges_to_the_converged_wave_sum(small_bidisperse):
+    # once the grid's Nyquist wavenumber pi M / L lies far beyond the
+    # converged cut-off, the grid k-set sum equals the converged wave sum
+    s, x = small_bidisperse
+    conv = ewald.converged_params(s.box, s.radius, xi=0.6, tol_exp=6.5)
+    yk = ewald.apply(s.pos, s.radius, s.box, x, ewald.EwaldParams(xi=0.6, rc=conv.rc, kc=conv.kc,
+                                                                   parts=ewald.PARTS_WAVE))
+    M = int(2 * np.ceil(conv.kc * s.L / (2 * np.pi))) + 4
+    yg = ewald.apply(s.pos, s.radius, s.box, x, ewald.EwaldParams(xi=0.6, rc=conv.rc, grid=(M, M, M),
+                                                                   parts=ewald.PARTS_WAVE))
+    assert np.linalg.norm(yg - yk) / np.linalg.norm(yk) < 1e-13
+    # a coarse grid truncates the sum visibly
+    yc = ewald.apply(s.pos, s.radius, s.box, x, ewald.EwaldParams(xi=0.6, rc=conv.rc, grid=(6, 6, 6),
+                                                                   parts=ewald.PARTS_WAVE))
+    assert np.linalg.norm(yc - yk) / np.linalg.norm(yk) > 1e-6
