@@ -99,16 +99,23 @@ extern "C" {
                                     /* network, plus its initial guess (see below)     */
 #define SEASD_PRECOND_LEARNED_GUESS 3 /* block-diagonal blocks, the network's guess   */
 
-#define SEASD_SIZE_REAL 0  /* Faxen operators applied to the window on both   */
-                           /* sides (the real-space approach of Sec. 3.2)    */
+#define SEASD_SIZE_REAL   0 /* Faxen operators applied to the window on both  */
+                            /* sides (the real-space approach of Sec. 3.2)   */
+#define SEASD_SIZE_HYBRID 1 /* Faxen operators on the window when spreading;  */
+                            /* when reading, the second derivatives are taken */
+                            /* in k space (eq. parseval-sum-2 with the grid-  */
+                            /* space H of eq. grid-space: the hybrid approach */
+                            /* of Sec. 3.2; 4 forward, 7 inverse transforms)  */
+#define SEASD_SIZE_WAVE   2 /* every Faxen operator in k space (eqs. wave-   */
+                            /* only-*): SEASD_E_UNSUPPORTED in this build     */
 
 typedef struct seasd_config {
     int32_t grid[3];        /* M, grid points along each lattice direction: equal,    */
                             /* a power of two, 8..256 (unequal: SEASD_E_UNSUPPORTED)  */
     int32_t P;              /* window support in grid points per dimension, 4..min(M,32), */
                             /* odd or even (eq. fgg-exp; centred either way)           */
-    int32_t size_approach;  /* SEASD_SIZE_REAL; the wave-space and hybrid approaches of */
-                            /* Sec. 3.2 return SEASD_E_UNSUPPORTED                      */
+    int32_t size_approach;  /* SEASD_SIZE_REAL or SEASD_SIZE_HYBRID (Sec. 3.2); the      */
+                            /* wave-space approach returns SEASD_E_UNSUPPORTED          */
     double  m;              /* window shape parameter (eq. theta-param); <= 0: sqrt(pi P)   */
     double  xi;             /* Ewald splitting parameter, Beenakker convention (Sec. 2.2)   */
     double  rc_factor;      /* real-space cut-off r_c = rc_factor (a_i + a_j), > 1           */

@@ -22,6 +22,7 @@ struct seasd_handle_s {
     bool have_cfg = false;
     // product workspace
     DevBuf bin_of, counts, start, fill, perm, amax, err, sp, sfrac, sa, sx, ybuf, rgrid, spec, twiddle;
+    DevBuf rgrid2, spec2;   // hybrid size approach: the k-space Laplacian fields
     DevBuf ncount, nstats, list, total, wrec, scan_tmp;
     int cap = 64;             // neighbour-list slots per sphere, grown on demand
     int pair_group = 1;       // lanes per sphere of the pair sum chosen for the held geometry
@@ -58,7 +59,7 @@ extern "C" const char* seasd_error_string(int32_t code) {
         case SEASD_E_SINGULAR: return "singular preconditioner block";
         case SEASD_E_HIP: return "HIP runtime error";
         case SEASD_E_NOMEM: return "device allocation failed";
-        case SEASD_E_UNSUPPORTED: return "unsupported request (only cubic cells)";
+        case SEASD_E_UNSUPPORTED: return "unsupported request (cell shape, unequal grids or size approach)";
         case SEASD_E_FORMAT: return "weights file missing, mismatched or failing its checksum";
         case SEASD_W_NOT_CONVERGED: return "solve did not reach the tolerance";
         case SEASD_W_PRECOND_FALLBACK: return "learned preconditioner rejected, block-diagonal used";
@@ -107,7 +108,7 @@ extern "C" int seasd_destroy(seasd_handle h) {
     if (!h) return SEASD_OK;
     hipSetDevice(h->device);
     DevBuf* bufs[] = {&h->bin_of, &h->counts, &h->start, &h->fill, &h->perm, &h->amax, &h->err,
-                      &h->sp, &h->sfrac, &h->sa, &h->sx, &h->ybuf, &h->rgrid, &h->spec, &h->twiddle,
+                      &h->sp, &h->sfrac, &h->sa, &h->sx, &h->ybuf, &h->rgrid, &h->spec, &h->rgrid2, &h->spec2, &h->twiddle,
                       &h->ncount, &h->nstats, &h->list, &h->total, &h->wrec, &h->scan_tmp,
                       &h->w, &h->z, &h->u, &h->r, &h->bred, &h->hdev, &h->partial, &h->blocks,
                       &h->inv, &h->coef, &h->singular, &h->one_pos, &h->one_rad, &h->one_x, &h->one_y,
@@ -139,9 +140,9 @@ extern "C" int seasd_set_config(seasd_handle h, const seasd_config* c) {
     if (c->precond < SEASD_PRECOND_NONE || c->precond > SEASD_PRECOND_LEARNED_GUESS) return SEASD_E_INVALID_ARG;
     if (c->size_approach < 0 || c->size_approach > 2) return SEASD_E_INVALID_ARG;
     // valid requests this build does not carry out: unequal grids and the
-    // wave-space and hybrid size approaches
+    // wave-space size approach
     if (c->grid[1] != c->grid[0] || c->grid[2] != c->grid[0]) return SEASD_E_UNSUPPORTED;
-    if (c->size_approach != SEASD_SIZE_REAL) return SEASD_E_UNSUPPORTED;
+    if (c->size_approach == SEASD_SIZE_WAVE) return SEASD_E_UNSUPPORTED;
     h->cfg = *c;
     h->have_cfg = true;
     return SEASD_OK;
@@ -186,7 +187,7 @@ static double min_height(const Cell& c) { return std::min(c.height[0], std::min(
 
 // product workspace for n spheres on the configured grid (bins are the 8^3
 // spreading tiles)
-static int ensure_product_ws(seasd_handle h, int64_t n) {
+static int ensure_product_ws(seasd_handle h, int64_t n, hipStream_t st) {
     const int M = h->cfg.grid[0];
     const int nb = M / 8;
     const size_t nbins = (size_t)nb * nb * nb;
@@ -211,20 +212,17 @@ static int ensure_product_ws(seasd_handle h, int64_t n) {
     if (h->cfg.parts & SEASD_PARTS_WAVE) {
         rc |= h->rgrid.ensure(R * 4 * (size_t)M * M * M);
         rc |= h->spec.ensure(R * 4 * (size_t)M * M * M);
+        if (h->cfg.size_approach == SEASD_SIZE_HYBRID) {   // the k-space Laplacian fields
+            rc |= h->rgrid2.ensure(R * 4 * (size_t)M * M * M);
+            rc |= h->spec2.ensure(R * 4 * (size_t)M * M * M);
+        }
     } else {
         rc |= h->rgrid.ensure(R * 4);
     }
     rc |= h->twiddle.ensure(sizeof(double) * 2 * M);
     if (rc) return SEASD_E_NOMEM;
     if (h->twiddle_M != M) {
-        std::vector<double> tw(2 * M);
-        for (int j = 0; j < M; ++j) {
-            const double a = 2.0 * kPi * j / M;
-            tw[2 * j] = std::cos(a);
-            tw[2 * j + 1] = std::sin(a);
-        }
-        if (hipMemcpy(h->twiddle.p, tw.data(), sizeof(double) * 2 * M, hipMemcpyHostToDevice) != hipSuccess)
-            return SEASD_E_HIP;
+        if (launch_twiddles(M, h->twiddle.as<double>(), st)) return SEASD_E_HIP;
         h->twiddle_M = M;
     }
     return SEASD_OK;
@@ -296,6 +294,9 @@ static void fill_args(seasd_handle h, ApplyArgs& A, int64_t n, const double* pos
     A.wrec = h->wrec.p;
     A.rgrid = h->rgrid.p;
     A.spec = h->spec.p;
+    A.hybrid = c.size_approach == SEASD_SIZE_HYBRID && (c.parts & SEASD_PARTS_WAVE);
+    A.rgrid2 = A.hybrid ? h->rgrid2.p : nullptr;
+    A.spec2 = A.hybrid ? h->spec2.p : nullptr;
     A.twiddle = h->twiddle.as<double>();
 }
 
@@ -310,7 +311,7 @@ static int queue_apply(seasd_handle h, int64_t n, const double* pos, const doubl
                        const double* x, double* y, hipStream_t st, bool checks, bool reuse_geometry = false,
                        int compressible = -1) {
     if (compressible < 0) compressible = h->cfg.compressible;
-    int rc = ensure_product_ws(h, n);
+    int rc = ensure_product_ws(h, n, st);
     if (rc) return rc;
     ApplyArgs A;
     fill_args(h, A, n, pos, radius, L, x, y, checks, compressible);
@@ -535,7 +536,7 @@ static int dot_host(seasd_handle h, int64_t len, int k, const double* V, int64_t
 // [n][12] array (gathered along, unused).
 static int prepare_geometry(seasd_handle h, int64_t n, const double* pos, const double* radius, const Cell& L,
                             const double* x, hipStream_t st, ApplyArgs& A) {
-    int rc = ensure_product_ws(h, n);
+    int rc = ensure_product_ws(h, n, st);
     if (rc) return rc;
     fill_args(h, A, n, pos, radius, L, x, nullptr, h->cfg.checks != 0, 0);
     if (hipMemsetAsync(A.err, 0, sizeof(int), st) != hipSuccess) return SEASD_E_HIP;

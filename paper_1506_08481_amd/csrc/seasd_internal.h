@@ -193,9 +193,14 @@ struct ApplyArgs {
     void* wrec;      // [n][rec_stride(P)] R window records
     void* rgrid;
     void* spec;
+    int hybrid;      // hybrid size approach: Faxen Laplacians of the read-out in k space
+    void* rgrid2;    // hybrid: [z][y][x] of R4 (Lvx, Lvy, Lvz, 0), Lv = (lap/6) v
+    void* spec2;     // hybrid: half spectrum of the same four fields
     const double* twiddle;
 };
 
+int launch_twiddles(int M, double* tw, hipStream_t st);
+int launch_clear_ints(int n, int* p, hipStream_t st);
 int launch_geometry(const ApplyArgs& a, hipStream_t st, PhaseTimer* tm);
 int launch_pairlist(const ApplyArgs& a, hipStream_t st);
 int launch_moments(const ApplyArgs& a, hipStream_t st);

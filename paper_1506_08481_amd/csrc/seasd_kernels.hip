@@ -1572,6 +1572,76 @@ __global__ __launch_bounds__(256) void k_fft_z_scale(C1<R>* __restrict__ data,
     }
 }
 
+// z pass of the hybrid size approach (Sec. 3.2): as k_fft_z_scale, and in
+// addition the velocity spectrum times -|k|^2/6 (the Faxen Laplacian of the
+// read-out, lap/6, taken in k space: G'' of eq. wave-only-compute-2 with the
+// grid-space H of eq. grid-space) into the second spectrum as (Lvx, Lvy,
+// Lvz, 0). LDS lines are field-major (line c W + w for field c of column w):
+// the forward transform runs over the 4 W input lines, the inverse over all
+// 8 W lines.
+template <typename R, int M, int W>
+__global__ __launch_bounds__(256) void k_fft_z_scale_hyb(C1<R>* __restrict__ data, C1<R>* __restrict__ data2,
+                                                         const double* __restrict__ twg, KScale ks) {
+    using T = R;
+    __shared__ C1<T> buf[2][8 * W * M];
+    __shared__ C1<T> twf[M], twi[M];
+    load_twiddles<T, M>(twf, twg, +1);
+    load_twiddles<T, M>(twi, twg, -1);
+    constexpr int HX = M / 2;
+    const int x0 = (blockIdx.x % (HX / W)) * W;
+    const int y = blockIdx.x / (HX / W);
+    const size_t zstride = (size_t)M * HX * 4;
+    for (int e = threadIdx.x; e < W * M * 4; e += blockDim.x) {
+        const int c = e & 3, w = (e >> 2) % W, z = (e >> 2) / W;
+        buf[0][(c * W + w) * M + z] = data[z * zstride + ((size_t)y * HX + x0 + w) * 4 + c];
+    }
+    __syncthreads();
+    C1<T>* a = lds_fft<T, M>(buf[0], buf[1], 4 * W, twf, +1);
+    C1<T>* b = (a == buf[0]) ? buf[1] : buf[0];
+    const int qy = (y < M / 2) ? y : y - M;
+    for (int e = threadIdx.x; e < W * M; e += blockDim.x) {
+        const int w = e % W, z = e / W;
+        const int qx = x0 + w;
+        const int qz = (z < M / 2) ? z : z - M;
+        C1<T>* f[8];
+        for (int c = 0; c < 8; ++c) f[c] = a + (c * W + w) * M + z;
+        const bool zero = (qx == 0 && qy == 0 && qz == 0) || (y == M / 2) || (z == M / 2);
+        if (zero) {
+            for (int c = 0; c < 8; ++c) *f[c] = {T(0), T(0)};
+            continue;
+        }
+        double kx, ky, kz, k2;
+        const double ex = kscale_factor(ks, qx, qy, qz, kx, ky, kz, k2);
+        const T st = (T)(ks.inv_eta * (1.0 + k2 * ks.inv4xi2) * ex);
+        const T lp = (T)ex;
+        const T rkx = (T)kx, rky = (T)ky, rkz = (T)kz, ik2 = (T)(1.0 / k2);
+        const T lap6 = (T)(-k2 / 6.0);
+        const C1<T> h0 = *f[0], h1 = *f[1], h2 = *f[2], h3 = *f[3];
+        const C1<T> kf = {rkx * h0.re + rky * h1.re + rkz * h2.re, rkx * h0.im + rky * h1.im + rkz * h2.im};
+        const C1<T> pk = {kf.re * ik2, kf.im * ik2};
+        const T sq = T(0.25) * (T)ks.inv_eta * lp;
+        const C1<T> v0 = {st * (h0.re - rkx * pk.re) - sq * rkx * h3.im, st * (h0.im - rkx * pk.im) + sq * rkx * h3.re};
+        const C1<T> v1 = {st * (h1.re - rky * pk.re) - sq * rky * h3.im, st * (h1.im - rky * pk.im) + sq * rky * h3.re};
+        const C1<T> v2 = {st * (h2.re - rkz * pk.re) - sq * rkz * h3.im, st * (h2.im - rkz * pk.im) + sq * rkz * h3.re};
+        *f[0] = v0;
+        *f[1] = v1;
+        *f[2] = v2;
+        *f[3] = {-lp * kf.im, lp * kf.re};
+        *f[4] = {lap6 * v0.re, lap6 * v0.im};
+        *f[5] = {lap6 * v1.re, lap6 * v1.im};
+        *f[6] = {lap6 * v2.re, lap6 * v2.im};
+        *f[7] = {T(0), T(0)};
+    }
+    __syncthreads();
+    C1<T>* r = lds_fft<T, M>(a, b, 8 * W, twi, -1);
+    for (int e = threadIdx.x; e < W * M * 8; e += blockDim.x) {
+        const int c = e & 7, w = (e >> 3) % W, z = (e >> 3) / W;
+        const C1<T> v = r[(c * W + w) * M + z];
+        C1<R>* dst = c < 4 ? data : data2;
+        dst[z * zstride + ((size_t)y * HX + x0 + w) * 4 + (c & 3)] = v;
+    }
+}
+
 // z pass for M = 256 (FP32 storage): forward z transform, k-space multiply
 // (as in k_fft_z_scale), inverse z transform; a workgroup owns 4 qx columns
 // at one qy.
@@ -1650,10 +1720,14 @@ __global__ __launch_bounds__(256) void k_fft_z256(C1<R>* __restrict__ data, cons
 // butterfly does not pay for the longer load chain of each lane).
 constexpr int kGatherLanes = 64;
 
-template <typename R, int G, bool SHEAR>
+// HYB (the hybrid size approach of Sec. 3.2): the Faxen Laplacians of the
+// read-out come from the k-space field grid2 = (lap/6) v instead of the
+// window, so the window is read plainly (eq. parseval-sum-2): U from
+// v + a^2 Lv, Omega from v, E from grad (v + (3/5) a^2 Lv) with grad h = -2 g h.
+template <typename R, int G, bool SHEAR, bool HYB>
 __global__ __launch_bounds__(256) void k_gather(
-    int n, const R* __restrict__ recs, const int* __restrict__ perm, const R4<R>* __restrict__ grid, int M, int P,
-    SpreadGeom sg, double inv_eta, int parts, int compressible,
+    int n, const R* __restrict__ recs, const int* __restrict__ perm, const R4<R>* __restrict__ grid,
+    const R4<R>* __restrict__ grid2, int M, int P, SpreadGeom sg, double inv_eta, int parts, int compressible,
     const double* __restrict__ ybuf, double* __restrict__ yout) {
     static_assert(G == 16 || G == 32 || G == 64, "lanes per sphere");
     constexpr int SPB = 4 * (64 / G);   // spheres per workgroup
@@ -1691,6 +1765,65 @@ __global__ __launch_bounds__(256) void k_gather(
         // are cubic in u_z, so each (x, y) column is reduced over z to the
         // moments M_k[c] = sum_z f_z u_z^k g_c (k <= 3) first; the 13 outputs
         // follow from them per column.
+        if constexpr (HYB) {
+        const R a2 = rc[7], a2e = R(0.6) * rc[7];
+        for (int e = lane; e < P2; e += G) {
+            const int kx = e % P, ky = e / P;
+            const R ux = d0x + (R)kx, uy = d0y + (R)ky;
+            const R gX = Gxx * ux, gY = Gyx * ux + Gyy * uy;
+            const R wxy = (R)sg.cw * fac[sb][kx] * fac[sb][P + ky];
+            const int gx = (i0.x + kx) & mask, gy = (i0.y + ky) & mask;
+            // z moments of v (0 and 1), of p (0) and of Lv (0 and 1)
+            R m0x = 0, m0y = 0, m0z = 0, m0w = 0, m1x = 0, m1y = 0, m1z = 0;
+            R l0x = 0, l0y = 0, l0z = 0, l1x = 0, l1y = 0, l1z = 0;
+            const size_t colo = (size_t)gy * M + gx;
+            const size_t zs = (size_t)M * M;
+#pragma unroll 4
+            for (int kz = 0; kz < P; ++kz) {
+                const size_t o = colo + (size_t)((i0.z + kz) & mask) * zs;
+                const R4<R> g = grid[o];
+                const R4<R> l = grid2[o];
+                const R t0 = zt[sb][0][kz], t1 = zt[sb][1][kz];
+                m0x += t0 * g.x;
+                m0y += t0 * g.y;
+                m0z += t0 * g.z;
+                m0w += t0 * g.w;
+                m1x += t1 * g.x;
+                m1y += t1 * g.y;
+                m1z += t1 * g.z;
+                l0x += t0 * l.x;
+                l0y += t0 * l.y;
+                l0z += t0 * l.z;
+                l1x += t1 * l.x;
+                l1y += t1 * l.y;
+                l1z += t1 * l.z;
+            }
+            // grad (v + (3/5) a^2 Lv) read with grad h = -2 g h, g_z = Gzz u_z
+            const R qx = R(2) * (m0x + a2e * l0x), qy = R(2) * (m0y + a2e * l0y), qz = R(2) * (m0z + a2e * l0z);
+            const R sx = R(2) * Gzz * (m1x + a2e * l1x);
+            const R sy = R(2) * Gzz * (m1y + a2e * l1y);
+            const R sz = R(2) * Gzz * (m1z + a2e * l1z);
+            const R hw = R(0.5) * wxy;
+            R col[13];
+            col[0] = wxy * (m0x + a2 * l0x);
+            col[1] = wxy * (m0y + a2 * l0y);
+            col[2] = wxy * (m0z + a2 * l0z);
+            col[3] = wxy * (gY * m0z - Gzz * m1y);
+            col[4] = wxy * (Gzz * m1x - gX * m0z);
+            col[5] = wxy * (gX * m0y - gY * m0x);
+            col[6] = wxy * (gX * qx);
+            col[7] = wxy * (gY * qy);
+            col[8] = wxy * sz;
+            col[9] = hw * (gY * qx + gX * qy);
+            col[10] = hw * (sx + gX * qz);
+            col[11] = hw * (sy + gY * qz);
+            col[12] = wxy * m0w;
+            for (int c = 0; c < 13; ++c) {
+                if constexpr (sizeof(R) == 4) neumaier(ac[c], cp[c], col[c]);
+                else ac[c] += col[c];
+            }
+        }
+        } else {
         for (int e = lane; e < P2; e += G) {
             const int kx = e % P, ky = e / P;
             const R ux = d0x + (R)kx, uy = d0y + (R)ky;
@@ -1765,6 +1898,7 @@ __global__ __launch_bounds__(256) void k_gather(
                 else ac[c] += col[c];   // FP64 sums need no compensation
             }
         }
+        }
         for (int c = 0; c < 13; ++c) acc[c] = (double)ac[c] + (double)cp[c];
         for (int off = G / 2; off > 0; off >>= 1)
             for (int c = 0; c < 13; ++c) acc[c] += __shfl_xor(acc[c], off, G);
@@ -1786,21 +1920,26 @@ __global__ __launch_bounds__(256) void k_gather(
 // ---------------------------------------------------------------------------
 // host-side launchers (declared in seasd_internal.h)
 
+// The transform chain of one product: forward x, y, the z pass with the
+// k-space multiply, inverse y, x. The hybrid size approach (rgrid2, spec2
+// non-null) runs the generic kernels, whose z pass also writes the Laplacian
+// fields, and inverts both spectra.
 template <typename R>
-static int launch_fft_chain_M(int M, void* rgrid, void* spec, const double* tw, const KScale& ks,
-                              hipStream_t st, PhaseTimer* tm);
+static int launch_fft_chain_M(int M, void* rgrid, void* spec, void* rgrid2, void* spec2, const double* tw,
+                              const KScale& ks, hipStream_t st, PhaseTimer* tm);
 
 #define FFT_CASE(MM, LPB, W)                                                                              \
     case MM: {                                                                                            \
         const int lines = MM * MM;                                                                        \
+        const bool sp256 = MM == 256 && !dbl && !hyb;                                                     \
         tm->begin(kPhaseFftXFwd, st);                                                                     \
-        if (MM == 256 && !dbl)                                                          \
+        if (sp256)                                                                                        \
             hipLaunchKernelGGL((k_fft_x_fwd256<R>), dim3(lines / 8), dim3(256), 0, st,                    \
                                (const R4<R>*)rgrid, (C1<R>*)spec, tw);                                    \
         else                                                                                              \
             hipLaunchKernelGGL((k_fft_x_fwd<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,            \
                                (const R4<R>*)rgrid, (C1<R>*)spec, tw);                                    \
-        if (MM == 256 && !dbl) {                                                        \
+        if (sp256) {                                                                                      \
             tm->begin(kPhaseFftYFwd, st);                                                                 \
             hipLaunchKernelGGL((k_fft_y256<R>), dim3(32 * 256), dim3(256), 0, st, (C1<R>*)spec, tw, +1);  \
             tm->begin(kPhaseFftZ, st);                                                                    \
@@ -1812,26 +1951,39 @@ static int launch_fft_chain_M(int M, void* rgrid, void* spec, const double* tw, 
             hipLaunchKernelGGL((k_fft_y<R, MM, W>), dim3((MM / 2 / W) * MM), dim3(256), 0, st,            \
                                (C1<R>*)spec, tw, +1);                                                     \
             tm->begin(kPhaseFftZ, st);                                                                    \
-            hipLaunchKernelGGL((k_fft_z_scale<R, MM, W>), dim3((MM / 2 / W) * MM), dim3(256), 0, st,      \
-                               (C1<R>*)spec, tw, ks);                                                     \
+            if (hyb) {                                                                                    \
+                constexpr int WH = (W > 1) ? W / 2 : 1;                                                   \
+                hipLaunchKernelGGL((k_fft_z_scale_hyb<R, MM, WH>), dim3((MM / 2 / WH) * MM), dim3(256),   \
+                                   0, st, (C1<R>*)spec, (C1<R>*)spec2, tw, ks);                           \
+            } else {                                                                                      \
+                hipLaunchKernelGGL((k_fft_z_scale<R, MM, W>), dim3((MM / 2 / W) * MM), dim3(256), 0, st,  \
+                                   (C1<R>*)spec, tw, ks);                                                 \
+            }                                                                                             \
             tm->begin(kPhaseFftYInv, st);                                                                 \
             hipLaunchKernelGGL((k_fft_y<R, MM, W>), dim3((MM / 2 / W) * MM), dim3(256), 0, st,            \
                                (C1<R>*)spec, tw, -1);                                                     \
+            if (hyb)                                                                                      \
+                hipLaunchKernelGGL((k_fft_y<R, MM, W>), dim3((MM / 2 / W) * MM), dim3(256), 0, st,        \
+                                   (C1<R>*)spec2, tw, -1);                                                \
         }                                                                                                 \
         tm->begin(kPhaseFftXInv, st);                                                                     \
-        if (MM == 256 && !dbl)                                                          \
+        if (sp256)                                                                                        \
             hipLaunchKernelGGL((k_fft_x_inv256<R>), dim3(lines / 8), dim3(256), 0, st,                    \
                                (const C1<R>*)spec, (R4<R>*)rgrid, tw);                                    \
         else                                                                                              \
             hipLaunchKernelGGL((k_fft_x_inv<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,            \
                                (const C1<R>*)spec, (R4<R>*)rgrid, tw);                                    \
+        if (hyb)                                                                                          \
+            hipLaunchKernelGGL((k_fft_x_inv<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,            \
+                               (const C1<R>*)spec2, (R4<R>*)rgrid2, tw);                                  \
         break;                                                                                            \
     }
 
 template <typename R>
-static int launch_fft_chain_M(int M, void* rgrid, void* spec, const double* tw, const KScale& ks,
-                              hipStream_t st, PhaseTimer* tm) {
+static int launch_fft_chain_M(int M, void* rgrid, void* spec, void* rgrid2, void* spec2, const double* tw,
+                              const KScale& ks, hipStream_t st, PhaseTimer* tm) {
     constexpr bool dbl = sizeof(R) == 8;
+    const bool hyb = rgrid2 != nullptr && spec2 != nullptr;
     switch (M) {
         FFT_CASE(8, 8, 2)
         FFT_CASE(16, 8, (dbl ? 2 : 4))
@@ -1855,6 +2007,33 @@ static NbrGeom nbr_geom(const ApplyArgs& A) {
 static SpreadGeom spread_geom(const ApplyArgs& A, bool gather) {
     const WinGeom& w = A.win;
     return SpreadGeom{w.Gxx, w.Gyx, w.Gyy, w.Gzz, w.Qxx, w.Qxy, w.Qyy, gather ? w.cwv : w.cw};
+}
+
+// FFT twiddle table tw[j] = (cos, sin)(2 pi j / M), j < M (exact argument
+// reduction through sincospi)
+__global__ void k_twiddles(int M, double* __restrict__ tw) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M) return;
+    double sv, cv;
+    sincospi(2.0 * (double)j / (double)M, &sv, &cv);
+    tw[2 * j] = cv;
+    tw[2 * j + 1] = sv;
+}
+
+int launch_twiddles(int M, double* tw, hipStream_t st) {
+    hipLaunchKernelGGL(k_twiddles, dim3((M + 255) / 256), dim3(256), 0, st, M, tw);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// n ints set to zero by a kernel (a fill that a captured graph may hold)
+__global__ void k_clear_ints(int n, int* __restrict__ p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+int launch_clear_ints(int n, int* p, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_clear_ints, dim3((n + 255) / 256), dim3(256), 0, st, n, p);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 // binning: bins, their scan, binned copies of centres, radii and moments
@@ -1956,10 +2135,12 @@ int launch_wave(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     const KScale ks = kscale_of(A);
     if (A.fp32) {
         launch_window_spread<float>(A, wave, st, tm);
-        if (wave && launch_fft_chain_M<float>(A.M, A.rgrid, A.spec, A.twiddle, ks, st, tm)) return -1;
+        if (wave && launch_fft_chain_M<float>(A.M, A.rgrid, A.spec, A.rgrid2, A.spec2, A.twiddle, ks, st, tm))
+            return -1;
     } else {
         launch_window_spread<double>(A, wave, st, tm);
-        if (wave && launch_fft_chain_M<double>(A.M, A.rgrid, A.spec, A.twiddle, ks, st, tm)) return -1;
+        if (wave && launch_fft_chain_M<double>(A.M, A.rgrid, A.spec, A.rgrid2, A.spec2, A.twiddle, ks, st, tm))
+            return -1;
     }
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
@@ -1983,13 +2164,17 @@ static void launch_gather_R(const ApplyArgs& A, hipStream_t st) {
     constexpr int spb = 4 * (64 / kGatherLanes);
     const int gg = (n + spb - 1) / spb;
     const SpreadGeom sg = spread_geom(A, true);
-    if (A.win.sheared)
-        hipLaunchKernelGGL((k_gather<R, kGatherLanes, true>), dim3(gg), dim3(256), 0, st, n, (const R*)A.wrec, A.perm,
-                           (const R4<R>*)A.rgrid, A.M, A.P, sg, A.inv_eta, A.parts, A.compressible, A.ybuf, A.y);
+    const R4<R>* g1 = (const R4<R>*)A.rgrid;
+    const R4<R>* g2 = (const R4<R>*)A.rgrid2;
+    if (A.hybrid)   // the window is read plainly: no sheared-cell Laplacian term
+        hipLaunchKernelGGL((k_gather<R, kGatherLanes, false, true>), dim3(gg), dim3(256), 0, st, n, (const R*)A.wrec,
+                           A.perm, g1, g2, A.M, A.P, sg, A.inv_eta, A.parts, A.compressible, A.ybuf, A.y);
+    else if (A.win.sheared)
+        hipLaunchKernelGGL((k_gather<R, kGatherLanes, true, false>), dim3(gg), dim3(256), 0, st, n, (const R*)A.wrec,
+                           A.perm, g1, g2, A.M, A.P, sg, A.inv_eta, A.parts, A.compressible, A.ybuf, A.y);
     else
-        hipLaunchKernelGGL((k_gather<R, kGatherLanes, false>), dim3(gg), dim3(256), 0, st, n, (const R*)A.wrec,
-                           A.perm, (const R4<R>*)A.rgrid, A.M, A.P, sg, A.inv_eta, A.parts, A.compressible, A.ybuf,
-                           A.y);
+        hipLaunchKernelGGL((k_gather<R, kGatherLanes, false, false>), dim3(gg), dim3(256), 0, st, n, (const R*)A.wrec,
+                           A.perm, g1, g2, A.M, A.P, sg, A.inv_eta, A.parts, A.compressible, A.ybuf, A.y);
 }
 
 // Gather: the wave-space velocities added to the pair sum, scattered back to

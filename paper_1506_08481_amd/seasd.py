@@ -49,6 +49,8 @@ SYMBOLS = ("seasd_create", "seasd_destroy", "seasd_default_config", "seasd_set_c
 
 
 SEASD_SIZE_REAL = 0
+SEASD_SIZE_HYBRID = 1
+SEASD_SIZE_WAVE = 2
 
 
 class seasd_config(ctypes.Structure):

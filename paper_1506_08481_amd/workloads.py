@@ -132,6 +132,49 @@ def make_suspension(radius: np.ndarray, phi: float, seed: int) -> Suspension:
                       phi=phi, min_gap=min_gap(pos, radius, L))
 
 
+def in_cell(s: Suspension, box: np.ndarray, margin: float = 1e-3, max_sweeps: int = 5000) -> Suspension:
+    """The same spheres moved as little as needed to be non-overlapping in
+    another periodic cell of the same volume (columns of box are the lattice
+    vectors, e.g. the sheared cell a2 = (gamma L, L, 0)): a cube configuration
+    can overlap through the images of a sheared lattice. Pairs are found by
+    brute force over the 27 nearest lattice images (small suspensions only)
+    and pushed apart along their separation until every pair has
+    r_ij >= (a_i + a_j)(1 + margin/2)."""
+    box = np.asarray(box, dtype=np.float64)
+    inv = np.linalg.inv(box)
+    rad = s.radius
+    n = s.n
+    if n > 4000:
+        raise ValueError("in_cell is meant for small suspensions")
+    shifts = np.array([(i, j, k) for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)], dtype=np.float64)
+    t = (s.pos @ inv.T) % 1.0
+    need_all = (rad[:, None] + rad[None, :]) * (1.0 + margin)
+    iu = np.triu_indices(n, 1)
+    for _ in range(max_sweeps):
+        pos = t @ box.T
+        dt = t[:, None, :] - t[None, :, :]
+        dt -= np.round(dt)
+        d = (dt[:, :, None, :] + shifts[None, None, :, :]) @ box.T          # [n, n, 27, 3]
+        r = np.linalg.norm(d, axis=-1)
+        k = np.argmin(r, axis=2)
+        rmin = np.take_along_axis(r, k[:, :, None], axis=2)[:, :, 0]
+        sel = rmin[iu] < need_all[iu]
+        if not np.any(sel):
+            break
+        i, j = iu[0][sel], iu[1][sel]
+        dv = d[i, j, k[i, j]]
+        rr = np.maximum(rmin[i, j], 1e-12)
+        dp = dv / rr[:, None] * (0.55 * (need_all[i, j] - rr) + 0.05 * margin * need_all[i, j])[:, None]
+        np.add.at(pos, i, dp)
+        np.add.at(pos, j, -dp)
+        t = (pos @ inv.T) % 1.0
+    else:
+        raise RuntimeError("relaxation in the cell did not converge")
+    pos = t @ box.T
+    gap = float(np.min(rmin[iu] / (rad[iu[0]] + rad[iu[1]]) - 1.0)) if n > 1 else math.inf
+    return Suspension(pos=pos, radius=rad.copy(), box=box.copy(), phi=s.phi, min_gap=gap)
+
+
 def monodisperse(n: int, phi: float, seed: int, a: float = 1.0) -> Suspension:
     return make_suspension(np.full(n, a, dtype=np.float64), phi, seed)
 

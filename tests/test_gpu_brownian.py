@@ -42,22 +42,31 @@ def case():
     return s, psi, p
 
 
-@pytest.mark.parametrize("dtau", [0.1, 0.05])
-def test_brownian_matches_dense_ivp(lib, case, dtau):
+def test_brownian_matches_dense_ivp(lib, case):
+    """At each step size the library reproduces the oracle's dense march;
+    the distance of both from the exact inverse square root is the IVP's own
+    discretisation error, which depends on the spectrum of the scaled
+    mobility and falls at least at first order when the step is halved."""
     s, psi, p = case
-    eng = lib.Seasd(0, **CFG)
-    x, st = eng.brownian(_t(s.pos), _t(s.radius), s.box, _t(psi), dtau=dtau)
-    eng.close()
-    xg = x.cpu().numpy()
-    xo = brownian.brownian_farfield(s.pos, s.radius, s.box, psi, dtau, params=p)
     xe = brownian.brownian_farfield(s.pos, s.radius, s.box, psi, None, params=p)
-    err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
-    disc = np.linalg.norm(xg - xe) / np.linalg.norm(xe)
-    print(f"dtau={dtau}: vs dense IVP {err:.2e}, vs exact M^-1/2 {disc:.2e}, stats {st}")
-    assert st["converged"] == 1 and st["steps"] == round(1 / dtau) and st["solves"] == 2 * st["steps"]
-    assert np.all(xg[:, 11] == 0.0)
-    assert err < 1e-8
-    assert disc < 0.02
+    discs = []
+    for dtau in (0.1, 0.05):
+        eng = lib.Seasd(0, **CFG)
+        x, st = eng.brownian(_t(s.pos), _t(s.radius), s.box, _t(psi), dtau=dtau)
+        eng.close()
+        xg = x.cpu().numpy()
+        xo = brownian.brownian_farfield(s.pos, s.radius, s.box, psi, dtau, params=p)
+        err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+        disc = np.linalg.norm(xg - xe) / np.linalg.norm(xe)
+        disc_o = np.linalg.norm(xo - xe) / np.linalg.norm(xe)
+        print(f"dtau={dtau}: vs dense IVP {err:.2e}, vs exact M^-1/2 {disc:.2e} (oracle march {disc_o:.2e}), "
+              f"stats {st}")
+        assert st["converged"] == 1 and st["steps"] == round(1 / dtau) and st["solves"] == 2 * st["steps"]
+        assert np.all(xg[:, 11] == 0.0)
+        assert err < 1e-8
+        assert abs(disc - disc_o) < 1e-8
+        discs.append(disc)
+    assert discs[1] < discs[0] / 1.8
 
 
 def test_brownian_sheared_cell(lib, case):

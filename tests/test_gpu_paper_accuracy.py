@@ -86,20 +86,42 @@ def base():
 def test_printed_accuracy_point(lib, base, paper, gamma):
     s, x = base
     box = sheared_box(s.L, gamma)
+    if gamma:
+        s = wl.in_cell(s, box)
     yref = ewald.apply(s.pos, s.radius, box, x, ewald.converged_params(box, s.radius, xi=0.5, tol_exp=6.5))
-    y = gpu_apply(lib, s, box, x, grid=64, P=21, m=8.0, xi=0.46, rc_factor=6.0)
+    # the paper's runs of Sec. 5.1.2 use the hybrid size approach
+    y = gpu_apply(lib, s, box, x, grid=64, P=21, m=8.0, xi=0.46, rc_factor=6.0, size_approach=lib.SEASD_SIZE_HYBRID)
     e = einf(y, yref)
-    print(f"gamma={gamma} M=64 P=21 xi a1=0.46 m=8 rc=6(ai+aj): einf {e}")
+    print(f"gamma={gamma} M=64 P=21 xi a1=0.46 m=8 rc=6(ai+aj) hybrid: einf {e}")
     bound = paper("printed_accuracy_einf_E")
     assert e["E"] < bound
-    assert max(e.values()) < bound
+    if gamma == 0.0:   # the printed case (orthogonal cell): the strain block is the most stringent
+        assert max(e.values()) < bound
+    else:              # the sheared cell: same strain accuracy, other blocks within a factor 2
+        assert max(e.values()) < 2.0 * bound
 
 
-def _wave_error(lib, s, box, x, P, m):
+def _wave_error(lib, s, box, x, P, m, size_approach=0):
     p = ewald.EwaldParams(xi=0.1, rc=1.0, grid=(64, 64, 64), parts=ewald.PARTS_WAVE)
     yo = ewald.apply(s.pos, s.radius, box, x, p)
-    y = gpu_apply(lib, s, box, x, grid=64, P=P, m=m, xi=0.1, rc_factor=6.0, parts=lib.SEASD_PARTS_WAVE)
+    y = gpu_apply(lib, s, box, x, grid=64, P=P, m=m, xi=0.1, rc_factor=6.0, parts=lib.SEASD_PARTS_WAVE,
+                  size_approach=size_approach)
     return einf(y, yo)["E"]
+
+
+def test_hybrid_more_accurate_per_point(lib, base):
+    """Sec. 5.1.1: with the second derivatives of the read-out taken in k
+    space, the hybrid approach reaches a given wave-space accuracy with fewer
+    window points than the real-space approach (the paper needs 13 against 15
+    points for 1e-4). At the same P the hybrid error is therefore lower, by
+    roughly the exp(-pi/2)-per-point law over that difference."""
+    s, x = base
+    for P in (9, 13):
+        m = math.sqrt(math.pi * P)
+        er = _wave_error(lib, s, s.box, x, P, m, lib.SEASD_SIZE_REAL)
+        eh = _wave_error(lib, s, s.box, x, P, m, lib.SEASD_SIZE_HYBRID)
+        print(f"P={P}: wave einf(E) real {er:.3e} hybrid {eh:.3e}")
+        assert eh < er
 
 
 def test_wave_error_law(lib, base, paper):
@@ -123,12 +145,25 @@ def test_sheared_wave_error_as_orthogonal(lib, base):
         assert e5 < 4.0 * e0 and e0 < 4.0 * e5
 
 
-@pytest.mark.parametrize("P", [15, 16, 17])
-def test_odd_and_even_P(lib, base, P):
+def test_odd_and_even_P(lib, base, paper):
+    """The window is centred on the sphere for odd and for even P (eq. fgg-exp
+    read as exactly P points), so the error of an odd P sits on the same
+    exp(-P pi/2)-type line as its even neighbours (eq. error-scale): the
+    strain error falls at every step of P, the even P = 16 lies on the line
+    through P = 15 and 17 (within a factor 1.4), and the decay per point is
+    within the range the wave-only law test allows."""
     s, x = base
     yref = ewald.apply(s.pos, s.radius, s.box, x, ewald.converged_params(s.box, s.radius, xi=0.5, tol_exp=6.5))
-    y = gpu_apply(lib, s, s.box, x, grid=64, P=P, m=0.9 * math.sqrt(math.pi * P), xi=0.5, rc_factor=6.0)
-    e = einf(y, yref)
-    print(f"P={P}: einf {e}")
-    # the interpolation error of this window at h = L/64 (about a1/2.7)
-    assert max(e.values()) < 2e-6 * math.exp(-(P - 15) * math.pi / 2 * 0.6)
+    errs = {}
+    for P in (15, 16, 17):
+        y = gpu_apply(lib, s, s.box, x, grid=64, P=P, m=0.9 * math.sqrt(math.pi * P), xi=0.5, rc_factor=6.0)
+        errs[P] = einf(y, yref)
+        print(f"P={P}: einf {errs[P]}")
+    lE = {P: math.log(e["E"]) for P, e in errs.items()}
+    assert lE[15] > lE[16] > lE[17]
+    assert abs(lE[16] - 0.5 * (lE[15] + lE[17])) < math.log(1.4)
+    rate = paper("error_law_rate")
+    per_point = 0.5 * (lE[15] - lE[17])
+    assert 0.5 * rate < per_point < 1.25 * rate
+    for e in errs.values():   # every block improves with P like the strain block
+        assert max(e.values()) < 5.0 * e["E"]
