@@ -80,6 +80,8 @@ extern "C" {
 #define SEASD_E_NOMEM          -7   /* workspace allocation failed              */
 #define SEASD_E_UNSUPPORTED    -8   /* valid request this build does not handle */
 #define SEASD_E_FORMAT         -9   /* weights file missing, wrong or corrupt   */
+#define SEASD_E_SCRATCH       -10   /* input too large for the static workspace */
+                                    /* of seasd_mobility_apply_static           */
 #define SEASD_W_NOT_CONVERGED   1   /* solve stopped at max_iter above tol      */
 #define SEASD_W_PRECOND_FALLBACK 2  /* learned preconditioner rejected; the     */
                                     /* block-diagonal one was used instead      */
@@ -180,6 +182,31 @@ int seasd_set_config(seasd_handle handle, const seasd_config* cfg);
 int seasd_mobility_apply(seasd_handle handle, int64_t n,
                          const double* pos, const double* radius, const double* box,
                          const double* x, double* y, void* stream);
+
+/* Allocation-free variant of seasd_mobility_apply, for callers that cannot
+ * allocate device memory: code recorded under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc. Same arguments, result and
+ * kernels as seasd_mobility_apply with the handle's configuration, but every
+ * workspace buffer (binned copies, neighbour list, window records, grids,
+ * spectra, twiddles, counters) is carved from one static device array of
+ * SEASD_STATIC_SCRATCH_BYTES per GPU, held until the process ends; the call
+ * makes no hipMalloc, hipFree or other allocating call. The neighbour list
+ * takes whatever the fixed buffers leave (at most 4096 slots per sphere).
+ * The call synchronises `stream` once, after queuing the pair sum and the
+ * spreading/FFT work, to check that every neighbour list fitted.
+ * Limits: about 1.2 kB per sphere (FP64, P = 32) plus the list, and
+ * 32 M^3 bytes of grids in FP64 (64 M^3 with the hybrid size approach):
+ * e.g. n = 16384 spheres on a 64^3 grid fit with room for 700-entry lists.
+ * Returns SEASD_E_SCRATCH, before queuing any work, when the fixed buffers do
+ * not fit, and after the product's first half when a neighbour list would
+ * overflow the remaining room (y is then not written); otherwise the codes of
+ * seasd_mobility_apply. Every call on one GPU shares that GPU's array, which
+ * keeps the last call's contents (each call clears what must start at zero):
+ * calls that overlap in time on one GPU, through any handles, race. */
+#define SEASD_STATIC_SCRATCH_BYTES (128u << 20)
+int seasd_mobility_apply_static(seasd_handle handle, int64_t n,
+                                const double* pos, const double* radius, const double* box,
+                                const double* x, double* y, void* stream);
 
 /* Far-field solve (Sec. 4.1, eq. HI-ff with no near-field resistance) by
  * right-preconditioned restarted GMRES in FP64 on the device, with the

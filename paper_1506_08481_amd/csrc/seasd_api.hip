@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/seasd.h"
@@ -26,6 +27,7 @@ struct seasd_handle_s {
     DevBuf ncount, nstats, list, total, wrec, scan_tmp;
     int cap = 64;             // neighbour-list slots per sphere, grown on demand
     int pair_group = 1;       // lanes per sphere of the pair sum chosen for the held geometry
+    int static_pair_group = 1;   // the same choice for the allocation-free product
     int64_t geom_n = -1;      // spheres in the geometry currently held in the workspace
     int twiddle_M = 0;
     // solver workspace
@@ -60,6 +62,7 @@ extern "C" const char* seasd_error_string(int32_t code) {
         case SEASD_E_HIP: return "HIP runtime error";
         case SEASD_E_NOMEM: return "device allocation failed";
         case SEASD_E_UNSUPPORTED: return "unsupported request (cell shape, unequal grids or size approach)";
+        case SEASD_E_SCRATCH: return "request exceeds the static workspace of the allocation-free product";
         case SEASD_E_FORMAT: return "weights file missing, mismatched or failing its checksum";
         case SEASD_W_NOT_CONVERGED: return "solve did not reach the tolerance";
         case SEASD_W_PRECOND_FALLBACK: return "learned preconditioner rejected, block-diagonal used";
@@ -88,6 +91,30 @@ extern "C" int seasd_default_config(seasd_config* c) {
     return SEASD_OK;
 }
 
+// Workspace of the allocation-free product (seasd_mobility_apply_static):
+// one array per GPU, held until the process ends. Host code never uses the
+// array's name as an address: its device address is looked up once per device
+// (hipGetSymbolAddress, with that device current) when a handle is created
+// there, and kept here.
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[SEASD_STATIC_SCRATCH_BYTES];
+static void* g_scratch_ptr[kMaxDevices] = {nullptr};
+static std::mutex g_scratch_mu;
+
+static int static_scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return SEASD_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return SEASD_OK;
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(device) != hipSuccess) return SEASD_E_HIP;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    hipSetDevice(prev);
+    if (e != hipSuccess || !p) return SEASD_E_HIP;
+    g_scratch_ptr[device] = p;
+    return SEASD_OK;
+}
+
 extern "C" int seasd_create(seasd_handle* out, int32_t device) {
     if (!out) return SEASD_E_INVALID_ARG;
     *out = nullptr;
@@ -96,6 +123,7 @@ extern "C" int seasd_create(seasd_handle* out, int32_t device) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return SEASD_E_HIP;
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return SEASD_E_HIP;
+    if (int rc = static_scratch_setup(device)) return rc;
     auto* h = new seasd_handle_s();
     h->device = device;
     seasd_default_config(&h->cfg);
@@ -396,6 +424,106 @@ extern "C" int seasd_mobility_apply(seasd_handle h, int64_t n, const double* pos
     rc = queue_apply(h, n, pos, radius, L, x, y, st, h->cfg.checks != 0);
     if (rc) return rc;
     if (h->cfg.checks) return read_err(h, st);
+    return SEASD_OK;
+}
+
+// Bump allocation of 256-byte aligned pieces from the static workspace.
+struct ScratchCarve {
+    char* base;
+    size_t off, cap;
+    bool ok = true;
+    template <typename T>
+    T* take(size_t count) {
+        const size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
+        if (off + bytes > cap) {
+            ok = false;
+            return nullptr;
+        }
+        T* p = reinterpret_cast<T*>(base + off);
+        off += bytes;
+        return p;
+    }
+};
+
+extern "C" int seasd_mobility_apply_static(seasd_handle h, int64_t n, const double* pos, const double* radius,
+                                           const double* box, const double* x, double* y, void* stream) {
+    if (!h || n < 1 || n > (int64_t)1 << 28 || !pos || !radius || !x || !y) return SEASD_E_INVALID_ARG;
+    if (x == y) return SEASD_E_INVALID_ARG;
+    Cell L;
+    int rc = parse_cell(box, &L);
+    if (rc) return rc;
+    if (h->device < 0 || h->device >= kMaxDevices || !g_scratch_ptr[h->device]) return SEASD_E_HIP;
+    if (hipSetDevice(h->device) != hipSuccess) return SEASD_E_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    const seasd_config& c = h->cfg;
+    const int M = c.grid[0];
+    const int nb = M / 8;
+    const size_t nbins = (size_t)nb * nb * nb;
+    const size_t R = c.precision == SEASD_FP32 ? 4 : 8;
+    const bool wave = (c.parts & SEASD_PARTS_WAVE) != 0;
+    const bool hyb = wave && c.size_approach == SEASD_SIZE_HYBRID;
+    const size_t g = wave ? R * 4 * (size_t)M * M * M : R * 4;
+
+    // every piece of the product workspace, in the order ensure_product_ws lists them
+    ScratchCarve cv{static_cast<char*>(g_scratch_ptr[h->device]), 0, (size_t)SEASD_STATIC_SCRATCH_BYTES};
+    ApplyArgs A;
+    fill_args(h, A, n, pos, radius, L, x, y, c.checks != 0, c.compressible);
+    A.bin_of = cv.take<int>(n);
+    A.counts = cv.take<int>(nbins);
+    A.start = cv.take<int>(nbins + 1);
+    A.fill = cv.take<int>(nbins);
+    A.perm = cv.take<int>(n);
+    A.amax_bits = cv.take<unsigned long long>(1);
+    A.err = cv.take<int>(1);
+    A.sp = cv.take<double>(3 * n);
+    A.st = cv.take<double>(3 * n);
+    A.sa = cv.take<double>(n);
+    A.sx = cv.take<double>(12 * n);
+    A.ybuf = cv.take<double>(12 * n);
+    A.ncount = cv.take<int>(n);
+    A.nstats = cv.take<unsigned long long>(2);
+    A.scan_tmp = cv.take<int>((std::max<size_t>((size_t)n, nbins) + 2047) / 2048 + 2);
+    A.wrec = cv.take<char>(R * rec_stride(c.P) * n);
+    A.rgrid = cv.take<char>(g);
+    A.spec = wave ? cv.take<char>(g) : nullptr;
+    A.rgrid2 = hyb ? cv.take<char>(g) : nullptr;
+    A.spec2 = hyb ? cv.take<char>(g) : nullptr;
+    double* tw = cv.take<double>(2 * (size_t)M);
+    A.twiddle = tw;
+    if (!cv.ok) return SEASD_E_SCRATCH;
+    // the neighbour list takes the rest
+    const size_t room = (cv.cap - cv.off) / (sizeof(int2) * (size_t)n);
+    A.cap = (int)std::min<size_t>(room, 4096);
+    if (A.cap < 1) return SEASD_E_SCRATCH;
+    A.list = cv.take<int2>((size_t)A.cap * n);
+    if (!cv.ok) return SEASD_E_SCRATCH;
+    A.pair_group = h->static_pair_group;
+
+    PhaseTimer off;
+    if (launch_twiddles(M, tw, st)) return SEASD_E_HIP;
+    if (launch_clear_ints(1, A.err, st)) return SEASD_E_HIP;
+    if (launch_geometry(A, st, &off)) return SEASD_E_HIP;
+    if (launch_pairlist(A, st)) return SEASD_E_HIP;
+    unsigned long long ns[2] = {0, 0};
+    const bool real = (A.parts & kPartsReal) != 0;
+    if (real && hipMemcpyAsync(ns, A.nstats, sizeof(ns), hipMemcpyDeviceToHost, st) != hipSuccess) return SEASD_E_HIP;
+    if (launch_pair(A, st, &off) || launch_wave(A, st, &off)) return SEASD_E_HIP;
+    if (real) {
+        if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
+        if (ns[0] > (unsigned long long)A.cap) return SEASD_E_SCRATCH;
+        // lanes per sphere of the pair sum for the next call (speed only)
+        h->static_pair_group = ((double)ns[0] > kPairImbalance * (double)ns[1] / (double)n) ? 64 : 1;
+    }
+    if (launch_gather(A, st, &off)) return SEASD_E_HIP;
+    if (c.checks) {
+        int e = 0;
+        if (hipMemcpyAsync(&e, A.err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return SEASD_E_HIP;
+        if (e & kErrNonfinite) return SEASD_E_NONFINITE;
+        if (e & kErrOverlap) return SEASD_E_OVERLAP;
+        if (e & kErrCutoff) return SEASD_E_CUTOFF;
+    }
     return SEASD_OK;
 }
 

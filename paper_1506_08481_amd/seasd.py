@@ -28,6 +28,7 @@ SEASD_E_HIP = -6
 SEASD_E_NOMEM = -7
 SEASD_E_UNSUPPORTED = -8
 SEASD_E_FORMAT = -9
+SEASD_E_SCRATCH = -10
 SEASD_W_NOT_CONVERGED = 1
 SEASD_W_PRECOND_FALLBACK = 2
 
@@ -40,7 +41,7 @@ PHASES = ("bin", "pair", "window", "spread", "fft_x_fwd", "fft_y_fwd", "fft_z_sc
 
 # exported symbols of include/seasd.h
 SYMBOLS = ("seasd_create", "seasd_destroy", "seasd_default_config", "seasd_set_config",
-           "seasd_mobility_apply", "seasd_solve_farfield", "seasd_brownian_farfield", "seasd_profile_enable",
+           "seasd_mobility_apply", "seasd_mobility_apply_static", "seasd_solve_farfield", "seasd_brownian_farfield", "seasd_profile_enable",
            "seasd_profile_read", "seasd_error_string", "seasd_autotune", "seasd_batch_create",
            "seasd_batch_apply", "seasd_batch_configs", "seasd_batch_destroy",
            "seasd_mobility_apply_batched", "seasd_net_create", "seasd_net_destroy", "seasd_net_param_count",
@@ -142,6 +143,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.seasd_default_config.argtypes = [ctypes.POINTER(seasd_config)]
     lib.seasd_set_config.argtypes = [vp, ctypes.POINTER(seasd_config)]
     lib.seasd_mobility_apply.argtypes = [vp, i64, dp, dp, ctypes.POINTER(ctypes.c_double), dp, dp, vp]
+    lib.seasd_mobility_apply_static.argtypes = [vp, i64, dp, dp, ctypes.POINTER(ctypes.c_double), dp, dp, vp]
     lib.seasd_solve_farfield.argtypes = [vp, i64, dp, dp, ctypes.POINTER(ctypes.c_double), dp, dp,
                                          ctypes.POINTER(seasd_solve_stats), vp]
     lib.seasd_brownian_farfield.argtypes = [vp, i64, dp, dp, ctypes.POINTER(ctypes.c_double), dp, dp,
@@ -286,6 +288,23 @@ class Seasd:
         return y
 
     apply = seasd_mobility_apply
+
+    def seasd_mobility_apply_static(self, pos, radius, box, x, y=None, stream=None):
+        """The allocation-free product (workspace in the library's static
+        device array; y must be supplied by a caller that cannot allocate)."""
+        import torch
+        n = _require_sphere_arrays(pos, radius, self.device)
+        _require(x, (n, 12), "x", self.device)
+        if y is None:
+            y = torch.empty((n, 12), dtype=torch.float64, device=pos.device)
+        _require(y, (n, 12), "y", self.device)
+        if y.data_ptr() == x.data_ptr():
+            raise ValueError("y may not alias x")
+        _check(lib().seasd_mobility_apply_static(self.h, n, pos.data_ptr(), radius.data_ptr(), _box9(box),
+                                                 x.data_ptr(), y.data_ptr(), ctypes.c_void_p(_stream_ptr(stream))))
+        return y
+
+    apply_static = seasd_mobility_apply_static
 
     def seasd_solve_farfield(self, pos, radius, box, b, x0=None, stream=None):
         import torch
