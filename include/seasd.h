@@ -97,8 +97,8 @@ extern "C" {
 
 #define SEASD_PRECOND_NONE      0
 #define SEASD_PRECOND_BLOCKDIAG 1   /* per-sphere inverse of the self block (Sec. 4.2) */
-#define SEASD_PRECOND_LEARNED   2   /* block-diagonal one rescaled by the attached     */
-                                    /* network, plus its initial guess (see below)     */
+/* 2 is not accepted: per-sphere rescalings S B S of the blocks by the        */
+/* network were measured to slow GMRES down (more iterations than the blocks) */
 #define SEASD_PRECOND_LEARNED_GUESS 3 /* block-diagonal blocks, the network's guess   */
 
 #define SEASD_SIZE_REAL   0 /* Faxen operators applied to the window on both  */
@@ -140,12 +140,13 @@ typedef struct seasd_solve_stats {
     int32_t matvecs;         /* all products with M, true-residual checks included  */
     int32_t converged;       /* 1 if the true residual met tol                      */
     double  true_residual;   /* ||b - M x|| / ||b|| from a fresh product at exit     */
-    double  setup_ms;        /* preconditioner construction                          */
+    double  setup_ms;        /* block-diagonal preconditioner construction           */
     double  solve_ms;        /* total wall time of the call                          */
     int32_t precond_used;    /* SEASD_PRECOND_* actually applied                     */
     int32_t guess_used;      /* 1 if the learned initial guess was kept              */
     double  initial_residual;/* ||b' - A x0|| / ||b'|| of the starting iterate       */
     double  guess_scale;     /* alpha applied to the learned guess (0: dropped)      */
+    double  learned_ms;      /* learned guess: graph, network, scaling product       */
 } seasd_solve_stats;
 
 typedef struct seasd_handle_s* seasd_handle;
@@ -395,12 +396,11 @@ int seasd_net_loss_grad(seasd_handle handle, seasd_net net, int64_t n, const dou
 int seasd_net_train_step(seasd_handle handle, seasd_net net, int64_t n, const double* pos, const double* radius,
                          const double* box, int32_t nrhs, const double* b, float lr, double* loss, void* stream);
 
-/* Attach a network for solves with precond = SEASD_PRECOND_LEARNED or
- * SEASD_PRECOND_LEARNED_GUESS (NULL detaches; the handle does not own it).
- * Such a solve builds the graph, runs the network once and starts GMRES from
- * the network's x0 (overwriting the caller's guess); with
- * SEASD_PRECOND_LEARNED it also replaces the block-diagonal blocks by S B S,
- * with SEASD_PRECOND_LEARNED_GUESS it keeps them. It falls
+/* Attach a network for solves with precond = SEASD_PRECOND_LEARNED_GUESS
+ * (NULL detaches; the handle does not own it). Such a solve builds the
+ * graph, runs the network once and starts GMRES from the network's x0
+ * (overwriting the caller's guess), preconditioned by the block-diagonal
+ * blocks. It falls
  * back to the block-diagonal blocks and a zero guess, and returns
  * SEASD_W_PRECOND_FALLBACK if the solve otherwise converged, when an output
  * is non-finite or a scaling is beyond e^8. The true residual judges the

@@ -165,7 +165,9 @@ extern "C" int seasd_set_config(seasd_handle h, const seasd_config* c) {
     if (c->parts < 0 || c->parts > SEASD_PARTS_ALL) return SEASD_E_INVALID_ARG;
     if (c->restart < 1 || c->restart > 200 || c->max_iter < 1) return SEASD_E_INVALID_ARG;
     if (!(c->tol > 0.0)) return SEASD_E_INVALID_ARG;
-    if (c->precond < SEASD_PRECOND_NONE || c->precond > SEASD_PRECOND_LEARNED_GUESS) return SEASD_E_INVALID_ARG;
+    if (c->precond != SEASD_PRECOND_NONE && c->precond != SEASD_PRECOND_BLOCKDIAG &&
+        c->precond != SEASD_PRECOND_LEARNED_GUESS)
+        return SEASD_E_INVALID_ARG;
     if (c->size_approach < 0 || c->size_approach > 2) return SEASD_E_INVALID_ARG;
     // valid requests this build does not carry out: unequal grids and the
     // wave-space size approach
@@ -741,7 +743,7 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
     double* u = h->u.as<double>();
     double* bred = h->bred.as<double>();
     const bool pc = c.precond != SEASD_PRECOND_NONE;
-    const bool learned = c.precond == SEASD_PRECOND_LEARNED || c.precond == SEASD_PRECOND_LEARNED_GUESS;
+    const bool learned = c.precond == SEASD_PRECOND_LEARNED_GUESS;
     if (learned && !h->net) return SEASD_E_INVALID_ARG;
     if (pc) {  // before the geometry: its single-sphere products use the shared workspace
         rc = build_preconditioner(h, n, radius, L, st);
@@ -790,7 +792,8 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
     if (launch_trace_op(n, 1, radius, c.eta, x, nullptr, z, st) ||
         hipMemcpyAsync(x, z, sizeof(double) * len, hipMemcpyDeviceToDevice, st) != hipSuccess)
         return SEASD_E_HIP;
-    // learned preconditioner: rescaled blocks and the network's initial guess
+    // learned preconditioner: the network's initial guess (its outputs also
+    // pass the finiteness and range checks of the rescaled blocks)
     int fallback = 0, guess = 0;
     if (learned) {
         auto tl = std::chrono::steady_clock::now();
@@ -799,7 +802,6 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
         if (fallback) {
             if (hipMemsetAsync(x, 0, sizeof(double) * len, st) != hipSuccess) return SEASD_E_HIP;
         } else {
-            if (c.precond == SEASD_PRECOND_LEARNED) pc_blocks = h->inv2.as<double>();
             guess = 1;
             // the true residual judges the guess: scale it by the alpha that
             // minimises |b' - alpha A x0|, dropping it when alpha <= 0
@@ -815,7 +817,8 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
                 return SEASD_E_HIP;
             S.guess_scale = alpha;
         }
-        S.setup_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tl).count();
+        if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
+        S.learned_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tl).count();
     }
     GmresResult G;
     rc = h->gm.solve(apply11, precond, bred, x, c.tol, c.max_iter, st, &G);

@@ -34,7 +34,7 @@ SEASD_W_PRECOND_FALLBACK = 2
 
 SEASD_FP64, SEASD_FP32 = 0, 1
 SEASD_PARTS_REAL, SEASD_PARTS_WAVE, SEASD_PARTS_SELF, SEASD_PARTS_ALL = 1, 2, 4, 7
-SEASD_PRECOND_NONE, SEASD_PRECOND_BLOCKDIAG, SEASD_PRECOND_LEARNED, SEASD_PRECOND_LEARNED_GUESS = 0, 1, 2, 3
+SEASD_PRECOND_NONE, SEASD_PRECOND_BLOCKDIAG, SEASD_PRECOND_LEARNED_GUESS = 0, 1, 3
 
 PHASES = ("bin", "pair", "window", "spread", "fft_x_fwd", "fft_y_fwd", "fft_z_scale", "fft_y_inv", "fft_x_inv",
           "gather")
@@ -105,6 +105,7 @@ class seasd_solve_stats(ctypes.Structure):
         ("guess_used", ctypes.c_int32),
         ("initial_residual", ctypes.c_double),
         ("guess_scale", ctypes.c_double),
+        ("learned_ms", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -342,7 +343,7 @@ class Seasd:
     brownian = seasd_brownian_farfield
 
     def seasd_precond_attach(self, net):
-        """Use `net` for solves with precond=SEASD_PRECOND_LEARNED (None detaches)."""
+        """Use `net` for solves with precond=SEASD_PRECOND_LEARNED_GUESS (None detaches)."""
         _check(lib().seasd_precond_attach(self.h, net.h if net is not None else None))
         self._net = net   # keep it alive while attached
 

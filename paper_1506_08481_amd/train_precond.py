@@ -126,8 +126,8 @@ def _make_star(args):
 
 def evaluate(net, s, tol: float = 1e-6, precision=None, seed: int = 5, repeats: int = 1):
     """Far-field solves of one suspension with the block-diagonal
-    preconditioner, the learned guess, and the learned guess with rescaled
-    blocks; returns the stats of each (last repeat) and the solve wall time."""
+    preconditioner and with the learned guess (same blocks); returns the stats
+    of each (last repeat) and the solve wall time."""
     import torch
 
     from . import seasd
@@ -144,8 +144,7 @@ def evaluate(net, s, tol: float = 1e-6, precision=None, seed: int = 5, repeats: 
     out = {}
     xs = {}
     for name, pc in (("blockdiag", seasd.SEASD_PRECOND_BLOCKDIAG),
-                     ("learned_guess", seasd.SEASD_PRECOND_LEARNED_GUESS),
-                     ("learned", seasd.SEASD_PRECOND_LEARNED)):
+                     ("learned_guess", seasd.SEASD_PRECOND_LEARNED_GUESS)):
         eng = seasd.Seasd(0, **{f: getattr(cfg, f) for f in ("grid", "P", "m", "xi", "rc_factor")},
                           precision=precision, tol=tol, restart=50, max_iter=3000, precond=pc, checks=0)
         if pc != seasd.SEASD_PRECOND_BLOCKDIAG:

@@ -199,6 +199,16 @@ def lognormal(n: int, phi: float, seed: int, median: float = 1.0, sigma: float =
     return make_suspension(rad, phi, seed)
 
 
+def batch_member(k: int, seed: int = 4000) -> Suspension:
+    """Member k of the many-suspension workload: N log-uniform in [500, 8000],
+    phi uniform in [0.1, 0.45], lognormal radii (median 1, sigma 0.2), each in
+    its own cube."""
+    rng = np.random.default_rng(seed + k)
+    n = int(np.exp(rng.uniform(np.log(500), np.log(8000))))
+    phi = float(rng.uniform(0.1, 0.45))
+    return lognormal(n, phi, seed + 1000 + k)
+
+
 def force_moments(n: int, seed: int, columns: int | None = None) -> np.ndarray:
     """x (or b) with 12 components per particle, i.i.d. N(0, 1), float64.
     Drawn from a stream independent of the placement stream."""

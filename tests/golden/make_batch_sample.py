@@ -1,0 +1,57 @@
+"""Write the FP64 oracle's y = M x at sampled spheres of three members of the
+many-suspension workload (workloads.batch_member, the benchmark's own
+generator): members 111 (N = 1780, phi = 0.38), 78 (N = 7632, phi = 0.32) and
+104 (N = 4540, phi = 0.12), which the autotuner puts on 32^3, 64^3 and 128^3
+grids for a 1e-6 target. Every sphere is a source; the oracle evaluates the
+sum at 64 targets per member. Calls only oracle/ and the seeded input
+generators.
+
+Oracle settings: both Gaussian tails cut at exp(-25) (tol_exp = 5); xi =
+5 / (0.45 L) keeps the real-space cut-off below L/2 (one image per pair).
+Run: python tests/golden/make_batch_sample.py  (about a minute on 8 cores)
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import ewald  # noqa: E402
+from paper_1506_08481_amd import workloads as wl  # noqa: E402
+
+MEMBERS = (111, 78, 104)
+X_SEED, NSAMPLE = 4100, 64
+
+
+def member_inputs(k):
+    s = wl.batch_member(k)
+    x = wl.force_moments(s.n, X_SEED + k)
+    return s, x
+
+
+def targets(n, k):
+    return np.sort(np.random.Generator(np.random.PCG64(77 + k)).choice(n, NSAMPLE, replace=False))
+
+
+def main():
+    out = {}
+    for k in MEMBERS:
+        t0 = time.time()
+        s, x = member_inputs(k)
+        tg = targets(s.n, k)
+        xi = 5.0 / (0.45 * s.L)
+        p = ewald.converged_params(s.box, s.radius, xi=xi, tol_exp=5.0)
+        y = ewald.apply(s.pos, s.radius, s.box, x, p, targets=tg)
+        out[f"targets_{k}"] = tg
+        out[f"y_{k}"] = y
+        out[f"pos_checksum_{k}"] = np.array([s.pos.sum(), (s.pos ** 2).sum()])
+        out[f"x_checksum_{k}"] = np.array([x.sum(), (x ** 2).sum()])
+        print(f"member {k}: N={s.n} L={s.L:.2f} xi={xi:.3f} {time.time() - t0:.0f}s", flush=True)
+    np.savez(os.path.join(HERE, "batch_oracle_sample.npz"), members=np.array(MEMBERS), **out)
+
+
+if __name__ == "__main__":
+    main()

@@ -87,3 +87,41 @@ def test_batch_autotuned_accuracy(lib, systems):
         assert err < 2e-6
     plan.close()
     eng.close()
+
+
+def test_batch_members_against_oracle(lib):
+    """Three members of the benchmark's own many-suspension generator
+    (workloads.batch_member; N = 1780, 7632 and 4540) that the autotuner puts
+    on 32^3, 64^3 and 128^3 grids for a 1e-6 target, in one batched plan: each
+    member's result at 64 sampled spheres against the FP64 oracle
+    (tests/golden/batch_oracle_sample.npz, written by
+    tests/golden/make_batch_sample.py from the oracle alone)."""
+    import os
+    import sys
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, os.path.join(here, "golden"))
+    import make_batch_sample as mk
+    d = np.load(os.path.join(here, "golden", "batch_oracle_sample.npz"))
+    sus, xs = [], []
+    for k in mk.MEMBERS:
+        s, x = mk.member_inputs(k)
+        np.testing.assert_allclose([s.pos.sum(), (s.pos ** 2).sum()], d[f"pos_checksum_{k}"], rtol=1e-12)
+        np.testing.assert_allclose([x.sum(), (x ** 2).sum()], d[f"x_checksum_{k}"], rtol=1e-12)
+        sus.append(s)
+        xs.append(x)
+    offs = np.concatenate([[0], np.cumsum([s.n for s in sus])])
+    eng = lib.Seasd(0, precision=lib.SEASD_FP32)
+    plan = lib.Batch(eng, offs, _t(np.concatenate([s.pos for s in sus])),
+                     _t(np.concatenate([s.radius for s in sus])), [s.box for s in sus], target=1e-6)
+    grids = [c.grid[0] for c in plan.configs()]
+    assert grids == [32, 64, 128]
+    y = plan.apply(_t(np.concatenate(xs))).cpu().numpy()
+    plan.close()
+    eng.close()
+    for j, k in enumerate(mk.MEMBERS):
+        tg, yo = d[f"targets_{k}"], d[f"y_{k}"]
+        yk = y[offs[j]:offs[j + 1]][tg]
+        err = float(np.linalg.norm(yk - yo) / np.linalg.norm(yo))
+        print(f"member {k}: N={sus[j].n} grid {grids[j]}^3 sample error {err:.3e}")
+        assert np.all(np.isfinite(yk))
+        assert err < 1e-6

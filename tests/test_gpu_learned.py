@@ -163,7 +163,7 @@ def test_training_lowers_loss_and_learned_solve_converges(lib, case):
     assert losses[-1] < 0.7 * losses[0] and held < 0.7 * losses[0]
     eng.close()
     x_bd, st_bd = _solve(lib, s, b[0], lib.SEASD_PRECOND_BLOCKDIAG)
-    for mode in (lib.SEASD_PRECOND_LEARNED_GUESS, lib.SEASD_PRECOND_LEARNED):
+    for mode in (lib.SEASD_PRECOND_LEARNED_GUESS,):
         x_l, st_l = _solve(lib, s, b[0], mode, net)
         print("block-diagonal", st_bd)
         print("learned mode", mode, st_l)
@@ -183,7 +183,7 @@ def test_rejected_network_falls_back_to_block_diagonal(lib, case):
     p[:] = np.nan
     net.set_params(p)
     x_bd, st_bd = _solve(lib, s, bb, lib.SEASD_PRECOND_BLOCKDIAG)
-    x_l, st_l = _solve(lib, s, bb, lib.SEASD_PRECOND_LEARNED, net)
+    x_l, st_l = _solve(lib, s, bb, lib.SEASD_PRECOND_LEARNED_GUESS, net)
     print(st_l)
     assert st_l["code"] == lib.SEASD_W_PRECOND_FALLBACK
     assert st_l["precond_used"] == lib.SEASD_PRECOND_BLOCKDIAG and st_l["guess_used"] == 0
@@ -221,10 +221,10 @@ WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 def test_trained_weights_gain_on_unseen_suspension(lib):
     """The shipped network on a suspension it was not trained on (N = 6000,
     bidisperse 1:2, phi = 0.35, FP64 product): the learned guess starts GMRES
-    well below the zero guess, every mode reaches the tolerance on the true
-    residual, and the guess-only mode takes at most 2 % more iterations than
-    the block-diagonal method (its measured gain at N = 50,000 is a few per
-    cent; at this size it can be none)."""
+    well below the zero guess, both solves reach the tolerance on the true
+    residual, and the learned guess takes fewer GMRES iterations than the
+    block-diagonal method alone (the gain the network brings; a few per cent,
+    see the design notes on why a per-sphere guess cannot reach further)."""
     from paper_1506_08481_amd import train_precond
     s = wl.bidisperse(6000, 0.35, 9191, a1=1.0, a2=2.0)
     eng = lib.Seasd(0)
@@ -232,13 +232,13 @@ def test_trained_weights_gain_on_unseen_suspension(lib):
     net = lib.Net(0)
     net.load(WEIGHTS)
     res = train_precond.evaluate(net, s, tol=1e-6, precision=lib.SEASD_FP64)
-    for k in ("blockdiag", "learned_guess", "learned"):
+    for k in ("blockdiag", "learned_guess"):
         print(k, {q: res[k][q] for q in ("iterations", "matvecs", "initial_residual", "true_residual", "wall_s")})
     bd, lg = res["blockdiag"], res["learned_guess"]
-    assert bd["converged"] == 1 and lg["converged"] == 1 and res["learned"]["converged"] == 1
+    assert bd["converged"] == 1 and lg["converged"] == 1
     print("iterations saved by the learned guess:", bd["iterations"] - lg["iterations"])
     assert lg["guess_used"] == 1 and lg["initial_residual"] < 0.8
-    assert lg["iterations"] <= 1.02 * bd["iterations"]
+    assert lg["iterations"] < bd["iterations"]
     assert lg["rel_diff_vs_blockdiag"] < 1e-4
     net.close()
     eng.close()
