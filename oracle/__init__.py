@@ -15,5 +15,9 @@ Contents:
   mpnn     - the project's learned preconditioner network on top of those
              blocks (not in the paper): forward, loss and backward in FP64,
              with optional bfloat16 rounding of matrix-product operands.
+  brownian - M^(-1/2) by eigendecomposition and by the paper's initial value
+             problem (Sec. 4.3).
+  mixed    - the near-field / far-field solve of Sec. 4.1 for a given
+             near-field resistance: directly and by eqs. HI-solve, fM-comp.
 """
-from . import symbols, ewald, solve, mpnn  # noqa: F401
+from . import symbols, ewald, solve, mpnn, brownian, mixed  # noqa: F401
