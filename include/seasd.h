@@ -147,7 +147,19 @@ typedef struct seasd_solve_stats {
     double  initial_residual;/* ||b' - A x0|| / ||b'|| of the starting iterate       */
     double  guess_scale;     /* alpha applied to the learned guess (0: dropped)      */
     double  learned_ms;      /* learned guess: graph, network, scaling product       */
+    int32_t inner_iterations;/* mixed solve: near-field GMRES iterations, all solves */
 } seasd_solve_stats;
+
+/* Near-field force-velocity resistance for seasd_solve_mixed: a symmetric
+ * positive semi-definite block-sparse matrix of 6x6 blocks (force and torque
+ * against velocity and spin) in compressed block-row form, on the device. */
+typedef struct seasd_bsr6 {
+    int64_t        nnzb;     /* stored blocks                                        */
+    const int32_t* rowptr;   /* [n + 1] device: blocks of block row i are            */
+                             /*   rowptr[i] .. rowptr[i + 1] - 1                     */
+    const int32_t* col;      /* [nnzb] device: block column of each stored block     */
+    const double*  val;      /* [nnzb][6][6] device, row-major                       */
+} seasd_bsr6;
 
 typedef struct seasd_handle_s* seasd_handle;
 
@@ -231,6 +243,38 @@ int seasd_mobility_apply_static(seasd_handle handle, int64_t n,
 int seasd_solve_farfield(seasd_handle handle, int64_t n,
                          const double* pos, const double* radius, const double* box,
                          const double* b, double* x, seasd_solve_stats* stats, void* stream);
+
+/* The near-field / far-field hydrodynamic solve of Sec. 4.1 for a
+ * caller-supplied near-field resistance R (eqs. HI-nf, HI-ff):
+ *   0 = -R U + F + Fp,   [U; -E] = -M [F; S],
+ * with M the force-torque-stresslet block of the grand mobility (the
+ * product of seasd_mobility_apply on components 0..10). Following eqs.
+ * HI-solve and fM-comp, with Rt = R + lambda I and D = diag(Rt^-1, 0), GMRES
+ * solves Mt y = (lambda M - I) D [Fp; 0] + [0; E], Mt = (I - lambda M) D + M,
+ * for y = [F + lambda U; S]; every application of Mt costs one product with M
+ * and one near-field solve with Rt. The near-field solves use GMRES with the
+ * inverses of the diagonal blocks of Rt as preconditioner (the paper's IC0
+ * after reverse Cuthill-McKee ordering is a sequential triangular solve);
+ * the outer preconditioner is the block-diagonal approximation of Sec. 4.2
+ * (eq. rfu-approx: per sphere (I - lambda M_ii) diag(Rt_ii^-1, 0) + M_ii,
+ * M_ii with its own periodic images, inverted in FP64). Pressure moments are
+ * not part of this solve.
+ *   rnf     near-field resistance (device arrays); every block row that has
+ *           no stored diagonal block needs lambda > 0
+ *   lambda  shift, > 0 (the paper suggests 6 pi eta a with a reference radius);
+ *           the solution does not depend on it
+ *   fp      device [n][6] interparticle plus near-field strain forces and torques
+ *   einf    device [n][5] imposed strain, traceless orthonormal basis
+ *   f, s, u device outputs: [n][6] far-field hydrodynamic force and torque,
+ *           [n][5] far-field stresslet, [n][6] velocity and spin
+ * Uses the handle's tol (outer GMRES on the true residual of the shifted
+ * system; the near-field solves use tol/10), restart and max_iter. Synchronises
+ * `stream`. Returns SEASD_W_NOT_CONVERGED when the outer solve stopped above
+ * tol, SEASD_E_SINGULAR for a singular diagonal block of Rt, and the errors
+ * of seasd_mobility_apply. */
+int seasd_solve_mixed(seasd_handle handle, int64_t n, const double* pos, const double* radius, const double* box,
+                      const seasd_bsr6* rnf, double lambda, const double* fp, const double* einf,
+                      double* f, double* s, double* u, seasd_solve_stats* stats, void* stream);
 
 /* Far-field Brownian force moments (Sec. 4.3, eq. br-f-ff): x = M^(-1/2) psi
  * on the 11 incompressible components (force, torque, stresslet), computed

@@ -33,6 +33,11 @@ struct seasd_handle_s {
     // solver workspace
     DevBuf w, z, u, r, bred, hdev, partial, blocks, inv, coef, singular, one_pos, one_rad, one_x, one_y;
     DeviceGmres gm;
+    // near-field / far-field solve: 6N vectors, diagonal-block inverses of
+    // R + lambda I, the near-field GMRES
+    DevBuf mv6, mw6, mp6, mu6, mt6, rinv, mbad;
+    DevBuf ic_rows, ic_lrp, ic_lcol, ic_lval, ic_urp, ic_ucol, ic_uval, ic_linv;   // incomplete factor
+    DeviceGmres gm_near;
     // block-diagonal fit cache: (a_min, a_max, grid, P, m, xi, rc_factor, eta, precision, cell A[9])
     double pc_key[18] = {0};
     bool pc_valid = false;
@@ -140,13 +145,16 @@ extern "C" int seasd_destroy(seasd_handle h) {
                       &h->ncount, &h->nstats, &h->list, &h->total, &h->wrec, &h->scan_tmp,
                       &h->w, &h->z, &h->u, &h->r, &h->bred, &h->hdev, &h->partial, &h->blocks,
                       &h->inv, &h->coef, &h->singular, &h->one_pos, &h->one_rad, &h->one_x, &h->one_y,
-                      &h->inv2, &h->bad, &h->lx0, &h->lg, &h->lb, &h->lax, &h->lres};
+                      &h->inv2, &h->bad, &h->lx0, &h->lg, &h->lb, &h->lax, &h->lres,
+                      &h->mv6, &h->mw6, &h->mp6, &h->mu6, &h->mt6, &h->rinv, &h->mbad, &h->ic_rows,
+                      &h->ic_lrp, &h->ic_lcol, &h->ic_lval, &h->ic_urp, &h->ic_ucol, &h->ic_uval, &h->ic_linv};
     for (DevBuf* b : bufs) b->release();
     if (h->ns_host) hipHostFree(h->ns_host);
     if (h->ev_stats) hipEventDestroy(h->ev_stats);
     if (h->own_net) seasd_net_destroy(h->own_net);
     h->timer.destroy();
     h->gm.release();
+    h->gm_near.release();
     delete h;
     return SEASD_OK;
 }
@@ -852,6 +860,200 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
 // ---------------------------------------------------------------------------
 // far-field Brownian forces: x = M^(-1/2) psi by the initial value problem of
 // Sec. 4.3 (eqs. ivp-1, ivp-forward, ivp-backward)
+
+extern "C" int seasd_solve_mixed(seasd_handle h, int64_t n, const double* pos, const double* radius,
+                                 const double* box, const seasd_bsr6* rnf, double lambda, const double* fp,
+                                 const double* einf, double* f, double* s, double* u, seasd_solve_stats* stats,
+                                 void* stream) {
+    if (!h || n < 1 || n > (int64_t)1 << 26 || !pos || !radius || !rnf || !fp || !einf || !f || !s || !u)
+        return SEASD_E_INVALID_ARG;
+    if (!rnf->rowptr || !rnf->col || !rnf->val || rnf->nnzb < 0 || rnf->nnzb > ((int64_t)1 << 31) - 1)
+        return SEASD_E_INVALID_ARG;
+    if (!(lambda > 0.0) || !std::isfinite(lambda)) return SEASD_E_INVALID_ARG;
+    Cell L;
+    int rc = parse_cell(box, &L);
+    if (rc) return rc;
+    if (hipSetDevice(h->device) != hipSuccess) return SEASD_E_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    const seasd_config c = h->cfg;
+    const int64_t len = 12 * n, len6 = 6 * n;
+    rc = 0;
+    rc |= h->w.ensure(sizeof(double) * len);
+    rc |= h->z.ensure(sizeof(double) * len);
+    rc |= h->u.ensure(sizeof(double) * len);
+    rc |= h->bred.ensure(sizeof(double) * len);
+    rc |= h->inv2.ensure(sizeof(double) * 144 * n);
+    rc |= h->singular.ensure(sizeof(int));
+    rc |= h->mv6.ensure(sizeof(double) * len6);
+    rc |= h->mw6.ensure(sizeof(double) * len6);
+    rc |= h->mp6.ensure(sizeof(double) * len6);
+    rc |= h->mu6.ensure(sizeof(double) * len6);
+    rc |= h->mt6.ensure(sizeof(double) * len6);
+    rc |= h->rinv.ensure(sizeof(double) * 36 * n);
+    rc |= h->mbad.ensure(sizeof(int));
+    if (rc) return SEASD_E_NOMEM;
+    if ((rc = h->gm.ensure(len, c.restart, c.max_iter))) return rc == -7 ? SEASD_E_NOMEM : SEASD_E_HIP;
+    const int near_iter = std::max(100, (int)(6 * n));
+    if ((rc = h->gm_near.ensure(len6, std::min(c.restart, 60), near_iter))) return rc == -7 ? SEASD_E_NOMEM : SEASD_E_HIP;
+    seasd_solve_stats S{};
+    // preconditioner blocks (Sec. 4.2): M_ii with the sphere's own images, the
+    // inverses of the diagonal blocks of R + lambda I, and their combination
+    if ((rc = build_preconditioner(h, n, radius, L, st))) return rc;
+    if (launch_clear_ints(1, h->mbad.as<int>(), st) ||
+        launch_bsr6_diag_inv(n, rnf->rowptr, rnf->col, rnf->val, lambda, h->rinv.as<double>(), h->mbad.as<int>(), st) ||
+        launch_mixed_blocks(n, h->blocks.as<double>(), h->rinv.as<double>(), lambda, h->inv2.as<double>(), st) ||
+        launch_clear_ints(1, h->singular.as<int>(), st) ||
+        launch_block_invert(n, h->inv2.as<double>(), h->inv2.as<double>(), h->singular.as<int>(), st))
+        return SEASD_E_HIP;
+    {
+        int bad = 0, sing = 0;
+        if (hipMemcpyAsync(&bad, h->mbad.p, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(&sing, h->singular.p, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return SEASD_E_HIP;
+        if (bad || sing) return SEASD_E_SINGULAR;
+    }
+    // near-field preconditioner: incomplete block Cholesky factor of Rt in a
+    // multicolour order, factorised on the host, applied on the device
+    BlockIC0Host ic;
+    {
+        std::vector<int32_t> rp_h(n + 1), col_h(rnf->nnzb);
+        std::vector<double> val_h(36 * (size_t)rnf->nnzb);
+        if (hipMemcpy(rp_h.data(), rnf->rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost) != hipSuccess)
+            return SEASD_E_HIP;
+        if (rp_h[0] != 0 || rp_h[n] != rnf->nnzb) return SEASD_E_INVALID_ARG;
+        for (int64_t i = 0; i < n; ++i)
+            if (rp_h[i + 1] < rp_h[i]) return SEASD_E_INVALID_ARG;
+        if (rnf->nnzb > 0 &&
+            (hipMemcpy(col_h.data(), rnf->col, sizeof(int32_t) * rnf->nnzb, hipMemcpyDeviceToHost) != hipSuccess ||
+             hipMemcpy(val_h.data(), rnf->val, sizeof(double) * 36 * rnf->nnzb, hipMemcpyDeviceToHost) != hipSuccess))
+            return SEASD_E_HIP;
+        for (int32_t j : col_h)
+            if (j < 0 || j >= n) return SEASD_E_INVALID_ARG;
+        if (build_block_ic0(n, rp_h, col_h, val_h, lambda, &ic)) return SEASD_E_SINGULAR;
+        auto up = [&](DevBuf& d, const void* src, size_t bytes) -> int {
+            if (d.ensure(std::max<size_t>(bytes, 8))) return SEASD_E_NOMEM;
+            if (bytes && hipMemcpyAsync(d.p, src, bytes, hipMemcpyHostToDevice, st) != hipSuccess) return SEASD_E_HIP;
+            return SEASD_OK;
+        };
+        int e = 0;
+        if ((e = up(h->ic_rows, ic.rows.data(), sizeof(int32_t) * ic.rows.size())) ||
+            (e = up(h->ic_lrp, ic.lrp.data(), sizeof(int32_t) * ic.lrp.size())) ||
+            (e = up(h->ic_lcol, ic.lcol.data(), sizeof(int32_t) * ic.lcol.size())) ||
+            (e = up(h->ic_lval, ic.lval.data(), sizeof(double) * ic.lval.size())) ||
+            (e = up(h->ic_urp, ic.urp.data(), sizeof(int32_t) * ic.urp.size())) ||
+            (e = up(h->ic_ucol, ic.ucol.data(), sizeof(int32_t) * ic.ucol.size())) ||
+            (e = up(h->ic_uval, ic.uval.data(), sizeof(double) * ic.uval.size())) ||
+            (e = up(h->ic_linv, ic.linv.data(), sizeof(double) * ic.linv.size())))
+            return e;
+        if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;   // host vectors leave scope
+    }
+    S.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    double* v6 = h->mv6.as<double>();
+    double* w6 = h->mw6.as<double>();
+    double* p6 = h->mp6.as<double>();
+    double* u6 = h->mu6.as<double>();
+    double* z12 = h->z.as<double>();
+    double* rhs = h->bred.as<double>();
+    double* y12 = h->u.as<double>();
+    const double near_tol = std::max(0.1 * c.tol, 1e-14);
+    bool near_ok = true;
+    // out = (L L^T)^-1 in with the incomplete factor: forward solve colour by
+    // colour into mt6, backward solve in reverse colour order into out
+    double* t6 = h->mt6.as<double>();
+    auto ic_apply = [&](const double* in, double* out) -> int {
+        const int32_t* rows = h->ic_rows.as<int32_t>();
+        for (int c = 0; c < ic.ncolours; ++c) {
+            const int a = ic.colour_start[c], cnt = ic.colour_start[c + 1] - a;
+            if (launch_ic_solve_colour(cnt, rows + a, h->ic_lrp.as<int32_t>(), h->ic_lcol.as<int32_t>(),
+                                       h->ic_lval.as<double>(), h->ic_linv.as<double>(), 0, in, t6, st))
+                return SEASD_E_HIP;
+        }
+        for (int c = ic.ncolours - 1; c >= 0; --c) {
+            const int a = ic.colour_start[c], cnt = ic.colour_start[c + 1] - a;
+            if (launch_ic_solve_colour(cnt, rows + a, h->ic_urp.as<int32_t>(), h->ic_ucol.as<int32_t>(),
+                                       h->ic_uval.as<double>(), h->ic_linv.as<double>(), 1, t6, out, st))
+                return SEASD_E_HIP;
+        }
+        return SEASD_OK;
+    };
+    // w = (R + lambda I)^-1 v on 6N vectors (GMRES with the incomplete factor as preconditioner)
+    auto near_solve = [&](const double* v, double* w) -> int {
+        auto op = [&](const double* in, double* out) -> int {
+            return launch_bsr6_spmv(n, rnf->rowptr, rnf->col, rnf->val, lambda, in, out, st) ? SEASD_E_HIP : SEASD_OK;
+        };
+        int e0 = ic_apply(v, w);   // start from the preconditioner's approximation
+        if (e0) return e0;
+        GmresResult G;
+        int e = h->gm_near.solve(op, ic_apply, v, w, near_tol, near_iter, st, &G);
+        if (e) return e == -6 ? SEASD_E_HIP : e;
+        S.inner_iterations += G.iterations;
+        if (!G.converged) near_ok = false;
+        return SEASD_OK;
+    };
+    bool have_geometry = false;
+    bool first = true;
+    int err_rc = SEASD_OK;
+    // out = M in on the 11 incompressible components (trace in and out zero)
+    auto apply11 = [&](const double* in, double* out) -> int {
+        const bool chk = first && c.checks;
+        first = false;
+        int e = queue_apply(h, n, pos, radius, L, in, out, st, chk, have_geometry, 0);
+        if (e) return e;
+        have_geometry = true;
+        if (chk && (e = read_err(h, st))) {
+            err_rc = e;
+            return e;
+        }
+        return SEASD_OK;
+    };
+    // Mt y = D y + M (y - lambda D y), D y = [Rt^-1 y_F; 0]
+    auto applyMt = [&](const double* in, double* out) -> int {
+        int e;
+        if (launch_ft_ops(n, 0, 0.0, in, nullptr, v6, st)) return SEASD_E_HIP;
+        if ((e = near_solve(v6, w6))) return e;
+        if (launch_ft_ops(n, 1, -lambda, in, w6, z12, st)) return SEASD_E_HIP;
+        if ((e = apply11(z12, out))) return e;
+        return launch_ft_ops(n, 1, 1.0, out, w6, out, st) ? SEASD_E_HIP : SEASD_OK;
+    };
+    auto precond = [&](const double* in, double* out) -> int {
+        return launch_block_apply(n, h->inv2.as<double>(), in, out, st) ? SEASD_E_HIP : SEASD_OK;
+    };
+    // right-hand side (eq. HI-solve): (lambda M - I) D [Fp; 0] + [0; E]
+    int extra = 0;
+    if (hipMemcpyAsync(p6, fp, sizeof(double) * len6, hipMemcpyDeviceToDevice, st) != hipSuccess) return SEASD_E_HIP;
+    if ((rc = near_solve(p6, w6))) return err_rc ? err_rc : rc;
+    if (hipMemsetAsync(z12, 0, sizeof(double) * len, st) != hipSuccess ||
+        launch_ft_ops(n, 1, lambda, z12, w6, z12, st))
+        return SEASD_E_HIP;
+    if ((rc = apply11(z12, rhs))) return err_rc ? err_rc : rc;
+    ++extra;
+    if (launch_ft_ops(n, 1, -1.0, rhs, w6, rhs, st) || launch_ft_ops(n, 2, 0.0, nullptr, einf, rhs, st))
+        return SEASD_E_HIP;
+    // y = 0 start
+    if (hipMemsetAsync(y12, 0, sizeof(double) * len, st) != hipSuccess) return SEASD_E_HIP;
+    GmresResult G;
+    rc = h->gm.solve(applyMt, precond, rhs, y12, c.tol, c.max_iter, st, &G);
+    if (rc) return err_rc ? err_rc : (rc == -6 ? SEASD_E_HIP : rc);
+    // U = Rt^-1 (y_F + Fp), F = y_F - lambda U, S = y_S
+    if (launch_ft_ops(n, 0, 0.0, y12, fp, v6, st)) return SEASD_E_HIP;
+    if ((rc = near_solve(v6, u6))) return rc;
+    if (launch_mixed_out(n, y12, u6, lambda, f, s, st) ||
+        hipMemcpyAsync(u, u6, sizeof(double) * len6, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return SEASD_E_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return SEASD_E_HIP;
+    S.iterations = G.iterations;
+    S.restarts = G.restarts;
+    S.matvecs = G.matvecs + extra;
+    S.converged = G.converged && near_ok;
+    S.true_residual = G.true_residual;
+    S.initial_residual = G.initial_residual;
+    S.precond_used = SEASD_PRECOND_BLOCKDIAG;
+    S.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = S;
+    return S.converged ? SEASD_OK : SEASD_W_NOT_CONVERGED;
+}
 
 extern "C" int seasd_brownian_farfield(seasd_handle h, int64_t n, const double* pos, const double* radius,
                                        const double* box, const double* psi, double* x, double dtau,

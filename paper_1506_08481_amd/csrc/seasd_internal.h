@@ -222,6 +222,33 @@ int launch_trace_op(int64_t n, int mode, const double* radius, double eta, const
                     double* out, hipStream_t st);
 int launch_build_blocks(int64_t n, const double* radius, const double* coef, double xi, double eta,
                         double* blocks, hipStream_t st);
+// near-field / far-field solve (seasd_solver.hip)
+// incomplete block Cholesky factor of R + lambda I, multicolour order (host side)
+struct BlockIC0Host {
+    int ncolours = 0;
+    double shift = 0.0;                   // relative diagonal scaling that avoided a breakdown
+    std::vector<int32_t> colour_start;    // [ncolours + 1] into rows
+    std::vector<int32_t> rows;            // block rows grouped by colour
+    std::vector<int32_t> lrp, lcol;       // forward rows: L_ik, k before i
+    std::vector<double> lval;
+    std::vector<int32_t> urp, ucol;       // backward rows: L_ji^T, j after i
+    std::vector<double> uval;
+    std::vector<double> linv;             // [n][6][6] inverses of the diagonal factors
+};
+int build_block_ic0(int64_t n, const std::vector<int32_t>& rowptr, const std::vector<int32_t>& col,
+                    const std::vector<double>& val, double lambda, BlockIC0Host* out);
+int launch_ic_solve_colour(int nrows, const int32_t* rows, const int32_t* rp, const int32_t* cl, const double* blk,
+                           const double* linv, int dir, const double* v, double* x, hipStream_t st);
+int launch_bsr6_spmv(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val, double lambda,
+                     const double* x, double* y, hipStream_t st);
+int launch_bsr6_diag_inv(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val, double lambda,
+                         double* out, int* bad, hipStream_t st);
+int launch_block6_apply(int64_t n, const double* B, const double* v, double* z, hipStream_t st);
+int launch_mixed_blocks(int64_t n, const double* M, const double* Rinv, double lambda, double* out, hipStream_t st);
+int launch_ft_ops(int64_t n, int mode, double alpha, const double* y12, const double* v6, double* out,
+                  hipStream_t st);
+int launch_mixed_out(int64_t n, const double* y12, const double* u6, double lambda, double* f6, double* s5,
+                     hipStream_t st);
 
 // Restarted right-preconditioned GMRES with the Arnoldi process on the device
 // (seasd_gmres.hip). apply_A(in, out) and apply_P(in, out) queue out = A in

@@ -41,7 +41,7 @@ PHASES = ("bin", "pair", "window", "spread", "fft_x_fwd", "fft_y_fwd", "fft_z_sc
 
 # exported symbols of include/seasd.h
 SYMBOLS = ("seasd_create", "seasd_destroy", "seasd_default_config", "seasd_set_config",
-           "seasd_mobility_apply", "seasd_mobility_apply_static", "seasd_solve_farfield", "seasd_brownian_farfield", "seasd_profile_enable",
+           "seasd_mobility_apply", "seasd_mobility_apply_static", "seasd_solve_farfield", "seasd_solve_mixed", "seasd_brownian_farfield", "seasd_profile_enable",
            "seasd_profile_read", "seasd_error_string", "seasd_autotune", "seasd_batch_create",
            "seasd_batch_apply", "seasd_batch_configs", "seasd_batch_destroy",
            "seasd_mobility_apply_batched", "seasd_net_create", "seasd_net_destroy", "seasd_net_param_count",
@@ -106,10 +106,20 @@ class seasd_solve_stats(ctypes.Structure):
         ("initial_residual", ctypes.c_double),
         ("guess_scale", ctypes.c_double),
         ("learned_ms", ctypes.c_double),
+        ("inner_iterations", ctypes.c_int32),
     ]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class seasd_bsr6(ctypes.Structure):
+    _fields_ = [
+        ("nnzb", ctypes.c_int64),
+        ("rowptr", ctypes.c_void_p),
+        ("col", ctypes.c_void_p),
+        ("val", ctypes.c_void_p),
+    ]
 
 
 class seasd_brownian_stats(ctypes.Structure):
@@ -145,6 +155,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.seasd_set_config.argtypes = [vp, ctypes.POINTER(seasd_config)]
     lib.seasd_mobility_apply.argtypes = [vp, i64, dp, dp, ctypes.POINTER(ctypes.c_double), dp, dp, vp]
     lib.seasd_mobility_apply_static.argtypes = [vp, i64, dp, dp, ctypes.POINTER(ctypes.c_double), dp, dp, vp]
+    lib.seasd_solve_mixed.argtypes = [vp, i64, dp, dp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(seasd_bsr6),
+                                      ctypes.c_double, dp, dp, dp, dp, dp, ctypes.POINTER(seasd_solve_stats), vp]
     lib.seasd_solve_farfield.argtypes = [vp, i64, dp, dp, ctypes.POINTER(ctypes.c_double), dp, dp,
                                          ctypes.POINTER(seasd_solve_stats), vp]
     lib.seasd_brownian_farfield.argtypes = [vp, i64, dp, dp, ctypes.POINTER(ctypes.c_double), dp, dp,
@@ -324,6 +336,44 @@ class Seasd:
         return x, out
 
     solve = seasd_solve_farfield
+
+    def seasd_solve_mixed(self, pos, radius, box, rowptr, col, val, lam, fp, einf, stream=None):
+        """Near-field / far-field solve (Sec. 4.1) for the near-field resistance
+        given as 6x6 blocks in block-row form (rowptr int32 [n+1], col int32
+        [nnzb], val float64 [nnzb, 6, 6], all on the device). Returns the
+        far-field force-torque [n, 6], stresslet [n, 5], velocity [n, 6] and
+        the solve statistics."""
+        import torch
+        n = _require_sphere_arrays(pos, radius, self.device)
+        for t, name in ((rowptr, "rowptr"), (col, "col")):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous():
+                raise TypeError(f"{name} must be a contiguous int32 GPU tensor")
+            if _device_of(t) != ("cuda", int(self.device)):
+                raise ValueError(f"{name} is on {t.device}, the engine on cuda:{self.device}")
+        if tuple(rowptr.shape) != (n + 1,):
+            raise ValueError(f"rowptr has shape {tuple(rowptr.shape)}, expected ({n + 1},)")
+        nnzb = int(col.shape[0])
+        _require(val, (nnzb, 6, 6), "val", self.device)
+        rp = rowptr.cpu().numpy()
+        cl = col.cpu().numpy()
+        if rp[0] != 0 or rp[-1] != nnzb or (rp[1:] < rp[:-1]).any() or (nnzb and (cl.min() < 0 or cl.max() >= n)):
+            raise ValueError("rowptr / col do not describe a block-row matrix of n block rows")
+        _require(fp, (n, 6), "fp", self.device)
+        _require(einf, (n, 5), "einf", self.device)
+        f = torch.empty((n, 6), dtype=torch.float64, device=pos.device)
+        s = torch.empty((n, 5), dtype=torch.float64, device=pos.device)
+        u = torch.empty((n, 6), dtype=torch.float64, device=pos.device)
+        m = seasd_bsr6(nnzb, rowptr.data_ptr(), col.data_ptr(), val.data_ptr())
+        st = seasd_solve_stats()
+        code = lib().seasd_solve_mixed(self.h, n, pos.data_ptr(), radius.data_ptr(), _box9(box), ctypes.byref(m),
+                                       float(lam), fp.data_ptr(), einf.data_ptr(), f.data_ptr(), s.data_ptr(),
+                                       u.data_ptr(), ctypes.byref(st), ctypes.c_void_p(_stream_ptr(stream)))
+        _check(code, allow=(SEASD_OK, SEASD_W_NOT_CONVERGED))
+        out = st.as_dict()
+        out["code"] = code
+        return f, s, u, out
+
+    solve_mixed = seasd_solve_mixed
 
     def seasd_brownian_farfield(self, pos, radius, box, psi, dtau: float = 0.1, stream=None):
         """x = M^(-1/2) psi (incompressible block) by the initial value problem."""

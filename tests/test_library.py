@@ -36,17 +36,24 @@ def _header_struct_fields(name):
         line = line.split("/*")[0].strip()
         if not line:
             continue
+        if line.startswith("const "):
+            line = line[len("const "):]
         typ, rest = line.split(None, 1)
         for f in rest.rstrip(";").split(","):
-            fields.append((typ, f.strip()))
+            f = f.strip()
+            if f.startswith("*"):   # pointer field
+                typ, f = typ + "*", f.lstrip("* ")
+            fields.append((typ, f))
     return fields
 
 
 @pytest.mark.parametrize("cname,pyclass", [("seasd_config", seasd.seasd_config),
                                            ("seasd_solve_stats", seasd.seasd_solve_stats),
-                                           ("seasd_brownian_stats", seasd.seasd_brownian_stats)])
+                                           ("seasd_brownian_stats", seasd.seasd_brownian_stats),
+                                           ("seasd_bsr6", seasd.seasd_bsr6)])
 def test_binding_struct_layout_matches_header(cname, pyclass):
-    cmap = {"int32_t": ctypes.c_int32, "double": ctypes.c_double}
+    cmap = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "double": ctypes.c_double,
+            "int32_t*": ctypes.c_void_p, "double*": ctypes.c_void_p}
     hdr = _header_struct_fields(cname)
     names = [re.sub(r"\[\d+\]$", "", f) for _, f in hdr]
     assert names == [f for f, _ in pyclass._fields_]
