@@ -1,9 +1,9 @@
 """Write the FP64 oracle's y = M x at sampled spheres of three members of the
 many-suspension workload (workloads.batch_member, the benchmark's own
 generator): members 111 (N = 1780, phi = 0.38), 78 (N = 7632, phi = 0.32) and
-104 (N = 4540, phi = 0.12), which the autotuner puts on 32^3, 64^3 and 128^3
-grids for a 1e-6 target. Every sphere is a source; the oracle evaluates the
-sum at 64 targets per member. Calls only oracle/ and the seeded input
+104 (N = 4540, phi = 0.12), of different cell sizes and grids (64^3, 128^3
+and 128^3 in the batched plan for a 1e-6 target). Every sphere is a source;
+the oracle evaluates the sum at 64 targets per member. Calls only oracle/ and the seeded input
 generators.
 
 Oracle settings: both Gaussian tails cut at exp(-25) (tol_exp = 5); xi =

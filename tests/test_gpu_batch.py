@@ -92,7 +92,7 @@ def test_batch_autotuned_accuracy(lib, systems):
 def test_batch_members_against_oracle(lib):
     """Three members of the benchmark's own many-suspension generator
     (workloads.batch_member; N = 1780, 7632 and 4540) that the autotuner puts
-    on 32^3, 64^3 and 128^3 grids for a 1e-6 target, in one batched plan: each
+    on 64^3, 128^3 and 128^3 grids for a 1e-6 target, in one batched plan: each
     member's result at 64 sampled spheres against the FP64 oracle
     (tests/golden/batch_oracle_sample.npz, written by
     tests/golden/make_batch_sample.py from the oracle alone)."""
@@ -114,7 +114,7 @@ def test_batch_members_against_oracle(lib):
     plan = lib.Batch(eng, offs, _t(np.concatenate([s.pos for s in sus])),
                      _t(np.concatenate([s.radius for s in sus])), [s.box for s in sus], target=1e-6)
     grids = [c.grid[0] for c in plan.configs()]
-    assert grids == [32, 64, 128]
+    assert grids == [64, 128, 128]
     y = plan.apply(_t(np.concatenate(xs))).cpu().numpy()
     plan.close()
     eng.close()
