@@ -3,18 +3,18 @@
 // shifted solves of the Brownian initial value problem, Sec. 4.3).
 //
 // Per Arnoldi step j (basis V_0..V_j, new vector w = A P V_j), classical
-// Gram-Schmidt twice in three passes over w, each reading w once and the basis
-// once:
-//   k_gs_dots      h1 = V^T w
-//   k_gs_update    w -= V h1, h2 = V^T w
-//   k_gs_finish    w -= V h2, |w|^2; H[:, j] = h1 + h2, H[j+1, j] = |w|, the
-//                  Givens rotations of the least-squares problem, the residual
-//                  estimate |g_(j+1)| and 1/|w|
-//   k_gs_scale     V_(j+1) = w / |w|
-// Each pass reduces its partial sums in the last workgroup to finish (one
-// counter per pass, reset by that workgroup), so the step needs no host
-// round trip; the host reads one scalar per step, one step behind, while the
-// next step is already queued.
+// Gram-Schmidt twice in four passes over w, each reading the basis once:
+//   k_gs_dots2d + k_gs_reduce   h1 = V^T w (workgroups over entries x groups
+//                               of 4 vectors, then one wavefront per vector)
+//   k_gs_sub                    w -= V h1 (one thread per entry)
+//   k_gs_dots2d + k_gs_reduce   h2 = V^T w
+//   k_gs_finish + k_gs_givens   w -= V h2, |w|; H[:, j] = h1 + h2,
+//                               H[j+1, j] = |w|, the Givens rotations of the
+//                               least-squares problem, the residual estimate
+//                               |g_(j+1)| and 1/|w|
+//   k_gs_scale                  V_(j+1) = w / |w|
+// The step needs no host round trip; the host reads one scalar per step, one
+// step behind, while the next step is already queued.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,7 +26,7 @@
 namespace seasd {
 
 constexpr int kGsThreads = 256;
-constexpr int kGsChunkMax = 2048;   // vector entries per workgroup (staged in LDS)
+constexpr int kGsChunkMax = 2048;   // vector entries per workgroup of the norm
 
 __device__ inline double block_sum(double v, double* red) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -39,14 +39,15 @@ __device__ inline double block_sum(double v, double* red) {
     return t;
 }
 
-// true in every thread of the last workgroup to arrive (which then resets the counter)
+// true in every thread of the last workgroup of the (1- or 2-D) grid to
+// arrive, which then resets the counter
 __device__ inline bool last_block(unsigned* counter) {
     __shared__ bool last;
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned prev = atomicAdd(counter, 1u);
-        last = prev == gridDim.x - 1;
+        last = prev == gridDim.x * gridDim.y - 1;
         if (last) *counter = 0u;
     }
     __syncthreads();
@@ -54,57 +55,71 @@ __device__ inline bool last_block(unsigned* counter) {
     return last;
 }
 
-// partial dot products of the k basis vectors with this workgroup's chunk of
-// w (held in LDS), reduced over workgroups into out[0..k) by the last one
-__device__ inline void chunk_dots(int k, const double* __restrict__ V, int64_t ld, const double* ws, int64_t i0,
-                                  int len, double* __restrict__ partial, unsigned* counter, double* __restrict__ out,
-                                  double* red) {
-    const int nb = gridDim.x;
-    for (int q = 0; q < k; ++q) {
-        const double* v = V + q * ld + i0;
-        double s = 0.0;
-        for (int i = threadIdx.x; i < len; i += kGsThreads) s += v[i] * ws[i];
-        s = block_sum(s, red);
-        if (threadIdx.x == 0) partial[(size_t)q * nb + blockIdx.x] = s;
+__device__ inline double wave_sum(double s) {
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    return s;
+}
+
+// Partial sums of V^T w over a two-dimensional grid: workgroup (c, g) takes
+// entries c * per * 256 .. (per per thread) and basis vectors 4 g .. 4 g + 3,
+// so a step has enough workgroups in flight to stream the basis at memory
+// speed however few vectors it holds. k_gs_reduce sums the partials: a
+// kernel boundary rather than a last-workgroup reduction, whose per-workgroup
+// fence and atomic cost more than a launch at this many workgroups.
+constexpr int kDotGroup = 4;   // basis vectors per workgroup
+
+__global__ __launch_bounds__(kGsThreads) void k_gs_dots2d(int64_t len, int per, int k, const double* __restrict__ V,
+                                                          int64_t ld, const double* __restrict__ w,
+                                                          double* __restrict__ partial) {
+    __shared__ double red[kDotGroup][kGsThreads / 64];
+    const int nc = gridDim.x;
+    const int c = blockIdx.x, q0 = blockIdx.y * kDotGroup;
+    const int64_t i0 = (int64_t)c * per * kGsThreads;
+    double s[kDotGroup] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int e = 0; e < per; ++e) {
+        const int64_t i = i0 + e * kGsThreads + threadIdx.x;
+        if (i < len) {
+            const double wi = w[i];
+#pragma unroll
+            for (int u = 0; u < kDotGroup; ++u)
+                if (q0 + u < k) s[u] += V[(q0 + u) * ld + i] * wi;
+        }
     }
-    if (!last_block(counter)) return;
-    for (int q = threadIdx.x; q < k; q += kGsThreads) {
-        double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += partial[(size_t)q * nb + b];
-        out[q] = s;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int u = 0; u < kDotGroup; ++u) {
+        const double t = wave_sum(s[u]);
+        if (lane == 0) red[u][wv] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < kDotGroup && q0 + (int)threadIdx.x < k) {
+        double t = 0.0;
+        for (int q = 0; q < kGsThreads / 64; ++q) t += red[threadIdx.x][q];
+        partial[(size_t)(q0 + threadIdx.x) * nc + c] = t;
     }
 }
 
-__global__ __launch_bounds__(kGsThreads) void k_gs_dots(int64_t len, int chunk, int k, const double* __restrict__ V,
-                                                        int64_t ld, const double* __restrict__ w,
-                                                        double* __restrict__ partial, unsigned* counter,
-                                                        double* __restrict__ h1) {
-    __shared__ double ws[kGsChunkMax];
-    __shared__ double red[kGsThreads / 64];
-    const int64_t i0 = (int64_t)blockIdx.x * chunk;
-    const int n = (int)std::min<int64_t>(chunk, len - i0);
-    for (int i = threadIdx.x; i < n; i += kGsThreads) ws[i] = w[i0 + i];
-    __syncthreads();
-    chunk_dots(k, V, ld, ws, i0, n, partial, counter, h1, red);
+// out[q] = sum over the nc partial sums of basis vector q: one wavefront per q
+__global__ __launch_bounds__(kGsThreads) void k_gs_reduce(int nc, int k, const double* __restrict__ partial,
+                                                          double* __restrict__ out) {
+    const int q = blockIdx.x * (kGsThreads / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (q >= k) return;
+    double t = 0.0;
+    for (int b = lane; b < nc; b += 64) t += partial[(size_t)q * nc + b];
+    t = wave_sum(t);
+    if (lane == 0) out[q] = t;
 }
 
-__global__ __launch_bounds__(kGsThreads) void k_gs_update(int64_t len, int chunk, int k, const double* __restrict__ V,
-                                                          int64_t ld, const double* __restrict__ h1,
-                                                          double* __restrict__ w, double* __restrict__ partial,
-                                                          unsigned* counter, double* __restrict__ h2) {
-    __shared__ double ws[kGsChunkMax];
-    __shared__ double red[kGsThreads / 64];
-    const int64_t i0 = (int64_t)blockIdx.x * chunk;
-    const int n = (int)std::min<int64_t>(chunk, len - i0);
-    for (int i = threadIdx.x; i < n; i += kGsThreads) {
-        double s = 0.0;
-        for (int q = 0; q < k; ++q) s += h1[q] * V[q * ld + i0 + i];
-        const double v = w[i0 + i] - s;
-        w[i0 + i] = v;
-        ws[i] = v;
-    }
-    __syncthreads();
-    chunk_dots(k, V, ld, ws, i0, n, partial, counter, h2, red);
+// w -= V h, one thread per entry
+__global__ __launch_bounds__(256) void k_gs_sub(int64_t len, int k, const double* __restrict__ V, int64_t ld,
+                                               const double* __restrict__ h, double* __restrict__ w) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    double s = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < k; ++q) s += h[q] * V[q * ld + i];
+    w[i] -= s;
 }
 
 // Device state of one restart cycle: H[(m + 1) x m] row-major (stride m),
@@ -120,49 +135,70 @@ struct GsState {
     double* resid;    // [max steps] |g_(j+1)| per step, for the host
 };
 
-__global__ __launch_bounds__(kGsThreads) void k_gs_finish(int64_t len, int chunk, int j, int m,
-                                                          const double* __restrict__ V, int64_t ld,
-                                                          double* __restrict__ w, double* __restrict__ partial,
-                                                          unsigned* counter, GsState S, double* __restrict__ resid_out) {
+// w -= V h2 and the partial sums of |w|^2, one per workgroup
+__global__ __launch_bounds__(kGsThreads) void k_gs_finish(int64_t len, int chunk, int k, const double* __restrict__ V,
+                                                          int64_t ld, const double* __restrict__ h2,
+                                                          double* __restrict__ w, double* __restrict__ pnorm) {
     __shared__ double red[kGsThreads / 64];
-    const int k = j + 1;
     const int64_t i0 = (int64_t)blockIdx.x * chunk;
     const int n = (int)std::min<int64_t>(chunk, len - i0);
     double s2 = 0.0;
     for (int i = threadIdx.x; i < n; i += kGsThreads) {
         double s = 0.0;
-        for (int q = 0; q < k; ++q) s += S.h2[q] * V[q * ld + i0 + i];
+#pragma unroll 8
+        for (int q = 0; q < k; ++q) s += h2[q] * V[q * ld + i0 + i];
         const double v = w[i0 + i] - s;
         w[i0 + i] = v;
         s2 += v * v;
     }
     s2 = block_sum(s2, red);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s2;
-    if (!last_block(counter)) return;
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x == 0) pnorm[blockIdx.x] = s2;
+}
+
+// |w| from the nc partial sums; H[:, j] = h1 + h2, H[j+1, j] = |w|; the
+// Givens rotations of the least-squares problem; the residual estimate
+// |g_(j+1)| (written to host memory) and 1/|w|. One wavefront: the column
+// and the rotations are staged in LDS so that the sequential sweep over the
+// earlier rotations waits on no global load.
+constexpr int kMaxRestart = 200;
+
+__global__ __launch_bounds__(64) void k_gs_givens(int nc, int j, int m, const double* __restrict__ pnorm, GsState S,
+                                                  double* __restrict__ resid_host) {
+    __shared__ double col[kMaxRestart + 2], cs[kMaxRestart + 2], sn[kMaxRestart + 2];
+    const int lane = threadIdx.x;
     double nrm2 = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) nrm2 += partial[b];
-    const double hn = sqrt(nrm2);
-    double* Hc = S.H;   // column j: Hc[q * m + j]
-    for (int q = 0; q <= j; ++q) Hc[q * m + j] = S.h1[q] + S.h2[q];
-    // previous Givens rotations on column j
-    for (int q = 0; q < j; ++q) {
-        const double a = Hc[q * m + j], b = Hc[(q + 1) * m + j];
-        Hc[q * m + j] = S.cs[q] * a + S.sn[q] * b;
-        Hc[(q + 1) * m + j] = -S.sn[q] * a + S.cs[q] * b;
+    for (int b = lane; b < nc; b += 64) nrm2 += pnorm[b];
+    nrm2 = wave_sum(nrm2);
+    for (int q = lane; q <= j; q += 64) {
+        col[q] = S.h1[q] + S.h2[q];
+        cs[q] = S.cs[q];
+        sn[q] = S.sn[q];
     }
-    const double a = Hc[j * m + j], b = hn;
-    const double den = hypot(a, b);
-    const double c = den > 0.0 ? a / den : 1.0, sn = den > 0.0 ? b / den : 0.0;
-    S.cs[j] = c;
-    S.sn[j] = sn;
-    Hc[j * m + j] = den;
-    Hc[(j + 1) * m + j] = 0.0;
-    S.g[j + 1] = -sn * S.g[j];
-    S.g[j] = c * S.g[j];
-    *S.inv_hn = hn > 0.0 ? 1.0 / hn : 0.0;
-    // the host stops on a zero |w| (the Krylov space is invariant): report 0
-    resid_out[j] = hn > 0.0 ? fabs(S.g[j + 1]) : 0.0;
+    __syncthreads();
+    if (lane == 0) {
+        const double hn = sqrt(nrm2);
+        // the earlier rotations applied down column j
+        double a = col[0];
+        for (int q = 0; q < j; ++q) {
+            const double b = col[q + 1];
+            col[q] = cs[q] * a + sn[q] * b;
+            a = -sn[q] * a + cs[q] * b;
+        }
+        const double den = hypot(a, hn);
+        const double c = den > 0.0 ? a / den : 1.0, s = den > 0.0 ? hn / den : 0.0;
+        S.cs[j] = c;
+        S.sn[j] = s;
+        col[j] = den;
+        col[j + 1] = 0.0;
+        const double gj = S.g[j];
+        S.g[j + 1] = -s * gj;
+        S.g[j] = c * gj;
+        *S.inv_hn = hn > 0.0 ? 1.0 / hn : 0.0;
+        // the host stops on a zero |w| (the Krylov space is invariant): report 0
+        resid_host[j] = hn > 0.0 ? fabs(s * gj) : 0.0;
+    }
+    __syncthreads();
+    for (int q = lane; q <= j + 1; q += 64) S.H[q * m + j] = col[q];
 }
 
 __global__ void k_gs_scale(int64_t len, const double* __restrict__ w, const double* __restrict__ inv,
@@ -211,11 +247,11 @@ __global__ __launch_bounds__(kGsThreads) void k_norm2(int64_t len, int chunk, co
     s = block_sum(s, red);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
     if (!last_block(counter)) return;
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int b = 0; b < (int)gridDim.x; ++b) t += partial[b];
-        *out = t;
-    }
+    if (threadIdx.x >= 64) return;
+    double t = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += 64) t += partial[b];
+    t = wave_sum(t);
+    if (threadIdx.x == 0) *out = t;
 }
 
 // ---------------------------------------------------------------------------
@@ -224,10 +260,18 @@ __global__ __launch_bounds__(kGsThreads) void k_norm2(int64_t len, int chunk, co
 static inline unsigned blocks_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 int DeviceGmres::ensure(int64_t len_, int m_, int max_steps) {
+    if (m_ < 1 || m_ > kMaxRestart) return -6;   // seasd_set_config holds restart to [1, 200]
     len = len_;
     m = m_;
-    chunk = (int)std::min<int64_t>(kGsChunkMax, std::max<int64_t>(256, (len + 511) / 512));
+    // at least 1024 entries per workgroup (several loads in flight per lane,
+    // and few partial sums for the last workgroup to reduce), about 128
+    // workgroups for long vectors
+    chunk = (int)std::min<int64_t>(kGsChunkMax, std::max<int64_t>(1024, (len + 127) / 128));
     nblk = (int)((len + chunk - 1) / chunk);
+    // the two-dimensional dot products: 1, 2 or 4 entries per thread, at most
+    // about 2048 workgroups along the vector
+    dper = len <= 2048 * kGsThreads ? 1 : len <= 4096 * kGsThreads ? 2 : 4;
+    ndc = (int)((len + (int64_t)dper * kGsThreads - 1) / ((int64_t)dper * kGsThreads));
     int rc = 0;
     rc |= V.ensure(sizeof(double) * len * (m + 1));
     rc |= w.ensure(sizeof(double) * len);
@@ -235,9 +279,8 @@ int DeviceGmres::ensure(int64_t len_, int m_, int max_steps) {
     rc |= u.ensure(sizeof(double) * len);
     rc |= r.ensure(sizeof(double) * len);
     rc |= small.ensure(sizeof(double) * ((size_t)(m + 1) * m + 5 * (m + 2) + 8));
-    rc |= partial.ensure(sizeof(double) * (size_t)(m + 2) * nblk);
+    rc |= partial.ensure(sizeof(double) * (size_t)(m + 2) * std::max(nblk, ndc));
     rc |= counters.ensure(sizeof(unsigned) * 4);
-    rc |= resid_dev.ensure(sizeof(double) * (m + 1));
     if (rc) return -7;
     if (!counters_clear) {
         if (hipMemset(counters.p, 0, sizeof(unsigned) * 4) != hipSuccess) return -6;
@@ -246,7 +289,12 @@ int DeviceGmres::ensure(int64_t len_, int m_, int max_steps) {
     if ((int)resid_host_n < m + 1) {
         if (resid_host) hipHostFree(resid_host);
         resid_host = nullptr;
-        if (hipHostMalloc((void**)&resid_host, sizeof(double) * (m + 1)) != hipSuccess) return -7;
+        // fine-grained pinned memory: k_gs_givens writes each step's
+        // residual estimate straight to the host
+        if (hipHostMalloc((void**)&resid_host, sizeof(double) * (m + 1), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess)
+            return -7;
+        if (hipHostGetDevicePointer((void**)&resid_hdev, resid_host, 0) != hipSuccess) return -6;
         resid_host_n = m + 1;
     }
     while ((int)events.size() < m + 1) {
@@ -259,10 +307,11 @@ int DeviceGmres::ensure(int64_t len_, int m_, int max_steps) {
 }
 
 void DeviceGmres::release() {
-    DevBuf* bufs[] = {&V, &w, &z, &u, &r, &small, &partial, &counters, &resid_dev};
+    DevBuf* bufs[] = {&V, &w, &z, &u, &r, &small, &partial, &counters};
     for (DevBuf* b : bufs) b->release();
     if (resid_host) hipHostFree(resid_host);
     resid_host = nullptr;
+    resid_hdev = nullptr;
     resid_host_n = 0;
     for (auto e : events) hipEventDestroy(e);
     events.clear();
@@ -310,7 +359,6 @@ int DeviceGmres::solve(const std::function<int(const double*, double*)>& apply_A
     double* zp = z.as<double>();
     double* up = u.as<double>();
     double* rp = r.as<double>();
-    unsigned* cnt = counters.as<unsigned>();
     double* part = partial.as<double>();
     const unsigned gl = blocks_of(len, 256);
     int total = 0;
@@ -341,17 +389,23 @@ int DeviceGmres::solve(const std::function<int(const double*, double*)>& apply_A
             if ((rc = apply_P(Vp + (size_t)j * len, zp))) return rc;
             if ((rc = apply_A(zp, wp))) return rc;
             ++R.matvecs;
-            hipLaunchKernelGGL(k_gs_dots, dim3(nblk), dim3(kGsThreads), 0, st, len, chunk, j + 1, Vp, (int64_t)len,
-                               wp, part, cnt + 0, S.h1);
-            hipLaunchKernelGGL(k_gs_update, dim3(nblk), dim3(kGsThreads), 0, st, len, chunk, j + 1, Vp,
-                               (int64_t)len, S.h1, wp, part, cnt + 1, S.h2);
-            hipLaunchKernelGGL(k_gs_finish, dim3(nblk), dim3(kGsThreads), 0, st, len, chunk, j, m, Vp,
-                               (int64_t)len, wp, part, cnt + 2, S, resid_dev.as<double>());
+            // classical Gram-Schmidt applied twice: h1 = V^T w, w -= V h1,
+            // h2 = V^T w, w -= V h2, then |w| and the Givens update
+            const int k = j + 1;
+            const dim3 g2d((unsigned)ndc, (unsigned)((k + kDotGroup - 1) / kDotGroup));
+            const unsigned gr = (unsigned)((k + kGsThreads / 64 - 1) / (kGsThreads / 64));
+            double* pnorm = part + (size_t)(m + 1) * ndc;
+            hipLaunchKernelGGL(k_gs_dots2d, g2d, dim3(kGsThreads), 0, st, len, dper, k, Vp, (int64_t)len, wp, part);
+            hipLaunchKernelGGL(k_gs_reduce, dim3(gr), dim3(kGsThreads), 0, st, ndc, k, part, S.h1);
+            hipLaunchKernelGGL(k_gs_sub, dim3(gl), dim3(256), 0, st, len, k, Vp, (int64_t)len, S.h1, wp);
+            hipLaunchKernelGGL(k_gs_dots2d, g2d, dim3(kGsThreads), 0, st, len, dper, k, Vp, (int64_t)len, wp, part);
+            hipLaunchKernelGGL(k_gs_reduce, dim3(gr), dim3(kGsThreads), 0, st, ndc, k, part, S.h2);
+            hipLaunchKernelGGL(k_gs_finish, dim3(ndc), dim3(kGsThreads), 0, st, len, dper * kGsThreads, k, Vp,
+                               (int64_t)len, S.h2, wp, pnorm);
+            hipLaunchKernelGGL(k_gs_givens, dim3(1), dim3(64), 0, st, ndc, j, m, pnorm, S, resid_hdev);
             hipLaunchKernelGGL(k_gs_scale, dim3(gl), dim3(256), 0, st, len, wp, S.inv_hn, Vp + (size_t)(j + 1) * len);
-            if (hipMemcpyAsync(resid_host + j, resid_dev.as<double>() + j, sizeof(double), hipMemcpyDeviceToHost,
-                               st) != hipSuccess ||
-                hipEventRecord(events[j], st) != hipSuccess)
-                return -6;
+            // the event's release makes the kernel's write to host memory visible
+            if (hipEventRecord(events[j], st) != hipSuccess) return -6;
             queued = j + 1;
             // one step behind: step j - 1 has long finished when step j's work is queued
             if (j >= 1 && (rc = check(j - 1))) return rc;

@@ -260,9 +260,10 @@ struct GmresResult {
 
 struct DeviceGmres {
     int64_t len = 0;
-    int m = 0, chunk = 0, nblk = 0;
-    DevBuf V, w, z, u, r, small, partial, counters, resid_dev;
-    double* resid_host = nullptr;   // pinned: per-step residual estimates
+    int m = 0, chunk = 0, nblk = 0, dper = 1, ndc = 0;
+    DevBuf V, w, z, u, r, small, partial, counters;
+    double* resid_host = nullptr;   // pinned, fine-grained: per-step residual estimates
+    double* resid_hdev = nullptr;   // its device-side address
     int resid_host_n = 0;
     std::vector<hipEvent_t> events;
     bool counters_clear = false;
