@@ -13,11 +13,12 @@ converged-mode comparison puts at about 1e-10 relative. The converged result
 does not depend on xi, so xi only balances the oracle's own cost: its
 real-space sum grows as (targets)/xi^3 and its structure sums as N xi^3.
 The 2,000 targets of the first workload are split over worker processes,
-each of which evaluates the oracle at its share of the targets (xi = 0.155
-balances the two parts per worker); the second workload uses xi = 0.12, which
+each of which evaluates the oracle at its share of the targets (xi = 0.2
+balances the two parts per worker; each worker peaks near 10 GB, so three
+run at once on a 64 GB machine); the second workload uses xi = 0.12, which
 keeps r_c = tol_exp / xi below L/2 (L = 94.7).
 Run: python tests/golden/make_large_sample.py [large|bidisperse]
-(about 15 minutes for the first on 6 worker processes, 90 s for the second)
+(about 30 minutes for the first on 3 worker processes, 90 s for the second)
 """
 import multiprocessing as mp
 import os
@@ -33,7 +34,7 @@ from oracle import ewald  # noqa: E402
 from paper_1506_08481_amd import workloads as wl  # noqa: E402
 
 SEED_POS, SEED_X, NSAMPLE = 3000, 3001, 2000
-XI_LARGE, WORKERS = 0.155, 6
+XI_LARGE, WORKERS = 0.2, 3
 BI_N, BI_PHI, BI_SEED_POS, BI_SEED_X, BI_NSAMPLE = 40000, 0.35, 4000, 4001, 64
 
 

@@ -1,7 +1,9 @@
 """Parity at the full benchmark size: N = 100,000 spheres at phi = 0.4,
-grid 256^3, in the launch configurations the benchmark times, checked at 64
-sampled spheres against the FP64 oracle (tests/golden/large_oracle_sample.npz,
-written by tests/golden/make_large_sample.py from the oracle alone). A second
+grid 256^3, in the launch configurations the benchmark times, checked at
+2,000 sampled spheres against the FP64 oracle
+(tests/golden/large_oracle_sample.npz, written by
+tests/golden/make_large_sample.py from the oracle alone): every FP32
+configuration the benchmark may time holds the 1e-6 target there. A second
 sample (bidisperse_oracle_sample.npz) covers a large suspension of two sphere
 sizes, whose uneven neighbour lists take the wavefront-per-sphere pair sum."""
 import math
@@ -44,6 +46,17 @@ def _sample_error(cfg, precision, large):
     return float(np.linalg.norm(y[tg] - yo) / np.linalg.norm(yo)), y
 
 
+BLOCKS = {"U": slice(0, 3), "W": slice(3, 6), "E": slice(6, 11), "e": slice(11, 12)}
+
+
+def _einf_blocks(y, yo):
+    """eq. err-E per block over the sampled spheres."""
+    out = {}
+    for k, sl in BLOCKS.items():
+        out[k] = float(np.max(np.linalg.norm(y[:, sl] - yo[:, sl], axis=1) / np.linalg.norm(yo[:, sl], axis=1)))
+    return out
+
+
 def test_large_fp64_reference(large):
     """The FP64 product that the benchmark measures its error against:
     Spectral Ewald error about 1e-8 at P = 18."""
@@ -57,12 +70,15 @@ def test_large_fp64_reference(large):
 @pytest.mark.parametrize("k", [0, 1])
 def test_large_fp32_candidates(large, k):
     """Each FP32 configuration the benchmark may time holds the 1e-6 target
-    on the sample (a factor 2 above it for the 64-sphere sampling spread)."""
+    on the 2,000-sphere sample; the per-block e_inf of eq. err-E is reported."""
     import bench
     from paper_1506_08481_amd import seasd
-    err, _ = _sample_error(bench.CANDIDATES[k], seasd.SEASD_FP32, large)
-    print(f"fp32 candidate {bench.CANDIDATES[k]} sample error {err:.3e}")
-    assert err < 2e-6
+    err, y = _sample_error(bench.CANDIDATES[k], seasd.SEASD_FP32, large)
+    tg, yo = large[2], large[3]
+    print(f"fp32 candidate {bench.CANDIDATES[k]} sample error {err:.3e} over {len(tg)} spheres, "
+          f"per-block e_inf {_einf_blocks(y[tg], yo)}")
+    assert len(tg) >= 2000
+    assert err <= 1e-6
 
 
 @pytest.fixture(scope="module")
