@@ -182,7 +182,7 @@ int seasd_default_config(seasd_config* cfg);
  * SEASD_E_INVALID_ARG for out-of-range values. */
 int seasd_set_config(seasd_handle handle, const seasd_config* cfg);
 
-/* y = M x (Sec. 3, "the action of M on the force moments").
+/* y = M x: the grand mobility applied to the force moments (Sec. 3).
  *   n      number of spheres, >= 1
  *   pos    device [n][3] centres (any real coordinates; wrapped into the cell)
  *   radius device [n] radii, > 0

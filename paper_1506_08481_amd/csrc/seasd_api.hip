@@ -1320,11 +1320,6 @@ extern "C" int seasd_autotune(int64_t n, const double* box, double a_min, double
     return SEASD_OK;
 }
 
-// streams the batch graph forks its suspensions over (256 suspensions,
-// 658,127 spheres: 24.8 / 24.6 / 24.3 ms per launch with 4 / 8 / 16 streams,
-// within run-to-run spread; HIP maps them onto 4 hardware queues)
-constexpr int kBatchStreams = 8;
-
 struct seasd_batch_s {
     int device = 0;
     int nsys = 0;
@@ -1333,8 +1328,9 @@ struct seasd_batch_s {
     std::vector<seasd_handle> sub;
     std::vector<seasd_config> cfg;
     DevBuf pos, rad, xin, yout;
-    hipStream_t streams[kBatchStreams] = {};
-    hipEvent_t fork = nullptr, join[kBatchStreams] = {};
+    MultiPlan* plan = nullptr;
+    hipStream_t streams[2] = {};
+    hipEvent_t fork = nullptr, join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -1344,9 +1340,9 @@ extern "C" int seasd_batch_destroy(seasd_batch b) {
     hipSetDevice(b->device);
     if (b->exec) hipGraphExecDestroy(b->exec);
     if (b->graph) hipGraphDestroy(b->graph);
-    for (auto& e : b->join)
-        if (e) hipEventDestroy(e);
+    if (b->join) hipEventDestroy(b->join);
     if (b->fork) hipEventDestroy(b->fork);
+    multi_plan_free(b->plan);
     for (auto& st : b->streams)
         if (st) hipStreamDestroy(st);
     for (auto h : b->sub) seasd_destroy(h);
@@ -1428,42 +1424,33 @@ extern "C" int seasd_batch_create(seasd_handle h, int32_t nsys, const int64_t* o
         if (rc) return fail(rc);
     }
     if (hipStreamSynchronize(st) != hipSuccess) return fail(SEASD_E_HIP);
-    // capture: fork to kBatchStreams streams, one product per suspension, join
-    for (auto& s8 : b->streams)
-        if (hipStreamCreateWithFlags(&s8, hipStreamNonBlocking) != hipSuccess) return fail(SEASD_E_HIP);
-    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) return fail(SEASD_E_HIP);
-    for (auto& e : b->join)
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(SEASD_E_HIP);
-    hipStream_t cap = b->streams[0];
-    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return fail(SEASD_E_HIP);
-    bool ok = hipEventRecord(b->fork, cap) == hipSuccess;
-    for (int k = 1; k < kBatchStreams && ok; ++k) ok = hipStreamWaitEvent(b->streams[k], b->fork, 0) == hipSuccess;
-    // heaviest suspensions first, round-robin over the streams
-    std::vector<int> order(nsys);
-    for (int k = 0; k < nsys; ++k) order[k] = k;
-    std::sort(order.begin(), order.end(), [&](int a, int c) {
-        const double ga = b->cfg[a].grid[0], gc = b->cfg[c].grid[0];
-        const double wa = ga * ga * ga + 50.0 * (offsets[a + 1] - offsets[a]);
-        const double wc = gc * gc * gc + 50.0 * (offsets[c + 1] - offsets[c]);
-        return wa > wc;
-    });
-    for (int r = 0; r < nsys && ok; ++r) {
-        const int k = order[r];
+    // one launch per phase and kernel variant for all suspensions
+    std::vector<ApplyArgs> args(nsys);
+    for (int k = 0; k < nsys; ++k) {
         const int64_t n = offsets[k + 1] - offsets[k], o = offsets[k];
-        rc = queue_apply(b->sub[k], n, b->pos.as<double>() + 3 * o, b->rad.as<double>() + o, b->cells[k],
-                         b->xin.as<double>() + 12 * o, b->yout.as<double>() + 12 * o, b->streams[r % kBatchStreams], false,
-                         true);
-        ok = rc == SEASD_OK;
+        fill_args(b->sub[k], args[k], n, b->pos.as<double>() + 3 * o, b->rad.as<double>() + o, b->cells[k],
+                  b->xin.as<double>() + 12 * o, b->yout.as<double>() + 12 * o, false, b->cfg[k].compressible);
     }
-    for (int k = 1; k < kBatchStreams && ok; ++k) {
-        ok = hipEventRecord(b->join[k], b->streams[k]) == hipSuccess &&
-             hipStreamWaitEvent(cap, b->join[k], 0) == hipSuccess;
-    }
+    if ((rc = multi_plan_build(args.data(), nsys, &b->plan, st)))
+        return fail(rc == -8 ? SEASD_E_UNSUPPORTED : (rc == -7 ? SEASD_E_NOMEM : SEASD_E_HIP));
+    // capture: the binned moments, then the pair sums on a second stream
+    // beside the wave-space chain, joined before the gather
+    for (auto& s2 : b->streams)
+        if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) return fail(SEASD_E_HIP);
+    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess)
+        return fail(SEASD_E_HIP);
+    hipStream_t cap = b->streams[0], side = b->streams[1];
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return fail(SEASD_E_HIP);
+    bool ok = multi_queue_moments(b->plan, cap) == 0 && hipEventRecord(b->fork, cap) == hipSuccess &&
+              hipStreamWaitEvent(side, b->fork, 0) == hipSuccess && multi_queue_pair(b->plan, side) == 0 &&
+              hipEventRecord(b->join, side) == hipSuccess && multi_queue_wave(b->plan, cap) == 0 &&
+              hipStreamWaitEvent(cap, b->join, 0) == hipSuccess && multi_queue_gather(b->plan, cap) == 0;
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(cap, &g);
     if (!ok || ec != hipSuccess || !g) {
         if (g) hipGraphDestroy(g);
-        return fail(rc ? rc : SEASD_E_HIP);
+        return fail(SEASD_E_HIP);
     }
     b->graph = g;
     if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) return fail(SEASD_E_HIP);

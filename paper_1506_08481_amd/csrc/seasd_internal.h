@@ -209,6 +209,18 @@ int launch_wave(const ApplyArgs& a, hipStream_t st, PhaseTimer* tm);
 int launch_pair(const ApplyArgs& a, hipStream_t st, PhaseTimer* tm);
 int launch_gather(const ApplyArgs& a, hipStream_t st, PhaseTimer* tm);
 
+// Batched launches over many suspensions (seasd_kernels.hip): each phase is
+// one launch per kernel variant for the whole batch, every workgroup taking a
+// (suspension, block) item. Build returns 0, -8 (mixed precisions, the hybrid
+// size approach or a partial product: not batched), -7 or -6.
+struct MultiPlan;
+int multi_plan_build(const ApplyArgs* args, int nsys, MultiPlan** out, hipStream_t st);
+void multi_plan_free(MultiPlan* p);
+int multi_queue_moments(const MultiPlan* p, hipStream_t st);   // binned copies of the moments
+int multi_queue_pair(const MultiPlan* p, hipStream_t st);      // pair sums into ybuf
+int multi_queue_wave(const MultiPlan* p, hipStream_t st);      // window records, spreading, FFT chain
+int multi_queue_gather(const MultiPlan* p, hipStream_t st);    // gather, y = ybuf + wave part
+
 // GMRES / preconditioner helpers (seasd_solver.hip)
 int launch_block_apply(int64_t n, const double* blocks, const double* v, double* z, hipStream_t st);
 int launch_block_invert(int64_t n, const double* a, double* inv, int* singular, hipStream_t st);

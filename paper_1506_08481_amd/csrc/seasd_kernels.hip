@@ -264,12 +264,12 @@ __global__ void k_bin_order(int nbins, const int* __restrict__ start, int* __res
 }
 
 // binned copies: wrapped centres (fractional and Cartesian), radii and moments (FP64)
-__global__ void k_bin_gather(int n, const int* __restrict__ perm, const double* __restrict__ pos,
-                             const double* __restrict__ rad, const double* __restrict__ x,
-                             Cell cell, int compressible, double* __restrict__ sp, double* __restrict__ stf,
-                             double* __restrict__ sa, double* __restrict__ sx,
-                             int* __restrict__ err) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void bin_gather_body(int n, const int* __restrict__ perm, const double* __restrict__ pos,
+                                                const double* __restrict__ rad, const double* __restrict__ x,
+                                                Cell cell, int compressible, double* __restrict__ sp, double* __restrict__ stf,
+                                                double* __restrict__ sa, double* __restrict__ sx,
+                                                int* __restrict__ err, int bid) {
+    int s = bid * blockDim.x + threadIdx.x;
     if (s >= n) return;
     int i = perm[s];
     double p[3];
@@ -297,6 +297,14 @@ __global__ void k_bin_gather(int n, const int* __restrict__ perm, const double* 
         sx[12 * (size_t)s + c] = v;
     }
     if (bad) atomicOr(err, kErrNonfinite);
+}
+
+__global__ void k_bin_gather(int n, const int* __restrict__ perm, const double* __restrict__ pos,
+                             const double* __restrict__ rad, const double* __restrict__ x,
+                             Cell cell, int compressible, double* __restrict__ sp, double* __restrict__ stf,
+                             double* __restrict__ sa, double* __restrict__ sx,
+                             int* __restrict__ err) {
+    bin_gather_body(n, perm, pos, rad, x, cell, compressible, sp, stf, sa, sx, err, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -657,12 +665,12 @@ __global__ __launch_bounds__(256) void k_count_stats(int n, const int* __restric
     }
 }
 
-__global__ __launch_bounds__(128) void k_pair_eval(int n, const double* __restrict__ sp,
-                                                   const double* __restrict__ sa, const double* __restrict__ sx,
-                                                   const int* __restrict__ ncount, int cap, const int2* __restrict__ list,
-                                                   Cell cell, double xi, double inv_eta, int parts,
-                                                   double* __restrict__ ybuf) {
-    const int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void pair_eval_body(int n, const double* __restrict__ sp,
+                                               const double* __restrict__ sa, const double* __restrict__ sx,
+                                               const int* __restrict__ ncount, int cap, const int2* __restrict__ list,
+                                               Cell cell, double xi, double inv_eta, int parts,
+                                               double* __restrict__ ybuf, int bid) {
+    const int s = bid * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const double px = sp[3 * s], py = sp[3 * s + 1], pz = sp[3 * s + 2];
     const double ai = sa[s];
@@ -697,6 +705,15 @@ __global__ __launch_bounds__(128) void k_pair_eval(int n, const double* __restri
     for (int c = 0; c < 12; ++c) ybuf[12 * (size_t)s + c] = y[c];
 }
 
+__global__ __launch_bounds__(128) void k_pair_eval(int n, const double* __restrict__ sp,
+                                                   const double* __restrict__ sa, const double* __restrict__ sx,
+                                                   const int* __restrict__ ncount, int cap, const int2* __restrict__ list,
+                                                   Cell cell, double xi, double inv_eta, int parts,
+                                                   double* __restrict__ ybuf) {
+    pair_eval_body(n, sp, sa, sx, ncount, cap, list, cell, xi, inv_eta, parts, ybuf,
+                   xcd_block(blockIdx.x, gridDim.x));
+}
+
 // Pair sum with a group of G lanes per sphere: lane l of the group evaluates
 // list entries l, l + G, ..., and the 12 partial sums are reduced across the
 // group in a fixed butterfly order. G = 64 (a wavefront) serves suspensions
@@ -704,14 +721,14 @@ __global__ __launch_bounds__(128) void k_pair_eval(int n, const double* __restri
 // lanes per sphere read runs of consecutive neighbours together, which cuts
 // the cache lines each load instruction touches.
 template <int G>
-__global__ __launch_bounds__(256) void k_pair_eval_group(int n, const double* __restrict__ sp,
-                                                         const double* __restrict__ sa,
-                                                         const double* __restrict__ sx,
-                                                         const int* __restrict__ ncount, int cap,
-                                                         const int2* __restrict__ list, Cell cell, double xi,
-                                                         double inv_eta, int parts, double* __restrict__ ybuf) {
+__device__ __forceinline__ void pair_eval_group_body(int n, const double* __restrict__ sp,
+                                                     const double* __restrict__ sa,
+                                                     const double* __restrict__ sx,
+                                                     const int* __restrict__ ncount, int cap,
+                                                     const int2* __restrict__ list, Cell cell, double xi,
+                                                     double inv_eta, int parts, double* __restrict__ ybuf, int bid) {
     const int lane = threadIdx.x & (G - 1);
-    const int s = xcd_block(blockIdx.x, gridDim.x) * (256 / G) + threadIdx.x / G;
+    const int s = bid * (256 / G) + threadIdx.x / G;
     if (s >= n) return;   // whole groups only; the kernel has no barrier
     const double px = sp[3 * s], py = sp[3 * s + 1], pz = sp[3 * s + 2];
     const double ai = sa[s];
@@ -747,6 +764,17 @@ __global__ __launch_bounds__(256) void k_pair_eval_group(int n, const double* __
         y[11] += d4[3] * xs[11];
     }
     for (int c = 0; c < 12; ++c) ybuf[12 * (size_t)s + c] = y[c];
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_pair_eval_group(int n, const double* __restrict__ sp,
+                                                         const double* __restrict__ sa,
+                                                         const double* __restrict__ sx,
+                                                         const int* __restrict__ ncount, int cap,
+                                                         const int2* __restrict__ list, Cell cell, double xi,
+                                                         double inv_eta, int parts, double* __restrict__ ybuf) {
+    pair_eval_group_body<G>(n, sp, sa, sx, ncount, cap, list, cell, xi, inv_eta, parts, ybuf,
+                            xcd_block(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -902,12 +930,12 @@ __device__ inline int rec_i0(const R* rec, int d) {
 constexpr int kWinSpheres = 64;
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_window(int n, const double* __restrict__ stf, const double* __restrict__ sa,
-                                                const double* __restrict__ sx, int P, int M, double beta, double bq,
-                                                double bz, R* __restrict__ rec_out) {
+__device__ __forceinline__ void window_body(int n, const double* __restrict__ stf, const double* __restrict__ sa,
+                                            const double* __restrict__ sx, int P, int M, double beta, double bq,
+                                            double bz, R* __restrict__ rec_out, int bid) {
     __shared__ __attribute__((aligned(16))) R buf[kWinSpheres * ((kRecHead + 3 * kMaxP + 3) & ~3)];
     const int RS = rec_stride(P);
-    const int s0 = blockIdx.x * kWinSpheres;
+    const int s0 = bid * kWinSpheres;
     const int ns = min(kWinSpheres, n - s0);
     const int t = threadIdx.x;
     const int q = t >> 2, piece = t & 3;
@@ -952,6 +980,13 @@ __global__ __launch_bounds__(256) void k_window(int n, const double* __restrict_
     for (int e = t; e < ns * RS / PV; e += 256) dst[e] = src[e];
 }
 
+template <typename R>
+__global__ __launch_bounds__(256) void k_window(int n, const double* __restrict__ stf, const double* __restrict__ sa,
+                                                const double* __restrict__ sx, int P, int M, double beta, double bq,
+                                                double bz, R* __restrict__ rec_out) {
+    window_body<R>(n, stf, sa, sx, P, M, beta, bq, bz, rec_out, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // spreading: one workgroup of 256 threads owns one 8^3 tile. The tile is cut
 // into eight 4^3 sub-blocks; wavefront w owns sub-blocks w and w + 4 (one
@@ -985,9 +1020,9 @@ struct SpreadGeom {
 };
 
 template <typename R, bool SHEAR>
-__global__ __launch_bounds__(64 * kSpreadWaves) void k_spread(
+__device__ __forceinline__ void spread_body(
     int n, const R* __restrict__ recs, const int* __restrict__ start, int nb, int M, int P, SpreadGeom sg,
-    R4<R>* __restrict__ grid) {
+    R4<R>* __restrict__ grid, int bid) {
     constexpr int TILE = kTile;
     constexpr int NT = 64 * kSpreadWaves;   // threads per workgroup
     constexpr int NW = kSpreadWaves;        // wavefronts
@@ -1002,9 +1037,7 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void k_spread(
     __shared__ int nbins_used;
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
-    const int tiles = M / TILE;
-    const int ntiles = tiles * tiles * tiles;
-    const unsigned tcode = (unsigned)xcd_block(blockIdx.x, ntiles);
+    const unsigned tcode = (unsigned)bid;   // Morton code of the tile
     const int tx = (int)compact_bits3(tcode), ty = (int)compact_bits3(tcode >> 1), tz = (int)compact_bits3(tcode >> 2);
     // 4^3 sub-blocks: sub-block b at offset (b&1, (b>>1)&1, b>>2) * 4; wavefront
     // w owns sub-blocks w and w + 4
@@ -1159,6 +1192,13 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void k_spread(
     }
 }
 
+template <typename R, bool SHEAR>
+__global__ __launch_bounds__(64 * kSpreadWaves) void k_spread(
+    int n, const R* __restrict__ recs, const int* __restrict__ start, int nb, int M, int P, SpreadGeom sg,
+    R4<R>* __restrict__ grid) {
+    spread_body<R, SHEAR>(n, recs, start, nb, M, P, sg, grid, xcd_block(blockIdx.x, gridDim.x));
+}
+
 // ---------------------------------------------------------------------------
 // FFT building block: Stockham autosort transform over `nlines` lines of
 // length M held in LDS (line-major), ping-ponging between a and b: one
@@ -1230,13 +1270,13 @@ __device__ inline C1<T> up(C1<R> a) { return C1<T>{(T)a.re, (T)a.im}; }
 // x pass, forward, real -> half spectrum. Two real fields share one complex
 // transform (A = f0 + i f1), separated with A(-q) = conj of the partner.
 template <typename R, int M, int LPB>
-__global__ __launch_bounds__(256) void k_fft_x_fwd(const R4<R>* __restrict__ in, C1<R>* __restrict__ out,
-                                                   const double* __restrict__ twg) {
+__device__ __forceinline__ void fft_x_fwd_body(const R4<R>* __restrict__ in, C1<R>* __restrict__ out,
+                                               const double* __restrict__ twg, int bid) {
     using T = R;
     __shared__ C1<T> buf[2][2 * LPB * M];
     __shared__ C1<T> tw[M];
     load_twiddles<T, M>(tw, twg, +1);
-    const size_t line0 = (size_t)blockIdx.x * LPB;
+    const size_t line0 = (size_t)bid * LPB;
     for (int e = threadIdx.x; e < LPB * M; e += blockDim.x) {
         const int l = e / M, x = e - l * M;
         const R4<R> v = in[(line0 + l) * M + x];
@@ -1261,15 +1301,21 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd(const R4<R>* __restrict__ in,
     }
 }
 
+template <typename R, int M, int LPB>
+__global__ __launch_bounds__(256) void k_fft_x_fwd(const R4<R>* __restrict__ in, C1<R>* __restrict__ out,
+                                                   const double* __restrict__ twg) {
+    fft_x_fwd_body<R, M, LPB>(in, out, twg, blockIdx.x);
+}
+
 // x pass, inverse, half spectrum -> real. The qx = M/2 plane is zero.
 template <typename R, int M, int LPB>
-__global__ __launch_bounds__(256) void k_fft_x_inv(const C1<R>* __restrict__ in, R4<R>* __restrict__ out,
-                                                   const double* __restrict__ twg) {
+__device__ __forceinline__ void fft_x_inv_body(const C1<R>* __restrict__ in, R4<R>* __restrict__ out,
+                                               const double* __restrict__ twg, int bid) {
     using T = R;
     __shared__ C1<T> buf[2][2 * LPB * M];
     __shared__ C1<T> tw[M];
     load_twiddles<T, M>(tw, twg, -1);
-    const size_t line0 = (size_t)blockIdx.x * LPB;
+    const size_t line0 = (size_t)bid * LPB;
     // thread (l, q) reads the four spectra at q once and fills x = q and M - q:
     // G0 + i G1 at q, conj G0 + i conj G1 at M - q, zero at the Nyquist plane
     for (int e = threadIdx.x; e < LPB * (M / 2); e += blockDim.x) {
@@ -1298,18 +1344,24 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(const C1<R>* __restrict__ in,
     }
 }
 
+template <typename R, int M, int LPB>
+__global__ __launch_bounds__(256) void k_fft_x_inv(const C1<R>* __restrict__ in, R4<R>* __restrict__ out,
+                                                   const double* __restrict__ twg) {
+    fft_x_inv_body<R, M, LPB>(in, out, twg, blockIdx.x);
+}
+
 // y pass (either direction) on the half spectrum: a block owns W columns of
 // qx at one z; 4 fields per element -> 4W lines of length M.
 template <typename R, int M, int W>
-__global__ __launch_bounds__(256) void k_fft_y(C1<R>* __restrict__ data, const double* __restrict__ twg,
-                                               int sgn) {
+__device__ __forceinline__ void fft_y_body(C1<R>* __restrict__ data, const double* __restrict__ twg,
+                                           int sgn, int bid) {
     using T = R;
     __shared__ C1<T> buf[2][4 * W * M];
     __shared__ C1<T> tw[M];
     load_twiddles<T, M>(tw, twg, sgn);
     constexpr int HX = M / 2;
-    const int x0 = (blockIdx.x % (HX / W)) * W;
-    const int z = blockIdx.x / (HX / W);
+    const int x0 = (bid % (HX / W)) * W;
+    const int z = bid / (HX / W);
     for (int e = threadIdx.x; e < W * M * 4; e += blockDim.x) {
         const int c = e & 3, w = (e >> 2) % W, y = (e >> 2) / W;
         buf[0][(w * 4 + c) * M + y] = up<T>(data[(((size_t)z * M + y) * HX + x0 + w) * 4 + c]);
@@ -1321,6 +1373,12 @@ __global__ __launch_bounds__(256) void k_fft_y(C1<R>* __restrict__ data, const d
         const C1<T> v = r[(w * 4 + c) * M + y];
         data[(((size_t)z * M + y) * HX + x0 + w) * 4 + c] = C1<R>{(R)v.re, (R)v.im};
     }
+}
+
+template <typename R, int M, int W>
+__global__ __launch_bounds__(256) void k_fft_y(C1<R>* __restrict__ data, const double* __restrict__ twg,
+                                               int sgn) {
+    fft_y_body<R, M, W>(data, twg, sgn, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1514,16 +1572,16 @@ __device__ inline double kscale_factor(const KScale& ks, int qx, int qy, int qz,
 // periodic Stokes propagator, the source flow and the pressure), inverse z
 // transform. A block owns W columns of qx at one qy.
 template <typename R, int M, int W>
-__global__ __launch_bounds__(256) void k_fft_z_scale(C1<R>* __restrict__ data,
-                                                     const double* __restrict__ twg, KScale ks) {
+__device__ __forceinline__ void fft_z_scale_body(C1<R>* __restrict__ data,
+                                                 const double* __restrict__ twg, KScale ks, int bid) {
     using T = R;
     __shared__ C1<T> buf[2][4 * W * M];
     __shared__ C1<T> twf[M], twi[M];
     load_twiddles<T, M>(twf, twg, +1);
     load_twiddles<T, M>(twi, twg, -1);
     constexpr int HX = M / 2;
-    const int x0 = (blockIdx.x % (HX / W)) * W;
-    const int y = blockIdx.x / (HX / W);
+    const int x0 = (bid % (HX / W)) * W;
+    const int y = bid / (HX / W);
     const size_t zstride = (size_t)M * HX * 4;
     for (int e = threadIdx.x; e < W * M * 4; e += blockDim.x) {
         const int c = e & 3, w = (e >> 2) % W, z = (e >> 2) / W;
@@ -1570,6 +1628,12 @@ __global__ __launch_bounds__(256) void k_fft_z_scale(C1<R>* __restrict__ data,
         const C1<T> v = r[(w * 4 + c) * M + z];
         data[z * zstride + ((size_t)y * HX + x0 + w) * 4 + c] = C1<R>{(R)v.re, (R)v.im};
     }
+}
+
+template <typename R, int M, int W>
+__global__ __launch_bounds__(256) void k_fft_z_scale(C1<R>* __restrict__ data,
+                                                     const double* __restrict__ twg, KScale ks) {
+    fft_z_scale_body<R, M, W>(data, twg, ks, blockIdx.x);
 }
 
 // z pass of the hybrid size approach (Sec. 3.2): as k_fft_z_scale, and in
@@ -1725,17 +1789,16 @@ constexpr int kGatherLanes = 64;
 // window, so the window is read plainly (eq. parseval-sum-2): U from
 // v + a^2 Lv, Omega from v, E from grad (v + (3/5) a^2 Lv) with grad h = -2 g h.
 template <typename R, int G, bool SHEAR, bool HYB>
-__global__ __launch_bounds__(256) void k_gather(
+__device__ __forceinline__ void gather_body(
     int n, const R* __restrict__ recs, const int* __restrict__ perm, const R4<R>* __restrict__ grid,
     const R4<R>* __restrict__ grid2, int M, int P, SpreadGeom sg, double inv_eta, int parts, int compressible,
-    const double* __restrict__ ybuf, double* __restrict__ yout) {
+    const double* __restrict__ ybuf, double* __restrict__ yout, int bid) {
     static_assert(G == 16 || G == 32 || G == 64, "lanes per sphere");
     constexpr int SPB = 4 * (64 / G);   // spheres per workgroup
     __shared__ R fac[SPB][2 * kMaxP];
     __shared__ R zt[SPB][4][kMaxP + 1];   // f_z(kz) u_z(kz)^k, k = 0..3 (zero past P)
     const int lane = threadIdx.x & (G - 1), sb = threadIdx.x / G;
-    const int nblk = (n + SPB - 1) / SPB;
-    const int s0 = xcd_block(blockIdx.x, nblk) * SPB + sb;
+    const int s0 = bid * SPB + sb;
     const bool active = s0 < n;       // every thread reaches the barrier
     const int s = active ? s0 : n - 1;
     const int mask = M - 1;
@@ -1917,6 +1980,15 @@ __global__ __launch_bounds__(256) void k_gather(
     }
 }
 
+template <typename R, int G, bool SHEAR, bool HYB>
+__global__ __launch_bounds__(256) void k_gather(
+    int n, const R* __restrict__ recs, const int* __restrict__ perm, const R4<R>* __restrict__ grid,
+    const R4<R>* __restrict__ grid2, int M, int P, SpreadGeom sg, double inv_eta, int parts, int compressible,
+    const double* __restrict__ ybuf, double* __restrict__ yout) {
+    gather_body<R, G, SHEAR, HYB>(n, recs, perm, grid, grid2, M, P, sg, inv_eta, parts, compressible, ybuf, yout,
+                                  xcd_block(blockIdx.x, gridDim.x));
+}
+
 // ---------------------------------------------------------------------------
 // host-side launchers (declared in seasd_internal.h)
 
@@ -1927,6 +1999,15 @@ __global__ __launch_bounds__(256) void k_gather(
 template <typename R>
 static int launch_fft_chain_M(int M, void* rgrid, void* spec, void* rgrid2, void* spec2, const double* tw,
                               const KScale& ks, hipStream_t st, PhaseTimer* tm);
+
+// Lines per workgroup of the x passes (LPB) and qx columns per workgroup of
+// the y and z passes (W) for a grid of edge M.
+template <typename R, int M>
+struct FftShape {
+    static constexpr bool dbl = sizeof(R) == 8;
+    static constexpr int LPB = M <= 16 ? 8 : (M <= 64 ? 4 : 2);
+    static constexpr int W = M == 8 ? 2 : (M == 256 ? (dbl ? 1 : 2) : (dbl ? 2 : 4));
+};
 
 #define FFT_CASE(MM, LPB, W)                                                                              \
     case MM: {                                                                                            \
@@ -1985,12 +2066,12 @@ static int launch_fft_chain_M(int M, void* rgrid, void* spec, void* rgrid2, void
     constexpr bool dbl = sizeof(R) == 8;
     const bool hyb = rgrid2 != nullptr && spec2 != nullptr;
     switch (M) {
-        FFT_CASE(8, 8, 2)
-        FFT_CASE(16, 8, (dbl ? 2 : 4))
-        FFT_CASE(32, 4, (dbl ? 2 : 4))
-        FFT_CASE(64, 4, (dbl ? 2 : 4))
-        FFT_CASE(128, 2, (dbl ? 2 : 4))
-        FFT_CASE(256, 2, (dbl ? 1 : 2))
+        FFT_CASE(8, (FftShape<R, 8>::LPB), (FftShape<R, 8>::W))
+        FFT_CASE(16, (FftShape<R, 16>::LPB), (FftShape<R, 16>::W))
+        FFT_CASE(32, (FftShape<R, 32>::LPB), (FftShape<R, 32>::W))
+        FFT_CASE(64, (FftShape<R, 64>::LPB), (FftShape<R, 64>::W))
+        FFT_CASE(128, (FftShape<R, 128>::LPB), (FftShape<R, 128>::W))
+        FFT_CASE(256, (FftShape<R, 256>::LPB), (FftShape<R, 256>::W))
         default:
             return -1;
     }
@@ -2192,6 +2273,277 @@ int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     if (launch_pair(A, st, tm)) return -2;
     if (launch_wave(A, st, tm)) return -1;
     return launch_gather(A, st, tm);
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches over many suspensions: each phase is one launch per kernel
+// variant (precision, sheared or not, pair-sum lanes, FFT size) for the whole
+// batch. Workgroup b takes item items[b] = (suspension, block of that
+// suspension) and runs the same body as the single-suspension kernel on that
+// suspension's arguments, read from a device array. Items are listed
+// suspension by suspension, and the XCD renumbering hands each XCD a
+// contiguous range of them, so one suspension's grid and spheres stay mostly
+// in one L2.
+
+struct MultiSys {
+    ApplyArgs A;
+    SpreadGeom sgs, sgg;   // window geometry of spreading and of the gather
+    KScale ks;
+};
+
+enum MultiKind {
+    kMkBin, kMkPair1, kMkPair64, kMkWindow, kMkSpread, kMkSpreadShear,
+    kMkFftXF, kMkFftY, kMkFftZ, kMkFftXI, kMkGather, kMkGatherShear, kMkCount
+};
+
+struct MultiList {
+    int kind, M;
+    int64_t off;   // first item in the item array
+    int count;     // items = workgroups of the launch
+};
+
+struct MultiPlan {
+    int fp32 = 0;
+    DevBuf sys, items;
+    std::vector<MultiList> lists;
+};
+
+#define MULTI_ITEM()                                              \
+    const int2 it = items[xcd_block(blockIdx.x, gridDim.x)];      \
+    const MultiSys& S = sys[it.x];                                \
+    const ApplyArgs& A = S.A;
+
+__global__ __launch_bounds__(256) void k_bin_gather_multi(const MultiSys* __restrict__ sys,
+                                                          const int2* __restrict__ items) {
+    MULTI_ITEM();
+    bin_gather_body((int)A.n, A.perm, A.pos, A.radius, A.x, A.cell, A.compressible, A.sp, A.st, A.sa, A.sx, A.err,
+                    it.y);
+}
+
+__global__ __launch_bounds__(128) void k_pair_eval_multi(const MultiSys* __restrict__ sys,
+                                                         const int2* __restrict__ items) {
+    MULTI_ITEM();
+    pair_eval_body((int)A.n, A.sp, A.sa, A.sx, A.ncount, A.cap, A.list, A.cell, A.xi, A.inv_eta, A.parts, A.ybuf,
+                   it.y);
+}
+
+__global__ __launch_bounds__(256) void k_pair_eval_group_multi(const MultiSys* __restrict__ sys,
+                                                               const int2* __restrict__ items) {
+    MULTI_ITEM();
+    pair_eval_group_body<64>((int)A.n, A.sp, A.sa, A.sx, A.ncount, A.cap, A.list, A.cell, A.xi, A.inv_eta, A.parts,
+                             A.ybuf, it.y);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_window_multi(const MultiSys* __restrict__ sys,
+                                                      const int2* __restrict__ items) {
+    MULTI_ITEM();
+    window_body<R>((int)A.n, A.st, A.sa, A.sx, A.P, A.M, A.win.beta, A.win.bq, A.win.bz, (R*)A.wrec, it.y);
+}
+
+template <typename R, bool SHEAR>
+__global__ __launch_bounds__(64 * kSpreadWaves) void k_spread_multi(const MultiSys* __restrict__ sys,
+                                                                    const int2* __restrict__ items) {
+    MULTI_ITEM();
+    spread_body<R, SHEAR>((int)A.n, (const R*)A.wrec, A.start, A.nb, A.M, A.P, S.sgs, (R4<R>*)A.rgrid, it.y);
+}
+
+template <typename R, int M, int LPB>
+__global__ __launch_bounds__(256) void k_fft_x_fwd_multi(const MultiSys* __restrict__ sys,
+                                                         const int2* __restrict__ items) {
+    MULTI_ITEM();
+    fft_x_fwd_body<R, M, LPB>((const R4<R>*)A.rgrid, (C1<R>*)A.spec, A.twiddle, it.y);
+}
+
+template <typename R, int M, int W>
+__global__ __launch_bounds__(256) void k_fft_y_multi(const MultiSys* __restrict__ sys, const int2* __restrict__ items,
+                                                     int sgn) {
+    MULTI_ITEM();
+    fft_y_body<R, M, W>((C1<R>*)A.spec, A.twiddle, sgn, it.y);
+}
+
+template <typename R, int M, int W>
+__global__ __launch_bounds__(256) void k_fft_z_scale_multi(const MultiSys* __restrict__ sys,
+                                                           const int2* __restrict__ items) {
+    MULTI_ITEM();
+    fft_z_scale_body<R, M, W>((C1<R>*)A.spec, A.twiddle, S.ks, it.y);
+}
+
+template <typename R, int M, int LPB>
+__global__ __launch_bounds__(256) void k_fft_x_inv_multi(const MultiSys* __restrict__ sys,
+                                                         const int2* __restrict__ items) {
+    MULTI_ITEM();
+    fft_x_inv_body<R, M, LPB>((const C1<R>*)A.spec, (R4<R>*)A.rgrid, A.twiddle, it.y);
+}
+
+template <typename R, bool SHEAR>
+__global__ __launch_bounds__(256) void k_gather_multi(const MultiSys* __restrict__ sys,
+                                                      const int2* __restrict__ items) {
+    MULTI_ITEM();
+    gather_body<R, kGatherLanes, SHEAR, false>((int)A.n, (const R*)A.wrec, A.perm, (const R4<R>*)A.rgrid,
+                                               (const R4<R>*)A.rgrid, A.M, A.P, S.sgg, A.inv_eta, A.parts,
+                                               A.compressible, A.ybuf, A.y, it.y);
+}
+
+static int fft_lpb(int M, bool dbl) { (void)dbl; return M <= 16 ? 8 : (M <= 64 ? 4 : 2); }
+static int fft_w(int M, bool dbl) { return M == 8 ? 2 : (M == 256 ? (dbl ? 1 : 2) : (dbl ? 2 : 4)); }
+
+int multi_plan_build(const ApplyArgs* args, int nsys, MultiPlan** out, hipStream_t st) {
+    *out = nullptr;
+    if (nsys < 1) return -1;
+    auto* P = new MultiPlan();
+    P->fp32 = args[0].fp32;
+    std::vector<MultiSys> sys(nsys);
+    std::vector<std::vector<int2>> per(kMkCount * 9);   // kind x log2(M) - 3 (FFT kinds), else slot 0
+    auto slot = [](int kind, int M) {
+        const int lm = M > 0 ? 31 - __builtin_clz((unsigned)M) - 3 : 0;
+        return kind * 9 + lm;
+    };
+    auto add = [&](int kind, int M, int k, int nblk) {
+        auto& v = per[slot(kind, M)];
+        for (int b = 0; b < nblk; ++b) v.push_back(make_int2(k, b));
+    };
+    for (int k = 0; k < nsys; ++k) {
+        const ApplyArgs& A = args[k];
+        // one precision, the real-space size approach and both parts
+        if (A.fp32 != P->fp32 || A.hybrid || A.parts != (kPartsReal | kPartsWave | kPartsSelf) || A.M < 8 ||
+            A.M > 256 || (A.M & (A.M - 1))) {
+            delete P;
+            return -8;
+        }
+        sys[k].A = A;
+        sys[k].sgs = spread_geom(A, false);
+        sys[k].sgg = spread_geom(A, true);
+        sys[k].ks = kscale_of(A);
+        const int n = (int)A.n, M = A.M;
+        const bool dbl = !A.fp32;
+        add(kMkBin, 0, k, (n + 255) / 256);
+        // the batch fills the GPU however small each suspension is: a
+        // wavefront per sphere only where its lists are uneven
+        if (A.pair_group == 64) add(kMkPair64, 0, k, (n + 3) / 4);
+        else add(kMkPair1, 0, k, (n + 127) / 128);
+        add(kMkWindow, 0, k, (n + kWinSpheres - 1) / kWinSpheres);
+        const int tiles = M / kTile;
+        add(A.win.sheared ? kMkSpreadShear : kMkSpread, 0, k, tiles * tiles * tiles);
+        add(kMkFftXF, M, k, M * M / fft_lpb(M, dbl));
+        add(kMkFftY, M, k, (M / 2 / fft_w(M, dbl)) * M);
+        add(kMkFftZ, M, k, (M / 2 / fft_w(M, dbl)) * M);
+        add(kMkFftXI, M, k, M * M / fft_lpb(M, dbl));
+        constexpr int spb = 4 * (64 / kGatherLanes);
+        add(A.win.sheared ? kMkGatherShear : kMkGather, 0, k, (n + spb - 1) / spb);
+    }
+    std::vector<int2> all;
+    for (int kind = 0; kind < kMkCount; ++kind)
+        for (int lm = 0; lm < 9; ++lm) {
+            auto& v = per[kind * 9 + lm];
+            if (v.empty()) continue;
+            const bool fft = kind == kMkFftXF || kind == kMkFftY || kind == kMkFftZ || kind == kMkFftXI;
+            P->lists.push_back(MultiList{kind, fft ? (8 << lm) : 0, (int64_t)all.size(), (int)v.size()});
+            all.insert(all.end(), v.begin(), v.end());
+        }
+    if (P->sys.ensure(sizeof(MultiSys) * nsys) || P->items.ensure(sizeof(int2) * all.size())) {
+        delete P;
+        return -7;
+    }
+    if (hipMemcpyAsync(P->sys.p, sys.data(), sizeof(MultiSys) * nsys, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(P->items.p, all.data(), sizeof(int2) * all.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        P->sys.release();
+        P->items.release();
+        delete P;
+        return -6;
+    }
+    *out = P;
+    return 0;
+}
+
+void multi_plan_free(MultiPlan* P) {
+    if (!P) return;
+    P->sys.release();
+    P->items.release();
+    delete P;
+}
+
+#define MULTI_LAUNCH(KERNEL, THREADS, ...)                                                                  \
+    hipLaunchKernelGGL(KERNEL, dim3(L.count), dim3(THREADS), 0, st, (const MultiSys*)P->sys.p,              \
+                       (const int2*)P->items.p + L.off, ##__VA_ARGS__)
+
+int multi_queue_moments(const MultiPlan* P, hipStream_t st) {
+    for (const MultiList& L : P->lists)
+        if (L.kind == kMkBin) MULTI_LAUNCH(k_bin_gather_multi, 256);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int multi_queue_pair(const MultiPlan* P, hipStream_t st) {
+    for (const MultiList& L : P->lists) {
+        if (L.kind == kMkPair1) MULTI_LAUNCH(k_pair_eval_multi, 128);
+        if (L.kind == kMkPair64) MULTI_LAUNCH(k_pair_eval_group_multi, 256);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+#define MULTI_FFT_CASE(MM)                                                                                \
+    case MM: {                                                                                            \
+        constexpr int LPB = FftShape<R, MM>::LPB, W = FftShape<R, MM>::W;                                 \
+        if (L.kind == kMkFftXF) MULTI_LAUNCH((k_fft_x_fwd_multi<R, MM, LPB>), 256);                       \
+        if (L.kind == kMkFftY) MULTI_LAUNCH((k_fft_y_multi<R, MM, W>), 256, sgn);                          \
+        if (L.kind == kMkFftZ) MULTI_LAUNCH((k_fft_z_scale_multi<R, MM, W>), 256);                        \
+        if (L.kind == kMkFftXI) MULTI_LAUNCH((k_fft_x_inv_multi<R, MM, LPB>), 256);                       \
+        break;                                                                                            \
+    }
+
+template <typename R>
+static void multi_fft_pass(const MultiPlan* P, int kind, int sgn, hipStream_t st) {
+    for (const MultiList& L : P->lists) {
+        if (L.kind != kind) continue;
+        switch (L.M) {
+            MULTI_FFT_CASE(8)
+            MULTI_FFT_CASE(16)
+            MULTI_FFT_CASE(32)
+            MULTI_FFT_CASE(64)
+            MULTI_FFT_CASE(128)
+            MULTI_FFT_CASE(256)
+            default:
+                break;
+        }
+    }
+}
+
+template <typename R>
+static void multi_wave_R(const MultiPlan* P, hipStream_t st) {
+    for (const MultiList& L : P->lists) {
+        if (L.kind == kMkWindow) MULTI_LAUNCH((k_window_multi<R>), 256);
+    }
+    for (const MultiList& L : P->lists) {
+        if (L.kind == kMkSpread) MULTI_LAUNCH((k_spread_multi<R, false>), 64 * kSpreadWaves);
+        if (L.kind == kMkSpreadShear) MULTI_LAUNCH((k_spread_multi<R, true>), 64 * kSpreadWaves);
+    }
+    multi_fft_pass<R>(P, kMkFftXF, 0, st);
+    multi_fft_pass<R>(P, kMkFftY, +1, st);
+    multi_fft_pass<R>(P, kMkFftZ, 0, st);
+    multi_fft_pass<R>(P, kMkFftY, -1, st);
+    multi_fft_pass<R>(P, kMkFftXI, 0, st);
+}
+
+// window records, spreading and the transform chain of every suspension
+int multi_queue_wave(const MultiPlan* P, hipStream_t st) {
+    if (P->fp32) multi_wave_R<float>(P, st);
+    else multi_wave_R<double>(P, st);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template <typename R>
+static void multi_gather_R(const MultiPlan* P, hipStream_t st) {
+    for (const MultiList& L : P->lists) {
+        if (L.kind == kMkGather) MULTI_LAUNCH((k_gather_multi<R, false>), 256);
+        if (L.kind == kMkGatherShear) MULTI_LAUNCH((k_gather_multi<R, true>), 256);
+    }
+}
+
+int multi_queue_gather(const MultiPlan* P, hipStream_t st) {
+    if (P->fp32) multi_gather_R<float>(P, st);
+    else multi_gather_R<double>(P, st);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 }  // namespace seasd

@@ -1,11 +1,14 @@
 """Batched products: many suspensions of uneven size in one hipGraph launch.
 
-* The plan's result equals, bit for bit, the single-suspension product with
-  the same configuration (same kernels, same binned order).
+* The plan's result equals the single-suspension product with the same
+  configuration (same kernel bodies, same binned order) up to the order of
+  the FP64 pair-sum additions.
 * Replays of the captured graph, with eager work and synchronisation between
   them, each equal the single-suspension result for their own input.
 * The autotuned FP32 configuration of a lognormal suspension meets 2e-6
   against the FP64 oracle.
+* Members of the many-suspension workload match the FP64 oracle inside the
+  batched plan.
 """
 import math
 
@@ -67,7 +70,12 @@ def test_batch_equals_single_products_and_replays(lib, systems):
         del z
         for k, s in enumerate(sus):
             yi = _individual(lib, s, cfgs[k], x[offs[k]:offs[k + 1]])
-            assert np.array_equal(y[offs[k]:offs[k + 1]], yi), (rep, k)
+            # the same kernels on the same data, except that a small
+            # suspension's FP64 pair sum runs a thread per sphere inside the
+            # batch and a wavefront per sphere alone: equal up to the order
+            # of FP64 additions
+            yb = y[offs[k]:offs[k + 1]]
+            assert np.linalg.norm(yb - yi) <= 1e-13 * np.linalg.norm(yi), (rep, k)
     plan.close()
     eng.close()
 
