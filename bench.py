@@ -48,8 +48,8 @@ REF = (0.7, 3.5, 18, 0.95)   # FP64 reference product (SE error ~1e-8)
 # profiles/product_n100000_phi0.4_grid256_traffic.md. Any other configuration
 # reports null.
 MEASURED_TRAFFIC = {
-    ("spread", 256, 16): 321.8e6,
-    ("gather", 256, 16): 1445.1e6,
+    ("spread", 256, 16): 322.9e6,
+    ("gather", 256, 16): 1433.0e6,
 }
 
 
@@ -57,18 +57,18 @@ def phase_cost(phase, n, M, P, s_bytes, pairs):
     """Algorithmic bytes and flops of one launch of a phase: FFT passes read
     and write the 4-field grid once, 8 M^3 s bytes; spreading writes the grid
     once (4 M^3 s) and reads the binned particles (16 doubles each); gather
-    reads the grid once (4 M^3 s) and the particles (28 doubles); flops per
-    (sphere, window point) counted from the kernels' inner loops: 55 for
-    spreading (43 per point for the window weight and the force, torque and
-    stresslet terms, plus the per-column terms shared by a lane's two points)
-    and 30 for gather (13 multiply-adds of the z moments per point plus the
-    per-column terms spread over the column's P points); the pair sum costs
-    about 700 FP64 flops per pair within r_c."""
+    reads the grid once (4 M^3 s) and the particles (28 doubles); flops
+    counted from the kernels' arithmetic per sphere: spreading 71 per window
+    column (its 13 z-polynomial coefficients) plus 26 per window point (13
+    multiply-adds into the four fields), gather 30 per window point (13
+    multiply-adds of the z moments plus the per-column terms spread over the
+    column's P points); the pair sum costs about 700 FP64 flops per pair
+    within r_c."""
     g = M ** 3
     if phase.startswith("fft"):
         return {"bytes": 8 * g * s_bytes, "flops": 0.0}
     if phase == "spread":
-        return {"bytes": 4 * g * s_bytes + n * 16 * 8, "flops": 55.0 * n * P ** 3}
+        return {"bytes": 4 * g * s_bytes + n * 16 * 8, "flops": n * (71.0 * P ** 2 + 26.0 * P ** 3)}
     if phase == "gather":
         return {"bytes": 4 * g * s_bytes + n * 28 * 8, "flops": 30.0 * n * P ** 3}
     if phase == "pair":

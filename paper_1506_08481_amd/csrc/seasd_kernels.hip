@@ -988,16 +988,16 @@ __global__ __launch_bounds__(256) void k_window(int n, const double* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// spreading: one workgroup of 256 threads owns one 8^3 tile. The tile is cut
-// into eight 4^3 sub-blocks; wavefront w owns sub-blocks w and w + 4 (one
-// point per lane in each), so a wavefront skips a sphere whose window misses
-// its sub-block. The spheres that can reach the tile are listed once in LDS,
-// their records are staged 32 at a time, and every point accumulates its sum
-// in registers with Neumaier compensation: each grid point is written by
-// exactly one lane, with no atomics.
+// spreading: one workgroup of 256 threads owns one 8^3 tile. The spheres that
+// can reach the tile are listed once in LDS and their records staged 16 at a
+// time. Lane l of every wavefront owns the tile's (x, y) column l and its 8
+// z-points; the wavefronts take different spheres (w, w + 4, ...), so a
+// sphere costs one wavefront pass: its column coefficients once per lane,
+// then 13 multiply-adds per z-point inside its window. The four wavefronts'
+// partial tiles are summed in FP64 at the end, and each grid point is written
+// by exactly one thread, with no atomics.
 
-// spheres staged per round (N = 1e5, 256^3: 0.82 ms with 16, 0.92 with 8,
-// 0.89 with 32, whose larger LDS buffer costs workgroups per CU)
+// spheres staged per round
 constexpr int kStage = 16;
 constexpr int kMaxCand = 2048; // candidate list held in LDS
 
@@ -1024,14 +1024,23 @@ __device__ __forceinline__ void spread_body(
     int n, const R* __restrict__ recs, const int* __restrict__ start, int nb, int M, int P, SpreadGeom sg,
     R4<R>* __restrict__ grid, int bid) {
     constexpr int TILE = kTile;
-    constexpr int NT = 64 * kSpreadWaves;   // threads per workgroup
     constexpr int NW = kSpreadWaves;        // wavefronts
-    constexpr int NPT = 8 / NW;             // points per lane
-    static_assert(NW == 4, "a lane's points must share x and y");
+    constexpr int NT = 64 * NW;             // threads per workgroup
+    static_assert(TILE * TILE == 64, "a lane owns one (x, y) column of the tile");
     constexpr int MAXB = 125;               // (2 reach + 1)^3 for reach <= 2 (P <= 32)
     constexpr int STAGE = kStage;
     constexpr int MAXC = kMaxCand;
-    __shared__ __attribute__((aligned(16))) R st[STAGE * (kRecHead + 3 * kMaxP)];
+    // staged records and their z bases; the closing cross-wavefront sum
+    // reuses the same bytes
+    constexpr int kStBytes = STAGE * (kRecHead + 3 * kMaxP) * (int)sizeof(R);
+    constexpr int kZbBytes = STAGE * kMaxP * (int)sizeof(R4<R>);
+    constexpr int kRedBytes = NW * 2 * 64 * (int)sizeof(R4<R>);   // two z-planes at a time
+    constexpr int kSmem = (kStBytes + kZbBytes) > kRedBytes ? (kStBytes + kZbBytes) : kRedBytes;
+    static_assert(kStBytes % 16 == 0, "z bases start on 16 bytes");
+    __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
+    R* st = reinterpret_cast<R*>(smem);
+    R4<R>* zb = reinterpret_cast<R4<R>*>(smem + kStBytes);   // [STAGE][kMaxP]: f_z g_z^k, k = 0..3
+    R4<R>* red = reinterpret_cast<R4<R>*>(smem);             // [NW][2][64]
     __shared__ int cand[MAXC];
     __shared__ int bins[MAXB], pre[MAXB + 1];
     __shared__ int nbins_used;
@@ -1039,16 +1048,7 @@ __device__ __forceinline__ void spread_body(
     const int lane = t & 63, wv = t >> 6;
     const unsigned tcode = (unsigned)bid;   // Morton code of the tile
     const int tx = (int)compact_bits3(tcode), ty = (int)compact_bits3(tcode >> 1), tz = (int)compact_bits3(tcode >> 2);
-    // 4^3 sub-blocks: sub-block b at offset (b&1, (b>>1)&1, b>>2) * 4; wavefront
-    // w owns sub-blocks w and w + 4
-    const int ox = lane & 3, oy = (lane >> 2) & 3, oz = lane >> 4;
-    int gx[NPT], gy[NPT], gz[NPT];
-    for (int p = 0; p < NPT; ++p) {
-        const int b = wv + NW * p;
-        gx[p] = tx * TILE + (b & 1) * 4 + ox;
-        gy[p] = ty * TILE + ((b >> 1) & 1) * 4 + oy;
-        gz[p] = tz * TILE + (b >> 2) * 4 + oz;
-    }
+    const int gx = tx * TILE + (lane & 7), gy = ty * TILE + (lane >> 3), gz0 = tz * TILE;
     const int mask = M - 1;
     const int RS = rec_stride(P);
 
@@ -1081,11 +1081,11 @@ __device__ __forceinline__ void spread_body(
     const int ncand = pre[nbins_used];
     const R Gxx = (R)sg.Gxx, Gyx = (R)sg.Gyx, Gyy = (R)sg.Gyy, Gzz = (R)sg.Gzz, cwr = (R)sg.cw;
     const R Qxx = (R)sg.Qxx, Qxy = (R)sg.Qxy, Qyy = (R)sg.Qyy;
-    // FP32: plain sums per stage (part) added to acc with Neumaier
-    // compensation (cmp); FP64 accumulates straight into part
-    R acc[NPT][4], cmp[NPT][4], part[NPT][4];
-    for (int a = 0; a < NPT; ++a)
-        for (int c = 0; c < 4; ++c) acc[a][c] = cmp[a][c] = part[a][c] = R(0);
+    // this wavefront's sums over its spheres at the 8 points of the lane's column
+    R part[TILE][4];
+#pragma unroll
+    for (int p = 0; p < TILE; ++p)
+        for (int c = 0; c < 4; ++c) part[p][c] = R(0);
 
     for (int cbase = 0; cbase < ncand; cbase += MAXC) {
         const int clen = min(MAXC, ncand - cbase);
@@ -1109,25 +1109,31 @@ __device__ __forceinline__ void spread_body(
                 }
             }
             __syncthreads();
-            if constexpr (sizeof(R) == 4)
-                for (int a = 0; a < NPT; ++a)
-                    for (int c = 0; c < 4; ++c) part[a][c] = R(0);
-            for (int q = 0; q < cnt; ++q) {
+            for (int e = t; e < cnt * P; e += NT) {
+                const int q = e / P, kz = e - q * P;
+                const R* rc = st + q * RS;
+                const R fz = rc[kRecHead + 2 * P + kz];
+                const R g = Gzz * (rc[6] + (R)kz);
+                zb[q * kMaxP + kz] = R4<R>{fz, fz * g, fz * g * g, fz * g * g * g};
+            }
+            __syncthreads();
+            // wavefront wv takes staged spheres wv, wv + 4, ...
+            for (int q = wv; q < cnt; q += NW) {
                 const R* rc = static_cast<const R*>(__builtin_assume_aligned(st + q * RS, 16));
                 const int i0x = rec_i0(rc, 0), i0y = rec_i0(rc, 1), i0z = rec_i0(rc, 2);
-                // a lane's points share x and y (they differ by 4 in z)
-                const int kx = (gx[0] - i0x) & mask, ky = (gy[0] - i0y) & mask;
+                // window index of the tile's first z-plane (the same in every lane)
+                const int kz0 = (gz0 - i0z) & mask;
+                bool anyz = false;
+#pragma unroll
+                for (int p = 0; p < TILE; ++p) anyz = anyz || (((kz0 + p) & mask) < P);
+                if (!anyz) continue;
+                const int kx = (gx - i0x) & mask, ky = (gy - i0y) & mask;
                 const bool inxy = (kx < P) && (ky < P);
-                bool in[NPT];
-                int kz[NPT];
-                bool any = false;
-                for (int p = 0; p < NPT; ++p) {
-                    kz[p] = (gz[p] - i0z) & mask;
-                    in[p] = inxy && (kz[p] < P);
-                    any = any || in[p];
-                }
-                if (!__any(any)) continue;
+                if (!__any(inxy)) continue;
                 if (!inxy) continue;
+                // The window is f_x f_y f_z and the Faxen polynomials are
+                // cubic in g_z = Gzz u_z, so the column's contribution at
+                // window z-index kz is sum_k C_k f_z g_z^k per component.
                 const R F0 = rc[8], F1 = rc[9], F2 = rc[10], T0 = rc[11], T1 = rc[12], T2 = rc[13];
                 const R S0 = rc[14], S1 = rc[15], S2 = rc[16], S3 = rc[17], S4 = rc[18], S5 = rc[19];
                 const R sq = rc[20], c0 = rc[21], c1 = rc[22], e0 = rc[23], d1 = rc[3];
@@ -1136,9 +1142,9 @@ __device__ __forceinline__ void spread_body(
                 const R gX = Gxx * ux, gY = Gyx * ux + Gyy * uy;
                 const R wxy = cwr * fa[kx] * fa[P + ky];
                 const R gxy2 = gX * gX + gY * gY;
+                const R a0 = c0 + c1 * gxy2, b0 = e0 + d1 * gxy2;
                 const R Sx = S0 * gX + S3 * gY, Sy = S3 * gX + S1 * gY, Sz = S4 * gX + S5 * gY;
-                const R tz = gX * T1 - gY * T0;
-                const R gz0 = Gzz * rc[6];
+                const R tzz = gX * T1 - gY * T0;
                 R Ex = R(0), Ey = R(0), Ez = R(0);
                 if constexpr (SHEAR) {   // S . (-(4/5) a^2 Qt g_xy)
                     const R ex = -d1 * (Qxx * gX + Qxy * gY), ey = -d1 * (Qxy * gX + Qyy * gY);
@@ -1146,49 +1152,50 @@ __device__ __forceinline__ void spread_body(
                     Ey = S3 * ex + S1 * ey;
                     Ez = S4 * ex + S5 * ey;
                 }
+                const R C0 = wxy * (F0 * a0 - gY * T2 + b0 * Sx + Ex), C1 = wxy * (T1 + b0 * S4);
+                const R C2 = wxy * (F0 * c1 + d1 * Sx), C3 = wxy * (d1 * S4);
+                const R C4 = wxy * (F1 * a0 + gX * T2 + b0 * Sy + Ey), C5 = wxy * (b0 * S5 - T0);
+                const R C6 = wxy * (F1 * c1 + d1 * Sy), C7 = wxy * (d1 * S5);
+                const R C8 = wxy * (F2 * a0 - tzz + b0 * Sz + Ez), C9 = wxy * (b0 * S2);
+                const R C10 = wxy * (F2 * c1 + d1 * Sz), C11 = wxy * (d1 * S2);
+                const R C12 = wxy * sq;
+                const R4<R>* zq = zb + q * kMaxP;
 #pragma unroll
-                for (int p = 0; p < NPT; ++p) {
-                    if (!in[p]) continue;
-                    const R gZ = gz0 + (R)kz[p] * Gzz;
-                    const R g2 = gxy2 + gZ * gZ;
-                    const R w = wxy * fa[2 * P + kz[p]];
-                    const R cF = w * (c0 + c1 * g2);
-                    const R cS = w * (e0 + d1 * g2);
-                    const R Srx = Sx + S4 * gZ;
-                    const R Sry = Sy + S5 * gZ;
-                    const R Srz = Sz + S2 * gZ;
-                    part[p][0] += cF * F0 - w * (gY * T2 - gZ * T1) + cS * Srx;
-                    part[p][1] += cF * F1 - w * (gZ * T0 - gX * T2) + cS * Sry;
-                    part[p][2] += cF * F2 - w * tz + cS * Srz;
-                    part[p][3] += w * sq;
-                    if constexpr (SHEAR) {
-                        part[p][0] += w * Ex;
-                        part[p][1] += w * Ey;
-                        part[p][2] += w * Ez;
-                    }
+                for (int p = 0; p < TILE; ++p) {
+                    const int kz = (kz0 + p) & mask;
+                    if (kz >= P) continue;   // the same in every lane
+                    const R4<R> z = zq[kz];
+                    part[p][0] += C0 * z.x + C1 * z.y + C2 * z.z + C3 * z.w;
+                    part[p][1] += C4 * z.x + C5 * z.y + C6 * z.z + C7 * z.w;
+                    part[p][2] += C8 * z.x + C9 * z.y + C10 * z.z + C11 * z.w;
+                    part[p][3] += C12 * z.x;
                 }
             }
-            if constexpr (sizeof(R) == 4)
-                for (int a = 0; a < NPT; ++a)
-                    for (int c = 0; c < 4; ++c) neumaier(acc[a][c], cmp[a][c], part[a][c]);
-            __syncthreads();
+            __syncthreads();   // the next stage overwrites the records
         }
     }
+    // Sum of the four wavefronts' partial sums in FP64, in a fixed order, two
+    // z-planes at a time: each grid point is written once, with no atomics.
 #pragma unroll
-    for (int p = 0; p < NPT; ++p) {
-        R4<R> out;
-        if constexpr (sizeof(R) == 4) {
-            out.x = acc[p][0] + cmp[p][0];
-            out.y = acc[p][1] + cmp[p][1];
-            out.z = acc[p][2] + cmp[p][2];
-            out.w = acc[p][3] + cmp[p][3];
-        } else {   // FP64 sums need no compensation
-            out.x = part[p][0];
-            out.y = part[p][1];
-            out.z = part[p][2];
-            out.w = part[p][3];
+    for (int p0 = 0; p0 < TILE; p0 += 2) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            red[(wv * 2 + h) * 64 + lane] = R4<R>{part[p0 + h][0], part[p0 + h][1], part[p0 + h][2], part[p0 + h][3]};
+        __syncthreads();
+        if (t < 128) {
+            const int h = t >> 6, l = t & 63;
+            double ox = 0.0, oy = 0.0, oz = 0.0, ow = 0.0;
+            for (int w = 0; w < NW; ++w) {
+                const R4<R> v = red[(w * 2 + h) * 64 + l];
+                ox += (double)v.x;
+                oy += (double)v.y;
+                oz += (double)v.z;
+                ow += (double)v.w;
+            }
+            const int x = tx * TILE + (l & 7), y = ty * TILE + (l >> 3), z = gz0 + p0 + h;
+            grid[((size_t)z * M + y) * M + x] = R4<R>{(R)ox, (R)oy, (R)oz, (R)ow};
         }
-        grid[((size_t)gz[p] * M + gy[p]) * M + gx[p]] = out;
+        __syncthreads();
     }
 }
 
