@@ -60,17 +60,17 @@ def phase_cost(phase, n, M, P, s_bytes, pairs):
     reads the grid once (4 M^3 s) and the particles (28 doubles); flops
     counted from the kernels' arithmetic per sphere: spreading 71 per window
     column (its 13 z-polynomial coefficients) plus 26 per window point (13
-    multiply-adds into the four fields), gather 30 per window point (13
-    multiply-adds of the z moments plus the per-column terms spread over the
-    column's P points); the pair sum costs about 700 FP64 flops per pair
-    within r_c."""
+    multiply-adds into the four fields), gather about 130 per window column
+    (moment polynomials and 13 compensated sums) plus 26 per window point (13
+    multiply-adds of the z moments); the pair sum costs about 700 FP64 flops
+    per pair within r_c."""
     g = M ** 3
     if phase.startswith("fft"):
         return {"bytes": 8 * g * s_bytes, "flops": 0.0}
     if phase == "spread":
         return {"bytes": 4 * g * s_bytes + n * 16 * 8, "flops": n * (71.0 * P ** 2 + 26.0 * P ** 3)}
     if phase == "gather":
-        return {"bytes": 4 * g * s_bytes + n * 28 * 8, "flops": 30.0 * n * P ** 3}
+        return {"bytes": 4 * g * s_bytes + n * 28 * 8, "flops": n * (130.0 * P ** 2 + 26.0 * P ** 3)}
     if phase == "pair":
         return {"bytes": n * 28 * 8, "flops": 700.0 * pairs}
     return {"bytes": n * 64, "flops": 0.0}
