@@ -26,11 +26,11 @@ from paper_1506_08481_amd import workloads as wl
 HASIMOTO_SC = 2.837297
 
 
-def _sc(a, L):
+def _sc(a, L, xi=0.5):
     pos = np.zeros((1, 3))
     rad = np.array([a])
     box = np.eye(3) * L
-    return pos, rad, box, mixed.mobility_fts(pos, rad, box, ewald.converged_params(box, rad, xi=0.5, tol_exp=6.5))
+    return pos, rad, box, mixed.mobility_fts(pos, rad, box, ewald.converged_params(box, rad, xi=xi, tol_exp=6.5))
 
 
 @pytest.mark.parametrize("r", [0.0, 3.0, 40.0])
@@ -57,7 +57,9 @@ def test_single_sphere_in_strain():
     S0 = 20.0 / 3.0 * math.pi * a ** 3 * E
     rel = {}
     for L in (40.0, 80.0):
-        pos, rad, box, M11 = _sc(a, L)
+        # the converged sum does not depend on xi; xi L fixed keeps the
+        # number of wave vectors the same for both cells
+        pos, rad, box, M11 = _sc(a, L, xi=10.0 / L)
         U, F, S = mixed.hi_solve(M11, np.zeros((6, 6)), np.zeros((1, 6)), E, lam=6.0 * math.pi * a)
         assert np.max(np.abs(F)) < 1e-12 and np.max(np.abs(U)) < 1e-12
         rel[L] = np.linalg.norm(S - S0) / np.linalg.norm(S0)
