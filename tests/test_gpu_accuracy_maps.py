@@ -18,8 +18,8 @@ what the text states about them:
 * system size (fig. err_size, P = 13, m = 6.7, r_c = 4 (a_i + a_j)): with
   the cell fixed the error changes little with N, at fixed phi the minimum
   rises with N (larger cells on the same grid), sharply on the coarser grid.
-The measured maps are also the data of the autotuner's error model
-(seasd_autotune), whose predictions are compared with them here.
+The autotuner (seasd_autotune) takes its operating points from scans of
+this kind rather than from a fitted continuous model of these maps.
 """
 import json
 import math
