@@ -1045,7 +1045,9 @@ __device__ __forceinline__ void spread_body(
     __shared__ int bins[MAXB], pre[MAXB + 1];
     __shared__ int nbins_used;
     const int t = threadIdx.x;
-    const int lane = t & 63, wv = t >> 6;
+    // the wavefront index is uniform: kept in a scalar register, the sphere
+    // loop below and its z-plane tests run on the scalar unit
+    const int lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const unsigned tcode = (unsigned)bid;   // Morton code of the tile
     const int tx = (int)compact_bits3(tcode), ty = (int)compact_bits3(tcode >> 1), tz = (int)compact_bits3(tcode >> 2);
     const int gx = tx * TILE + (lane & 7), gy = ty * TILE + (lane >> 3), gz0 = tz * TILE;
@@ -1122,7 +1124,7 @@ __device__ __forceinline__ void spread_body(
                 const R* rc = static_cast<const R*>(__builtin_assume_aligned(st + q * RS, 16));
                 const int i0x = rec_i0(rc, 0), i0y = rec_i0(rc, 1), i0z = rec_i0(rc, 2);
                 // window index of the tile's first z-plane (the same in every lane)
-                const int kz0 = (gz0 - i0z) & mask;
+                const int kz0 = __builtin_amdgcn_readfirstlane((gz0 - i0z) & mask);
                 bool anyz = false;
 #pragma unroll
                 for (int p = 0; p < TILE; ++p) anyz = anyz || (((kz0 + p) & mask) < P);
@@ -1145,18 +1147,18 @@ __device__ __forceinline__ void spread_body(
                 const R a0 = c0 + c1 * gxy2, b0 = e0 + d1 * gxy2;
                 const R Sx = S0 * gX + S3 * gY, Sy = S3 * gX + S1 * gY, Sz = S4 * gX + S5 * gY;
                 const R tzz = gX * T1 - gY * T0;
-                R Ex = R(0), Ey = R(0), Ez = R(0);
+                R u0 = F0 * a0 - gY * T2 + b0 * Sx, u1 = F1 * a0 + gX * T2 + b0 * Sy, u2 = F2 * a0 - tzz + b0 * Sz;
                 if constexpr (SHEAR) {   // S . (-(4/5) a^2 Qt g_xy)
                     const R ex = -d1 * (Qxx * gX + Qxy * gY), ey = -d1 * (Qxy * gX + Qyy * gY);
-                    Ex = S0 * ex + S3 * ey;
-                    Ey = S3 * ex + S1 * ey;
-                    Ez = S4 * ex + S5 * ey;
+                    u0 += S0 * ex + S3 * ey;
+                    u1 += S3 * ex + S1 * ey;
+                    u2 += S4 * ex + S5 * ey;
                 }
-                const R C0 = wxy * (F0 * a0 - gY * T2 + b0 * Sx + Ex), C1 = wxy * (T1 + b0 * S4);
+                const R C0 = wxy * u0, C1 = wxy * (T1 + b0 * S4);
                 const R C2 = wxy * (F0 * c1 + d1 * Sx), C3 = wxy * (d1 * S4);
-                const R C4 = wxy * (F1 * a0 + gX * T2 + b0 * Sy + Ey), C5 = wxy * (b0 * S5 - T0);
+                const R C4 = wxy * u1, C5 = wxy * (b0 * S5 - T0);
                 const R C6 = wxy * (F1 * c1 + d1 * Sy), C7 = wxy * (d1 * S5);
-                const R C8 = wxy * (F2 * a0 - tzz + b0 * Sz + Ez), C9 = wxy * (b0 * S2);
+                const R C8 = wxy * u2, C9 = wxy * (b0 * S2);
                 const R C10 = wxy * (F2 * c1 + d1 * Sz), C11 = wxy * (d1 * S2);
                 const R C12 = wxy * sq;
                 const R4<R>* zq = zb + q * kMaxP;
@@ -1165,10 +1167,11 @@ __device__ __forceinline__ void spread_body(
                     const int kz = (kz0 + p) & mask;
                     if (kz >= P) continue;   // the same in every lane
                     const R4<R> z = zq[kz];
-                    part[p][0] += C0 * z.x + C1 * z.y + C2 * z.z + C3 * z.w;
-                    part[p][1] += C4 * z.x + C5 * z.y + C6 * z.z + C7 * z.w;
-                    part[p][2] += C8 * z.x + C9 * z.y + C10 * z.z + C11 * z.w;
-                    part[p][3] += C12 * z.x;
+                    // one fused multiply-add per term, straight into the sums
+                    part[p][0] = fma(C3, z.w, fma(C2, z.z, fma(C1, z.y, fma(C0, z.x, part[p][0]))));
+                    part[p][1] = fma(C7, z.w, fma(C6, z.z, fma(C5, z.y, fma(C4, z.x, part[p][1]))));
+                    part[p][2] = fma(C11, z.w, fma(C10, z.z, fma(C9, z.y, fma(C8, z.x, part[p][2]))));
+                    part[p][3] = fma(C12, z.x, part[p][3]);
                 }
             }
             __syncthreads();   // the next stage overwrites the records
