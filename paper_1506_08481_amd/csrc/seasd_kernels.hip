@@ -1409,16 +1409,18 @@ __device__ inline void dft4(C1<T>& a0, C1<T>& a1, C1<T>& a2, C1<T>& a3, int sgn)
     a3 = csub(d02, d13);
 }
 
-// 16-point DFT in registers (4 x 4); tw256 is the table of w256^j (same
-// sign), so w16^j = tw256[16 j]. On return X_k sits in v[4 (k % 4) + k / 4].
-template <typename T>
-__device__ inline void dft16(C1<T>* v, const C1<T>* tw256, int sgn) {
+// 16-point DFT in registers (4 x 4); tw is the table of wM^j (same sign)
+// for lines of M points, so w16^j = tw[(M / 16) j]. On return X_k sits in
+// v[4 (k % 4) + k / 4].
+template <typename T, int M = 256>
+__device__ inline void dft16(C1<T>* v, const C1<T>* tw, int sgn) {
 #pragma unroll
     for (int m2 = 0; m2 < 4; ++m2) dft4(v[m2], v[4 + m2], v[8 + m2], v[12 + m2], sgn);
 #pragma unroll
     for (int k1 = 1; k1 < 4; ++k1)
 #pragma unroll
-        for (int m2 = 1; m2 < 4; ++m2) v[4 * k1 + m2] = cmul(tw256[(16 * m2 * k1) & 255], v[4 * k1 + m2]);
+        for (int m2 = 1; m2 < 4; ++m2)
+            v[4 * k1 + m2] = cmul(tw[((M / 16) * m2 * k1) & (M - 1)], v[4 * k1 + m2]);
 #pragma unroll
     for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3], sgn);
 }
@@ -1782,6 +1784,269 @@ __global__ __launch_bounds__(256) void k_fft_z256(C1<R>* __restrict__ data, cons
 }
 
 // ---------------------------------------------------------------------------
+// 128-point lines as 16 x 8 (four-step), FP32 storage: 8 threads own a line;
+// thread t holds x[8 n1 + t], n1 = 0..15, transforms over n1 (16 points) in
+// registers, applies w^(t k1), exchanges through LDS once and transforms
+// rows k1 = t and t + 8 over the former thread index (8 points each):
+// X[k1 + 16 k2] = sum_t w^(16 t k2) w^(t k1) sum_n1 x[8 n1 + t] w^(8 n1 k1).
+// 32 lines per workgroup, so the y and z passes read whole 256-byte rows.
+
+constexpr int kL8Row = 9;             // padded row of the 16 x 8 exchange
+constexpr int kL8Line = 16 * 9 + 1;   // padded line (145 complex)
+
+// 8-point DFT of v[0..7] in place (two 4-point DFTs and w8^k = tw128[16 k])
+template <typename T>
+__device__ inline void dft8_128(C1<T>* v, const C1<T>* tw128, int sgn) {
+    dft4(v[0], v[2], v[4], v[6], sgn);
+    dft4(v[1], v[3], v[5], v[7], sgn);
+    C1<T> o[8];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const C1<T> b = k == 0 ? v[1] : cmul(tw128[16 * k], v[2 * k + 1]);
+        o[k] = cadd(v[2 * k], b);
+        o[k + 4] = csub(v[2 * k], b);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = o[k];
+}
+
+// v[n1] = x[8 n1 + t] of one line in; X[t + 16 k2] = v[k2] and
+// X[t + 8 + 16 k2] = v[8 + k2] out (k2 = 0..7). Every thread of the
+// workgroup calls it (one barrier inside).
+template <typename T>
+__device__ inline void fft128_line(C1<T>* v, C1<T>* ln, const C1<T>* tw, int t, int sgn) {
+    dft16<T, 128>(v, tw, sgn);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1)
+        ln[k1 * kL8Row + t] = cmul(tw[(t * k1) & 127], v[4 * (k1 & 3) + (k1 >> 2)]);
+    __syncthreads();
+#pragma unroll
+    for (int n2 = 0; n2 < 8; ++n2) {
+        v[n2] = ln[t * kL8Row + n2];
+        v[8 + n2] = ln[(t + 8) * kL8Row + n2];
+    }
+    dft8_128(v, tw, sgn);
+    dft8_128(v + 8, tw, sgn);
+}
+
+// y pass, M = 128: a workgroup owns 8 qx columns at one z (32 lines)
+template <typename R>
+__device__ __forceinline__ void fft_y128_body(C1<R>* __restrict__ data, const double* __restrict__ twg, int sgn,
+                                              int bid) {
+    constexpr int M = 128, HX = 64, W = 8;
+    __shared__ C1<R> buf[32 * kL8Line];
+    __shared__ C1<R> tw[M];
+    load_twiddles<R, M>(tw, twg, sgn);
+    const int lane = threadIdx.x & 63;
+    const int l = lane & 31, t = (lane >> 5) + 2 * (threadIdx.x >> 6);
+    const int x0 = (bid % (HX / W)) * W;
+    const int z = bid / (HX / W);
+    C1<R>* base = data + ((size_t)z * M * HX + x0) * 4 + l;   // + (y HX) * 4
+    C1<R> v[16];
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) v[n1] = base[(size_t)(8 * n1 + t) * HX * 4];
+    __syncthreads();   // twiddles
+    fft128_line(v, buf + l * kL8Line, tw, t, sgn);
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) {
+        base[(size_t)(t + 16 * k2) * HX * 4] = v[k2];
+        base[(size_t)(t + 8 + 16 * k2) * HX * 4] = v[8 + k2];
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_y128(C1<R>* __restrict__ data, const double* __restrict__ twg,
+                                                  int sgn) {
+    fft_y128_body<R>(data, twg, sgn, blockIdx.x);
+}
+
+// z pass, M = 128: forward z transform, k-space multiply (as in
+// k_fft_z_scale), inverse z transform; a workgroup owns 8 qx columns at one qy
+template <typename R>
+__device__ __forceinline__ void fft_z128_body(C1<R>* __restrict__ data, const double* __restrict__ twg, KScale ks,
+                                              int bid) {
+    constexpr int M = 128, HX = 64, W = 8;
+    __shared__ C1<R> buf[32 * kL8Line];
+    __shared__ C1<R> twf[M], twi[M];
+    load_twiddles<R, M>(twf, twg, +1);
+    load_twiddles<R, M>(twi, twg, -1);
+    const int lane = threadIdx.x & 63;
+    const int l = lane & 31, t = (lane >> 5) + 2 * (threadIdx.x >> 6);
+    const int x0 = (bid % (HX / W)) * W;
+    const int y = bid / (HX / W);
+    const size_t zstride = (size_t)M * HX * 4;
+    C1<R>* base = data + ((size_t)y * HX + x0) * 4 + l;   // + z zstride
+    C1<R>* ln = buf + l * kL8Line;
+    C1<R> v[16];
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) v[n1] = base[(size_t)(8 * n1 + t) * zstride];
+    __syncthreads();   // twiddles
+    fft128_line(v, ln, twf, t, +1);
+    __syncthreads();   // every thread has read its exchange rows
+    // spectrum of this line in natural order: element qz at ln[qz]
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) {
+        ln[t + 16 * k2] = v[k2];
+        ln[t + 8 + 16 * k2] = v[8 + k2];
+    }
+    __syncthreads();
+    const int qy = (y < M / 2) ? y : y - M;
+    for (int e = threadIdx.x; e < W * M; e += 256) {
+        const int w = e & 7, z = e >> 3;
+        const int qx = x0 + w;
+        const int qz = (z < M / 2) ? z : z - M;
+        C1<R>* f0 = buf + (w * 4 + 0) * kL8Line + z;
+        C1<R>* f1 = buf + (w * 4 + 1) * kL8Line + z;
+        C1<R>* f2 = buf + (w * 4 + 2) * kL8Line + z;
+        C1<R>* f3 = buf + (w * 4 + 3) * kL8Line + z;
+        const bool zero = (qx == 0 && qy == 0 && qz == 0) || (y == M / 2) || (z == M / 2);
+        if (zero) {
+            *f0 = *f1 = *f2 = *f3 = {R(0), R(0)};
+            continue;
+        }
+        double kx, ky, kz, k2;
+        const double ex = kscale_factor(ks, qx, qy, qz, kx, ky, kz, k2);
+        const R st = (R)(ks.inv_eta * (1.0 + k2 * ks.inv4xi2) * ex);
+        const R lp = (R)ex;
+        const R rkx = (R)kx, rky = (R)ky, rkz = (R)kz, ik2 = (R)(1.0 / k2);
+        const C1<R> h0 = *f0, h1 = *f1, h2 = *f2, h3 = *f3;
+        const C1<R> kf = {rkx * h0.re + rky * h1.re + rkz * h2.re, rkx * h0.im + rky * h1.im + rkz * h2.im};
+        const C1<R> pk = {kf.re * ik2, kf.im * ik2};
+        const R sq = R(0.25) * (R)ks.inv_eta * lp;
+        *f0 = {st * (h0.re - rkx * pk.re) - sq * rkx * h3.im, st * (h0.im - rkx * pk.im) + sq * rkx * h3.re};
+        *f1 = {st * (h1.re - rky * pk.re) - sq * rky * h3.im, st * (h1.im - rky * pk.im) + sq * rky * h3.re};
+        *f2 = {st * (h2.re - rkz * pk.re) - sq * rkz * h3.im, st * (h2.im - rkz * pk.im) + sq * rkz * h3.re};
+        *f3 = {-lp * kf.im, lp * kf.re};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) v[n1] = ln[8 * n1 + t];
+    __syncthreads();   // the exchange below reuses the line
+    fft128_line(v, ln, twi, t, -1);
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) {
+        base[(size_t)(t + 16 * k2) * zstride] = v[k2];
+        base[(size_t)(t + 8 + 16 * k2) * zstride] = v[8 + k2];
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_z128(C1<R>* __restrict__ data, const double* __restrict__ twg,
+                                                  KScale ks) {
+    fft_z128_body<R>(data, twg, ks, blockIdx.x);
+}
+
+// x pass, forward, M = 128: 16 real lines per workgroup, each a pair of
+// complex transforms (x + i y fields, z + i w fields), then the same
+// half-spectrum unpacking as k_fft_x_fwd
+template <typename R>
+__device__ __forceinline__ void fft_x_fwd128_body(const R4<R>* __restrict__ in, C1<R>* __restrict__ out,
+                                                  const double* __restrict__ twg, int bid) {
+    constexpr int M = 128;
+    __shared__ C1<R> buf[32 * kL8Line];
+    __shared__ C1<R> tw[M];
+    load_twiddles<R, M>(tw, twg, +1);
+    const int lane = threadIdx.x & 63;
+    const int l32 = (lane >> 3) + 8 * (threadIdx.x >> 6), t = lane & 7;
+    const int line = l32 >> 1, g = l32 & 1;
+    const size_t line0 = (size_t)bid * 16;
+    // fields (x, y) and (z, w) of one line sit side by side in a wavefront
+    const C1<R>* src = reinterpret_cast<const C1<R>*>(in) + ((line0 + line) * M + t) * 2 + g;
+    C1<R> v[16];
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) v[n1] = src[16 * n1];
+    __syncthreads();   // twiddles
+    C1<R>* ln = buf + l32 * kL8Line;
+    fft128_line(v, ln, tw, t, +1);
+    __syncthreads();
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) {
+        ln[t + 16 * k2] = v[k2];
+        ln[t + 8 + 16 * k2] = v[8 + k2];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 16 * (M / 2); e += 256) {
+        const int l = e >> 6, q = e & 63;
+        const int qn = (M - q) & (M - 1);
+        C1<R> o[4];
+#pragma unroll
+        for (int gg = 0; gg < 2; ++gg) {
+            const C1<R> A = buf[(2 * l + gg) * kL8Line + q];
+            const C1<R> B = buf[(2 * l + gg) * kL8Line + qn];
+            o[2 * gg] = {R(0.5) * (A.re + B.re), R(0.5) * (A.im - B.im)};
+            o[2 * gg + 1] = {R(0.5) * (A.im + B.im), R(-0.5) * (A.re - B.re)};
+        }
+        C1<R>* dst = out + ((line0 + l) * (M / 2) + q) * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) dst[c] = o[c];
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_x_fwd128(const R4<R>* __restrict__ in, C1<R>* __restrict__ out,
+                                                      const double* __restrict__ twg) {
+    fft_x_fwd128_body<R>(in, out, twg, blockIdx.x);
+}
+
+// x pass, inverse, M = 128: half spectrum -> 16 real lines per workgroup
+template <typename R>
+__device__ __forceinline__ void fft_x_inv128_body(const C1<R>* __restrict__ in, R4<R>* __restrict__ out,
+                                                  const double* __restrict__ twg, int bid) {
+    constexpr int M = 128;
+    __shared__ C1<R> buf[32 * kL8Line];
+    __shared__ C1<R> tw[M];
+    load_twiddles<R, M>(tw, twg, -1);
+    const size_t line0 = (size_t)bid * 16;
+    // thread (l, q) reads the four spectra at q once and fills x = q and M - q
+    for (int e = threadIdx.x; e < 16 * (M / 2); e += 256) {
+        const int l = e >> 6, q = e & 63;
+        const C1<R>* sp = in + ((line0 + l) * (M / 2) + q) * 4;
+        C1<R> S[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) S[c] = sp[c];
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const C1<R> a = S[2 * g], b = S[2 * g + 1];
+            C1<R>* ln = buf + (2 * l + g) * kL8Line;
+            if (q == 0) {
+                ln[0] = {a.re, b.re};
+                ln[M / 2] = {R(0), R(0)};
+            } else {
+                ln[q] = {a.re - b.im, a.im + b.re};
+                ln[M - q] = {a.re + b.im, b.re - a.im};
+            }
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int l32 = (lane >> 3) + 8 * (threadIdx.x >> 6), t = lane & 7;
+    C1<R>* ln = buf + l32 * kL8Line;
+    C1<R> v[16];
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) v[n1] = ln[8 * n1 + t];
+    __syncthreads();   // the exchange below reuses the line
+    fft128_line(v, ln, tw, t, -1);
+    __syncthreads();
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) {
+        ln[t + 16 * k2] = v[k2];
+        ln[t + 8 + 16 * k2] = v[8 + k2];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 16 * M; e += 256) {
+        const int l = e >> 7, x = e & 127;
+        const C1<R> A = buf[(2 * l) * kL8Line + x], B = buf[(2 * l + 1) * kL8Line + x];
+        out[(line0 + l) * M + x] = {A.re, A.im, B.re, B.im};
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_x_inv128(const C1<R>* __restrict__ in, R4<R>* __restrict__ out,
+                                                      const double* __restrict__ twg) {
+    fft_x_inv128_body<R>(in, out, twg, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
 // gather: one wavefront per sphere (binned order, contiguous per XCD); each
 // lane owns some (x, y) columns of the window and sums them over z in R, the
 // column sums are added with Neumaier compensation and the wavefront reduces
@@ -2023,9 +2288,13 @@ struct FftShape {
     case MM: {                                                                                            \
         const int lines = MM * MM;                                                                        \
         const bool sp256 = MM == 256 && !dbl && !hyb;                                                     \
+        const bool sp128 = MM == 128 && !dbl && !hyb;                                                     \
         tm->begin(kPhaseFftXFwd, st);                                                                     \
         if (sp256)                                                                                        \
             hipLaunchKernelGGL((k_fft_x_fwd256<R>), dim3(lines / 8), dim3(256), 0, st,                    \
+                               (const R4<R>*)rgrid, (C1<R>*)spec, tw);                                    \
+        else if (sp128)                                                                                   \
+            hipLaunchKernelGGL((k_fft_x_fwd128<R>), dim3(lines / 16), dim3(256), 0, st,                   \
                                (const R4<R>*)rgrid, (C1<R>*)spec, tw);                                    \
         else                                                                                              \
             hipLaunchKernelGGL((k_fft_x_fwd<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,            \
@@ -2037,6 +2306,13 @@ struct FftShape {
             hipLaunchKernelGGL((k_fft_z256<R>), dim3(32 * 256), dim3(256), 0, st, (C1<R>*)spec, tw, ks);  \
             tm->begin(kPhaseFftYInv, st);                                                                 \
             hipLaunchKernelGGL((k_fft_y256<R>), dim3(32 * 256), dim3(256), 0, st, (C1<R>*)spec, tw, -1);  \
+        } else if (sp128) {                                                                               \
+            tm->begin(kPhaseFftYFwd, st);                                                                 \
+            hipLaunchKernelGGL((k_fft_y128<R>), dim3(8 * 128), dim3(256), 0, st, (C1<R>*)spec, tw, +1);   \
+            tm->begin(kPhaseFftZ, st);                                                                    \
+            hipLaunchKernelGGL((k_fft_z128<R>), dim3(8 * 128), dim3(256), 0, st, (C1<R>*)spec, tw, ks);   \
+            tm->begin(kPhaseFftYInv, st);                                                                 \
+            hipLaunchKernelGGL((k_fft_y128<R>), dim3(8 * 128), dim3(256), 0, st, (C1<R>*)spec, tw, -1);   \
         } else {                                                                                          \
             tm->begin(kPhaseFftYFwd, st);                                                                 \
             hipLaunchKernelGGL((k_fft_y<R, MM, W>), dim3((MM / 2 / W) * MM), dim3(256), 0, st,            \
@@ -2060,6 +2336,9 @@ struct FftShape {
         tm->begin(kPhaseFftXInv, st);                                                                     \
         if (sp256)                                                                                        \
             hipLaunchKernelGGL((k_fft_x_inv256<R>), dim3(lines / 8), dim3(256), 0, st,                    \
+                               (const C1<R>*)spec, (R4<R>*)rgrid, tw);                                    \
+        else if (sp128)                                                                                   \
+            hipLaunchKernelGGL((k_fft_x_inv128<R>), dim3(lines / 16), dim3(256), 0, st,                   \
                                (const C1<R>*)spec, (R4<R>*)rgrid, tw);                                    \
         else                                                                                              \
             hipLaunchKernelGGL((k_fft_x_inv<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,            \
@@ -2386,6 +2665,35 @@ __global__ __launch_bounds__(256) void k_fft_x_inv_multi(const MultiSys* __restr
     fft_x_inv_body<R, M, LPB>((const C1<R>*)A.spec, (R4<R>*)A.rgrid, A.twiddle, it.y);
 }
 
+// the 16 x 8 four-step passes of FP32 grids of edge 128
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_x_fwd128_multi(const MultiSys* __restrict__ sys,
+                                                            const int2* __restrict__ items) {
+    MULTI_ITEM();
+    fft_x_fwd128_body<R>((const R4<R>*)A.rgrid, (C1<R>*)A.spec, A.twiddle, it.y);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_y128_multi(const MultiSys* __restrict__ sys,
+                                                        const int2* __restrict__ items, int sgn) {
+    MULTI_ITEM();
+    fft_y128_body<R>((C1<R>*)A.spec, A.twiddle, sgn, it.y);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_z128_multi(const MultiSys* __restrict__ sys,
+                                                        const int2* __restrict__ items) {
+    MULTI_ITEM();
+    fft_z128_body<R>((C1<R>*)A.spec, A.twiddle, S.ks, it.y);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_x_inv128_multi(const MultiSys* __restrict__ sys,
+                                                            const int2* __restrict__ items) {
+    MULTI_ITEM();
+    fft_x_inv128_body<R>((const C1<R>*)A.spec, (R4<R>*)A.rgrid, A.twiddle, it.y);
+}
+
 template <typename R, bool SHEAR>
 __global__ __launch_bounds__(256) void k_gather_multi(const MultiSys* __restrict__ sys,
                                                       const int2* __restrict__ items) {
@@ -2435,10 +2743,11 @@ int multi_plan_build(const ApplyArgs* args, int nsys, MultiPlan** out, hipStream
         add(kMkWindow, 0, k, (n + kWinSpheres - 1) / kWinSpheres);
         const int tiles = M / kTile;
         add(A.win.sheared ? kMkSpreadShear : kMkSpread, 0, k, tiles * tiles * tiles);
-        add(kMkFftXF, M, k, M * M / fft_lpb(M, dbl));
-        add(kMkFftY, M, k, (M / 2 / fft_w(M, dbl)) * M);
-        add(kMkFftZ, M, k, (M / 2 / fft_w(M, dbl)) * M);
-        add(kMkFftXI, M, k, M * M / fft_lpb(M, dbl));
+        const bool f128 = M == 128 && !dbl;   // the 16 x 8 four-step passes
+        add(kMkFftXF, M, k, f128 ? M * M / 16 : M * M / fft_lpb(M, dbl));
+        add(kMkFftY, M, k, f128 ? 8 * M : (M / 2 / fft_w(M, dbl)) * M);
+        add(kMkFftZ, M, k, f128 ? 8 * M : (M / 2 / fft_w(M, dbl)) * M);
+        add(kMkFftXI, M, k, f128 ? M * M / 16 : M * M / fft_lpb(M, dbl));
         constexpr int spb = 4 * (64 / kGatherLanes);
         add(A.win.sheared ? kMkGatherShear : kMkGather, 0, k, (n + spb - 1) / spb);
     }
@@ -2506,6 +2815,13 @@ template <typename R>
 static void multi_fft_pass(const MultiPlan* P, int kind, int sgn, hipStream_t st) {
     for (const MultiList& L : P->lists) {
         if (L.kind != kind) continue;
+        if (L.M == 128 && sizeof(R) == 4) {
+            if (kind == kMkFftXF) MULTI_LAUNCH((k_fft_x_fwd128_multi<R>), 256);
+            if (kind == kMkFftY) MULTI_LAUNCH((k_fft_y128_multi<R>), 256, sgn);
+            if (kind == kMkFftZ) MULTI_LAUNCH((k_fft_z128_multi<R>), 256);
+            if (kind == kMkFftXI) MULTI_LAUNCH((k_fft_x_inv128_multi<R>), 256);
+            continue;
+        }
         switch (L.M) {
             MULTI_FFT_CASE(8)
             MULTI_FFT_CASE(16)
