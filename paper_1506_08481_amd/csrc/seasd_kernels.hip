@@ -1784,25 +1784,35 @@ __global__ __launch_bounds__(256) void k_fft_z256(C1<R>* __restrict__ data, cons
 }
 
 // ---------------------------------------------------------------------------
-// 128-point lines as 16 x 8 (four-step), FP32 storage: 8 threads own a line;
-// thread t holds x[8 n1 + t], n1 = 0..15, transforms over n1 (16 points) in
-// registers, applies w^(t k1), exchanges through LDS once and transforms
-// rows k1 = t and t + 8 over the former thread index (8 points each):
-// X[k1 + 16 k2] = sum_t w^(16 t k2) w^(t k1) sum_n1 x[8 n1 + t] w^(8 n1 k1).
+// 128- and 64-point lines as four-step transforms, FP32 storage: 8 threads
+// own a line and thread t holds x[8 n1 + t], n1 = 0..M/8 - 1.
+//   M = 128 (16 x 8): a 16-point DFT over n1 in registers, w^(t k1), one LDS
+//     exchange, then the rows k1 = t and t + 8 as 8-point DFTs over the
+//     former thread index: X[k1 + 16 k2] = sum_t w^(16 t k2) w^(t k1)
+//     sum_n1 x[8 n1 + t] w^(8 n1 k1).
+//   M = 64 (8 x 8): the same with an 8-point DFT over n1 and one row per
+//     thread: X[t + 8 k2].
 // 32 lines per workgroup, so the y and z passes read whole 256-byte rows.
 
-constexpr int kL8Row = 9;             // padded row of the 16 x 8 exchange
-constexpr int kL8Line = 16 * 9 + 1;   // padded line (145 complex)
+constexpr int kL8Row = 9;   // padded row of the exchange (8 entries)
 
-// 8-point DFT of v[0..7] in place (two 4-point DFTs and w8^k = tw128[16 k])
-template <typename T>
-__device__ inline void dft8_128(C1<T>* v, const C1<T>* tw128, int sgn) {
+template <int M>
+struct Fft8Line {
+    static constexpr int NV = M / 8;                    // values per thread
+    static constexpr int LINE = NV * kL8Row + 1;        // padded line in LDS
+    // position along the line of the thread's j-th output value
+    __device__ static int out(int t, int j) { return M == 128 ? t + (j >> 3) * 8 + 16 * (j & 7) : t + 8 * j; }
+};
+
+// 8-point DFT of v[0..7] in place (two 4-point DFTs and w8^k = tw[(M/8) k])
+template <typename T, int M>
+__device__ inline void dft8(C1<T>* v, const C1<T>* tw, int sgn) {
     dft4(v[0], v[2], v[4], v[6], sgn);
     dft4(v[1], v[3], v[5], v[7], sgn);
     C1<T> o[8];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const C1<T> b = k == 0 ? v[1] : cmul(tw128[16 * k], v[2 * k + 1]);
+        const C1<T> b = k == 0 ? v[1] : cmul(tw[(M / 8) * k], v[2 * k + 1]);
         o[k] = cadd(v[2 * k], b);
         o[k + 4] = csub(v[2 * k], b);
     }
@@ -1810,31 +1820,35 @@ __device__ inline void dft8_128(C1<T>* v, const C1<T>* tw128, int sgn) {
     for (int k = 0; k < 8; ++k) v[k] = o[k];
 }
 
-// v[n1] = x[8 n1 + t] of one line in; X[t + 16 k2] = v[k2] and
-// X[t + 8 + 16 k2] = v[8 + k2] out (k2 = 0..7). Every thread of the
-// workgroup calls it (one barrier inside).
-template <typename T>
-__device__ inline void fft128_line(C1<T>* v, C1<T>* ln, const C1<T>* tw, int t, int sgn) {
-    dft16<T, 128>(v, tw, sgn);
+// v[n1] = x[8 n1 + t] of one line in; X[Fft8Line<M>::out(t, j)] = v[j] out.
+// Every thread of the workgroup calls it (one barrier inside).
+template <typename T, int M>
+__device__ inline void fft8_line(C1<T>* v, C1<T>* ln, const C1<T>* tw, int t, int sgn) {
+    static_assert(M == 64 || M == 128, "lines of 64 or 128 points");
+    constexpr int NV = M / 8;
+    if constexpr (M == 128) dft16<T, 128>(v, tw, sgn);
+    else dft8<T, 64>(v, tw, sgn);
 #pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1)
-        ln[k1 * kL8Row + t] = cmul(tw[(t * k1) & 127], v[4 * (k1 & 3) + (k1 >> 2)]);
+    for (int k1 = 0; k1 < NV; ++k1) {
+        // the k1-th output of the first DFT
+        const int src = M == 128 ? 4 * (k1 & 3) + (k1 >> 2) : k1;
+        ln[k1 * kL8Row + t] = cmul(tw[(t * k1) & (M - 1)], v[src]);
+    }
     __syncthreads();
 #pragma unroll
-    for (int n2 = 0; n2 < 8; ++n2) {
-        v[n2] = ln[t * kL8Row + n2];
-        v[8 + n2] = ln[(t + 8) * kL8Row + n2];
-    }
-    dft8_128(v, tw, sgn);
-    dft8_128(v + 8, tw, sgn);
+    for (int r = 0; r < NV / 8; ++r)
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) v[8 * r + n2] = ln[(t + 8 * r) * kL8Row + n2];
+#pragma unroll
+    for (int r = 0; r < NV / 8; ++r) dft8<T, M>(v + 8 * r, tw, sgn);
 }
 
-// y pass, M = 128: a workgroup owns 8 qx columns at one z (32 lines)
-template <typename R>
-__device__ __forceinline__ void fft_y128_body(C1<R>* __restrict__ data, const double* __restrict__ twg, int sgn,
+// y pass, M = 64 or 128: a workgroup owns 8 qx columns at one z (32 lines)
+template <typename R, int M>
+__device__ __forceinline__ void fft_y8_body(C1<R>* __restrict__ data, const double* __restrict__ twg, int sgn,
                                               int bid) {
-    constexpr int M = 128, HX = 64, W = 8;
-    __shared__ C1<R> buf[32 * kL8Line];
+    constexpr int HX = M / 2, W = 8, NV = Fft8Line<M>::NV;
+    __shared__ C1<R> buf[32 * Fft8Line<M>::LINE];
     __shared__ C1<R> tw[M];
     load_twiddles<R, M>(tw, twg, sgn);
     const int lane = threadIdx.x & 63;
@@ -1842,31 +1856,28 @@ __device__ __forceinline__ void fft_y128_body(C1<R>* __restrict__ data, const do
     const int x0 = (bid % (HX / W)) * W;
     const int z = bid / (HX / W);
     C1<R>* base = data + ((size_t)z * M * HX + x0) * 4 + l;   // + (y HX) * 4
-    C1<R> v[16];
+    C1<R> v[NV];
 #pragma unroll
-    for (int n1 = 0; n1 < 16; ++n1) v[n1] = base[(size_t)(8 * n1 + t) * HX * 4];
+    for (int n1 = 0; n1 < NV; ++n1) v[n1] = base[(size_t)(8 * n1 + t) * HX * 4];
     __syncthreads();   // twiddles
-    fft128_line(v, buf + l * kL8Line, tw, t, sgn);
+    fft8_line<R, M>(v, buf + l * Fft8Line<M>::LINE, tw, t, sgn);
 #pragma unroll
-    for (int k2 = 0; k2 < 8; ++k2) {
-        base[(size_t)(t + 16 * k2) * HX * 4] = v[k2];
-        base[(size_t)(t + 8 + 16 * k2) * HX * 4] = v[8 + k2];
-    }
+    for (int j = 0; j < NV; ++j) base[(size_t)Fft8Line<M>::out(t, j) * HX * 4] = v[j];
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_fft_y128(C1<R>* __restrict__ data, const double* __restrict__ twg,
+template <typename R, int M>
+__global__ __launch_bounds__(256) void k_fft_y8(C1<R>* __restrict__ data, const double* __restrict__ twg,
                                                   int sgn) {
-    fft_y128_body<R>(data, twg, sgn, blockIdx.x);
+    fft_y8_body<R, M>(data, twg, sgn, blockIdx.x);
 }
 
-// z pass, M = 128: forward z transform, k-space multiply (as in
+// z pass, M = 64 or 128: forward z transform, k-space multiply (as in
 // k_fft_z_scale), inverse z transform; a workgroup owns 8 qx columns at one qy
-template <typename R>
-__device__ __forceinline__ void fft_z128_body(C1<R>* __restrict__ data, const double* __restrict__ twg, KScale ks,
+template <typename R, int M>
+__device__ __forceinline__ void fft_z8_body(C1<R>* __restrict__ data, const double* __restrict__ twg, KScale ks,
                                               int bid) {
-    constexpr int M = 128, HX = 64, W = 8;
-    __shared__ C1<R> buf[32 * kL8Line];
+    constexpr int HX = M / 2, W = 8, NV = Fft8Line<M>::NV;
+    __shared__ C1<R> buf[32 * Fft8Line<M>::LINE];
     __shared__ C1<R> twf[M], twi[M];
     load_twiddles<R, M>(twf, twg, +1);
     load_twiddles<R, M>(twi, twg, -1);
@@ -1876,29 +1887,26 @@ __device__ __forceinline__ void fft_z128_body(C1<R>* __restrict__ data, const do
     const int y = bid / (HX / W);
     const size_t zstride = (size_t)M * HX * 4;
     C1<R>* base = data + ((size_t)y * HX + x0) * 4 + l;   // + z zstride
-    C1<R>* ln = buf + l * kL8Line;
-    C1<R> v[16];
+    C1<R>* ln = buf + l * Fft8Line<M>::LINE;
+    C1<R> v[NV];
 #pragma unroll
-    for (int n1 = 0; n1 < 16; ++n1) v[n1] = base[(size_t)(8 * n1 + t) * zstride];
+    for (int n1 = 0; n1 < NV; ++n1) v[n1] = base[(size_t)(8 * n1 + t) * zstride];
     __syncthreads();   // twiddles
-    fft128_line(v, ln, twf, t, +1);
+    fft8_line<R, M>(v, ln, twf, t, +1);
     __syncthreads();   // every thread has read its exchange rows
     // spectrum of this line in natural order: element qz at ln[qz]
 #pragma unroll
-    for (int k2 = 0; k2 < 8; ++k2) {
-        ln[t + 16 * k2] = v[k2];
-        ln[t + 8 + 16 * k2] = v[8 + k2];
-    }
+    for (int j = 0; j < NV; ++j) ln[Fft8Line<M>::out(t, j)] = v[j];
     __syncthreads();
     const int qy = (y < M / 2) ? y : y - M;
     for (int e = threadIdx.x; e < W * M; e += 256) {
         const int w = e & 7, z = e >> 3;
         const int qx = x0 + w;
         const int qz = (z < M / 2) ? z : z - M;
-        C1<R>* f0 = buf + (w * 4 + 0) * kL8Line + z;
-        C1<R>* f1 = buf + (w * 4 + 1) * kL8Line + z;
-        C1<R>* f2 = buf + (w * 4 + 2) * kL8Line + z;
-        C1<R>* f3 = buf + (w * 4 + 3) * kL8Line + z;
+        C1<R>* f0 = buf + (w * 4 + 0) * Fft8Line<M>::LINE + z;
+        C1<R>* f1 = buf + (w * 4 + 1) * Fft8Line<M>::LINE + z;
+        C1<R>* f2 = buf + (w * 4 + 2) * Fft8Line<M>::LINE + z;
+        C1<R>* f3 = buf + (w * 4 + 3) * Fft8Line<M>::LINE + z;
         const bool zero = (qx == 0 && qy == 0 && qz == 0) || (y == M / 2) || (z == M / 2);
         if (zero) {
             *f0 = *f1 = *f2 = *f3 = {R(0), R(0)};
@@ -1920,30 +1928,27 @@ __device__ __forceinline__ void fft_z128_body(C1<R>* __restrict__ data, const do
     }
     __syncthreads();
 #pragma unroll
-    for (int n1 = 0; n1 < 16; ++n1) v[n1] = ln[8 * n1 + t];
+    for (int n1 = 0; n1 < NV; ++n1) v[n1] = ln[8 * n1 + t];
     __syncthreads();   // the exchange below reuses the line
-    fft128_line(v, ln, twi, t, -1);
+    fft8_line<R, M>(v, ln, twi, t, -1);
 #pragma unroll
-    for (int k2 = 0; k2 < 8; ++k2) {
-        base[(size_t)(t + 16 * k2) * zstride] = v[k2];
-        base[(size_t)(t + 8 + 16 * k2) * zstride] = v[8 + k2];
-    }
+    for (int j = 0; j < NV; ++j) base[(size_t)Fft8Line<M>::out(t, j) * zstride] = v[j];
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_fft_z128(C1<R>* __restrict__ data, const double* __restrict__ twg,
+template <typename R, int M>
+__global__ __launch_bounds__(256) void k_fft_z8(C1<R>* __restrict__ data, const double* __restrict__ twg,
                                                   KScale ks) {
-    fft_z128_body<R>(data, twg, ks, blockIdx.x);
+    fft_z8_body<R, M>(data, twg, ks, blockIdx.x);
 }
 
-// x pass, forward, M = 128: 16 real lines per workgroup, each a pair of
+// x pass, forward, M = 64 or 128: 16 real lines per workgroup, each a pair of
 // complex transforms (x + i y fields, z + i w fields), then the same
 // half-spectrum unpacking as k_fft_x_fwd
-template <typename R>
-__device__ __forceinline__ void fft_x_fwd128_body(const R4<R>* __restrict__ in, C1<R>* __restrict__ out,
+template <typename R, int M>
+__device__ __forceinline__ void fft_x_fwd8_body(const R4<R>* __restrict__ in, C1<R>* __restrict__ out,
                                                   const double* __restrict__ twg, int bid) {
-    constexpr int M = 128;
-    __shared__ C1<R> buf[32 * kL8Line];
+    constexpr int NV = Fft8Line<M>::NV;
+    __shared__ C1<R> buf[32 * Fft8Line<M>::LINE];
     __shared__ C1<R> tw[M];
     load_twiddles<R, M>(tw, twg, +1);
     const int lane = threadIdx.x & 63;
@@ -1952,27 +1957,24 @@ __device__ __forceinline__ void fft_x_fwd128_body(const R4<R>* __restrict__ in, 
     const size_t line0 = (size_t)bid * 16;
     // fields (x, y) and (z, w) of one line sit side by side in a wavefront
     const C1<R>* src = reinterpret_cast<const C1<R>*>(in) + ((line0 + line) * M + t) * 2 + g;
-    C1<R> v[16];
+    C1<R> v[NV];
 #pragma unroll
-    for (int n1 = 0; n1 < 16; ++n1) v[n1] = src[16 * n1];
+    for (int n1 = 0; n1 < NV; ++n1) v[n1] = src[16 * n1];
     __syncthreads();   // twiddles
-    C1<R>* ln = buf + l32 * kL8Line;
-    fft128_line(v, ln, tw, t, +1);
+    C1<R>* ln = buf + l32 * Fft8Line<M>::LINE;
+    fft8_line<R, M>(v, ln, tw, t, +1);
     __syncthreads();
 #pragma unroll
-    for (int k2 = 0; k2 < 8; ++k2) {
-        ln[t + 16 * k2] = v[k2];
-        ln[t + 8 + 16 * k2] = v[8 + k2];
-    }
+    for (int j = 0; j < NV; ++j) ln[Fft8Line<M>::out(t, j)] = v[j];
     __syncthreads();
     for (int e = threadIdx.x; e < 16 * (M / 2); e += 256) {
-        const int l = e >> 6, q = e & 63;
+        const int l = e / (M / 2), q = e % (M / 2);
         const int qn = (M - q) & (M - 1);
         C1<R> o[4];
 #pragma unroll
         for (int gg = 0; gg < 2; ++gg) {
-            const C1<R> A = buf[(2 * l + gg) * kL8Line + q];
-            const C1<R> B = buf[(2 * l + gg) * kL8Line + qn];
+            const C1<R> A = buf[(2 * l + gg) * Fft8Line<M>::LINE + q];
+            const C1<R> B = buf[(2 * l + gg) * Fft8Line<M>::LINE + qn];
             o[2 * gg] = {R(0.5) * (A.re + B.re), R(0.5) * (A.im - B.im)};
             o[2 * gg + 1] = {R(0.5) * (A.im + B.im), R(-0.5) * (A.re - B.re)};
         }
@@ -1982,24 +1984,24 @@ __device__ __forceinline__ void fft_x_fwd128_body(const R4<R>* __restrict__ in, 
     }
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_fft_x_fwd128(const R4<R>* __restrict__ in, C1<R>* __restrict__ out,
+template <typename R, int M>
+__global__ __launch_bounds__(256) void k_fft_x_fwd8(const R4<R>* __restrict__ in, C1<R>* __restrict__ out,
                                                       const double* __restrict__ twg) {
-    fft_x_fwd128_body<R>(in, out, twg, blockIdx.x);
+    fft_x_fwd8_body<R, M>(in, out, twg, blockIdx.x);
 }
 
-// x pass, inverse, M = 128: half spectrum -> 16 real lines per workgroup
-template <typename R>
-__device__ __forceinline__ void fft_x_inv128_body(const C1<R>* __restrict__ in, R4<R>* __restrict__ out,
+// x pass, inverse, M = 64 or 128: half spectrum -> 16 real lines per workgroup
+template <typename R, int M>
+__device__ __forceinline__ void fft_x_inv8_body(const C1<R>* __restrict__ in, R4<R>* __restrict__ out,
                                                   const double* __restrict__ twg, int bid) {
-    constexpr int M = 128;
-    __shared__ C1<R> buf[32 * kL8Line];
+    constexpr int NV = Fft8Line<M>::NV;
+    __shared__ C1<R> buf[32 * Fft8Line<M>::LINE];
     __shared__ C1<R> tw[M];
     load_twiddles<R, M>(tw, twg, -1);
     const size_t line0 = (size_t)bid * 16;
     // thread (l, q) reads the four spectra at q once and fills x = q and M - q
     for (int e = threadIdx.x; e < 16 * (M / 2); e += 256) {
-        const int l = e >> 6, q = e & 63;
+        const int l = e / (M / 2), q = e % (M / 2);
         const C1<R>* sp = in + ((line0 + l) * (M / 2) + q) * 4;
         C1<R> S[4];
 #pragma unroll
@@ -2007,7 +2009,7 @@ __device__ __forceinline__ void fft_x_inv128_body(const C1<R>* __restrict__ in, 
 #pragma unroll
         for (int g = 0; g < 2; ++g) {
             const C1<R> a = S[2 * g], b = S[2 * g + 1];
-            C1<R>* ln = buf + (2 * l + g) * kL8Line;
+            C1<R>* ln = buf + (2 * l + g) * Fft8Line<M>::LINE;
             if (q == 0) {
                 ln[0] = {a.re, b.re};
                 ln[M / 2] = {R(0), R(0)};
@@ -2020,30 +2022,27 @@ __device__ __forceinline__ void fft_x_inv128_body(const C1<R>* __restrict__ in, 
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int l32 = (lane >> 3) + 8 * (threadIdx.x >> 6), t = lane & 7;
-    C1<R>* ln = buf + l32 * kL8Line;
-    C1<R> v[16];
+    C1<R>* ln = buf + l32 * Fft8Line<M>::LINE;
+    C1<R> v[NV];
 #pragma unroll
-    for (int n1 = 0; n1 < 16; ++n1) v[n1] = ln[8 * n1 + t];
+    for (int n1 = 0; n1 < NV; ++n1) v[n1] = ln[8 * n1 + t];
     __syncthreads();   // the exchange below reuses the line
-    fft128_line(v, ln, tw, t, -1);
+    fft8_line<R, M>(v, ln, tw, t, -1);
     __syncthreads();
 #pragma unroll
-    for (int k2 = 0; k2 < 8; ++k2) {
-        ln[t + 16 * k2] = v[k2];
-        ln[t + 8 + 16 * k2] = v[8 + k2];
-    }
+    for (int j = 0; j < NV; ++j) ln[Fft8Line<M>::out(t, j)] = v[j];
     __syncthreads();
     for (int e = threadIdx.x; e < 16 * M; e += 256) {
-        const int l = e >> 7, x = e & 127;
-        const C1<R> A = buf[(2 * l) * kL8Line + x], B = buf[(2 * l + 1) * kL8Line + x];
+        const int l = e / M, x = e % M;
+        const C1<R> A = buf[(2 * l) * Fft8Line<M>::LINE + x], B = buf[(2 * l + 1) * Fft8Line<M>::LINE + x];
         out[(line0 + l) * M + x] = {A.re, A.im, B.re, B.im};
     }
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_fft_x_inv128(const C1<R>* __restrict__ in, R4<R>* __restrict__ out,
+template <typename R, int M>
+__global__ __launch_bounds__(256) void k_fft_x_inv8(const C1<R>* __restrict__ in, R4<R>* __restrict__ out,
                                                       const double* __restrict__ twg) {
-    fft_x_inv128_body<R>(in, out, twg, blockIdx.x);
+    fft_x_inv8_body<R, M>(in, out, twg, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -2286,15 +2285,16 @@ struct FftShape {
 
 #define FFT_CASE(MM, LPB, W)                                                                              \
     case MM: {                                                                                            \
+        constexpr int MM8 = (MM == 64) ? 64 : 128; /* the four-step kernels' M (used when sp8) */        \
         const int lines = MM * MM;                                                                        \
         const bool sp256 = MM == 256 && !dbl && !hyb;                                                     \
-        const bool sp128 = MM == 128 && !dbl && !hyb;                                                     \
+        const bool sp8 = (MM == 128 || MM == 64) && !dbl && !hyb;                                         \
         tm->begin(kPhaseFftXFwd, st);                                                                     \
         if (sp256)                                                                                        \
             hipLaunchKernelGGL((k_fft_x_fwd256<R>), dim3(lines / 8), dim3(256), 0, st,                    \
                                (const R4<R>*)rgrid, (C1<R>*)spec, tw);                                    \
-        else if (sp128)                                                                                   \
-            hipLaunchKernelGGL((k_fft_x_fwd128<R>), dim3(lines / 16), dim3(256), 0, st,                   \
+        else if (sp8)                                                                                     \
+            hipLaunchKernelGGL((k_fft_x_fwd8<R, MM8>), dim3(lines / 16), dim3(256), 0, st,                \
                                (const R4<R>*)rgrid, (C1<R>*)spec, tw);                                    \
         else                                                                                              \
             hipLaunchKernelGGL((k_fft_x_fwd<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,            \
@@ -2306,13 +2306,14 @@ struct FftShape {
             hipLaunchKernelGGL((k_fft_z256<R>), dim3(32 * 256), dim3(256), 0, st, (C1<R>*)spec, tw, ks);  \
             tm->begin(kPhaseFftYInv, st);                                                                 \
             hipLaunchKernelGGL((k_fft_y256<R>), dim3(32 * 256), dim3(256), 0, st, (C1<R>*)spec, tw, -1);  \
-        } else if (sp128) {                                                                               \
+        } else if (sp8) {                                                                                 \
+            const dim3 g8((MM8 / 16) * MM8);                                                              \
             tm->begin(kPhaseFftYFwd, st);                                                                 \
-            hipLaunchKernelGGL((k_fft_y128<R>), dim3(8 * 128), dim3(256), 0, st, (C1<R>*)spec, tw, +1);   \
+            hipLaunchKernelGGL((k_fft_y8<R, MM8>), g8, dim3(256), 0, st, (C1<R>*)spec, tw, +1);           \
             tm->begin(kPhaseFftZ, st);                                                                    \
-            hipLaunchKernelGGL((k_fft_z128<R>), dim3(8 * 128), dim3(256), 0, st, (C1<R>*)spec, tw, ks);   \
+            hipLaunchKernelGGL((k_fft_z8<R, MM8>), g8, dim3(256), 0, st, (C1<R>*)spec, tw, ks);           \
             tm->begin(kPhaseFftYInv, st);                                                                 \
-            hipLaunchKernelGGL((k_fft_y128<R>), dim3(8 * 128), dim3(256), 0, st, (C1<R>*)spec, tw, -1);   \
+            hipLaunchKernelGGL((k_fft_y8<R, MM8>), g8, dim3(256), 0, st, (C1<R>*)spec, tw, -1);           \
         } else {                                                                                          \
             tm->begin(kPhaseFftYFwd, st);                                                                 \
             hipLaunchKernelGGL((k_fft_y<R, MM, W>), dim3((MM / 2 / W) * MM), dim3(256), 0, st,            \
@@ -2337,8 +2338,8 @@ struct FftShape {
         if (sp256)                                                                                        \
             hipLaunchKernelGGL((k_fft_x_inv256<R>), dim3(lines / 8), dim3(256), 0, st,                    \
                                (const C1<R>*)spec, (R4<R>*)rgrid, tw);                                    \
-        else if (sp128)                                                                                   \
-            hipLaunchKernelGGL((k_fft_x_inv128<R>), dim3(lines / 16), dim3(256), 0, st,                   \
+        else if (sp8)                                                                                     \
+            hipLaunchKernelGGL((k_fft_x_inv8<R, MM8>), dim3(lines / 16), dim3(256), 0, st,                \
                                (const C1<R>*)spec, (R4<R>*)rgrid, tw);                                    \
         else                                                                                              \
             hipLaunchKernelGGL((k_fft_x_inv<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,            \
@@ -2665,33 +2666,33 @@ __global__ __launch_bounds__(256) void k_fft_x_inv_multi(const MultiSys* __restr
     fft_x_inv_body<R, M, LPB>((const C1<R>*)A.spec, (R4<R>*)A.rgrid, A.twiddle, it.y);
 }
 
-// the 16 x 8 four-step passes of FP32 grids of edge 128
-template <typename R>
-__global__ __launch_bounds__(256) void k_fft_x_fwd128_multi(const MultiSys* __restrict__ sys,
-                                                            const int2* __restrict__ items) {
+// the four-step passes of FP32 grids of edge 64 and 128
+template <typename R, int M>
+__global__ __launch_bounds__(256) void k_fft_x_fwd8_multi(const MultiSys* __restrict__ sys,
+                                                          const int2* __restrict__ items) {
     MULTI_ITEM();
-    fft_x_fwd128_body<R>((const R4<R>*)A.rgrid, (C1<R>*)A.spec, A.twiddle, it.y);
+    fft_x_fwd8_body<R, M>((const R4<R>*)A.rgrid, (C1<R>*)A.spec, A.twiddle, it.y);
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_fft_y128_multi(const MultiSys* __restrict__ sys,
-                                                        const int2* __restrict__ items, int sgn) {
+template <typename R, int M>
+__global__ __launch_bounds__(256) void k_fft_y8_multi(const MultiSys* __restrict__ sys,
+                                                      const int2* __restrict__ items, int sgn) {
     MULTI_ITEM();
-    fft_y128_body<R>((C1<R>*)A.spec, A.twiddle, sgn, it.y);
+    fft_y8_body<R, M>((C1<R>*)A.spec, A.twiddle, sgn, it.y);
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_fft_z128_multi(const MultiSys* __restrict__ sys,
-                                                        const int2* __restrict__ items) {
+template <typename R, int M>
+__global__ __launch_bounds__(256) void k_fft_z8_multi(const MultiSys* __restrict__ sys,
+                                                      const int2* __restrict__ items) {
     MULTI_ITEM();
-    fft_z128_body<R>((C1<R>*)A.spec, A.twiddle, S.ks, it.y);
+    fft_z8_body<R, M>((C1<R>*)A.spec, A.twiddle, S.ks, it.y);
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_fft_x_inv128_multi(const MultiSys* __restrict__ sys,
-                                                            const int2* __restrict__ items) {
+template <typename R, int M>
+__global__ __launch_bounds__(256) void k_fft_x_inv8_multi(const MultiSys* __restrict__ sys,
+                                                          const int2* __restrict__ items) {
     MULTI_ITEM();
-    fft_x_inv128_body<R>((const C1<R>*)A.spec, (R4<R>*)A.rgrid, A.twiddle, it.y);
+    fft_x_inv8_body<R, M>((const C1<R>*)A.spec, (R4<R>*)A.rgrid, A.twiddle, it.y);
 }
 
 template <typename R, bool SHEAR>
@@ -2743,11 +2744,11 @@ int multi_plan_build(const ApplyArgs* args, int nsys, MultiPlan** out, hipStream
         add(kMkWindow, 0, k, (n + kWinSpheres - 1) / kWinSpheres);
         const int tiles = M / kTile;
         add(A.win.sheared ? kMkSpreadShear : kMkSpread, 0, k, tiles * tiles * tiles);
-        const bool f128 = M == 128 && !dbl;   // the 16 x 8 four-step passes
-        add(kMkFftXF, M, k, f128 ? M * M / 16 : M * M / fft_lpb(M, dbl));
-        add(kMkFftY, M, k, f128 ? 8 * M : (M / 2 / fft_w(M, dbl)) * M);
-        add(kMkFftZ, M, k, f128 ? 8 * M : (M / 2 / fft_w(M, dbl)) * M);
-        add(kMkFftXI, M, k, f128 ? M * M / 16 : M * M / fft_lpb(M, dbl));
+        const bool f8 = (M == 128 || M == 64) && !dbl;   // the four-step passes
+        add(kMkFftXF, M, k, f8 ? M * M / 16 : M * M / fft_lpb(M, dbl));
+        add(kMkFftY, M, k, f8 ? (M / 16) * M : (M / 2 / fft_w(M, dbl)) * M);
+        add(kMkFftZ, M, k, f8 ? (M / 16) * M : (M / 2 / fft_w(M, dbl)) * M);
+        add(kMkFftXI, M, k, f8 ? M * M / 16 : M * M / fft_lpb(M, dbl));
         constexpr int spb = 4 * (64 / kGatherLanes);
         add(A.win.sheared ? kMkGatherShear : kMkGather, 0, k, (n + spb - 1) / spb);
     }
@@ -2815,11 +2816,18 @@ template <typename R>
 static void multi_fft_pass(const MultiPlan* P, int kind, int sgn, hipStream_t st) {
     for (const MultiList& L : P->lists) {
         if (L.kind != kind) continue;
-        if (L.M == 128 && sizeof(R) == 4) {
-            if (kind == kMkFftXF) MULTI_LAUNCH((k_fft_x_fwd128_multi<R>), 256);
-            if (kind == kMkFftY) MULTI_LAUNCH((k_fft_y128_multi<R>), 256, sgn);
-            if (kind == kMkFftZ) MULTI_LAUNCH((k_fft_z128_multi<R>), 256);
-            if (kind == kMkFftXI) MULTI_LAUNCH((k_fft_x_inv128_multi<R>), 256);
+        if ((L.M == 128 || L.M == 64) && sizeof(R) == 4) {
+            if (L.M == 128) {
+                if (kind == kMkFftXF) MULTI_LAUNCH((k_fft_x_fwd8_multi<R, 128>), 256);
+                if (kind == kMkFftY) MULTI_LAUNCH((k_fft_y8_multi<R, 128>), 256, sgn);
+                if (kind == kMkFftZ) MULTI_LAUNCH((k_fft_z8_multi<R, 128>), 256);
+                if (kind == kMkFftXI) MULTI_LAUNCH((k_fft_x_inv8_multi<R, 128>), 256);
+            } else {
+                if (kind == kMkFftXF) MULTI_LAUNCH((k_fft_x_fwd8_multi<R, 64>), 256);
+                if (kind == kMkFftY) MULTI_LAUNCH((k_fft_y8_multi<R, 64>), 256, sgn);
+                if (kind == kMkFftZ) MULTI_LAUNCH((k_fft_z8_multi<R, 64>), 256);
+                if (kind == kMkFftXI) MULTI_LAUNCH((k_fft_x_inv8_multi<R, 64>), 256);
+            }
             continue;
         }
         switch (L.M) {
