@@ -2077,7 +2077,10 @@ __device__ __forceinline__ void gather_body(
     const int s = active ? s0 : n - 1;
     const int mask = M - 1;
     const R* rc = recs + (size_t)rec_stride(P) * s;
-    const int Pe = (P + 1) & ~1;      // z loop runs in pairs of points
+    // the z loop loads ZC points of a column at once (many loads in flight
+    // per lane); weights past P are zero
+    constexpr int ZC = sizeof(R) == 4 ? 4 : 2;
+    const int Pe = (P + ZC - 1) / ZC * ZC;
     for (int k = lane; k < 2 * P; k += G) fac[sb][k] = rc[kRecHead + k];
     for (int kz = lane; kz < Pe; kz += G) {
         const R uz = rc[6] + (R)kz, fz = kz < P ? rc[kRecHead + 2 * P + kz] : R(0);
@@ -2113,27 +2116,36 @@ __device__ __forceinline__ void gather_body(
             // z moments of v (0 and 1), of p (0) and of Lv (0 and 1)
             R m0x = 0, m0y = 0, m0z = 0, m0w = 0, m1x = 0, m1y = 0, m1z = 0;
             R l0x = 0, l0y = 0, l0z = 0, l1x = 0, l1y = 0, l1z = 0;
-            const size_t colo = (size_t)gy * M + gx;
-            const size_t zs = (size_t)M * M;
-#pragma unroll 4
-            for (int kz = 0; kz < P; ++kz) {
-                const size_t o = colo + (size_t)((i0.z + kz) & mask) * zs;
-                const R4<R> g = grid[o];
-                const R4<R> l = grid2[o];
-                const R t0 = zt[sb][0][kz], t1 = zt[sb][1][kz];
-                m0x += t0 * g.x;
-                m0y += t0 * g.y;
-                m0z += t0 * g.z;
-                m0w += t0 * g.w;
-                m1x += t1 * g.x;
-                m1y += t1 * g.y;
-                m1z += t1 * g.z;
-                l0x += t0 * l.x;
-                l0y += t0 * l.y;
-                l0z += t0 * l.z;
-                l1x += t1 * l.x;
-                l1y += t1 * l.y;
-                l1z += t1 * l.z;
+            // 32-bit offsets (a grid of at most 256^3 points)
+            const R4<R>* colp = grid + (gy * M + gx);
+            const R4<R>* colq = grid2 + (gy * M + gx);
+            const unsigned zs = (unsigned)M * (unsigned)M;
+            for (int kc = 0; kc < Pe; kc += ZC) {
+                R4<R> gv[ZC], lv[ZC];
+#pragma unroll
+                for (int j = 0; j < ZC; ++j) {
+                    const unsigned o = (unsigned)((i0.z + kc + j) & mask) * zs;
+                    gv[j] = colp[o];
+                    lv[j] = colq[o];
+                }
+#pragma unroll
+                for (int j = 0; j < ZC; ++j) {
+                    const R4<R> g = gv[j], l = lv[j];
+                    const R t0 = zt[sb][0][kc + j], t1 = zt[sb][1][kc + j];
+                    m0x += t0 * g.x;
+                    m0y += t0 * g.y;
+                    m0z += t0 * g.z;
+                    m0w += t0 * g.w;
+                    m1x += t1 * g.x;
+                    m1y += t1 * g.y;
+                    m1z += t1 * g.z;
+                    l0x += t0 * l.x;
+                    l0y += t0 * l.y;
+                    l0z += t0 * l.z;
+                    l1x += t1 * l.x;
+                    l1y += t1 * l.y;
+                    l1z += t1 * l.z;
+                }
             }
             // grad (v + (3/5) a^2 Lv) read with grad h = -2 g h, g_z = Gzz u_z
             const R qx = R(2) * (m0x + a2e * l0x), qy = R(2) * (m0y + a2e * l0y), qz = R(2) * (m0z + a2e * l0z);
@@ -2170,17 +2182,18 @@ __device__ __forceinline__ void gather_body(
             const int gx = (i0.x + kx) & mask, gy = (i0.y + ky) & mask;
             R m0x = 0, m0y = 0, m0z = 0, m0w = 0, m1x = 0, m1y = 0, m1z = 0;
             R m2x = 0, m2y = 0, m2z = 0, m3x = 0, m3y = 0, m3z = 0;
-            const R4<R>* colp = grid + (size_t)gy * M + gx;
-            const size_t zs = (size_t)M * M;
-            // two grid loads in flight per step, several steps unrolled (a
-            // point past an odd P has zero weight)
-#pragma unroll 4
-            for (int kz2 = 0; kz2 < Pe; kz2 += 2) {
-              const R4<R> gpair[2] = {colp[(size_t)((i0.z + kz2) & mask) * zs],
-                                      colp[(size_t)((i0.z + kz2 + 1) & mask) * zs]};
-              for (int hz = 0; hz < 2; ++hz) {
-                const int kz = kz2 + hz;
-                const R4<R> g = gpair[hz];
+            // 32-bit offsets (a grid of at most 256^3 points); ZC loads in
+            // flight per chunk (a point past P has zero weight)
+            const R4<R>* colp = grid + (gy * M + gx);
+            const unsigned zs = (unsigned)M * (unsigned)M;
+            for (int kc = 0; kc < Pe; kc += ZC) {
+              R4<R> gv[ZC];
+#pragma unroll
+              for (int j = 0; j < ZC; ++j) gv[j] = colp[(unsigned)((i0.z + kc + j) & mask) * zs];
+#pragma unroll
+              for (int j = 0; j < ZC; ++j) {
+                const int kz = kc + j;
+                const R4<R> g = gv[j];
                 const R t0 = zt[sb][0][kz], t1 = zt[sb][1][kz], t2 = zt[sb][2][kz], t3 = zt[sb][3][kz];
                 m0x += t0 * g.x;
                 m0y += t0 * g.y;
