@@ -49,8 +49,8 @@ REF = (0.7, 3.5, 18, 0.95)   # FP64 reference product (SE error ~1e-8)
 # profiles/product_n100000_phi0.4_grid256_traffic.md. Any other configuration
 # reports null.
 MEASURED_TRAFFIC = {
-    ("spread", 256, 16): 322.9e6,
-    ("gather", 256, 16): 1433.0e6,
+    ("spread", 256, 16): 322.4e6,
+    ("gather", 256, 16): 995.4e6,
 }
 
 
@@ -392,7 +392,7 @@ def main():
     ap.add_argument("--save-weights", default=None)
     ap.add_argument("--weights", default=None, help="learned workload: use these weights instead of training")
     ap.add_argument("--pmc-probe", action="store_true")
-    ap.add_argument("--pmc-candidate", type=int, default=0)
+    ap.add_argument("--pmc-candidate", type=int, default=2)
     ap.add_argument("--candidate", type=int, default=None,
                     help="time this candidate without the selection pass (profiling runs)")
     args = ap.parse_args()
