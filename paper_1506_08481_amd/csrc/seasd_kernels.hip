@@ -1843,16 +1843,23 @@ __device__ inline void fft8_line(C1<T>* v, C1<T>* ln, const C1<T>* tw, int t, in
     for (int r = 0; r < NV / 8; ++r) dft8<T, M>(v + 8 * r, tw, sgn);
 }
 
-// y pass, M = 64 or 128: a workgroup owns 8 qx columns at one z (32 lines)
+// Lines per workgroup of the four-step passes: 32 in FP32 and 16 in FP64
+// (8 threads per line, so 256 and 128 threads; the LDS buffer is the same
+// size, and the y and z passes read whole 256-byte rows either way)
+template <typename R>
+struct Fft8Lines {
+    static constexpr int value = sizeof(R) == 4 ? 32 : 16;
+};
+
+// y pass, M = 64 or 128: a workgroup owns LN / 4 qx columns at one z
 template <typename R, int M>
 __device__ __forceinline__ void fft_y8_body(C1<R>* __restrict__ data, const double* __restrict__ twg, int sgn,
                                               int bid) {
-    constexpr int HX = M / 2, W = 8, NV = Fft8Line<M>::NV;
-    __shared__ C1<R> buf[32 * Fft8Line<M>::LINE];
+    constexpr int LN = Fft8Lines<R>::value, HX = M / 2, W = LN / 4, NV = Fft8Line<M>::NV;
+    __shared__ C1<R> buf[LN * Fft8Line<M>::LINE];
     __shared__ C1<R> tw[M];
     load_twiddles<R, M>(tw, twg, sgn);
-    const int lane = threadIdx.x & 63;
-    const int l = lane & 31, t = (lane >> 5) + 2 * (threadIdx.x >> 6);
+    const int l = threadIdx.x % LN, t = threadIdx.x / LN;   // consecutive lanes: consecutive lines
     const int x0 = (bid % (HX / W)) * W;
     const int z = bid / (HX / W);
     C1<R>* base = data + ((size_t)z * M * HX + x0) * 4 + l;   // + (y HX) * 4
@@ -1872,17 +1879,16 @@ __global__ __launch_bounds__(256) void k_fft_y8(C1<R>* __restrict__ data, const 
 }
 
 // z pass, M = 64 or 128: forward z transform, k-space multiply (as in
-// k_fft_z_scale), inverse z transform; a workgroup owns 8 qx columns at one qy
+// k_fft_z_scale), inverse z transform; a workgroup owns LN / 4 qx columns at one qy
 template <typename R, int M>
 __device__ __forceinline__ void fft_z8_body(C1<R>* __restrict__ data, const double* __restrict__ twg, KScale ks,
                                               int bid) {
-    constexpr int HX = M / 2, W = 8, NV = Fft8Line<M>::NV;
-    __shared__ C1<R> buf[32 * Fft8Line<M>::LINE];
+    constexpr int LN = Fft8Lines<R>::value, HX = M / 2, W = LN / 4, NV = Fft8Line<M>::NV;
+    __shared__ C1<R> buf[LN * Fft8Line<M>::LINE];
     __shared__ C1<R> twf[M], twi[M];
     load_twiddles<R, M>(twf, twg, +1);
     load_twiddles<R, M>(twi, twg, -1);
-    const int lane = threadIdx.x & 63;
-    const int l = lane & 31, t = (lane >> 5) + 2 * (threadIdx.x >> 6);
+    const int l = threadIdx.x % LN, t = threadIdx.x / LN;   // consecutive lanes: consecutive lines
     const int x0 = (bid % (HX / W)) * W;
     const int y = bid / (HX / W);
     const size_t zstride = (size_t)M * HX * 4;
@@ -1899,8 +1905,8 @@ __device__ __forceinline__ void fft_z8_body(C1<R>* __restrict__ data, const doub
     for (int j = 0; j < NV; ++j) ln[Fft8Line<M>::out(t, j)] = v[j];
     __syncthreads();
     const int qy = (y < M / 2) ? y : y - M;
-    for (int e = threadIdx.x; e < W * M; e += 256) {
-        const int w = e & 7, z = e >> 3;
+    for (int e = threadIdx.x; e < W * M; e += 8 * LN) {
+        const int w = e % W, z = e / W;
         const int qx = x0 + w;
         const int qz = (z < M / 2) ? z : z - M;
         C1<R>* f0 = buf + (w * 4 + 0) * Fft8Line<M>::LINE + z;
@@ -1941,20 +1947,19 @@ __global__ __launch_bounds__(256) void k_fft_z8(C1<R>* __restrict__ data, const 
     fft_z8_body<R, M>(data, twg, ks, blockIdx.x);
 }
 
-// x pass, forward, M = 64 or 128: 16 real lines per workgroup, each a pair of
+// x pass, forward, M = 64 or 128: LN / 2 real lines per workgroup, each a pair of
 // complex transforms (x + i y fields, z + i w fields), then the same
 // half-spectrum unpacking as k_fft_x_fwd
 template <typename R, int M>
 __device__ __forceinline__ void fft_x_fwd8_body(const R4<R>* __restrict__ in, C1<R>* __restrict__ out,
                                                   const double* __restrict__ twg, int bid) {
-    constexpr int NV = Fft8Line<M>::NV;
-    __shared__ C1<R> buf[32 * Fft8Line<M>::LINE];
+    constexpr int LN = Fft8Lines<R>::value, RL = LN / 2, NV = Fft8Line<M>::NV;   // RL real lines
+    __shared__ C1<R> buf[LN * Fft8Line<M>::LINE];
     __shared__ C1<R> tw[M];
     load_twiddles<R, M>(tw, twg, +1);
-    const int lane = threadIdx.x & 63;
-    const int l32 = (lane >> 3) + 8 * (threadIdx.x >> 6), t = lane & 7;
+    const int l32 = threadIdx.x / 8, t = threadIdx.x % 8;   // complex line, thread in line
     const int line = l32 >> 1, g = l32 & 1;
-    const size_t line0 = (size_t)bid * 16;
+    const size_t line0 = (size_t)bid * RL;
     // fields (x, y) and (z, w) of one line sit side by side in a wavefront
     const C1<R>* src = reinterpret_cast<const C1<R>*>(in) + ((line0 + line) * M + t) * 2 + g;
     C1<R> v[NV];
@@ -1967,7 +1972,7 @@ __device__ __forceinline__ void fft_x_fwd8_body(const R4<R>* __restrict__ in, C1
 #pragma unroll
     for (int j = 0; j < NV; ++j) ln[Fft8Line<M>::out(t, j)] = v[j];
     __syncthreads();
-    for (int e = threadIdx.x; e < 16 * (M / 2); e += 256) {
+    for (int e = threadIdx.x; e < RL * (M / 2); e += 8 * LN) {
         const int l = e / (M / 2), q = e % (M / 2);
         const int qn = (M - q) & (M - 1);
         C1<R> o[4];
@@ -1990,17 +1995,17 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd8(const R4<R>* __restrict__ in
     fft_x_fwd8_body<R, M>(in, out, twg, blockIdx.x);
 }
 
-// x pass, inverse, M = 64 or 128: half spectrum -> 16 real lines per workgroup
+// x pass, inverse, M = 64 or 128: half spectrum -> LN / 2 real lines per workgroup
 template <typename R, int M>
 __device__ __forceinline__ void fft_x_inv8_body(const C1<R>* __restrict__ in, R4<R>* __restrict__ out,
                                                   const double* __restrict__ twg, int bid) {
-    constexpr int NV = Fft8Line<M>::NV;
-    __shared__ C1<R> buf[32 * Fft8Line<M>::LINE];
+    constexpr int LN = Fft8Lines<R>::value, RL = LN / 2, NV = Fft8Line<M>::NV;   // RL real lines
+    __shared__ C1<R> buf[LN * Fft8Line<M>::LINE];
     __shared__ C1<R> tw[M];
     load_twiddles<R, M>(tw, twg, -1);
-    const size_t line0 = (size_t)bid * 16;
+    const size_t line0 = (size_t)bid * RL;
     // thread (l, q) reads the four spectra at q once and fills x = q and M - q
-    for (int e = threadIdx.x; e < 16 * (M / 2); e += 256) {
+    for (int e = threadIdx.x; e < RL * (M / 2); e += 8 * LN) {
         const int l = e / (M / 2), q = e % (M / 2);
         const C1<R>* sp = in + ((line0 + l) * (M / 2) + q) * 4;
         C1<R> S[4];
@@ -2020,8 +2025,7 @@ __device__ __forceinline__ void fft_x_inv8_body(const C1<R>* __restrict__ in, R4
         }
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int l32 = (lane >> 3) + 8 * (threadIdx.x >> 6), t = lane & 7;
+    const int l32 = threadIdx.x / 8, t = threadIdx.x % 8;   // complex line, thread in line
     C1<R>* ln = buf + l32 * Fft8Line<M>::LINE;
     C1<R> v[NV];
 #pragma unroll
@@ -2032,7 +2036,7 @@ __device__ __forceinline__ void fft_x_inv8_body(const C1<R>* __restrict__ in, R4
 #pragma unroll
     for (int j = 0; j < NV; ++j) ln[Fft8Line<M>::out(t, j)] = v[j];
     __syncthreads();
-    for (int e = threadIdx.x; e < 16 * M; e += 256) {
+    for (int e = threadIdx.x; e < RL * M; e += 8 * LN) {
         const int l = e / M, x = e % M;
         const C1<R> A = buf[(2 * l) * Fft8Line<M>::LINE + x], B = buf[(2 * l + 1) * Fft8Line<M>::LINE + x];
         out[(line0 + l) * M + x] = {A.re, A.im, B.re, B.im};
@@ -2301,13 +2305,14 @@ struct FftShape {
         constexpr int MM8 = (MM == 64) ? 64 : 128; /* the four-step kernels' M (used when sp8) */        \
         const int lines = MM * MM;                                                                        \
         const bool sp256 = MM == 256 && !dbl && !hyb;                                                     \
-        const bool sp8 = (MM == 128 || MM == 64) && !dbl && !hyb;                                         \
+        const bool sp8 = (MM == 128 || MM == 64) && !hyb;                                                 \
+        constexpr int LN8 = Fft8Lines<R>::value; /* lines per workgroup of the four-step passes */        \
         tm->begin(kPhaseFftXFwd, st);                                                                     \
         if (sp256)                                                                                        \
             hipLaunchKernelGGL((k_fft_x_fwd256<R>), dim3(lines / 8), dim3(256), 0, st,                    \
                                (const R4<R>*)rgrid, (C1<R>*)spec, tw);                                    \
         else if (sp8)                                                                                     \
-            hipLaunchKernelGGL((k_fft_x_fwd8<R, MM8>), dim3(lines / 16), dim3(256), 0, st,                \
+            hipLaunchKernelGGL((k_fft_x_fwd8<R, MM8>), dim3(lines / (LN8 / 2)), dim3(8 * LN8), 0, st,     \
                                (const R4<R>*)rgrid, (C1<R>*)spec, tw);                                    \
         else                                                                                              \
             hipLaunchKernelGGL((k_fft_x_fwd<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,            \
@@ -2320,13 +2325,13 @@ struct FftShape {
             tm->begin(kPhaseFftYInv, st);                                                                 \
             hipLaunchKernelGGL((k_fft_y256<R>), dim3(32 * 256), dim3(256), 0, st, (C1<R>*)spec, tw, -1);  \
         } else if (sp8) {                                                                                 \
-            const dim3 g8((MM8 / 16) * MM8);                                                              \
+            const dim3 g8((MM8 / 2 / (LN8 / 4)) * MM8), b8(8 * LN8);                                     \
             tm->begin(kPhaseFftYFwd, st);                                                                 \
-            hipLaunchKernelGGL((k_fft_y8<R, MM8>), g8, dim3(256), 0, st, (C1<R>*)spec, tw, +1);           \
+            hipLaunchKernelGGL((k_fft_y8<R, MM8>), g8, b8, 0, st, (C1<R>*)spec, tw, +1);                  \
             tm->begin(kPhaseFftZ, st);                                                                    \
-            hipLaunchKernelGGL((k_fft_z8<R, MM8>), g8, dim3(256), 0, st, (C1<R>*)spec, tw, ks);           \
+            hipLaunchKernelGGL((k_fft_z8<R, MM8>), g8, b8, 0, st, (C1<R>*)spec, tw, ks);                  \
             tm->begin(kPhaseFftYInv, st);                                                                 \
-            hipLaunchKernelGGL((k_fft_y8<R, MM8>), g8, dim3(256), 0, st, (C1<R>*)spec, tw, -1);           \
+            hipLaunchKernelGGL((k_fft_y8<R, MM8>), g8, b8, 0, st, (C1<R>*)spec, tw, -1);                  \
         } else {                                                                                          \
             tm->begin(kPhaseFftYFwd, st);                                                                 \
             hipLaunchKernelGGL((k_fft_y<R, MM, W>), dim3((MM / 2 / W) * MM), dim3(256), 0, st,            \
@@ -2352,7 +2357,7 @@ struct FftShape {
             hipLaunchKernelGGL((k_fft_x_inv256<R>), dim3(lines / 8), dim3(256), 0, st,                    \
                                (const C1<R>*)spec, (R4<R>*)rgrid, tw);                                    \
         else if (sp8)                                                                                     \
-            hipLaunchKernelGGL((k_fft_x_inv8<R, MM8>), dim3(lines / 16), dim3(256), 0, st,                \
+            hipLaunchKernelGGL((k_fft_x_inv8<R, MM8>), dim3(lines / (LN8 / 2)), dim3(8 * LN8), 0, st,     \
                                (const C1<R>*)spec, (R4<R>*)rgrid, tw);                                    \
         else                                                                                              \
             hipLaunchKernelGGL((k_fft_x_inv<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,            \
@@ -2764,11 +2769,13 @@ int multi_plan_build(const ApplyArgs* args, int nsys, MultiPlan** out, hipStream
         add(kMkWindow, 0, k, (n + kWinSpheres - 1) / kWinSpheres);
         const int tiles = M / kTile;
         add(A.win.sheared ? kMkSpreadShear : kMkSpread, 0, k, tiles * tiles * tiles);
-        const bool f8 = (M == 128 || M == 64) && !dbl;   // the four-step passes
-        add(kMkFftXF, M, k, f8 ? M * M / 16 : M * M / fft_lpb(M, dbl));
-        add(kMkFftY, M, k, f8 ? (M / 16) * M : (M / 2 / fft_w(M, dbl)) * M);
-        add(kMkFftZ, M, k, f8 ? (M / 16) * M : (M / 2 / fft_w(M, dbl)) * M);
-        add(kMkFftXI, M, k, f8 ? M * M / 16 : M * M / fft_lpb(M, dbl));
+        // the four-step passes: ln lines per workgroup (32 FP32, 16 FP64)
+        const bool f8 = M == 128 || M == 64;
+        const int ln = dbl ? Fft8Lines<double>::value : Fft8Lines<float>::value;
+        add(kMkFftXF, M, k, f8 ? M * M / (ln / 2) : M * M / fft_lpb(M, dbl));
+        add(kMkFftY, M, k, f8 ? (M / 2 / (ln / 4)) * M : (M / 2 / fft_w(M, dbl)) * M);
+        add(kMkFftZ, M, k, f8 ? (M / 2 / (ln / 4)) * M : (M / 2 / fft_w(M, dbl)) * M);
+        add(kMkFftXI, M, k, f8 ? M * M / (ln / 2) : M * M / fft_lpb(M, dbl));
         constexpr int spb = 4 * (64 / kGatherLanes);
         add(A.win.sheared ? kMkGatherShear : kMkGather, 0, k, (n + spb - 1) / spb);
     }
@@ -2836,17 +2843,18 @@ template <typename R>
 static void multi_fft_pass(const MultiPlan* P, int kind, int sgn, hipStream_t st) {
     for (const MultiList& L : P->lists) {
         if (L.kind != kind) continue;
-        if ((L.M == 128 || L.M == 64) && sizeof(R) == 4) {
+        if (L.M == 128 || L.M == 64) {
+            constexpr int b8 = 8 * Fft8Lines<R>::value;
             if (L.M == 128) {
-                if (kind == kMkFftXF) MULTI_LAUNCH((k_fft_x_fwd8_multi<R, 128>), 256);
-                if (kind == kMkFftY) MULTI_LAUNCH((k_fft_y8_multi<R, 128>), 256, sgn);
-                if (kind == kMkFftZ) MULTI_LAUNCH((k_fft_z8_multi<R, 128>), 256);
-                if (kind == kMkFftXI) MULTI_LAUNCH((k_fft_x_inv8_multi<R, 128>), 256);
+                if (kind == kMkFftXF) MULTI_LAUNCH((k_fft_x_fwd8_multi<R, 128>), b8);
+                if (kind == kMkFftY) MULTI_LAUNCH((k_fft_y8_multi<R, 128>), b8, sgn);
+                if (kind == kMkFftZ) MULTI_LAUNCH((k_fft_z8_multi<R, 128>), b8);
+                if (kind == kMkFftXI) MULTI_LAUNCH((k_fft_x_inv8_multi<R, 128>), b8);
             } else {
-                if (kind == kMkFftXF) MULTI_LAUNCH((k_fft_x_fwd8_multi<R, 64>), 256);
-                if (kind == kMkFftY) MULTI_LAUNCH((k_fft_y8_multi<R, 64>), 256, sgn);
-                if (kind == kMkFftZ) MULTI_LAUNCH((k_fft_z8_multi<R, 64>), 256);
-                if (kind == kMkFftXI) MULTI_LAUNCH((k_fft_x_inv8_multi<R, 64>), 256);
+                if (kind == kMkFftXF) MULTI_LAUNCH((k_fft_x_fwd8_multi<R, 64>), b8);
+                if (kind == kMkFftY) MULTI_LAUNCH((k_fft_y8_multi<R, 64>), b8, sgn);
+                if (kind == kMkFftZ) MULTI_LAUNCH((k_fft_z8_multi<R, 64>), b8);
+                if (kind == kMkFftXI) MULTI_LAUNCH((k_fft_x_inv8_multi<R, 64>), b8);
             }
             continue;
         }
