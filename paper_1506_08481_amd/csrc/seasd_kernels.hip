@@ -1517,34 +1517,28 @@ __global__ __launch_bounds__(256) void k_fft_x_inv256(const C1<R>* __restrict__ 
     __shared__ C1<R> tw[M];
     load_twiddles<R, M>(tw, twg, -1);
     const size_t line0 = (size_t)blockIdx.x * 8;
-    // thread (l, q) reads the four spectra at q once and fills x = q and M - q
-    for (int e = threadIdx.x; e < 8 * (M / 2); e += 256) {
-        const int l = e >> 7, q = e & 127;
-        const C1<R>* sp = in + ((line0 + l) * (M / 2) + q) * 4;
-        C1<R> S[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) S[c] = sp[c];
-#pragma unroll
-        for (int g = 0; g < 2; ++g) {
-            const C1<R> a = S[2 * g], b = S[2 * g + 1];
-            C1<R>* ln = buf + (2 * l + g) * kL16Line;
-            if (q == 0) {
-                ln[0] = {a.re, b.re};
-                ln[M / 2] = {R(0), R(0)};
-            } else {
-                ln[q] = {a.re - b.im, a.im + b.re};
-                ln[M - q] = {a.re + b.im, b.re - a.im};
-            }
-        }
-    }
-    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int l16 = (lane >> 4) + 4 * (threadIdx.x >> 6), t = lane & 15;
-    C1<R>* ln = buf + l16 * kL16Line;
+    const int line = l16 >> 1, g = l16 & 1;
+    // complex line g of real line `line` packs fields 2g (real part) and
+    // 2g + 1 (imaginary part): its element x comes from the two half spectra
+    // at q = x (x < M/2) or at q = M - x (conjugated); x = M/2 is zero. The
+    // two spectra sit side by side, one 16-byte load per element.
+    const R4<R>* sp = reinterpret_cast<const R4<R>*>(in + (line0 + line) * (M / 2) * 4) + g;
     C1<R> v[16];
 #pragma unroll
-    for (int n1 = 0; n1 < 16; ++n1) v[n1] = ln[16 * n1 + t];
-    __syncthreads();   // the exchange below reuses the line
+    for (int n1 = 0; n1 < 16; ++n1) {
+        const int x = 16 * n1 + t;
+        const int q = n1 < 8 ? x : (x == M / 2 ? 0 : M - x);
+        const R4<R> ab = sp[2 * q];
+        if (n1 < 8) {
+            v[n1] = x == 0 ? C1<R>{ab.x, ab.z} : C1<R>{ab.x - ab.w, ab.y + ab.z};
+        } else {
+            v[n1] = x == M / 2 ? C1<R>{R(0), R(0)} : C1<R>{ab.x + ab.w, ab.z - ab.y};
+        }
+    }
+    C1<R>* ln = buf + l16 * kL16Line;
+    __syncthreads();   // twiddles
     fft256_line(v, ln, tw, t, -1);
     __syncthreads();
 #pragma unroll
@@ -2004,33 +1998,25 @@ __device__ __forceinline__ void fft_x_inv8_body(const C1<R>* __restrict__ in, R4
     __shared__ C1<R> tw[M];
     load_twiddles<R, M>(tw, twg, -1);
     const size_t line0 = (size_t)bid * RL;
-    // thread (l, q) reads the four spectra at q once and fills x = q and M - q
-    for (int e = threadIdx.x; e < RL * (M / 2); e += 8 * LN) {
-        const int l = e / (M / 2), q = e % (M / 2);
-        const C1<R>* sp = in + ((line0 + l) * (M / 2) + q) * 4;
-        C1<R> S[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) S[c] = sp[c];
-#pragma unroll
-        for (int g = 0; g < 2; ++g) {
-            const C1<R> a = S[2 * g], b = S[2 * g + 1];
-            C1<R>* ln = buf + (2 * l + g) * Fft8Line<M>::LINE;
-            if (q == 0) {
-                ln[0] = {a.re, b.re};
-                ln[M / 2] = {R(0), R(0)};
-            } else {
-                ln[q] = {a.re - b.im, a.im + b.re};
-                ln[M - q] = {a.re + b.im, b.re - a.im};
-            }
-        }
-    }
-    __syncthreads();
     const int l32 = threadIdx.x / 8, t = threadIdx.x % 8;   // complex line, thread in line
-    C1<R>* ln = buf + l32 * Fft8Line<M>::LINE;
+    const int line = l32 >> 1, g = l32 & 1;
+    // as in k_fft_x_inv256: element x of complex line g from the two half
+    // spectra at q = x or M - x, one 16-byte load (two in FP64) per element
+    const R4<R>* sp = reinterpret_cast<const R4<R>*>(in + (line0 + line) * (M / 2) * 4) + g;
     C1<R> v[NV];
 #pragma unroll
-    for (int n1 = 0; n1 < NV; ++n1) v[n1] = ln[8 * n1 + t];
-    __syncthreads();   // the exchange below reuses the line
+    for (int n1 = 0; n1 < NV; ++n1) {
+        const int x = 8 * n1 + t;
+        const int q = n1 < NV / 2 ? x : (x == M / 2 ? 0 : M - x);
+        const R4<R> ab = sp[2 * q];
+        if (n1 < NV / 2) {
+            v[n1] = x == 0 ? C1<R>{ab.x, ab.z} : C1<R>{ab.x - ab.w, ab.y + ab.z};
+        } else {
+            v[n1] = x == M / 2 ? C1<R>{R(0), R(0)} : C1<R>{ab.x + ab.w, ab.z - ab.y};
+        }
+    }
+    C1<R>* ln = buf + l32 * Fft8Line<M>::LINE;
+    __syncthreads();   // twiddles
     fft8_line<R, M>(v, ln, tw, t, -1);
     __syncthreads();
 #pragma unroll
@@ -2061,6 +2047,8 @@ __global__ __launch_bounds__(256) void k_fft_x_inv8(const C1<R>* __restrict__ in
 // N = 1e5, 256^3: 504 / 579 / 740 us for G = 64 / 32 / 16 (the shorter
 // butterfly does not pay for the longer load chain of each lane).
 constexpr int kGatherLanes = 64;
+// wavefronts per gather workgroup (consecutive spheres of the binned order)
+constexpr int kGatherWaves = 4;
 
 // HYB (the hybrid size approach of Sec. 3.2): the Faxen Laplacians of the
 // read-out come from the k-space field grid2 = (lap/6) v instead of the
@@ -2072,7 +2060,7 @@ __device__ __forceinline__ void gather_body(
     const R4<R>* __restrict__ grid2, int M, int P, SpreadGeom sg, double inv_eta, int parts, int compressible,
     const double* __restrict__ ybuf, double* __restrict__ yout, int bid) {
     static_assert(G == 16 || G == 32 || G == 64, "lanes per sphere");
-    constexpr int SPB = 4 * (64 / G);   // spheres per workgroup
+    constexpr int SPB = kGatherWaves * (64 / G);   // spheres per workgroup
     __shared__ R fac[SPB][2 * kMaxP];
     __shared__ R zt[SPB][4][kMaxP + 1];   // f_z(kz) u_z(kz)^k, k = 0..3 (zero past P)
     const int lane = threadIdx.x & (G - 1), sb = threadIdx.x / G;
@@ -2272,7 +2260,7 @@ __device__ __forceinline__ void gather_body(
 }
 
 template <typename R, int G, bool SHEAR, bool HYB>
-__global__ __launch_bounds__(256) void k_gather(
+__global__ __launch_bounds__(64 * kGatherWaves) void k_gather(
     int n, const R* __restrict__ recs, const int* __restrict__ perm, const R4<R>* __restrict__ grid,
     const R4<R>* __restrict__ grid2, int M, int P, SpreadGeom sg, double inv_eta, int parts, int compressible,
     const double* __restrict__ ybuf, double* __restrict__ yout) {
@@ -2550,19 +2538,20 @@ int launch_pair(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
 template <typename R>
 static void launch_gather_R(const ApplyArgs& A, hipStream_t st) {
     const int n = (int)A.n;
-    constexpr int spb = 4 * (64 / kGatherLanes);
+    constexpr int spb = kGatherWaves * (64 / kGatherLanes);
+    constexpr int nt = 64 * kGatherWaves;
     const int gg = (n + spb - 1) / spb;
     const SpreadGeom sg = spread_geom(A, true);
     const R4<R>* g1 = (const R4<R>*)A.rgrid;
     const R4<R>* g2 = (const R4<R>*)A.rgrid2;
     if (A.hybrid)   // the window is read plainly: no sheared-cell Laplacian term
-        hipLaunchKernelGGL((k_gather<R, kGatherLanes, false, true>), dim3(gg), dim3(256), 0, st, n, (const R*)A.wrec,
+        hipLaunchKernelGGL((k_gather<R, kGatherLanes, false, true>), dim3(gg), dim3(nt), 0, st, n, (const R*)A.wrec,
                            A.perm, g1, g2, A.M, A.P, sg, A.inv_eta, A.parts, A.compressible, A.ybuf, A.y);
     else if (A.win.sheared)
-        hipLaunchKernelGGL((k_gather<R, kGatherLanes, true, false>), dim3(gg), dim3(256), 0, st, n, (const R*)A.wrec,
+        hipLaunchKernelGGL((k_gather<R, kGatherLanes, true, false>), dim3(gg), dim3(nt), 0, st, n, (const R*)A.wrec,
                            A.perm, g1, g2, A.M, A.P, sg, A.inv_eta, A.parts, A.compressible, A.ybuf, A.y);
     else
-        hipLaunchKernelGGL((k_gather<R, kGatherLanes, false, false>), dim3(gg), dim3(256), 0, st, n, (const R*)A.wrec,
+        hipLaunchKernelGGL((k_gather<R, kGatherLanes, false, false>), dim3(gg), dim3(nt), 0, st, n, (const R*)A.wrec,
                            A.perm, g1, g2, A.M, A.P, sg, A.inv_eta, A.parts, A.compressible, A.ybuf, A.y);
 }
 
@@ -2720,7 +2709,7 @@ __global__ __launch_bounds__(256) void k_fft_x_inv8_multi(const MultiSys* __rest
 }
 
 template <typename R, bool SHEAR>
-__global__ __launch_bounds__(256) void k_gather_multi(const MultiSys* __restrict__ sys,
+__global__ __launch_bounds__(64 * kGatherWaves) void k_gather_multi(const MultiSys* __restrict__ sys,
                                                       const int2* __restrict__ items) {
     MULTI_ITEM();
     gather_body<R, kGatherLanes, SHEAR, false>((int)A.n, (const R*)A.wrec, A.perm, (const R4<R>*)A.rgrid,
@@ -2776,7 +2765,7 @@ int multi_plan_build(const ApplyArgs* args, int nsys, MultiPlan** out, hipStream
         add(kMkFftY, M, k, f8 ? (M / 2 / (ln / 4)) * M : (M / 2 / fft_w(M, dbl)) * M);
         add(kMkFftZ, M, k, f8 ? (M / 2 / (ln / 4)) * M : (M / 2 / fft_w(M, dbl)) * M);
         add(kMkFftXI, M, k, f8 ? M * M / (ln / 2) : M * M / fft_lpb(M, dbl));
-        constexpr int spb = 4 * (64 / kGatherLanes);
+        constexpr int spb = kGatherWaves * (64 / kGatherLanes);
         add(A.win.sheared ? kMkGatherShear : kMkGather, 0, k, (n + spb - 1) / spb);
     }
     std::vector<int2> all;
@@ -2897,8 +2886,8 @@ int multi_queue_wave(const MultiPlan* P, hipStream_t st) {
 template <typename R>
 static void multi_gather_R(const MultiPlan* P, hipStream_t st) {
     for (const MultiList& L : P->lists) {
-        if (L.kind == kMkGather) MULTI_LAUNCH((k_gather_multi<R, false>), 256);
-        if (L.kind == kMkGatherShear) MULTI_LAUNCH((k_gather_multi<R, true>), 256);
+        if (L.kind == kMkGather) MULTI_LAUNCH((k_gather_multi<R, false>), 64 * kGatherWaves);
+        if (L.kind == kMkGatherShear) MULTI_LAUNCH((k_gather_multi<R, true>), 64 * kGatherWaves);
     }
 }
 
