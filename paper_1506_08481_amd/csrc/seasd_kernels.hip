@@ -1396,7 +1396,13 @@ __global__ __launch_bounds__(256) void k_fft_y(C1<R>* __restrict__ data, const d
 // thread t holds x[16 n1 + t], n1 = 0..15, transforms over n1 in registers,
 // applies the twiddle w^(t k1), exchanges through LDS once and transforms
 // over the other index. One LDS buffer (padded rows of 17, lines of 273) and
-// 16 lines per workgroup, so a workgroup reads whole 128-byte rows.
+// 16 complex lines per workgroup in FP32, 8 in FP64 (Fft16Lines), so a
+// workgroup reads whole 128-byte rows.
+
+template <typename R>
+struct Fft16Lines {
+    static constexpr int value = sizeof(R) == 4 ? 16 : 8;
+};
 
 // 4-point DFT in place, exponent sign sgn: Y_k = sum_n a_n (sgn i)^(n k)
 template <typename T>
@@ -1441,17 +1447,16 @@ __device__ inline void fft256_line(C1<T>* v, C1<T>* ln, const C1<T>* tw, int t, 
     dft16(v, tw, sgn);
 }
 
-// y pass for M = 256 (FP32 storage): a workgroup owns 4 qx columns at one z,
-// 16 lines (4 columns x 4 fields).
+// y pass for M = 256: a workgroup owns LN / 4 qx columns at one z, LN lines
+// (columns x 4 fields), 16 threads per line.
 template <typename R>
 __global__ __launch_bounds__(256) void k_fft_y256(C1<R>* __restrict__ data, const double* __restrict__ twg,
                                                   int sgn) {
-    constexpr int M = 256, HX = 128, W = 4;
-    __shared__ C1<R> buf[16 * kL16Line];
+    constexpr int M = 256, HX = 128, LN = Fft16Lines<R>::value, W = LN / 4;
+    __shared__ C1<R> buf[LN * kL16Line];
     __shared__ C1<R> tw[M];
     load_twiddles<R, M>(tw, twg, sgn);
-    const int lane = threadIdx.x & 63;
-    const int l = lane & 15, t = (lane >> 4) + 4 * (threadIdx.x >> 6);
+    const int l = threadIdx.x % LN, t = threadIdx.x / LN;   // consecutive lanes: consecutive lines
     const int x0 = (blockIdx.x % (HX / W)) * W;
     const int z = blockIdx.x / (HX / W);
     C1<R>* base = data + ((size_t)z * M * HX + x0) * 4 + l;   // + (y HX) * 4
@@ -1464,20 +1469,19 @@ __global__ __launch_bounds__(256) void k_fft_y256(C1<R>* __restrict__ data, cons
     for (int k2 = 0; k2 < 16; ++k2) base[(size_t)(16 * k2 + t) * HX * 4] = v[4 * (k2 & 3) + (k2 >> 2)];
 }
 
-// x pass, forward, M = 256 (FP32): 8 real lines per workgroup, each a pair
-// of complex transforms (x + i y fields, z + i w fields), then the same
-// half-spectrum unpacking as k_fft_x_fwd.
+// x pass, forward, M = 256: LN / 2 real lines per workgroup (8 in FP32, 4 in
+// FP64), each a pair of complex transforms (x + i y fields, z + i w fields),
+// then the same half-spectrum unpacking as k_fft_x_fwd.
 template <typename R>
 __global__ __launch_bounds__(256) void k_fft_x_fwd256(const R4<R>* __restrict__ in, C1<R>* __restrict__ out,
                                                       const double* __restrict__ twg) {
-    constexpr int M = 256;
-    __shared__ C1<R> buf[16 * kL16Line];
+    constexpr int M = 256, LN = Fft16Lines<R>::value, RL = LN / 2;
+    __shared__ C1<R> buf[LN * kL16Line];
     __shared__ C1<R> tw[M];
     load_twiddles<R, M>(tw, twg, +1);
-    const int lane = threadIdx.x & 63;
-    const int l16 = (lane >> 4) + 4 * (threadIdx.x >> 6), t = lane & 15;
+    const int l16 = threadIdx.x >> 4, t = threadIdx.x & 15;   // complex line, thread in line
     const int line = l16 >> 1, g = l16 & 1;
-    const size_t line0 = (size_t)blockIdx.x * 8;
+    const size_t line0 = (size_t)blockIdx.x * RL;
     // the lanes of fields (x, y) and (z, w) of one line sit side by side in a
     // wavefront, so each load instruction covers whole 256-byte rows once
     const C1<R>* src = reinterpret_cast<const C1<R>*>(in) + ((line0 + line) * M + t) * 2 + g;
@@ -1491,7 +1495,7 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd256(const R4<R>* __restrict__ 
 #pragma unroll
     for (int k2 = 0; k2 < 16; ++k2) ln[16 * k2 + t] = v[4 * (k2 & 3) + (k2 >> 2)];
     __syncthreads();
-    for (int e = threadIdx.x; e < 8 * (M / 2); e += 256) {
+    for (int e = threadIdx.x; e < RL * (M / 2); e += 16 * LN) {
         const int l = e >> 7, q = e & 127;
         const int qn = (M - q) & (M - 1);
         C1<R> o[4];
@@ -1508,17 +1512,16 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd256(const R4<R>* __restrict__ 
     }
 }
 
-// x pass, inverse, M = 256 (FP32): half spectrum -> 8 real lines per workgroup
+// x pass, inverse, M = 256: half spectrum -> LN / 2 real lines per workgroup
 template <typename R>
 __global__ __launch_bounds__(256) void k_fft_x_inv256(const C1<R>* __restrict__ in, R4<R>* __restrict__ out,
                                                       const double* __restrict__ twg) {
-    constexpr int M = 256;
-    __shared__ C1<R> buf[16 * kL16Line];
+    constexpr int M = 256, LN = Fft16Lines<R>::value, RL = LN / 2;
+    __shared__ C1<R> buf[LN * kL16Line];
     __shared__ C1<R> tw[M];
     load_twiddles<R, M>(tw, twg, -1);
-    const size_t line0 = (size_t)blockIdx.x * 8;
-    const int lane = threadIdx.x & 63;
-    const int l16 = (lane >> 4) + 4 * (threadIdx.x >> 6), t = lane & 15;
+    const size_t line0 = (size_t)blockIdx.x * RL;
+    const int l16 = threadIdx.x >> 4, t = threadIdx.x & 15;   // complex line, thread in line
     const int line = l16 >> 1, g = l16 & 1;
     // complex line g of real line `line` packs fields 2g (real part) and
     // 2g + 1 (imaginary part): its element x comes from the two half spectra
@@ -1544,7 +1547,7 @@ __global__ __launch_bounds__(256) void k_fft_x_inv256(const C1<R>* __restrict__ 
 #pragma unroll
     for (int k2 = 0; k2 < 16; ++k2) ln[16 * k2 + t] = v[4 * (k2 & 3) + (k2 >> 2)];
     __syncthreads();
-    for (int e = threadIdx.x; e < 8 * M; e += 256) {
+    for (int e = threadIdx.x; e < RL * M; e += 16 * LN) {
         const int l = e >> 8, x = e & 255;
         const C1<R> A = buf[(2 * l) * kL16Line + x], B = buf[(2 * l + 1) * kL16Line + x];
         out[(line0 + l) * M + x] = {A.re, A.im, B.re, B.im};
@@ -1718,13 +1721,12 @@ __global__ __launch_bounds__(256) void k_fft_z_scale_hyb(C1<R>* __restrict__ dat
 template <typename R>
 __global__ __launch_bounds__(256) void k_fft_z256(C1<R>* __restrict__ data, const double* __restrict__ twg,
                                                   KScale ks) {
-    constexpr int M = 256, HX = 128, W = 4;
-    __shared__ C1<R> buf[16 * kL16Line];
+    constexpr int M = 256, HX = 128, LN = Fft16Lines<R>::value, W = LN / 4;
+    __shared__ C1<R> buf[LN * kL16Line];
     __shared__ C1<R> twf[M], twi[M];
     load_twiddles<R, M>(twf, twg, +1);
     load_twiddles<R, M>(twi, twg, -1);
-    const int lane = threadIdx.x & 63;
-    const int l = lane & 15, t = (lane >> 4) + 4 * (threadIdx.x >> 6);
+    const int l = threadIdx.x % LN, t = threadIdx.x / LN;
     const int x0 = (blockIdx.x % (HX / W)) * W;
     const int y = blockIdx.x / (HX / W);
     const size_t zstride = (size_t)M * HX * 4;
@@ -1741,8 +1743,8 @@ __global__ __launch_bounds__(256) void k_fft_z256(C1<R>* __restrict__ data, cons
     for (int k2 = 0; k2 < 16; ++k2) ln[16 * k2 + t] = v[4 * (k2 & 3) + (k2 >> 2)];
     __syncthreads();
     const int qy = (y < M / 2) ? y : y - M;
-    for (int e = threadIdx.x; e < W * M; e += 256) {
-        const int w = e & 3, z = e >> 2;
+    for (int e = threadIdx.x; e < W * M; e += 16 * LN) {
+        const int w = e % W, z = e / W;
         const int qx = x0 + w;
         const int qz = (z < M / 2) ? z : z - M;
         C1<R>* f0 = buf + (w * 4 + 0) * kL16Line + z;
@@ -2292,12 +2294,13 @@ struct FftShape {
     case MM: {                                                                                            \
         constexpr int MM8 = (MM == 64) ? 64 : 128; /* the four-step kernels' M (used when sp8) */        \
         const int lines = MM * MM;                                                                        \
-        const bool sp256 = MM == 256 && !dbl && !hyb;                                                     \
+        const bool sp256 = MM == 256 && !hyb;                                                             \
         const bool sp8 = (MM == 128 || MM == 64) && !hyb;                                                 \
         constexpr int LN8 = Fft8Lines<R>::value; /* lines per workgroup of the four-step passes */        \
+        constexpr int LN16 = Fft16Lines<R>::value;                                                        \
         tm->begin(kPhaseFftXFwd, st);                                                                     \
         if (sp256)                                                                                        \
-            hipLaunchKernelGGL((k_fft_x_fwd256<R>), dim3(lines / 8), dim3(256), 0, st,                    \
+            hipLaunchKernelGGL((k_fft_x_fwd256<R>), dim3(lines / (LN16 / 2)), dim3(16 * LN16), 0, st,     \
                                (const R4<R>*)rgrid, (C1<R>*)spec, tw);                                    \
         else if (sp8)                                                                                     \
             hipLaunchKernelGGL((k_fft_x_fwd8<R, MM8>), dim3(lines / (LN8 / 2)), dim3(8 * LN8), 0, st,     \
@@ -2306,12 +2309,13 @@ struct FftShape {
             hipLaunchKernelGGL((k_fft_x_fwd<R, MM, LPB>), dim3(lines / LPB), dim3(256), 0, st,            \
                                (const R4<R>*)rgrid, (C1<R>*)spec, tw);                                    \
         if (sp256) {                                                                                      \
+            const dim3 g16((128 / (LN16 / 4)) * 256), b16(16 * LN16);                                     \
             tm->begin(kPhaseFftYFwd, st);                                                                 \
-            hipLaunchKernelGGL((k_fft_y256<R>), dim3(32 * 256), dim3(256), 0, st, (C1<R>*)spec, tw, +1);  \
+            hipLaunchKernelGGL((k_fft_y256<R>), g16, b16, 0, st, (C1<R>*)spec, tw, +1);                   \
             tm->begin(kPhaseFftZ, st);                                                                    \
-            hipLaunchKernelGGL((k_fft_z256<R>), dim3(32 * 256), dim3(256), 0, st, (C1<R>*)spec, tw, ks);  \
+            hipLaunchKernelGGL((k_fft_z256<R>), g16, b16, 0, st, (C1<R>*)spec, tw, ks);                   \
             tm->begin(kPhaseFftYInv, st);                                                                 \
-            hipLaunchKernelGGL((k_fft_y256<R>), dim3(32 * 256), dim3(256), 0, st, (C1<R>*)spec, tw, -1);  \
+            hipLaunchKernelGGL((k_fft_y256<R>), g16, b16, 0, st, (C1<R>*)spec, tw, -1);                   \
         } else if (sp8) {                                                                                 \
             const dim3 g8((MM8 / 2 / (LN8 / 4)) * MM8), b8(8 * LN8);                                     \
             tm->begin(kPhaseFftYFwd, st);                                                                 \
@@ -2342,7 +2346,7 @@ struct FftShape {
         }                                                                                                 \
         tm->begin(kPhaseFftXInv, st);                                                                     \
         if (sp256)                                                                                        \
-            hipLaunchKernelGGL((k_fft_x_inv256<R>), dim3(lines / 8), dim3(256), 0, st,                    \
+            hipLaunchKernelGGL((k_fft_x_inv256<R>), dim3(lines / (LN16 / 2)), dim3(16 * LN16), 0, st,     \
                                (const C1<R>*)spec, (R4<R>*)rgrid, tw);                                    \
         else if (sp8)                                                                                     \
             hipLaunchKernelGGL((k_fft_x_inv8<R, MM8>), dim3(lines / (LN8 / 2)), dim3(8 * LN8), 0, st,     \
