@@ -1491,24 +1491,22 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd256(const R4<R>* __restrict__ 
     __syncthreads();   // twiddles
     C1<R>* ln = buf + l16 * kL16Line;
     fft256_line(v, ln, tw, t, +1);
-    __syncthreads();
+    // Half-spectrum unpacking in registers: the thread holds X[16 k2 + t] in
+    // v[4 (k2 % 4) + k2 / 4]; X[M - q] of q = 16 k2 + t (t > 0) sits in lane
+    // 16 - t of the same line at k2' = 15 - k2, and for t = 0 in the thread
+    // itself at k2' = (16 - k2) mod 16.
+    const int pl = (int)(threadIdx.x & 63 & ~15) | ((16 - t) & 15);   // partner lane
+    C1<R>* dst = out + (line0 + line) * (M / 2) * 4 + 2 * g;
 #pragma unroll
-    for (int k2 = 0; k2 < 16; ++k2) ln[16 * k2 + t] = v[4 * (k2 & 3) + (k2 >> 2)];
-    __syncthreads();
-    for (int e = threadIdx.x; e < RL * (M / 2); e += 16 * LN) {
-        const int l = e >> 7, q = e & 127;
-        const int qn = (M - q) & (M - 1);
-        C1<R> o[4];
-#pragma unroll
-        for (int gg = 0; gg < 2; ++gg) {
-            const C1<R> A = buf[(2 * l + gg) * kL16Line + q];
-            const C1<R> B = buf[(2 * l + gg) * kL16Line + qn];
-            o[2 * gg] = {R(0.5) * (A.re + B.re), R(0.5) * (A.im - B.im)};
-            o[2 * gg + 1] = {R(0.5) * (A.im + B.im), R(-0.5) * (A.re - B.re)};
-        }
-        C1<R>* dst = out + ((line0 + l) * (M / 2) + q) * 4;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) dst[c] = o[c];
+    for (int k2 = 0; k2 < 8; ++k2) {
+        const int q = 16 * k2 + t;
+        const C1<R> A = v[4 * (k2 & 3) + (k2 >> 2)];
+        const int kp = 15 - k2, k0 = (16 - k2) & 15;
+        const C1<R> Bp = v[4 * (kp & 3) + (kp >> 2)];
+        const C1<R> Bs = {__shfl(Bp.re, pl), __shfl(Bp.im, pl)};
+        const C1<R> B = t == 0 ? v[4 * (k0 & 3) + (k0 >> 2)] : Bs;
+        dst[4 * q] = {R(0.5) * (A.re + B.re), R(0.5) * (A.im - B.im)};
+        dst[4 * q + 1] = {R(0.5) * (A.im + B.im), R(-0.5) * (A.re - B.re)};
     }
 }
 
@@ -1964,24 +1962,22 @@ __device__ __forceinline__ void fft_x_fwd8_body(const R4<R>* __restrict__ in, C1
     __syncthreads();   // twiddles
     C1<R>* ln = buf + l32 * Fft8Line<M>::LINE;
     fft8_line<R, M>(v, ln, tw, t, +1);
-    __syncthreads();
+    // Half-spectrum unpacking in registers, as in k_fft_x_fwd256: element
+    // 8 c + t sits in v[jof(c)]; X[M - q] of q = 8 c + t (t > 0) sits in
+    // lane 8 - t of the same line at c' = NV - 1 - c, and for t = 0 in the
+    // thread itself at c' = (NV - c) mod NV.
+    auto jof = [](int c) { return M == 128 ? 8 * (c & 1) + (c >> 1) : c; };
+    const int pl = (int)(threadIdx.x & 63 & ~7) | ((8 - t) & 7);   // partner lane
+    C1<R>* dst = out + (line0 + line) * (M / 2) * 4 + 2 * g;
 #pragma unroll
-    for (int j = 0; j < NV; ++j) ln[Fft8Line<M>::out(t, j)] = v[j];
-    __syncthreads();
-    for (int e = threadIdx.x; e < RL * (M / 2); e += 8 * LN) {
-        const int l = e / (M / 2), q = e % (M / 2);
-        const int qn = (M - q) & (M - 1);
-        C1<R> o[4];
-#pragma unroll
-        for (int gg = 0; gg < 2; ++gg) {
-            const C1<R> A = buf[(2 * l + gg) * Fft8Line<M>::LINE + q];
-            const C1<R> B = buf[(2 * l + gg) * Fft8Line<M>::LINE + qn];
-            o[2 * gg] = {R(0.5) * (A.re + B.re), R(0.5) * (A.im - B.im)};
-            o[2 * gg + 1] = {R(0.5) * (A.im + B.im), R(-0.5) * (A.re - B.re)};
-        }
-        C1<R>* dst = out + ((line0 + l) * (M / 2) + q) * 4;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) dst[c] = o[c];
+    for (int c = 0; c < NV / 2; ++c) {
+        const int q = 8 * c + t;
+        const C1<R> A = v[jof(c)];
+        const C1<R> Bp = v[jof(NV - 1 - c)];
+        const C1<R> Bs = {__shfl(Bp.re, pl), __shfl(Bp.im, pl)};
+        const C1<R> B = t == 0 ? v[jof((NV - c) % NV)] : Bs;
+        dst[4 * q] = {R(0.5) * (A.re + B.re), R(0.5) * (A.im - B.im)};
+        dst[4 * q + 1] = {R(0.5) * (A.im + B.im), R(-0.5) * (A.re - B.re)};
     }
 }
 
