@@ -3,9 +3,8 @@
 TEST INFRASTRUCTURE ONLY: imported by tests/, the smoke check and the
 CPU-baseline leg of the benchmark; the library never calls it.
 
-This is the paper's own yardstick, the "well-converged value from direct Ewald
-summation" against which the Spectral Ewald result is measured (Sec. 5.1,
-eq. err-E). It is not the Spectral Ewald method: there is no grid, no window
+This is the paper's own yardstick: the Spectral Ewald result is measured
+against a converged direct Ewald sum (Sec. 5.1, eq. err-E). It is not the Spectral Ewald method: there is no grid, no window
 and no FFT. Every block symbol comes from oracle.symbols; this file only sums
 them.
 
