@@ -89,6 +89,10 @@ extern "C" {
 /* ---- configuration --------------------------------------------------------- */
 #define SEASD_FP64 0
 #define SEASD_FP32 1
+#define SEASD_MIXED 2  /* FP64 products, except inside the Arnoldi steps of    */
+                       /* seasd_solve_farfield, which take the FP32 product:    */
+                       /* each restart's true residual stays FP64, so the       */
+                       /* restart cycles are steps of iterative refinement      */
 
 #define SEASD_PARTS_REAL 1  /* real-space pair sum (Sec. 3.3)                 */
 #define SEASD_PARTS_WAVE 2  /* Spectral Ewald wave-space sum (Sec. 3.1)       */
@@ -122,7 +126,8 @@ typedef struct seasd_config {
     double  xi;             /* Ewald splitting parameter, Beenakker convention (Sec. 2.2)   */
     double  rc_factor;      /* real-space cut-off r_c = rc_factor (a_i + a_j), > 1           */
     double  eta;            /* solvent viscosity, > 0                                        */
-    int32_t precision;      /* SEASD_FP64 or SEASD_FP32: spreading, FFTs and gather; the     */
+    int32_t precision;      /* SEASD_FP64, SEASD_FP32 or SEASD_MIXED: spreading, FFTs and    */
+                            /* gather (SEASD_MIXED: FP32 only in solve Arnoldi steps); the */
                             /* real-space pair sum and the solver always run in FP64        */
     int32_t parts;          /* SEASD_PARTS_* bit mask; SEASD_PARTS_ALL for the operator      */
     int32_t compressible;   /* 1: include the pressure-moment row and column; 0: zero them  */
@@ -237,6 +242,11 @@ int seasd_mobility_apply_static(seasd_handle handle, int64_t n,
  *          out: solution
  *   stats  host, may be NULL; true_residual is ||b' - A f|| / ||b'|| of the
  *          incompressible system (b' = b_f - C s_self) from a fresh product
+ * With precision SEASD_MIXED the Arnoldi steps use the FP32 product and
+ * every restart's true residual the FP64 one: each cycle solves for the
+ * correction of the current iterate with the FP32 operator (iterative
+ * refinement), is also ended once its residual estimate falls by 1e-5, and
+ * tol is met on the FP64 residual.
  * Synchronises `stream`. Returns SEASD_W_NOT_CONVERGED if max_iter was reached
  * with the true residual above tol (x then holds the last iterate), and the
  * errors of seasd_mobility_apply or SEASD_E_SINGULAR. */

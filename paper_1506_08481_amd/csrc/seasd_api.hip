@@ -52,9 +52,17 @@ struct seasd_handle_s {
     // words and the event that marks their copy
     unsigned long long* ns_host = nullptr;
     hipEvent_t ev_stats = nullptr;
+    // SEASD_MIXED: set while a solve's Arnoldi step runs its product
+    bool step_fp32 = false;
 };
 
 static int hip_ok(hipError_t e) { return e == hipSuccess ? 0 : SEASD_E_HIP; }
+
+// A restart cycle of a SEASD_MIXED solve ends once its residual estimate has
+// fallen by this factor: the FP32 product's relative error (below 1e-6 at the
+// configurations the autotuner picks) times the preconditioned system's
+// condition number bounds what one cycle can gain on the FP64 residual.
+constexpr double kMixedCycleRtol = 1e-5;
 
 extern "C" const char* seasd_error_string(int32_t code) {
     switch (code) {
@@ -169,7 +177,8 @@ extern "C" int seasd_set_config(seasd_handle h, const seasd_config* c) {
     if (!(std::isfinite(c->m)) || !(c->xi > 0.0) || !std::isfinite(c->xi)) return SEASD_E_INVALID_ARG;
     if (!(c->rc_factor > 1.0) || !std::isfinite(c->rc_factor)) return SEASD_E_INVALID_ARG;
     if (!(c->eta > 0.0) || !std::isfinite(c->eta)) return SEASD_E_INVALID_ARG;
-    if (c->precision != SEASD_FP64 && c->precision != SEASD_FP32) return SEASD_E_INVALID_ARG;
+    if (c->precision != SEASD_FP64 && c->precision != SEASD_FP32 && c->precision != SEASD_MIXED)
+        return SEASD_E_INVALID_ARG;
     if (c->parts < 0 || c->parts > SEASD_PARTS_ALL) return SEASD_E_INVALID_ARG;
     if (c->restart < 1 || c->restart > 200 || c->max_iter < 1) return SEASD_E_INVALID_ARG;
     if (!(c->tol > 0.0)) return SEASD_E_INVALID_ARG;
@@ -310,7 +319,9 @@ static void fill_args(seasd_handle h, ApplyArgs& A, int64_t n, const double* pos
     A.parts = c.parts;
     A.compressible = compressible;
     A.checks = checks ? 1 : 0;
-    A.fp32 = c.precision == SEASD_FP32;
+    // SEASD_MIXED: FP32 only for the Arnoldi steps of a far-field solve (the
+    // FP64 workspace holds the FP32 grids and records as well)
+    A.fp32 = c.precision == SEASD_FP32 || (c.precision == SEASD_MIXED && h->step_fp32);
     A.bin_of = h->bin_of.as<int>();
     A.counts = h->counts.as<int>();
     A.start = h->start.as<int>();
@@ -829,7 +840,17 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
         S.learned_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tl).count();
     }
     GmresResult G;
-    rc = h->gm.solve(apply11, precond, bred, x, c.tol, c.max_iter, st, &G);
+    // SEASD_MIXED: the FP32 product inside the cycles, the FP64 one for every
+    // restart's true residual
+    const std::function<int(const double*, double*)> apply_step = [&](const double* in, double* out) -> int {
+        h->step_fp32 = true;
+        const int e = apply11(in, out);
+        h->step_fp32 = false;
+        return e;
+    };
+    const bool mixed = c.precision == SEASD_MIXED;
+    rc = h->gm.solve(apply11, precond, bred, x, c.tol, c.max_iter, st, &G, mixed ? &apply_step : nullptr,
+                     mixed ? kMixedCycleRtol : 0.0);
     if (rc) return err_rc ? err_rc : (rc == -6 ? SEASD_E_HIP : rc);
     // pressure moments from the pressure Faxen law: s = M_self^-1 (b_trace - p-coupling(F, S))
     if (launch_trace_op(n, 1, radius, c.eta, x, nullptr, z, st)) return SEASD_E_HIP;   // z = (F, T, S, 0)

@@ -333,7 +333,8 @@ double DeviceGmres::norm(const double* v, hipStream_t st, int* rc) {
 
 int DeviceGmres::solve(const std::function<int(const double*, double*)>& apply_A,
                        const std::function<int(const double*, double*)>& apply_P, const double* b, double* x,
-                       double tol, int max_iter, hipStream_t st, GmresResult* res) {
+                       double tol, int max_iter, hipStream_t st, GmresResult* res,
+                       const std::function<int(const double*, double*)>* apply_step, double cycle_rtol) {
     GmresResult R{};
     int rc = 0;
     const double bnorm = norm(b, st, &rc);
@@ -382,12 +383,12 @@ int DeviceGmres::solve(const std::function<int(const double*, double*)>& apply_A
             if (hipEventSynchronize(events[q]) != hipSuccess) return -6;
             const double e = resid_host[q];
             jend = q + 1;
-            if (e / bnorm <= 0.5 * tol || e == 0.0 || !std::isfinite(e)) stop = true;
+            if (e / bnorm <= 0.5 * tol || e <= cycle_rtol * beta || e == 0.0 || !std::isfinite(e)) stop = true;
             return 0;
         };
         for (int j = 0; j < m && total + j < max_iter && !stop; ++j) {
             if ((rc = apply_P(Vp + (size_t)j * len, zp))) return rc;
-            if ((rc = apply_A(zp, wp))) return rc;
+            if ((rc = apply_step ? (*apply_step)(zp, wp) : apply_A(zp, wp))) return rc;
             ++R.matvecs;
             // classical Gram-Schmidt applied twice: h1 = V^T w, w -= V h1,
             // h2 = V^T w, w -= V h2, then |w| and the Givens update

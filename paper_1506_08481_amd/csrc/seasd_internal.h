@@ -283,10 +283,15 @@ struct DeviceGmres {
     void release();
     double norm(const double* v, hipStream_t st, int* rc);   // synchronises
     // x in: initial guess, out: solution; stops when |b - A x| <= tol |b| (true
-    // residual at each restart) or after max_iter Arnoldi steps
+    // residual at each restart) or after max_iter Arnoldi steps. With
+    // apply_step the Arnoldi steps use that operator instead of apply_A (a
+    // cheaper approximation: the restart cycles become iterative refinement)
+    // and a cycle also ends once its residual estimate is below cycle_rtol
+    // times the residual it started from.
     int solve(const std::function<int(const double*, double*)>& apply_A,
               const std::function<int(const double*, double*)>& apply_P, const double* b, double* x, double tol,
-              int max_iter, hipStream_t st, GmresResult* res);
+              int max_iter, hipStream_t st, GmresResult* res,
+              const std::function<int(const double*, double*)>* apply_step = nullptr, double cycle_rtol = 0.0);
 };
 
 // neighbour graph of the learned preconditioner (seasd_kernels.hip): edges

@@ -32,7 +32,7 @@ SEASD_E_SCRATCH = -10
 SEASD_W_NOT_CONVERGED = 1
 SEASD_W_PRECOND_FALLBACK = 2
 
-SEASD_FP64, SEASD_FP32 = 0, 1
+SEASD_FP64, SEASD_FP32, SEASD_MIXED = 0, 1, 2
 SEASD_PARTS_REAL, SEASD_PARTS_WAVE, SEASD_PARTS_SELF, SEASD_PARTS_ALL = 1, 2, 4, 7
 SEASD_PRECOND_NONE, SEASD_PRECOND_BLOCKDIAG, SEASD_PRECOND_LEARNED_GUESS = 0, 1, 3
 

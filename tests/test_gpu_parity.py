@@ -304,6 +304,49 @@ def test_gmres_preconditioner_helps_bidisperse(lib):
     assert stats[lib.SEASD_PRECOND_BLOCKDIAG]["iterations"] < stats[lib.SEASD_PRECOND_NONE]["iterations"]
 
 
+def test_mixed_precision_gmres_matches_dense_solve(lib):
+    """SEASD_MIXED: FP32 products inside the Arnoldi cycles, FP64 restart
+    residuals. The refinement still reaches the FP64 tolerance and the dense
+    one-way solve of the oracle."""
+    s = wl.bidisperse(12, 0.2, 4242)
+    b = wl.force_moments(s.n, 4343)
+    xo = solve.one_way_solve(s.pos, s.radius, s.box, b,
+                             ewald.converged_params(s.box, s.radius, xi=0.75, tol_exp=6.5), compressible=True)
+    eng = lib.Seasd(0, grid=32, P=24, m=0.9 * math.sqrt(math.pi * 24), xi=0.75, rc_factor=4.0,
+                    tol=1e-11, restart=60, max_iter=400, precision=lib.SEASD_MIXED)
+    x, st = eng.solve(_t(s.pos), _t(s.radius), s.box, _t(b))
+    xg = x.cpu().numpy()
+    print("mixed gmres", st, "rel err", _rel(xg, xo))
+    assert st["converged"] == 1 and st["true_residual"] <= 1e-11
+    assert st["restarts"] >= 2   # the cycles end at a 1e-5 reduction: refinement steps
+    assert _rel(xg, xo) < 1e-8
+    eng.close()
+
+
+def test_mixed_precision_solve_matches_fp64_solve(lib):
+    """N = 2,000 bidisperse spheres at the autotuned 1e-8 configuration: the
+    mixed-precision solve meets the same FP64 residual as the FP64 solve, in
+    about as many iterations, and the two solutions agree to the level the
+    tolerance allows."""
+    s = wl.bidisperse(2000, 0.3, 515, a1=1.0, a2=2.0)
+    b = wl.force_moments(s.n, 516)
+    c = lib.seasd_autotune(s.n, s.box, 1.0, 2.0, 1e-8, lib.SEASD_FP64)
+    out = {}
+    for prec in (lib.SEASD_FP64, lib.SEASD_MIXED):
+        eng = lib.Seasd(0, grid=tuple(c.grid), P=c.P, m=c.m, xi=c.xi, rc_factor=c.rc_factor, precision=prec,
+                        tol=1e-8, restart=50, max_iter=1500, precond=lib.SEASD_PRECOND_BLOCKDIAG, checks=1)
+        x, st = eng.solve(_t(s.pos), _t(s.radius), s.box, _t(b))
+        out[prec] = (x.cpu().numpy(), st)
+        eng.close()
+    (x64, s64), (xm, sm) = out[lib.SEASD_FP64], out[lib.SEASD_MIXED]
+    d = _rel(xm, x64)
+    print("grid", tuple(c.grid), "fp64", s64, "mixed", sm, "rel diff", d)
+    assert s64["converged"] == 1 and sm["converged"] == 1
+    assert sm["true_residual"] <= 1e-8
+    assert sm["iterations"] <= 1.25 * s64["iterations"] + 10
+    assert d < 1e-6
+
+
 def test_phase_timing_reports_every_phase(lib, small_case):
     """Per-phase timing: every documented phase of a product is recorded, in
     the documented order, and the profiled products give the same result as
