@@ -89,8 +89,9 @@ extern "C" {
 /* ---- configuration --------------------------------------------------------- */
 #define SEASD_FP64 0
 #define SEASD_FP32 1
-#define SEASD_MIXED 2  /* FP64 products, except inside the Arnoldi steps of    */
-                       /* seasd_solve_farfield, which take the FP32 product:    */
+#define SEASD_MIXED 2  /* FP64 products, except inside the GMRES Arnoldi steps  */
+                       /* of seasd_solve_farfield, seasd_solve_mixed and        */
+                       /* seasd_brownian_farfield, which take the FP32 product: */
                        /* each restart's true residual stays FP64, so the       */
                        /* restart cycles are steps of iterative refinement      */
 

@@ -64,6 +64,18 @@ static int hip_ok(hipError_t e) { return e == hipSuccess ? 0 : SEASD_E_HIP; }
 // condition number bounds what one cycle can gain on the FP64 residual.
 constexpr double kMixedCycleRtol = 1e-5;
 
+// The same operator with the mobility products it queues in FP32 (for the
+// Arnoldi steps of a SEASD_MIXED solve); every other step stays as it is.
+template <typename Op>
+static std::function<int(const double*, double*)> fp32_steps(seasd_handle h, Op& op) {
+    return [h, &op](const double* in, double* out) -> int {
+        h->step_fp32 = true;
+        const int e = op(in, out);
+        h->step_fp32 = false;
+        return e;
+    };
+}
+
 extern "C" const char* seasd_error_string(int32_t code) {
     switch (code) {
         case SEASD_OK: return "success";
@@ -842,12 +854,7 @@ extern "C" int seasd_solve_farfield(seasd_handle h, int64_t n, const double* pos
     GmresResult G;
     // SEASD_MIXED: the FP32 product inside the cycles, the FP64 one for every
     // restart's true residual
-    const std::function<int(const double*, double*)> apply_step = [&](const double* in, double* out) -> int {
-        h->step_fp32 = true;
-        const int e = apply11(in, out);
-        h->step_fp32 = false;
-        return e;
-    };
+    const std::function<int(const double*, double*)> apply_step = fp32_steps(h, apply11);
     const bool mixed = c.precision == SEASD_MIXED;
     rc = h->gm.solve(apply11, precond, bred, x, c.tol, c.max_iter, st, &G, mixed ? &apply_step : nullptr,
                      mixed ? kMixedCycleRtol : 0.0);
@@ -1055,7 +1062,10 @@ extern "C" int seasd_solve_mixed(seasd_handle h, int64_t n, const double* pos, c
     // y = 0 start
     if (hipMemsetAsync(y12, 0, sizeof(double) * len, st) != hipSuccess) return SEASD_E_HIP;
     GmresResult G;
-    rc = h->gm.solve(applyMt, precond, rhs, y12, c.tol, c.max_iter, st, &G);
+    const std::function<int(const double*, double*)> step32 = fp32_steps(h, applyMt);
+    const bool mixed = c.precision == SEASD_MIXED;
+    rc = h->gm.solve(applyMt, precond, rhs, y12, c.tol, c.max_iter, st, &G, mixed ? &step32 : nullptr,
+                     mixed ? kMixedCycleRtol : 0.0);
     if (rc) return err_rc ? err_rc : (rc == -6 ? SEASD_E_HIP : rc);
     // U = Rt^-1 (y_F + Fp), F = y_F - lambda U, S = y_S
     if (launch_ft_ops(n, 0, 0.0, y12, fp, v6, st)) return SEASD_E_HIP;
@@ -1145,7 +1155,10 @@ extern "C" int seasd_brownian_farfield(seasd_handle h, int64_t n, const double* 
         // start from the right-hand side scaled by the operator's diagonal size
         if (hipMemcpyAsync(y, b, sizeof(double) * len, hipMemcpyDeviceToDevice, st) != hipSuccess) return SEASD_E_HIP;
         GmresResult G;
-        e = h->gm.solve(op, pcond, b, y, c.tol, c.max_iter, st, &G);
+        const std::function<int(const double*, double*)> step32 = fp32_steps(h, op);
+        const bool mixed = c.precision == SEASD_MIXED;
+        e = h->gm.solve(op, pcond, b, y, c.tol, c.max_iter, st, &G, mixed ? &step32 : nullptr,
+                        mixed ? kMixedCycleRtol : 0.0);
         if (e) return e == -6 ? SEASD_E_HIP : e;
         B.iterations += G.iterations;
         B.matvecs += G.matvecs;

@@ -69,6 +69,21 @@ def test_brownian_matches_dense_ivp(lib, case):
     assert discs[1] < discs[0] / 1.8
 
 
+def test_brownian_mixed_precision(lib, case):
+    """SEASD_MIXED (FP32 products in the Arnoldi steps of every shifted
+    solve, FP64 restart residuals) reproduces the oracle's dense march to the
+    same bar as the FP64 solves."""
+    s, psi, p = case
+    eng = lib.Seasd(0, precision=lib.SEASD_MIXED, **CFG)
+    x, st = eng.brownian(_t(s.pos), _t(s.radius), s.box, _t(psi), dtau=0.1)
+    eng.close()
+    xo = brownian.brownian_farfield(s.pos, s.radius, s.box, psi, 0.1, params=p)
+    err = np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo)
+    print(f"mixed precision: vs dense IVP {err:.2e}, stats {st}")
+    assert st["converged"] == 1 and st["max_residual"] <= CFG["tol"]
+    assert err < 1e-8
+
+
 def test_brownian_sheared_cell(lib, case):
     s, psi, p = case
     box = np.array([[s.L, 0.5 * s.L, 0.0], [0.0, s.L, 0.0], [0.0, 0.0, s.L]])

@@ -61,8 +61,8 @@ def case():
     return s, M11, R, Fp, E
 
 
-def _gpu(lib, s, R, Fp, E, lam):
-    eng = lib.Seasd(0, **CFG)
+def _gpu(lib, s, R, Fp, E, lam, **extra):
+    eng = lib.Seasd(0, **CFG, **extra)
     rp, cl, vl = to_bsr6(R, s.n)
     f, sv, u, st = eng.solve_mixed(_t(s.pos), _t(s.radius), s.box, _t(rp, torch.int32), _t(cl, torch.int32),
                                    _t(vl), lam, _t(Fp), _t(E))
@@ -81,6 +81,18 @@ def test_mixed_matches_oracle(lib, case):
     U0, F0, S0 = mixed.direct_solve(M11, R, Fp, E)
     f, sv, u, st = _gpu(lib, s, R, Fp, E, lam)
     print(f"mixed solve: F {_rel(f, F0):.2e} S {_rel(sv, S0):.2e} U {_rel(u, U0):.2e} stats {st}")
+    assert st["converged"] == 1 and st["true_residual"] <= 1e-11
+    assert _rel(f, F0) < 1e-8 and _rel(sv, S0) < 1e-8 and _rel(u, U0) < 1e-8
+
+
+def test_mixed_with_mixed_precision_matches_oracle(lib, case):
+    """SEASD_MIXED: FP32 far-field products in the outer Arnoldi steps, FP64
+    restart residuals; the same bar as the FP64 solve."""
+    s, M11, R, Fp, E = case
+    lam = 6.0 * math.pi * float(s.radius.min())
+    U0, F0, S0 = mixed.direct_solve(M11, R, Fp, E)
+    f, sv, u, st = _gpu(lib, s, R, Fp, E, lam, precision=lib.SEASD_MIXED)
+    print(f"mixed precision: F {_rel(f, F0):.2e} S {_rel(sv, S0):.2e} U {_rel(u, U0):.2e} stats {st}")
     assert st["converged"] == 1 and st["true_residual"] <= 1e-11
     assert _rel(f, F0) < 1e-8 and _rel(sv, S0) < 1e-8 and _rel(u, U0) < 1e-8
 
