@@ -347,7 +347,8 @@ int seasd_profile_read(seasd_handle handle, double* ms, int32_t count);
  * cut-off factor so that xi r_c is fixed for a pair of spheres of radius
  * a_min (the batch planner passes the 10th-percentile radius, and the
  * 99th-percentile radius as a_max), and the window (P, m) from accuracy
- * scans of the method against the oracle (Sec. 5.1).
+ * scans of the method against the oracle (Sec. 5.1). SEASD_MIXED takes the
+ * FP64 choices (its products outside solve steps are FP64).
  * Other fields take the defaults. */
 int seasd_autotune(int64_t n, const double* box, double a_min, double a_max, double target, int32_t precision,
                    seasd_config* cfg);
