@@ -308,7 +308,8 @@ def bench_learned(args):
     problems, see paper_1506_08481_amd/train_precond.py), then solve one unseen
     suspension, N = 50,000 bidisperse (radii 1 and 2, equal volume per
     species), phi = 0.35, to relative residual 1e-6 with the block-diagonal
-    preconditioner and with the learned one; reports iterations and wall time."""
+    preconditioner and with the learned one; reports iterations and wall time,
+    also with FP32 products in the Arnoldi steps (precision SEASD_MIXED)."""
     from paper_1506_08481_amd import train_precond as tp
     from paper_1506_08481_amd import workloads as wl
     t0 = time.time()
@@ -335,6 +336,8 @@ def bench_learned(args):
     log(f"trained {len(hist)} steps in {t_train:.0f}s; test N={s.n} L={s.L:.2f}")
     res = tp.evaluate(net, s, tol=1e-6, precision=seasd.SEASD_FP64, repeats=2)
     bd, lg = res["blockdiag"], res["learned_guess"]
+    # the same two solves with FP32 products in the Arnoldi steps (FP64 restart residuals)
+    rmx = tp.evaluate(net, s, tol=1e-6, precision=seasd.SEASD_MIXED, repeats=2)
     out = {
         "metric": "far-field solve time, learned vs block-diagonal, N=5e4 bidisperse phi=0.35, 1e-6 residual",
         "value": lg["wall_s"], "unit": "s", "higher_is_better": False, "n_gpus": 1,
@@ -349,6 +352,9 @@ def bench_learned(args):
                                              "rel_diff_vs_blockdiag")},
         "iterations_saved": bd["iterations"] - lg["iterations"],
         "speedup_vs_blockdiag": bd["wall_s"] / lg["wall_s"],
+        "mixed_precision": {k: {q: rmx[k][q] for q in ("iterations", "true_residual", "wall_s",
+                                                      "rel_diff_vs_blockdiag")}
+                            for k in ("blockdiag", "learned_guess")},
         "training": ({"weights": args.weights} if args.weights else
                      {"configs": args.train_configs, "epochs": args.train_epochs, "rhs_per_step": 8,
                       "steps": len(hist), "problems_seen": len(hist) * 8,
