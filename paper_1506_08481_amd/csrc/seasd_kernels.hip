@@ -1457,8 +1457,13 @@ __global__ __launch_bounds__(256) void k_fft_y256(C1<R>* __restrict__ data, cons
     __shared__ C1<R> tw[M];
     load_twiddles<R, M>(tw, twg, sgn);
     const int l = threadIdx.x % LN, t = threadIdx.x / LN;   // consecutive lanes: consecutive lines
-    const int x0 = (blockIdx.x % (HX / W)) * W;
-    const int z = blockIdx.x / (HX / W);
+    // The forward pass takes the z-planes from last to first: the x pass has
+    // just written them first to last, and the planes it wrote last are the
+    // ones still in the memory-side cache (the spectrum is slightly larger
+    // than that cache; measured 95 -> 83 us at FP32).
+    const int bq = sgn > 0 ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
+    const int x0 = (bq % (HX / W)) * W;
+    const int z = bq / (HX / W);
     C1<R>* base = data + ((size_t)z * M * HX + x0) * 4 + l;   // + (y HX) * 4
     C1<R> v[16];
 #pragma unroll
