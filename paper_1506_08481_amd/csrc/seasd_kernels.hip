@@ -1523,7 +1523,10 @@ __global__ __launch_bounds__(256) void k_fft_x_inv256(const C1<R>* __restrict__ 
     __shared__ C1<R> buf[LN * kL16Line];
     __shared__ C1<R> tw[M];
     load_twiddles<R, M>(tw, twg, -1);
-    const size_t line0 = (size_t)blockIdx.x * RL;
+    // lines last to first: the inverse y pass wrote the planes first to last,
+    // so this pass starts on the ones still in the memory-side cache (101 ->
+    // 99 us at FP32)
+    const size_t line0 = (size_t)(gridDim.x - 1 - blockIdx.x) * RL;
     const int l16 = threadIdx.x >> 4, t = threadIdx.x & 15;   // complex line, thread in line
     const int line = l16 >> 1, g = l16 & 1;
     // complex line g of real line `line` packs fields 2g (real part) and
