@@ -84,3 +84,16 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=300, cwd=ROOT)
     assert r.returncode == 2
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_binding_constants_match_header():
+    """Every SEASD_* integer constant the binding defines has the header's value."""
+    src = open(os.path.join(ROOT, "include", "seasd.h")).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"^#define\s+(SEASD_\w+)\s+(-?\d+)\b", src, re.M)}
+    assert {"SEASD_FP64", "SEASD_FP32", "SEASD_MIXED"} <= set(defs)
+    checked = 0
+    for name, value in defs.items():
+        if hasattr(seasd, name):
+            assert getattr(seasd, name) == value, name
+            checked += 1
+    assert checked >= 10
