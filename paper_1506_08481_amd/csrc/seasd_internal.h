@@ -39,14 +39,19 @@ enum Phase {
 };
 
 // When enabled, records one HIP event at the start of each phase (and one at
-// the end) of every product on the launching stream, without synchronising.
+// the end of each stream's part) of every product on the stream that runs the
+// phase, without synchronising.
 // Event sets are kept per product until read, so a run of back-to-back
 // products can be timed phase by phase.
 struct PhaseTimer {
-    static constexpr int kSlots = kNumPhases + 1;
+    // a product marks each phase's start on the stream that runs it and ends
+    // each stream's sequence with an end marker; a phase lasts until the next
+    // mark on its own stream (a product may use two streams)
+    static constexpr int kSlots = kNumPhases + 6;
     bool enabled = false;
     std::vector<hipEvent_t> ev;     // kSlots per recorded product
     std::vector<int> order;         // phase of each slot (-1: end marker)
+    std::vector<hipStream_t> on;    // stream of each slot
     std::vector<int> used;          // slots used per product
     int products = 0;
     void start_product() {
@@ -59,6 +64,7 @@ struct PhaseTimer {
                 hipEventCreate(&e);
                 ev.push_back(e);
                 order.push_back(-1);
+                on.push_back(nullptr);
             }
         }
         used[products - 1] = 0;
@@ -69,6 +75,7 @@ struct PhaseTimer {
         if (u >= kSlots) return;
         const int slot = (products - 1) * kSlots + u;
         order[slot] = phase;
+        on[slot] = st;
         hipEventRecord(ev[slot], st);
         ++u;
     }
@@ -78,6 +85,7 @@ struct PhaseTimer {
         for (auto e : ev) hipEventDestroy(e);
         ev.clear();
         order.clear();
+        on.clear();
         used.clear();
         products = 0;
     }
@@ -204,7 +212,6 @@ int launch_clear_ints(int n, int* p, hipStream_t st);
 int launch_geometry(const ApplyArgs& a, hipStream_t st, PhaseTimer* tm);
 int launch_pairlist(const ApplyArgs& a, hipStream_t st);
 int launch_moments(const ApplyArgs& a, hipStream_t st);
-int launch_compute(const ApplyArgs& a, hipStream_t st, PhaseTimer* tm);
 int launch_wave(const ApplyArgs& a, hipStream_t st, PhaseTimer* tm);
 int launch_pair(const ApplyArgs& a, hipStream_t st, PhaseTimer* tm);
 int launch_gather(const ApplyArgs& a, hipStream_t st, PhaseTimer* tm);

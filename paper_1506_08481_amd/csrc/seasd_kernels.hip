@@ -2573,13 +2573,6 @@ int launch_gather(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-// pair sum, wave-space part and gather on an existing geometry
-int launch_compute(const ApplyArgs& A, hipStream_t st, PhaseTimer* tm) {
-    if (launch_pair(A, st, tm)) return -2;
-    if (launch_wave(A, st, tm)) return -1;
-    return launch_gather(A, st, tm);
-}
-
 // ---------------------------------------------------------------------------
 // Batched launches over many suspensions: each phase is one launch per kernel
 // variant (precision, sheared or not, pair-sum lanes, FFT size) for the whole
