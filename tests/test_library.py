@@ -97,3 +97,17 @@ def test_binding_constants_match_header():
             assert getattr(seasd, name) == value, name
             checked += 1
     assert checked >= 10
+
+
+def test_binding_rejects_bad_tensors_before_the_library():
+    """The binding's argument checks run on the host: host memory, a
+    non-tensor or an FP32 tensor is refused with TypeError before any pointer
+    reaches the library (the GPU tests cover short tensors)."""
+    import torch
+    pos = torch.zeros((8, 3), dtype=torch.float64)
+    with pytest.raises(TypeError):
+        seasd._require(pos, (None, 3), "pos")                  # host memory
+    with pytest.raises(TypeError):
+        seasd._require([0.0] * 24, (None, 3), "pos")           # not a tensor
+    with pytest.raises(TypeError):
+        seasd._require_sphere_arrays(pos.float(), torch.ones(8), None)
