@@ -371,15 +371,19 @@ static void fill_args(seasd_handle h, ApplyArgs& A, int64_t n, const double* pos
 
 // The product's second stream (created once per handle), forked from st.
 static int fork_side(seasd_handle h, hipStream_t st) {
-    if (!h->side) {
-        // default priority (as every stream here); ordered against st by events only
-        if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) {
-            h->side = nullptr;
-            return SEASD_E_HIP;
-        }
-        if (hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess)
-            return SEASD_E_HIP;
+    // each object is created once; one that failed is tried again on the next call
+    if (!h->ev_fork && hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess) {
+        h->ev_fork = nullptr;
+        return SEASD_E_HIP;
+    }
+    if (!h->ev_join && hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
+        h->ev_join = nullptr;
+        return SEASD_E_HIP;
+    }
+    // default priority (as every stream here); ordered against st by events only
+    if (!h->side && hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) {
+        h->side = nullptr;
+        return SEASD_E_HIP;
     }
     if (hipEventRecord(h->ev_fork, st) != hipSuccess || hipStreamWaitEvent(h->side, h->ev_fork, 0) != hipSuccess)
         return SEASD_E_HIP;
