@@ -27,6 +27,15 @@ f_n = ((1/r) d/dr)^n f, with
 and for erfc(xi r)/r the hierarchy is the standard upward recurrence
   B_0 = erfc(xi r)/r,  B_n = [(2n-1) B_(n-1) + (2 xi^2)^n exp(-xi^2 r^2)/(xi sqrt(pi))]/r^2,
   ((1/r) d/dr)^n erfc(xi r)/r = (-1)^n B_n.
+
+Pins (tests/test_oracle.py) fix every block of the sum against closed forms,
+printed values, finite differences and invariances, the periodic images of
+the velocity, spin and strain rows included. Parity unpinned: the absolute
+size of the periodic-image part of the velocity of a pressure-moment source
+(the trace column of the velocity row, and through the gradient relation of
+the strain row) and of the trace output row; the paper prints no value for
+them, and only their free-space limits, symmetry and xi-independence are
+checked.
 """
 from __future__ import annotations
 

@@ -294,6 +294,46 @@ def test_invariances(small_bidisperse):
     assert np.allclose(yr, _rotate_moments(y, R), rtol=0, atol=1e-13 * np.abs(y).max())
 
 
+@pytest.mark.parametrize("aj", [1.0, 1.5])
+def test_periodic_strain_row_is_the_gradient_of_the_velocity_row(aj):
+    """With a vanishing target radius the Faxen laws of the target reduce to
+    point values (Sec. 2.2: eqs. faxen-f, faxen-s), so in the periodic sum
+    the strain output of any source moment is the symmetric gradient of the
+    velocity output with respect to the target position. Checked by
+    fourth-order finite differences of the full Ewald sum in a box of edge 8,
+    where the periodic images carry 22-43 % of these couplings: the image
+    parts of E<-F, E<-S (whose velocity rows Hasimoto's array and the
+    symmetry M_US = M_EF^T fix) and E<-trace are pinned in absolute size."""
+    import dataclasses
+    Y = symbols.traceless_basis()
+    box = np.eye(3) * 8.0
+    d = np.array([2.1, -1.3, 2.6])
+    rad = np.array([0.0, aj])
+    p = ewald.converged_params(box, np.array([1.0, aj]), xi=0.6)
+    # the target carries no moments: its self part (1/a terms) is left out
+    p = dataclasses.replace(p, parts=ewald.PARTS_REAL | ewald.PARTS_WAVE)
+    x = np.zeros((2, 12, 12))
+    x[1] = np.eye(12)                      # every moment of the source, one per column
+
+    def y(q):
+        return ewald.apply(np.stack([q, np.zeros(3)]), rad, box, x, p, targets=np.array([0]))[0]
+
+    h = 5e-3
+    g = np.zeros((3, 3, 12))               # g[b, a, c] = d U_b / d q_a for source column c
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        g[:, a, :] = (-y(d + 2 * e)[0:3] + 8 * y(d + e)[0:3] - 8 * y(d - e)[0:3] + y(d - 2 * e)[0:3]) / (12 * h)
+    strain = np.einsum("mab,abc->mc", Y, 0.5 * (g + g.transpose(1, 0, 2)))
+    E = y(d)[6:11]
+    for cols in (slice(0, 3), slice(6, 11), slice(11, 12)):
+        ref = strain[:, cols]
+        assert np.linalg.norm(E[:, cols] - ref) < 1e-9 * np.linalg.norm(ref)
+        # a flipped sign or a dropped image sum fails by far more than the bound
+        free = ewald.pair_block_real(d, 0.0, aj, 0.0)[6:11, cols]
+        assert np.linalg.norm(free - ref) > 0.2 * np.linalg.norm(ref)
+
+
 def test_pair_image_correction_tends_to_hasimoto():
     # two spheres close together in a large box: the periodic coupling differs
     # from the free-space one by the self-image constant, -2.837297/(6 pi eta L)
