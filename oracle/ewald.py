@@ -30,12 +30,11 @@ and for erfc(xi r)/r the hierarchy is the standard upward recurrence
 
 Pins (tests/test_oracle.py) fix every block of the sum against closed forms,
 printed values, finite differences and invariances, the periodic images of
-the velocity, spin and strain rows included. Parity unpinned: the absolute
-size of the periodic-image part of the velocity of a pressure-moment source
-(the trace column of the velocity row, and through the gradient relation of
-the strain row) and of the trace output row; the paper prints no value for
-them, and only their free-space limits, symmetry and xi-independence are
-checked.
+the velocity, spin and strain rows included (for a pressure-moment source
+through the identities of its periodic source flow). Parity unpinned: the
+absolute size of the periodic-image part of the trace output row (the
+pressure Faxen read-out); the paper prints no value for it, and only its
+free-space limit, symmetry and xi-independence are checked.
 """
 from __future__ import annotations
 

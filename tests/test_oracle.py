@@ -334,6 +334,46 @@ def test_periodic_strain_row_is_the_gradient_of_the_velocity_row(aj):
         assert np.linalg.norm(free - ref) > 0.2 * np.linalg.norm(ref)
 
 
+def test_periodic_source_flow_identities():
+    """The velocity of a pressure-moment source (Sec. 2.3: a point source of
+    fluid, a potential flow) summed over the periodic images, with the k = 0
+    mode left out, is curl-free and has divergence -kappa / (4 eta V) away
+    from the source (the uniform sink that keeps the cell's volume fixed),
+    kappa the source strength of the free-space closed form; by the point
+    symmetry of the lattice it vanishes at the half-lattice points. Checked
+    with fourth-order finite differences of the full sum at a point target:
+    this fixes the image part of the velocity of a pressure moment (and
+    through the gradient relation of the strain row, of E<-trace)."""
+    import dataclasses
+    L, aj = 8.0, 1.0
+    box = np.eye(3) * L
+    rad = np.array([0.0, aj])
+    p = ewald.converged_params(box, np.array([1.0, aj]), xi=0.6)
+    p = dataclasses.replace(p, parts=ewald.PARTS_REAL | ewald.PARTS_WAVE)
+    x = np.zeros((2, 12))
+    x[1, 11] = 1.0
+
+    def u(q):
+        return ewald.apply(np.stack([q, np.zeros(3)]), rad, box, x, p, targets=np.array([0]))[0][0:3]
+
+    d0 = np.array([2.1, -1.3, 2.6])
+    free = ewald.pair_block_real(d0, 0.0, aj, 0.0)[0:3, 11]     # kappa d / (16 pi eta |d|^3)
+    kappa = float(free @ d0) * 16.0 * math.pi * np.linalg.norm(d0) ** 3 / float(d0 @ d0)
+    assert abs(kappa - math.sqrt(3.0)) < 1e-12   # trace coordinate s6 = tr(S)/sqrt(3)
+    for d in (d0, np.array([-3.0, 0.7, 1.1])):
+        h = 5e-3
+        g = np.zeros((3, 3))
+        for a in range(3):
+            e = np.zeros(3)
+            e[a] = h
+            g[:, a] = (-u(d + 2 * e) + 8 * u(d + e) - 8 * u(d - e) + u(d - 2 * e)) / (12 * h)
+        div = -kappa / (4.0 * L ** 3)
+        assert abs(np.trace(g) - div) < 1e-8 * abs(div)
+        assert np.linalg.norm(g - g.T) < 1e-9 * np.linalg.norm(g)
+    for d in ([L / 2, 0, 0], [0, L / 2, 0], [L / 2, L / 2, 0], [L / 2, L / 2, L / 2]):
+        assert np.linalg.norm(u(np.array(d, dtype=float))) < 1e-12 * np.linalg.norm(free)
+
+
 def test_pair_image_correction_tends_to_hasimoto():
     # two spheres close together in a large box: the periodic coupling differs
     # from the free-space one by the self-image constant, -2.837297/(6 pi eta L)
