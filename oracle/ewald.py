@@ -30,11 +30,11 @@ and for erfc(xi r)/r the hierarchy is the standard upward recurrence
 
 Pins (tests/test_oracle.py) fix every block of the sum against closed forms,
 printed values, finite differences and invariances, the periodic images of
-the velocity, spin and strain rows included (for a pressure-moment source
-through the identities of its periodic source flow). Parity unpinned: the
-absolute size of the periodic-image part of the trace output row (the
-pressure Faxen read-out); the paper prints no value for it, and only its
-free-space limit, symmetry and xi-independence are checked.
+the velocity, spin, strain and pressure read-out rows included: the image
+parts, for which the paper prints no value, are fixed by the identities the
+exact periodic fields satisfy (Hasimoto's array, symmetry, the gradient and
+curl relations between the read-outs, the source-flow divergence and Stokes'
+equations between pressure and velocity).
 """
 from __future__ import annotations
 

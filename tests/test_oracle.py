@@ -297,9 +297,10 @@ def test_invariances(small_bidisperse):
 @pytest.mark.parametrize("aj", [1.0, 1.5])
 def test_periodic_strain_row_is_the_gradient_of_the_velocity_row(aj):
     """With a vanishing target radius the Faxen laws of the target reduce to
-    point values (Sec. 2.2: eqs. faxen-f, faxen-s), so in the periodic sum
-    the strain output of any source moment is the symmetric gradient of the
-    velocity output with respect to the target position. Checked by
+    point values (Sec. 2.2: eqs. faxen-f, faxen-t, faxen-s), so in the
+    periodic sum the strain output of any source moment is the symmetric
+    gradient of the velocity output with respect to the target position, and
+    the spin output half its curl. Checked by
     fourth-order finite differences of the full Ewald sum in a box of edge 8,
     where the periodic images carry 22-43 % of these couplings: the image
     parts of E<-F, E<-S (whose velocity rows Hasimoto's array and the
@@ -325,7 +326,11 @@ def test_periodic_strain_row_is_the_gradient_of_the_velocity_row(aj):
         e[a] = h
         g[:, a, :] = (-y(d + 2 * e)[0:3] + 8 * y(d + e)[0:3] - 8 * y(d - e)[0:3] + y(d - 2 * e)[0:3]) / (12 * h)
     strain = np.einsum("mab,abc->mc", Y, 0.5 * (g + g.transpose(1, 0, 2)))
-    E = y(d)[6:11]
+    y0 = y(d)
+    # the spin read-out is half the curl of the velocity (eq. faxen-t)
+    curl = np.stack([g[2, 1] - g[1, 2], g[0, 2] - g[2, 0], g[1, 0] - g[0, 1]])
+    assert np.linalg.norm(y0[3:6] - 0.5 * curl) < 1e-9 * np.linalg.norm(0.5 * curl)
+    E = y0[6:11]
     for cols in (slice(0, 3), slice(6, 11), slice(11, 12)):
         ref = strain[:, cols]
         assert np.linalg.norm(E[:, cols] - ref) < 1e-9 * np.linalg.norm(ref)
@@ -372,6 +377,50 @@ def test_periodic_source_flow_identities():
         assert np.linalg.norm(g - g.T) < 1e-9 * np.linalg.norm(g)
     for d in ([L / 2, 0, 0], [0, L / 2, 0], [L / 2, L / 2, 0], [L / 2, L / 2, L / 2]):
         assert np.linalg.norm(u(np.array(d, dtype=float))) < 1e-12 * np.linalg.norm(free)
+
+
+def test_periodic_pressure_readout_obeys_stokes():
+    """The trace output row at a point target reads out the disturbance
+    pressure (pressure Faxen law, eq. faxen-p; the factor c is that of the
+    free-space closed form). Away from the sources the periodic fields obey
+    Stokes' equations, grad p = eta lap u - F / V for a force (the uniform
+    pressure gradient that carries the dropped k = 0 force) and grad p =
+    eta lap u for torques and stresslets. Checked with fourth-order finite
+    differences of the full sum (first derivatives of the pressure row,
+    second of the velocity row): this fixes the image part of the trace
+    output row of force, torque and stresslet sources through the velocity
+    rows."""
+    import dataclasses
+    L, aj = 8.0, 1.5
+    box = np.eye(3) * L
+    rad = np.array([0.0, aj])
+    p = ewald.converged_params(box, np.array([1.0, aj]), xi=0.6)
+    p = dataclasses.replace(p, parts=ewald.PARTS_REAL | ewald.PARTS_WAVE)
+    x = np.zeros((2, 12, 11))
+    x[1, :11] = np.eye(11)                 # force, torque and stresslet sources
+
+    def y(q):
+        return ewald.apply(np.stack([q, np.zeros(3)]), rad, box, x, p, targets=np.array([0]))[0]
+
+    d = np.array([2.1, -1.3, 2.6])
+    free = ewald.pair_block_real(d, 0.0, aj, 0.0)
+    c = float(free[11, 0:3] @ d) * 4.0 * math.pi * np.linalg.norm(d) ** 3 / float(d @ d)   # e6 = c p
+    y0 = y(d)
+    gp = np.zeros((3, 11))
+    lap = np.zeros((3, 11))
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = 5e-3
+        gp[a] = (-y(d + 2 * e)[11] + 8 * y(d + e)[11] - 8 * y(d - e)[11] + y(d - 2 * e)[11]) / (12 * 5e-3) / c
+        e[a] = 2e-2
+        lap += (-y(d + 2 * e)[0:3] + 16 * y(d + e)[0:3] - 30 * y0[0:3] + 16 * y(d - e)[0:3]
+                - y(d - 2 * e)[0:3]) / (12 * 2e-2 ** 2)
+    rhs = lap.copy()
+    rhs[:, 0:3] -= np.eye(3) / L ** 3
+    for cols in (slice(0, 3), slice(3, 11)):
+        assert np.linalg.norm(gp[:, cols] - rhs[:, cols]) < 1e-7 * np.linalg.norm(gp[:, cols])
+    # the background term is not negligible: its sign flipped misses by far
+    assert np.linalg.norm(gp[:, 0:3] - lap[:, 0:3] - np.eye(3) / L ** 3) > 0.5 * np.linalg.norm(gp[:, 0:3])
 
 
 def test_pair_image_correction_tends_to_hasimoto():
